@@ -1,0 +1,190 @@
+"""CPU oracle for the two-scale domain-decomposition Eikonal solver.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The oracle is a plain
+serial C implementation (eikref.c) of what the method computes, written from
+Martin & Tsai, arXiv 1805.04198, Sec. 1.1 (FSM, FMM) and Sec. 3.2 (the DD
+iteration).  It shares no code with the GPU library.
+
+Functions take numpy arrays (host memory) and return numpy arrays.  Winds
+are returned per axis: array of shape (d, N), int8, +1 = flow from the minus
+side (the upwind neighbour lies at the smaller index).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "eikref.c")
+_LIB = os.path.join(_HERE, "libeikref.so")
+
+STATUS = {0: "OK", -1: "ARG", -2: "SHAPE", -3: "NOCONV", -7: "NOMEM"}
+
+
+def build(force: bool = True) -> str:
+    """Compile eikref.c twice (double and float) into libeikref.so."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-std=c99", "-Wall",
+             "-Wno-unused-function"]
+    objs = []
+    for tag, defs in (("f64", ["-DREAL=double", "-DSFX=_f64"]),
+                      ("f32", ["-DREAL=float", "-DSFX=_f32", "-DORACLE_FLOAT"])):
+        obj = os.path.join(_HERE, f"eikref_{tag}.o")
+        subprocess.check_call(["gcc", *flags, *defs, "-c", _SRC, "-o", obj])
+        objs.append(obj)
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(["gcc", "-shared", "-o", tmp, *objs, "-lm"])
+    os.replace(tmp, _LIB)
+    for o in objs:
+        os.remove(o)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        vp = ctypes.c_void_p
+        for sfx in ("_f64", "_f32"):
+            f = getattr(L, "eikref_fsm" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp,
+                          ctypes.c_int, vp, vp, i64p]
+            f = getattr(L, "eikref_fmm" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp, vp]
+            f = getattr(L, "eikref_dd" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp,
+                          ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
+                          vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+            f = getattr(L, "eikref_local" + sfx)
+            f.restype = ctypes.c_int
+            rt = ctypes.c_float if sfx == "_f32" else ctypes.c_double
+            f.argtypes = [ctypes.c_int, vp, vp, rt, ctypes.c_int, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _sfx(dtype) -> str:
+    return "_f32" if np.dtype(dtype) == np.float32 else "_f64"
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def _prep(n, r, gidx, gval, dtype):
+    n64 = np.zeros(3, dtype=np.int64)
+    n64[: len(n)] = n
+    r = np.ascontiguousarray(np.asarray(r, dtype=dtype).reshape(-1))
+    gidx = np.ascontiguousarray(np.asarray(gidx, dtype=np.int64))
+    gval = np.ascontiguousarray(np.asarray(gval, dtype=dtype))
+    return n64, r, gidx, gval
+
+
+def fsm(n, h, r, gidx, gval, dtype=np.float64, max_sweeps=10000, with_info=False):
+    """u^f: FSM on the whole grid (Sec. 1.1).  Returns u, winds (d, N)."""
+    d = len(n)
+    n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
+    N = int(np.prod(n))
+    u = np.empty(N, dtype=dtype)
+    w = np.zeros(d * N, dtype=np.int8)
+    info = np.zeros(3, dtype=np.int64)
+    st = getattr(lib(), "eikref_fsm" + _sfx(dtype))(d, _i64(n64), float(h), _p(r), len(gidx),
+                                                    _i64(gidx), _p(gval), int(max_sweeps),
+                                                    _p(u), _p(w), _i64(info))
+    if st not in (0, -3):
+        raise ValueError(f"eikref_fsm: {STATUS.get(st, st)}")
+    out = (u, w.reshape(d, N))
+    if with_info:
+        return out + ({"sweeps": int(info[0]), "updates": int(info[1]), "converged": bool(info[2])},)
+    return out
+
+
+def fmm(n, h, r, gidx, gval, dtype=np.float64):
+    """Fast marching on the same discrete system (an independent solver)."""
+    d = len(n)
+    n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
+    N = int(np.prod(n))
+    u = np.empty(N, dtype=dtype)
+    st = getattr(lib(), "eikref_fmm" + _sfx(dtype))(d, _i64(n64), float(h), _p(r), len(gidx),
+                                                    _i64(gidx), _p(gval), _p(u))
+    if st != 0:
+        raise ValueError(f"eikref_fmm: {STATUS.get(st, st)}")
+    return u
+
+
+def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.float64,
+       max_fine_sweeps=256, max_coarse_sweeps=256, U_init=None, W_init=None, hist_cap=4096):
+    """The DD iteration of Sec. 3.2.  Returns a dict with the patched fine
+    solution u, coarse values U (NaN off the skeleton), coarse winds W (d, N),
+    the last iteration's reconciled fine values uk / winds wk, the last
+    corrected U before its causal sweep (Upre), and the counters."""
+    d = len(n)
+    n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
+    N = int(np.prod(n))
+    if max_iter is None:
+        max_iter = 4 * (int(n[0]) - 1) // M + 16
+    u = np.empty(N, dtype=dtype)
+    U = np.empty(N, dtype=dtype)
+    W = np.zeros(d * N, dtype=np.int8)
+    uk = np.empty(N, dtype=dtype)
+    wk = np.zeros(d * N, dtype=np.int8)
+    Upre = np.full(N, np.nan, dtype=dtype)
+    info = np.zeros(5, dtype=np.int64)
+    hist = np.zeros(max(1, hist_cap), dtype=np.float64)
+    Ui = None if U_init is None else np.ascontiguousarray(np.asarray(U_init, dtype=dtype).reshape(-1))
+    Wi = None if W_init is None else np.ascontiguousarray(np.asarray(W_init, dtype=np.int8).reshape(-1))
+    st = getattr(lib(), "eikref_dd" + _sfx(dtype))(
+        d, _i64(n64), float(h), _p(r), len(gidx), _i64(gidx), _p(gval), int(S), int(M),
+        float(theta), float(tol), int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps),
+        _p(Ui), _p(Wi), _p(u), _p(U), _p(W), _p(uk), _p(wk), _p(Upre), _i64(info),
+        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(hist_cap))
+    if st not in (0, -3):
+        raise ValueError(f"eikref_dd: {STATUS.get(st, st)}")
+    it = int(info[0])
+    return {"u": u, "U": U, "W": W.reshape(d, N), "uk": uk, "wk": wk.reshape(d, N),
+            "Upre": Upre, "iterations": it, "converged": bool(info[1]),
+            "fine_updates": int(info[2]), "coarse_updates": int(info[3]),
+            "status": int(info[4]), "residuals": hist[: min(it, hist_cap)].copy()}
+
+
+def local(m, ws, rd, rule=0, dtype=np.float64):
+    """The local solve alone (eq. godonuv in the closed form of C_H, with
+    the fine (rule 0, Alg. fineupdate2D) or coarse (rule 1, Alg. update2D)
+    wind rule).  m: per-axis neighbour minima, ws: their wind signs."""
+    d = len(m)
+    mm = np.full(3, np.inf, dtype=dtype)
+    mm[:d] = m
+    w = np.zeros(3, dtype=np.int8)
+    w[:d] = ws
+    wt = np.zeros(3, dtype=np.int8)
+    out = np.zeros(1, dtype=dtype)
+    st = getattr(lib(), "eikref_local" + _sfx(dtype))(d, _p(mm), _p(w), rd, int(rule), _p(wt), _p(out))
+    if st != 0:
+        raise ValueError("eikref_local")
+    return out[0], wt[:d].copy()
+
+
+def solve_problem(p, dtype=np.float64, **kw):
+    """Convenience: run dd() on a workloads.Problem."""
+    return dd(p.n, p.h, p.r_as(np.float64), p.gamma_idx, p.gamma_val.astype(np.float64),
+              p.S, p.M, theta=kw.pop("theta", p.theta), tol=kw.pop("tol", p.tol), dtype=dtype,
+              **kw)

@@ -1,0 +1,1120 @@
+/*
+ * eikref.c -- CPU ORACLE for the two-scale domain-decomposition Eikonal
+ * solver of Martin & Tsai (arXiv 1805.04198).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header or table with the GPU library: every step below is written out
+ * again, serially and plainly, from the paper.
+ *
+ * It is compiled twice: with REAL=double (the oracle proper) and with
+ * REAL=float (so that an fp32 kernel's discrete decisions -- winds, branch
+ * choices, stopping -- can be compared in the kernel's own precision).
+ * Build with -O2 -ffp-contract=off and without fast-math: every expression
+ * below is evaluated exactly as written, in REAL precision.
+ *
+ * Grid: d = 2 or 3 axes, n[a] nodes per axis, node (i,j,k) at linear index
+ * i + n0*(j + n1*k) (x fastest).  Winds are stored per axis as signed chars,
+ * array [a*N + node], with the flow-direction convention: component +1
+ * means the upwind neighbour lies on the minus side of that axis.
+ *
+ * Function map (paper section / algorithm):
+ *   local_solve      -- Godunov upwind scheme (eq. godonuv, Sec. 1.1) in the
+ *                       closed form of the coarse solver C_H (Sec. 3.2), with
+ *                       the wind rules of Alg. fineupdate2D (fine) and
+ *                       Alg. update2D (coarse); 3D by the sorted cascade.
+ *   fsm_run          -- fast sweeping method (Sec. 1.1: initialisation, the
+ *                       2^d orderings, eq. FSMupdate).
+ *   eikref_fsm       -- FSM on the whole fine grid: the "overall fine
+ *                       solution" u^f.
+ *   eikref_fmm       -- fast marching (Sec. 1.1), an independent solver of
+ *                       the same discrete system, used only to pin eikref_fsm.
+ *   eikref_dd        -- the domain-decomposition iteration of Sec. 3.2:
+ *                       Step 1 (coarse FSM on every shifted lattice with
+ *                       Alg. update2D, then Alg. causalsweep2D), Step 2
+ *                       (subdomain boundary data g), Step 3 (subdomain FSM with
+ *                       Alg. fineupdate2D, then Alg. fineupdate), Step 4
+ *                       (Alg. 2Dweightedupdate sweeps, then the causal sweep),
+ *                       repeated until max|U^{k+1}-U^k| < tol.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef REAL
+#define REAL double
+#endif
+#ifndef SFX
+#define SFX _f64
+#endif
+#define CAT2(a, b) a##b
+#define CAT(a, b) CAT2(a, b)
+#define NAME(x) CAT(x, SFX)
+
+typedef REAL real;
+#define RINF ((real)INFINITY)
+
+#if defined(ORACLE_FLOAT)
+#define RSQRT_(x) sqrtf(x)
+#define RABS_(x) fabsf(x)
+#else
+#define RSQRT_(x) sqrt(x)
+#define RABS_(x) fabs(x)
+#endif
+
+enum { OK = 0, ERR_ARG = -1, ERR_SHAPE = -2, ERR_NOCONV = -3, ERR_NOMEM = -7 };
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int d;
+    int64_t L[3];   /* extent per axis (1 for unused axes) */
+    int64_t st[3];  /* strides */
+    int64_t cnt;
+} box;
+
+static void box_init(box* B, int d, const int64_t* L) {
+    B->d = d;
+    for (int a = 0; a < 3; a++) B->L[a] = (a < d) ? L[a] : 1;
+    B->st[0] = 1;
+    B->st[1] = B->L[0];
+    B->st[2] = B->L[0] * B->L[1];
+    B->cnt = B->L[0] * B->L[1] * B->L[2];
+}
+
+static void box_coords(const box* B, int64_t idx, int64_t c[3]) {
+    c[0] = idx % B->L[0];
+    idx /= B->L[0];
+    c[1] = idx % B->L[1];
+    c[2] = idx / B->L[1];
+}
+
+/* Sweep direction number dir in [0, 2^d): the paper's loop nest takes
+ * s1 in {-1,+1} outermost, then s2 (then s3), so bit (d-1-a) of dir gives
+ * the sign of axis a. */
+static int dir_sign(int d, int dir, int a) { return ((dir >> (d - 1 - a)) & 1) ? 1 : -1; }
+
+/* ------------------------------------------------------------------ */
+/* local solve (eq. godonuv; closed form of C_H in Sec. 3.2)           */
+/* ------------------------------------------------------------------ */
+
+/* m[a]  : the smaller of the two neighbours along axis a (+inf if none)
+ * ws[a] : wind sign of that choice (+1: minus-side neighbour, -1: plus side;
+ *         ties take the plus side, as the strict '<' in the algorithms)
+ * rd    : r * Delta (Delta = h on the fine grid, H on a coarse lattice)
+ * rule  : 0 = fine wind rule (Alg. fineupdate2D), 1 = coarse (Alg. update2D)
+ * wt    : output wind of the candidate value */
+static real local_solve(int d, const real* m, const signed char* ws, real rd, int rule,
+                        signed char* wt) {
+    if (d == 2) {
+        real a = m[0], b = m[1];
+        real dd = a - b;
+        real ut;
+        int two = RABS_(dd) < rd;
+        if (two) {
+            real t = rd * rd;
+            t = t + t;
+            t = t - dd * dd;
+            ut = ((a + b) + RSQRT_(t)) * (real)0.5;
+        } else {
+            ut = (a < b) ? (a + rd) : (b + rd);
+        }
+        if (rule == 0) {
+            /* Alg. fineupdate2D: two-sided -> both axes; one-sided -> the
+             * axis of the smaller neighbour */
+            if (two) {
+                wt[0] = ws[0];
+                wt[1] = ws[1];
+            } else if (a < b) {
+                wt[0] = ws[0];
+                wt[1] = 0;
+            } else {
+                wt[0] = 0;
+                wt[1] = ws[1];
+            }
+        } else {
+            /* Alg. update2D: U~ < b -> x only; else U~ < a -> y only; else both */
+            if (ut < b) {
+                wt[0] = ws[0];
+                wt[1] = 0;
+            } else if (ut < a) {
+                wt[0] = 0;
+                wt[1] = ws[1];
+            } else {
+                wt[0] = ws[0];
+                wt[1] = ws[1];
+            }
+        }
+        return ut;
+    }
+    /* d == 3: sort the three axis minima ascending (stable in axis order),
+     * take the one-sided value, then the two-, then the three-sided root of
+     * sum_a ((u - m_a)^+)^2 = rd^2 as long as the next neighbour is below. */
+    int p[3] = {0, 1, 2};
+    for (int x = 1; x < 3; x++)
+        for (int y = x; y > 0 && m[p[y]] < m[p[y - 1]]; y--) {
+            int t = p[y];
+            p[y] = p[y - 1];
+            p[y - 1] = t;
+        }
+    real a1 = m[p[0]], a2 = m[p[1]], a3 = m[p[2]];
+    real ut;
+    int used;
+    real d12 = a1 - a2;
+    if (!(RABS_(d12) < rd)) {
+        ut = a1 + rd;
+        used = 1;
+    } else {
+        real t = rd * rd;
+        t = t + t;
+        t = t - d12 * d12;
+        real u2 = ((a1 + a2) + RSQRT_(t)) * (real)0.5;
+        if (!(a3 < u2)) {
+            ut = u2;
+            used = 2;
+        } else {
+            real d13 = a1 - a3, d23 = a2 - a3;
+            real q = rd * rd;
+            q = (q + q) + q;
+            q = q - ((d12 * d12 + d13 * d13) + d23 * d23);
+            if (q < (real)0) q = (real)0;
+            ut = (((a1 + a2) + a3) + RSQRT_(q)) / (real)3;
+            used = 3;
+        }
+    }
+    for (int a = 0; a < 3; a++) wt[a] = 0;
+    if (rule == 0) {
+        for (int x = 0; x < used; x++) wt[p[x]] = ws[p[x]];
+    } else {
+        /* coarse rule in 3D: an axis contributes unless U~ lies below its
+         * neighbour minimum (the 2D Alg. update2D tests, taken per axis) */
+        for (int a = 0; a < 3; a++) wt[a] = (ut < m[a]) ? 0 : ws[a];
+    }
+    return ut;
+}
+
+/* neighbour minima of node idx in box B along each axis */
+static void gather(const box* B, const real* u, int64_t idx, real* m, signed char* ws) {
+    int64_t c[3];
+    box_coords(B, idx, c);
+    for (int a = 0; a < B->d; a++) {
+        real lo = (c[a] > 0) ? u[idx - B->st[a]] : RINF;
+        real hi = (c[a] < B->L[a] - 1) ? u[idx + B->st[a]] : RINF;
+        if (lo < hi) {
+            m[a] = lo;
+            ws[a] = 1;
+        } else {
+            m[a] = hi;
+            ws[a] = -1;
+        }
+    }
+    for (int a = B->d; a < 3; a++) {
+        m[a] = RINF;
+        ws[a] = 0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* fast sweeping (Sec. 1.1)                                            */
+/* ------------------------------------------------------------------ */
+
+/* visit every node of box B in the lexicographic order of sweep dir
+ * (axis 0 outermost) and call fn on it */
+typedef int (*node_fn)(const box* B, int64_t idx, void* ctx);
+
+static int64_t sweep_box(const box* B, int dir, node_fn fn, void* ctx) {
+    int64_t changed = 0;
+    int s0 = dir_sign(B->d, dir, 0), s1 = dir_sign(B->d, dir, 1);
+    int s2 = (B->d == 3) ? dir_sign(B->d, dir, 2) : 1;
+    for (int64_t q0 = 0; q0 < B->L[0]; q0++) {
+        int64_t i = (s0 > 0) ? q0 : B->L[0] - 1 - q0;
+        for (int64_t q1 = 0; q1 < B->L[1]; q1++) {
+            int64_t j = (s1 > 0) ? q1 : B->L[1] - 1 - q1;
+            for (int64_t q2 = 0; q2 < B->L[2]; q2++) {
+                int64_t k = (s2 > 0) ? q2 : B->L[2] - 1 - q2;
+                changed += fn(B, i + B->L[0] * (j + B->L[1] * k), ctx);
+            }
+        }
+    }
+    return changed;
+}
+
+/* Sweep in the 2^d orders in turn until a whole sweep changes nothing.  A
+ * sweep that changes nothing has evaluated every node on the final state,
+ * so the state is then stationary for every ordering.  Returns 1 if that
+ * happened within max_sweeps, and the number of sweeps run. */
+static int run_sweeps(const box* B, int max_sweeps, node_fn fn, void* ctx, int64_t* nsweeps) {
+    int nd = 1 << B->d;
+    int64_t s = 0;
+    int conv = 0;
+    while (s < max_sweeps) {
+        int64_t ch = sweep_box(B, (int)(s % nd), fn, ctx);
+        s++;
+        if (ch == 0) {
+            conv = 1;
+            break;
+        }
+    }
+    *nsweeps = s;
+    return conv;
+}
+
+typedef struct {
+    real* u;
+    signed char* w;        /* [a*cnt + idx] */
+    const unsigned char* fixed;
+    const real* rd;        /* r*Delta per node */
+    int rule;
+} fsm_ctx;
+
+/* eq. FSMupdate: u_new = min(u_curr, u~), wind recorded with the value */
+static int fsm_node(const box* B, int64_t idx, void* vctx) {
+    fsm_ctx* C = (fsm_ctx*)vctx;
+    if (C->fixed[idx]) return 0;
+    real m[3];
+    signed char ws[3], wt[3];
+    gather(B, C->u, idx, m, ws);
+    real ut = local_solve(B->d, m, ws, C->rd[idx], C->rule, wt);
+    if (ut < C->u[idx]) {
+        C->u[idx] = ut;
+        for (int a = 0; a < B->d; a++) C->w[a * B->cnt + idx] = wt[a];
+        return 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* argument checks                                                     */
+/* ------------------------------------------------------------------ */
+
+static int check_problem(int d, const int64_t* n, double h, const real* r, int64_t ng,
+                         const int64_t* gidx, const real* gval, int64_t* Nout) {
+    if (d != 2 && d != 3) return ERR_ARG;
+    if (!(h > 0) || !isfinite(h)) return ERR_ARG;
+    int64_t N = 1;
+    for (int a = 0; a < d; a++) {
+        if (n[a] < 2) return ERR_SHAPE;
+        N *= n[a];
+    }
+    for (int64_t x = 0; x < N; x++)
+        if (!(r[x] > 0) || !isfinite((double)r[x])) return ERR_ARG;
+    if (ng < 0) return ERR_ARG;
+    for (int64_t g = 0; g < ng; g++) {
+        if (gidx[g] < 0 || gidx[g] >= N) return ERR_ARG;
+        if (g > 0 && gidx[g] <= gidx[g - 1]) return ERR_ARG;
+        if (!isfinite((double)gval[g])) return ERR_ARG;
+    }
+    *Nout = N;
+    return OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* FSM on the whole fine grid: u^f                                     */
+/* ------------------------------------------------------------------ */
+
+/* info[0] = sweeps run, info[1] = local solves evaluated (free nodes x
+ * sweeps), info[2] = 1 if stationary.  w may be NULL. */
+int NAME(eikref_fsm)(int d, const int64_t* n, double h, const real* r, int64_t ng,
+                     const int64_t* gidx, const real* gval, int max_sweeps, real* u,
+                     signed char* w, int64_t* info) {
+    int64_t N;
+    int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
+    if (st != OK) return st;
+    box B;
+    box_init(&B, d, n);
+    real hT = (real)h;
+    unsigned char* fixed = (unsigned char*)calloc((size_t)N, 1);
+    real* rd = (real*)malloc(sizeof(real) * (size_t)N);
+    signed char* ww = (signed char*)calloc((size_t)(d * N), 1);
+    if (!fixed || !rd || !ww) {
+        free(fixed);
+        free(rd);
+        free(ww);
+        return ERR_NOMEM;
+    }
+    for (int64_t x = 0; x < N; x++) {
+        u[x] = RINF;
+        rd[x] = r[x] * hT;
+    }
+    /* initialisation: boundary data fixed, all else a large value (+inf) */
+    for (int64_t g = 0; g < ng; g++) {
+        fixed[gidx[g]] = 1;
+        u[gidx[g]] = gval[g];
+    }
+    fsm_ctx C = {u, ww, fixed, rd, 0};
+    int64_t ns = 0;
+    int conv = run_sweeps(&B, max_sweeps, fsm_node, &C, &ns);
+    if (info) {
+        info[0] = ns;
+        info[1] = (N - ng) * ns;
+        info[2] = conv;
+    }
+    if (w) memcpy(w, ww, (size_t)(d * N));
+    free(fixed);
+    free(rd);
+    free(ww);
+    return conv ? OK : ERR_NOCONV;
+}
+
+/* ------------------------------------------------------------------ */
+/* fast marching on the same discrete system (independent check)       */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    real* key;
+    int64_t* node;
+    int64_t* pos;  /* heap position per grid node, -1 if absent */
+    int64_t size;
+} heap;
+
+static void heap_swap(heap* Hp, int64_t a, int64_t b) {
+    real k = Hp->key[a];
+    Hp->key[a] = Hp->key[b];
+    Hp->key[b] = k;
+    int64_t t = Hp->node[a];
+    Hp->node[a] = Hp->node[b];
+    Hp->node[b] = t;
+    Hp->pos[Hp->node[a]] = a;
+    Hp->pos[Hp->node[b]] = b;
+}
+
+static void heap_up(heap* Hp, int64_t x) {
+    while (x > 0) {
+        int64_t p = (x - 1) / 2;
+        if (Hp->key[x] < Hp->key[p]) {
+            heap_swap(Hp, x, p);
+            x = p;
+        } else
+            break;
+    }
+}
+
+static void heap_down(heap* Hp, int64_t x) {
+    for (;;) {
+        int64_t l = 2 * x + 1, r = l + 1, m = x;
+        if (l < Hp->size && Hp->key[l] < Hp->key[m]) m = l;
+        if (r < Hp->size && Hp->key[r] < Hp->key[m]) m = r;
+        if (m == x) break;
+        heap_swap(Hp, x, m);
+        x = m;
+    }
+}
+
+static void heap_push_or_decrease(heap* Hp, int64_t node, real key) {
+    int64_t p = Hp->pos[node];
+    if (p < 0) {
+        p = Hp->size++;
+        Hp->key[p] = key;
+        Hp->node[p] = node;
+        Hp->pos[node] = p;
+        heap_up(Hp, p);
+    } else if (key < Hp->key[p]) {
+        Hp->key[p] = key;
+        heap_up(Hp, p);
+    }
+}
+
+static int64_t heap_pop(heap* Hp) {
+    int64_t node = Hp->node[0];
+    Hp->pos[node] = -1;
+    Hp->size--;
+    if (Hp->size > 0) {
+        Hp->key[0] = Hp->key[Hp->size];
+        Hp->node[0] = Hp->node[Hp->size];
+        Hp->pos[Hp->node[0]] = 0;
+        heap_down(Hp, 0);
+    }
+    return node;
+}
+
+/* Nodes are accepted in increasing value order; a trial node's value is
+ * the local solve over its accepted neighbours only. */
+int NAME(eikref_fmm)(int d, const int64_t* n, double h, const real* r, int64_t ng,
+                     const int64_t* gidx, const real* gval, real* u) {
+    int64_t N;
+    int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
+    if (st != OK) return st;
+    box B;
+    box_init(&B, d, n);
+    real hT = (real)h;
+    unsigned char* acc = (unsigned char*)calloc((size_t)N, 1);
+    unsigned char* fixed = (unsigned char*)calloc((size_t)N, 1);
+    real* known = (real*)malloc(sizeof(real) * (size_t)N);
+    heap Hp;
+    Hp.key = (real*)malloc(sizeof(real) * (size_t)N);
+    Hp.node = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    Hp.pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
+    Hp.size = 0;
+    if (!acc || !fixed || !known || !Hp.key || !Hp.node || !Hp.pos) {
+        free(acc); free(fixed); free(known); free(Hp.key); free(Hp.node); free(Hp.pos);
+        return ERR_NOMEM;
+    }
+    for (int64_t x = 0; x < N; x++) {
+        u[x] = RINF;
+        known[x] = RINF;
+        Hp.pos[x] = -1;
+    }
+    for (int64_t g = 0; g < ng; g++) {
+        fixed[gidx[g]] = 1;
+        u[gidx[g]] = gval[g];
+        heap_push_or_decrease(&Hp, gidx[g], gval[g]);
+    }
+    while (Hp.size > 0) {
+        int64_t x = heap_pop(&Hp);
+        acc[x] = 1;
+        known[x] = u[x];
+        int64_t c[3];
+        box_coords(&B, x, c);
+        for (int a = 0; a < d; a++) {
+            for (int sg = -1; sg <= 1; sg += 2) {
+                int64_t cc = c[a] + sg;
+                if (cc < 0 || cc >= B.L[a]) continue;
+                int64_t y = x + sg * B.st[a];
+                if (acc[y] || fixed[y]) continue;
+                real m[3];
+                signed char ws[3], wt[3];
+                gather(&B, known, y, m, ws);
+                real ut = local_solve(d, m, ws, r[y] * hT, 0, wt);
+                if (ut < u[y]) {
+                    u[y] = ut;
+                    heap_push_or_decrease(&Hp, y, ut);
+                }
+            }
+        }
+    }
+    free(acc); free(fixed); free(known); free(Hp.key); free(Hp.node); free(Hp.pos);
+    return OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* the domain-decomposition iteration (Sec. 3.2)                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int d;
+    int64_t n[3], st[3], N;
+    int S, M;
+    int64_t P[3];   /* subdomains per axis */
+    real hT, HT, thetaT;
+    const real* r;
+    unsigned char* isg;   /* Gamma flag per node */
+    real* gv;             /* Gamma data per node */
+} ddp;
+
+static void node_coords(const ddp* D, int64_t x, int64_t c[3]) {
+    c[0] = x % D->n[0];
+    x /= D->n[0];
+    c[1] = x % D->n[1];
+    c[2] = x / D->n[1];
+    if (D->d == 2) c[2] = 0;
+}
+
+static int64_t node_index(const ddp* D, const int64_t c[3]) {
+    return c[0] + D->n[0] * (c[1] + D->n[1] * (D->d == 3 ? c[2] : 0));
+}
+
+/* a coarse node lies on a coarse grid line/plane: some index = 0 mod M */
+static int is_coarse(const ddp* D, const int64_t c[3]) {
+    for (int a = 0; a < D->d; a++)
+        if (c[a] % D->M == 0) return 1;
+    return 0;
+}
+
+/* axis a is an interface axis of the node: the node lies on a subdomain
+ * boundary plane that is not the domain boundary */
+static int is_iface_axis(const ddp* D, const int64_t c[3], int a) {
+    return (c[a] % D->S == 0) && c[a] > 0 && c[a] < D->n[a] - 1;
+}
+
+/* ---- one coarse lattice as a dense box ---- */
+typedef struct {
+    int64_t off[3];   /* offsets in [0, M) */
+    box B;
+} lattice;
+
+/* number of lattices = offsets in [0,M)^d with at least one zero */
+static int64_t lattice_list(const ddp* D, lattice** out) {
+    int64_t M = D->M;
+    int64_t tot = (D->d == 2) ? M * M : M * M * M;
+    lattice* L = (lattice*)malloc(sizeof(lattice) * (size_t)tot);
+    int64_t cnt = 0;
+    for (int64_t o0 = 0; o0 < M; o0++)
+        for (int64_t o1 = 0; o1 < M; o1++)
+            for (int64_t o2 = 0; o2 < (D->d == 3 ? M : 1); o2++) {
+                int64_t o[3] = {o0, o1, o2};
+                int z = 0;
+                for (int a = 0; a < D->d; a++) z |= (o[a] == 0);
+                if (!z) continue;
+                lattice* l = &L[cnt++];
+                int64_t ext[3];
+                for (int a = 0; a < 3; a++) {
+                    l->off[a] = o[a];
+                    ext[a] = (a < D->d) ? (D->n[a] - 1 - o[a]) / M + 1 : 1;
+                }
+                box_init(&l->B, D->d, ext);
+            }
+    *out = L;
+    return cnt;
+}
+
+static int64_t lattice_global(const ddp* D, const lattice* l, int64_t li) {
+    int64_t p[3], c[3];
+    box_coords(&l->B, li, p);
+    for (int a = 0; a < 3; a++) c[a] = l->off[a] + p[a] * D->M;
+    return node_index(D, c);
+}
+
+/* ---- Step 1: coarse initialisation on every lattice ---- */
+static int64_t step1_init(const ddp* D, real* U, signed char* W, int max_sweeps,
+                          int64_t ng, const int64_t* gidx, const real* gval) {
+    lattice* L;
+    int64_t nl = lattice_list(D, &L);
+    int64_t upd = 0;
+    int d = D->d;
+    for (int64_t q = 0; q < nl; q++) {
+        lattice* l = &L[q];
+        int64_t cnt = l->B.cnt;
+        real* u = (real*)malloc(sizeof(real) * (size_t)cnt);
+        real* rd = (real*)malloc(sizeof(real) * (size_t)cnt);
+        signed char* w = (signed char*)calloc((size_t)(d * cnt), 1);
+        unsigned char* fixed = (unsigned char*)calloc((size_t)cnt, 1);
+        int64_t nfree = 0;
+        for (int64_t li = 0; li < cnt; li++) {
+            int64_t X = lattice_global(D, l, li);
+            int64_t c[3];
+            node_coords(D, X, c);
+            rd[li] = D->r[X] * D->HT;
+            u[li] = RINF;
+            /* Initialisation "on or near" the boundary: lattice nodes within
+             * max-norm distance < H of a Gamma node start at the smallest
+             * g + r*|X - x_g| (wind: direction from x_g to X); Gamma nodes
+             * themselves are included at distance 0. */
+            real best = RINF;
+            int64_t bestg = -1;
+            if (D->isg[X]) {
+                /* a Gamma node keeps its own boundary value, wind 0 */
+                fixed[li] = 1;
+                u[li] = D->gv[X];
+                continue;
+            }
+            for (int64_t g = 0; g < ng; g++) {
+                int64_t cg[3];
+                node_coords(D, gidx[g], cg);
+                int near = 1;
+                int64_t d2 = 0;
+                for (int a = 0; a < d; a++) {
+                    int64_t df = c[a] - cg[a];
+                    if (df <= -D->M || df >= D->M) near = 0;
+                    d2 += df * df;
+                }
+                if (!near) continue;
+                real sq = RSQRT_((real)d2);
+                real dist = D->hT * sq;
+                real v = gval[g] + D->r[X] * dist;
+                if (v < best) {
+                    best = v;
+                    bestg = g;
+                }
+            }
+            if (bestg >= 0) {
+                fixed[li] = 1;
+                u[li] = best;
+                int64_t cg[3];
+                node_coords(D, gidx[bestg], cg);
+                for (int a = 0; a < d; a++) {
+                    int64_t df = c[a] - cg[a];
+                    w[a * cnt + li] = (signed char)((df > 0) - (df < 0));
+                }
+            } else {
+                nfree++;
+            }
+        }
+        fsm_ctx C = {u, w, fixed, rd, 1};
+        int64_t ns = 0;
+        run_sweeps(&l->B, max_sweeps, fsm_node, &C, &ns);
+        upd += nfree * ns;
+        for (int64_t li = 0; li < cnt; li++) {
+            int64_t X = lattice_global(D, l, li);
+            U[X] = u[li];
+            for (int a = 0; a < d; a++) W[a * D->N + X] = w[a * cnt + li];
+        }
+        free(u);
+        free(rd);
+        free(w);
+        free(fixed);
+    }
+    free(L);
+    return upd;
+}
+
+/* ---- causal sweep (Alg. causalsweep2D) ----
+ * The 2^d directions once each, every coarse node in lexicographic fine-index
+ * order.  At a non-Gamma coarse node X and for each axis e (x, y, z in turn):
+ *   if W_e(X) < 0 (flow from the plus side) and U(X) < U(X+e): U(X) = U(X+e)
+ *   if W_e(X) > 0 (flow from the minus side) and U(X) < U(X-e): U(X) = U(X-e)
+ * where each comparison needs that fine neighbour to be a coarse node. */
+static void causal_sweep(const ddp* D, real* U, const signed char* W) {
+    box B;
+    box_init(&B, D->d, D->n);
+    int nd = 1 << D->d;
+    for (int dir = 0; dir < nd; dir++) {
+        int s0 = dir_sign(D->d, dir, 0), s1 = dir_sign(D->d, dir, 1);
+        int s2 = (D->d == 3) ? dir_sign(D->d, dir, 2) : 1;
+        for (int64_t q0 = 0; q0 < B.L[0]; q0++) {
+            int64_t i = (s0 > 0) ? q0 : B.L[0] - 1 - q0;
+            for (int64_t q1 = 0; q1 < B.L[1]; q1++) {
+                int64_t j = (s1 > 0) ? q1 : B.L[1] - 1 - q1;
+                for (int64_t q2 = 0; q2 < B.L[2]; q2++) {
+                    int64_t k = (s2 > 0) ? q2 : B.L[2] - 1 - q2;
+                    int64_t c[3] = {i, j, k};
+                    if (!is_coarse(D, c)) continue;
+                    int64_t X = node_index(D, c);
+                    if (D->isg[X]) continue;
+                    for (int e = 0; e < D->d; e++) {
+                        int we = W[e * D->N + X];
+                        if (we < 0 && c[e] + 1 < D->n[e]) {
+                            int64_t cn[3] = {c[0], c[1], c[2]};
+                            cn[e] += 1;
+                            if (is_coarse(D, cn)) {
+                                int64_t Y = X + D->st[e];
+                                if (U[X] < U[Y]) U[X] = U[Y];
+                            }
+                        }
+                        if (we > 0 && c[e] > 0) {
+                            int64_t cn[3] = {c[0], c[1], c[2]};
+                            cn[e] -= 1;
+                            if (is_coarse(D, cn)) {
+                                int64_t Y = X - D->st[e];
+                                if (U[X] < U[Y]) U[X] = U[Y];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* ---- Steps 2 and 3 on one subdomain ----
+ * Step 2: nodes of the subdomain that are Gamma nodes are fixed at g (wind 0);
+ * a boundary node of the subdomain lying on an interface (a subdomain
+ * boundary that is not the domain boundary) is fixed at U with its wind W if
+ * W . n_in > 0 for an inward normal n_in of the subdomain there (a corner has
+ * one normal per interface axis); every other node is free and starts at
+ * +inf (boundary data "infinity").  Step 3: FSM on the subdomain grid with
+ * one-sided differences at its boundary. */
+static int64_t tile_solve(const ddp* D, const int64_t T[3], const real* U, const signed char* W,
+                          real* tu, signed char* tw, int max_sweeps) {
+    int d = D->d;
+    int64_t ext[3] = {D->S + 1, D->S + 1, D->S + 1};
+    box B;
+    box_init(&B, d, ext);
+    int64_t cnt = B.cnt;
+    real* rd = (real*)malloc(sizeof(real) * (size_t)cnt);
+    unsigned char* fixed = (unsigned char*)calloc((size_t)cnt, 1);
+    int64_t nfree = 0;
+    for (int64_t li = 0; li < cnt; li++) {
+        int64_t lc[3], c[3];
+        box_coords(&B, li, lc);
+        for (int a = 0; a < 3; a++) c[a] = (a < d) ? T[a] * D->S + lc[a] : 0;
+        int64_t X = node_index(D, c);
+        rd[li] = D->r[X] * D->hT;
+        tu[li] = RINF;
+        for (int a = 0; a < d; a++) tw[a * cnt + li] = 0;
+        if (D->isg[X]) {
+            fixed[li] = 1;
+            tu[li] = D->gv[X];
+            continue;
+        }
+        int inflow = 0;
+        for (int a = 0; a < d; a++) {
+            if (!is_iface_axis(D, c, a)) continue;
+            int we = W[a * D->N + X];
+            if (lc[a] == 0 && we > 0) inflow = 1;          /* inward normal +e_a */
+            if (lc[a] == D->S && we < 0) inflow = 1;       /* inward normal -e_a */
+        }
+        if (inflow) {
+            tu[li] = U[X];
+            for (int a = 0; a < d; a++) tw[a * cnt + li] = W[a * D->N + X];
+        }
+        nfree++;
+    }
+    fsm_ctx C = {tu, tw, fixed, rd, 0};
+    int64_t ns = 0;
+    run_sweeps(&B, max_sweeps, fsm_node, &C, &ns);
+    free(rd);
+    free(fixed);
+    return nfree * ns;
+}
+
+/* ---- reconciliation at a node (Alg. fineupdate, one axis at a time) ----
+ * Candidates: the subdomains containing X, ordered lexicographically with x
+ * slowest and the minus side first.  Candidates at +inf are set aside unless
+ * all are.  For each interface axis e: if every remaining candidate's fine
+ * wind and the coarse wind W^k satisfy w . (-e) >= 0, the plus-side
+ * subdomains are kept; otherwise if all satisfy w . e >= 0 the minus side is
+ * kept; otherwise both.  u^k is the smallest kept value (first candidate on
+ * ties), w^k its wind.  If no candidate survives the side filter, the
+ * smallest finite one is taken. */
+typedef struct {
+    real u;
+    signed char w[3];
+    int side[3];  /* 0 = minus, 1 = plus (only for interface axes) */
+} cand;
+
+static void reconcile_node(int d, const cand* cs, int nc, const int* iface, const signed char* Wk,
+                           real* uk, signed char* wk) {
+    int fin[8], nf = 0;
+    for (int x = 0; x < nc; x++)
+        if (cs[x].u < RINF) fin[nf++] = x;
+    if (nf == 0) {
+        for (int x = 0; x < nc; x++) fin[nf++] = x;
+    }
+    int allow[3][2];
+    for (int e = 0; e < 3; e++) allow[e][0] = allow[e][1] = 1;
+    for (int e = 0; e < d; e++) {
+        if (!iface[e]) continue;
+        int le = (Wk[e] <= 0), ge = (Wk[e] >= 0);
+        for (int y = 0; y < nf; y++) {
+            int we = cs[fin[y]].w[e];
+            le = le && (we <= 0);
+            ge = ge && (we >= 0);
+        }
+        if (le) {
+            allow[e][0] = 0;  /* keep plus side */
+        } else if (ge) {
+            allow[e][1] = 0;  /* keep minus side */
+        }
+    }
+    int best = -1;
+    for (int y = 0; y < nf; y++) {
+        const cand* c = &cs[fin[y]];
+        int ok = 1;
+        for (int e = 0; e < d; e++)
+            if (iface[e] && !allow[e][c->side[e]]) ok = 0;
+        if (!ok) continue;
+        if (best < 0 || c->u < cs[best].u) best = fin[y];
+    }
+    if (best < 0) {
+        for (int y = 0; y < nf; y++)
+            if (best < 0 || cs[fin[y]].u < cs[best].u) best = fin[y];
+    }
+    *uk = cs[best].u;
+    for (int e = 0; e < d; e++) wk[e] = cs[best].w[e];
+}
+
+/* ---- Step 4 on one lattice (Alg. 2Dweightedupdate) ---- */
+typedef struct {
+    const ddp* D;
+    const lattice* l;
+    real* u;                /* current U on the lattice */
+    const real* Uk;         /* U^k */
+    const real* uk;         /* reconciled fine values u^k */
+    const real* Ck;         /* C_H(nbrs^H(U^k)) */
+    const signed char* wk;  /* [a*cnt+li] */
+    const signed char* Wk;
+    const real* rd;
+    const unsigned char* fixed;
+    const unsigned char* normal;  /* bit a set: axis a is a normal of the node's coarse line */
+} corr_ctx;
+
+static int corr_node(const box* B, int64_t li, void* vctx) {
+    corr_ctx* C = (corr_ctx*)vctx;
+    if (C->fixed[li]) return 0;
+    int d = B->d;
+    real m[3];
+    signed char ws[3], wt[3];
+    gather(B, C->u, li, m, ws);
+    real Ut = local_solve(d, m, ws, C->rd[li], 1, wt);
+    int cond = 1;
+    for (int e = 0; e < d; e++) {
+        if (!((C->normal[li] >> e) & 1)) continue;
+        int a = C->wk[e * B->cnt + li], b = C->Wk[e * B->cnt + li], t = wt[e];
+        int le = (a <= 0) && (b <= 0) && (t <= 0);
+        int ge = (a >= 0) && (b >= 0) && (t >= 0);
+        if (!(le || ge)) cond = 0;
+    }
+    real v;
+    if (cond && isfinite((double)Ut) && isfinite((double)C->Ck[li]))
+        v = C->uk[li] + C->D->thetaT * (Ut - C->Ck[li]);
+    else
+        v = C->uk[li];
+    if (v != C->u[li]) {
+        C->u[li] = v;
+        return 1;
+    }
+    return 0;
+}
+
+static int64_t step4_correct(const ddp* D, const real* Uk, const signed char* Wk, const real* ukg,
+                             const signed char* wkg, real* Un, signed char* Wn, int max_sweeps) {
+    lattice* L;
+    int64_t nl = lattice_list(D, &L);
+    int d = D->d;
+    int64_t upd = 0;
+    for (int64_t q = 0; q < nl; q++) {
+        lattice* l = &L[q];
+        int64_t cnt = l->B.cnt;
+        real* u = (real*)malloc(sizeof(real) * cnt);
+        real* lUk = (real*)malloc(sizeof(real) * cnt);
+        real* luk = (real*)malloc(sizeof(real) * cnt);
+        real* lCk = (real*)malloc(sizeof(real) * cnt);
+        real* rd = (real*)malloc(sizeof(real) * cnt);
+        signed char* lwk = (signed char*)malloc((size_t)(d * cnt));
+        signed char* lWk = (signed char*)malloc((size_t)(d * cnt));
+        unsigned char* fixed = (unsigned char*)calloc((size_t)cnt, 1);
+        unsigned char* normal = (unsigned char*)calloc((size_t)cnt, 1);
+        int64_t nfree = 0;
+        for (int64_t li = 0; li < cnt; li++) {
+            int64_t X = lattice_global(D, l, li);
+            int64_t c[3];
+            node_coords(D, X, c);
+            lUk[li] = Uk[X];
+            luk[li] = ukg[X];
+            rd[li] = D->r[X] * D->HT;
+            for (int a = 0; a < d; a++) {
+                lwk[a * cnt + li] = wkg[a * D->N + X];
+                lWk[a * cnt + li] = Wk[a * D->N + X];
+                if (c[a] % D->M == 0) normal[li] |= (unsigned char)(1 << a);
+            }
+            if (D->isg[X]) {
+                fixed[li] = 1;
+                u[li] = D->gv[X];
+            } else {
+                u[li] = RINF;
+                nfree++;
+            }
+        }
+        /* C^k = C_H(nbrs^H(U^k)) at every node, evaluated once (Jacobi) */
+        for (int64_t li = 0; li < cnt; li++) {
+            real m[3];
+            signed char ws[3], wt[3];
+            gather(&l->B, lUk, li, m, ws);
+            lCk[li] = local_solve(d, m, ws, rd[li], 1, wt);
+        }
+        corr_ctx C = {D, l, u, lUk, luk, lCk, lwk, lWk, rd, fixed, normal};
+        int64_t ns = 0;
+        run_sweeps(&l->B, max_sweeps, corr_node, &C, &ns);
+        upd += nfree * ns;
+        for (int64_t li = 0; li < cnt; li++) {
+            int64_t X = lattice_global(D, l, li);
+            Un[X] = u[li];
+            for (int a = 0; a < d; a++) Wn[a * D->N + X] = fixed[li] ? 0 : lwk[a * cnt + li];
+        }
+        free(u); free(lUk); free(luk); free(lCk); free(rd); free(lwk); free(lWk);
+        free(fixed); free(normal);
+    }
+    free(L);
+    return upd;
+}
+
+/* info: [0] iterations, [1] converged, [2] fine updates (Step 3 local solves),
+ *       [3] coarse updates (Steps 1 and 4 local solves), [4] status
+ * hist: max|U^{k+1}-U^k| per iteration (up to hist_cap entries) */
+int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng,
+                    const int64_t* gidx, const real* gval, int S, int M, double theta,
+                    double tol, int max_iter, int max_fine_sweeps, int max_coarse_sweeps,
+                    const real* U_init, const signed char* W_init, real* u_out, real* U_out,
+                    signed char* W_out, real* uk_out, signed char* wk_out, real* Upre_out,
+                    int64_t* info, double* hist, int hist_cap) {
+    int64_t N;
+    int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
+    if (st != OK) return st;
+    if (M < 2 || S < M || S % M != 0) return ERR_SHAPE;
+    if (!(theta >= 0.0 && theta <= 1.0)) return ERR_ARG;
+    if (max_iter < 0 || max_fine_sweeps < 1 || max_coarse_sweeps < 1) return ERR_ARG;
+    ddp D;
+    memset(&D, 0, sizeof(D));
+    D.d = d;
+    D.N = N;
+    D.S = S;
+    D.M = M;
+    for (int a = 0; a < 3; a++) {
+        D.n[a] = (a < d) ? n[a] : 1;
+        if (a < d && (n[a] - 1) % S != 0) return ERR_SHAPE;
+        D.P[a] = (a < d) ? (n[a] - 1) / S : 1;
+    }
+    D.st[0] = 1;
+    D.st[1] = D.n[0];
+    D.st[2] = D.n[0] * D.n[1];
+    D.hT = (real)h;
+    D.HT = (real)((double)M * h);
+    D.thetaT = (real)theta;
+    D.r = r;
+    D.isg = (unsigned char*)calloc((size_t)N, 1);
+    D.gv = (real*)calloc((size_t)N, sizeof(real));
+    for (int64_t g = 0; g < ng; g++) {
+        D.isg[gidx[g]] = 1;
+        D.gv[gidx[g]] = gval[g];
+    }
+
+    real* U = (real*)malloc(sizeof(real) * N);
+    real* Un = (real*)malloc(sizeof(real) * N);
+    real* uk = (real*)malloc(sizeof(real) * N);
+    signed char* W = (signed char*)calloc((size_t)(d * N), 1);
+    signed char* Wn = (signed char*)calloc((size_t)(d * N), 1);
+    signed char* wk = (signed char*)calloc((size_t)(d * N), 1);
+    int64_t ntile = D.P[0] * D.P[1] * D.P[2];
+    int64_t V = 1;
+    for (int a = 0; a < d; a++) V *= (S + 1);
+    real* tu = (real*)malloc(sizeof(real) * (size_t)(ntile * V));
+    signed char* tw = (signed char*)malloc((size_t)(ntile * V * d));
+    for (int64_t x = 0; x < N; x++) {
+        U[x] = (real)NAN;
+        uk[x] = (real)NAN;
+        u_out[x] = (real)NAN;
+    }
+
+    int64_t coarse_upd = 0, fine_upd = 0;
+    if (U_init) {
+        for (int64_t x = 0; x < N; x++) {
+            int64_t c[3];
+            node_coords(&D, x, c);
+            if (is_coarse(&D, c)) U[x] = U_init[x];
+        }
+        if (W_init) memcpy(W, W_init, (size_t)(d * N));
+    } else {
+        coarse_upd += step1_init(&D, U, W, max_coarse_sweeps, ng, gidx, gval);
+        causal_sweep(&D, U, W);
+    }
+
+    int it = 0, conv = 0;
+    for (int k = 0; k < max_iter; k++) {
+        /* Steps 2-3: every subdomain independently */
+        for (int64_t t = 0; t < ntile; t++) {
+            int64_t T[3] = {t % D.P[0], (t / D.P[0]) % D.P[1], t / (D.P[0] * D.P[1])};
+            fine_upd += tile_solve(&D, T, U, W, tu + t * V, tw + t * V * d, max_fine_sweeps);
+        }
+        /* reconciliation at coarse nodes and the patched fine solution */
+        for (int64_t X = 0; X < N; X++) {
+            int64_t c[3];
+            node_coords(&D, X, c);
+            int iface[3] = {0, 0, 0};
+            int64_t tl[3][2];
+            int ns[3];
+            for (int a = 0; a < 3; a++) {
+                if (a >= d) {
+                    tl[a][0] = 0;
+                    ns[a] = 1;
+                    continue;
+                }
+                if (is_iface_axis(&D, c, a)) {
+                    iface[a] = 1;
+                    tl[a][0] = c[a] / S - 1;
+                    tl[a][1] = c[a] / S;
+                    ns[a] = 2;
+                } else {
+                    int64_t tt = c[a] / S;
+                    if (tt >= D.P[a]) tt = D.P[a] - 1;
+                    tl[a][0] = tt;
+                    ns[a] = 1;
+                }
+            }
+            cand cs[8];
+            int nc = 0;
+            for (int x0 = 0; x0 < ns[0]; x0++)
+                for (int x1 = 0; x1 < ns[1]; x1++)
+                    for (int x2 = 0; x2 < ns[2]; x2++) {
+                        int sd[3] = {x0, x1, x2};
+                        int64_t T[3], lc[3];
+                        for (int a = 0; a < 3; a++) {
+                            T[a] = tl[a][sd[a]];
+                            lc[a] = (a < d) ? c[a] - T[a] * S : 0;
+                        }
+                        int64_t t = T[0] + D.P[0] * (T[1] + D.P[1] * T[2]);
+                        int64_t li = lc[0] + (S + 1) * (lc[1] + (S + 1) * lc[2]);
+                        cand* cc = &cs[nc++];
+                        cc->u = tu[t * V + li];
+                        for (int a = 0; a < 3; a++) {
+                            cc->w[a] = (a < d) ? tw[t * V * d + a * V + li] : 0;
+                            cc->side[a] = sd[a];
+                        }
+                    }
+            real v;
+            signed char wv[3] = {0, 0, 0};
+            if (nc == 1) {
+                v = cs[0].u;
+                for (int a = 0; a < d; a++) wv[a] = cs[0].w[a];
+            } else {
+                signed char Wx[3] = {0, 0, 0};
+                for (int a = 0; a < d; a++) Wx[a] = W[a * N + X];
+                reconcile_node(d, cs, nc, iface, Wx, &v, wv);
+            }
+            u_out[X] = v;
+            if (is_coarse(&D, c)) {
+                uk[X] = v;
+                for (int a = 0; a < d; a++) wk[a * N + X] = wv[a];
+            }
+        }
+        /* Step 4: weighted correction on every lattice, then causal sweep */
+        for (int64_t x = 0; x < N; x++) Un[x] = (real)NAN;
+        coarse_upd += step4_correct(&D, U, W, uk, wk, Un, Wn, max_coarse_sweeps);
+        if (Upre_out) memcpy(Upre_out, Un, sizeof(real) * N);
+        causal_sweep(&D, Un, Wn);
+        /* max|U^{k+1} - U^k| over coarse nodes, |inf - inf| = 0 */
+        double delta = 0.0;
+        for (int64_t X = 0; X < N; X++) {
+            int64_t c[3];
+            node_coords(&D, X, c);
+            if (!is_coarse(&D, c)) continue;
+            double a = (double)Un[X], b = (double)U[X];
+            double df;
+            if (isinf(a) && isinf(b))
+                df = 0.0;
+            else
+                df = fabs(a - b);
+            if (df > delta || isnan(df)) delta = isnan(df) ? INFINITY : df;
+        }
+        if (hist && k < hist_cap) hist[k] = delta;
+        real* tU = U;
+        U = Un;
+        Un = tU;
+        signed char* tW = W;
+        W = Wn;
+        Wn = tW;
+        it = k + 1;
+        if (delta < tol || delta == 0.0) {
+            conv = 1;
+            break;
+        }
+    }
+
+    if (U_out) {
+        for (int64_t x = 0; x < N; x++) {
+            int64_t c[3];
+            node_coords(&D, x, c);
+            U_out[x] = is_coarse(&D, c) ? U[x] : (real)NAN;
+        }
+    }
+    if (W_out) memcpy(W_out, W, (size_t)(d * N));
+    if (uk_out) memcpy(uk_out, uk, sizeof(real) * N);
+    if (wk_out) memcpy(wk_out, wk, (size_t)(d * N));
+    if (info) {
+        info[0] = it;
+        info[1] = conv;
+        info[2] = fine_upd;
+        info[3] = coarse_upd;
+        info[4] = (max_iter == 0 || conv) ? OK : ERR_NOCONV;
+    }
+    free(D.isg); free(D.gv); free(U); free(Un); free(uk); free(W); free(Wn); free(wk);
+    free(tu); free(tw);
+    return (max_iter == 0 || conv) ? OK : ERR_NOCONV;
+}
+
+/* Test hook: the local solve alone.  m, ws, wt have 3 entries (unused axes
+ * ignored); returns u~ in *out. */
+int NAME(eikref_local)(int d, const real* m, const signed char* ws, real rd, int rule,
+                       signed char* wt, real* out) {
+    if (d != 2 && d != 3) return ERR_ARG;
+    real mm[3] = {RINF, RINF, RINF};
+    signed char ww[3] = {0, 0, 0};
+    for (int a = 0; a < d; a++) {
+        mm[a] = m[a];
+        ww[a] = ws[a];
+    }
+    *out = local_solve(d, mm, ww, rd, rule, wt);
+    return OK;
+}

@@ -1,0 +1,265 @@
+"""Seeded synthetic inputs for the Eikonal domain-decomposition solver.
+
+This module only *generates inputs*: slowness fields r_eps sampled on the
+nodes of a uniform grid on [0,1]^d, the boundary set Gamma (linear node
+indices, sorted and unique) with its data g, and the partition parameters.
+It contains none of the solver's arithmetic, so both the CPU oracle's tests
+and the GPU path draw from it.
+
+Layout: x is the fastest axis.  A 2D field has numpy shape (n1, n0) and node
+(i, j) sits at linear index i + n0*j; a 3D field has shape (n2, n1, n0) and
+node (i, j, k) sits at i + n0*(j + n1*k).
+
+Every field is produced in float64 with numpy's default_rng(seed); an fp32
+run uses the float32 rounding of the same field.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Problem:
+    """One boundary value problem |grad u| = r on [0,1]^d, u = g on Gamma,
+    with its two-scale partition (Section 3.2 of the paper: subdomain side S
+    and coarse spacing M = H/h, both in fine cells)."""
+
+    name: str
+    n: tuple                   # nodes per axis (x first)
+    h: float                   # fine spacing
+    r: np.ndarray              # float64 slowness, shape n[::-1]
+    gamma_idx: np.ndarray      # int64, sorted unique linear indices
+    gamma_val: np.ndarray      # float64 boundary data g
+    S: int = 0                 # subdomain side in fine cells
+    M: int = 0                 # coarse spacing H/h in fine cells
+    theta: float = 0.5         # parareal weight
+    tol: float = 1e-12         # stop when max|U^{k+1}-U^k| < tol
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.n))
+
+    def r_as(self, dtype) -> np.ndarray:
+        return np.ascontiguousarray(self.r.astype(dtype))
+
+    def g_as(self, dtype) -> np.ndarray:
+        return np.ascontiguousarray(self.gamma_val.astype(dtype))
+
+
+def _coords(n, h):
+    """Node coordinates as float64 arrays broadcast to the field shape."""
+    axes = [np.arange(m, dtype=np.float64) * h for m in n]
+    # meshgrid with indexing='ij' over reversed axes gives shape n[::-1]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")
+    return grids[::-1]  # x, y[, z]
+
+
+def linear_index(n, *ijk) -> int:
+    idx = 0
+    stride = 1
+    for a, c in enumerate(ijk):
+        idx += int(c) * stride
+        stride *= int(n[a])
+    return idx
+
+
+def _gamma(n, nodes, vals):
+    idx = np.array([linear_index(n, *c) for c in nodes], dtype=np.int64)
+    val = np.asarray(vals, dtype=np.float64)
+    order = np.argsort(idx, kind="stable")
+    idx, val = idx[order], val[order]
+    keep = np.ones(len(idx), dtype=bool)
+    keep[1:] = idx[1:] != idx[:-1]
+    return idx[keep], val[keep]
+
+
+# ---------------------------------------------------------------------------
+# the workloads the solver is measured and checked on
+# ---------------------------------------------------------------------------
+
+def config1() -> Problem:
+    """129^2, h = 1/128, 4x4 subdomains (S = 32), H = 1/16 (M = 8).
+    r = 1 + 0.5 sin(2 pi x / eps) sin(2 pi y / eps), eps = 1/16; point source
+    g = 0 at node (64, 64) = (0.5, 0.5); theta = 0.5; fp64 to 1e-12."""
+    n = (129, 129)
+    h = 1.0 / 128
+    x, y = _coords(n, h)
+    eps = 1.0 / 16
+    r = 1.0 + 0.5 * np.sin(2 * np.pi * x / eps) * np.sin(2 * np.pi * y / eps)
+    gi, gv = _gamma(n, [(64, 64)], [0.0])
+    return Problem("c1_129sq_S32_M8", n, h, r, gi, gv, S=32, M=8, theta=0.5, tol=1e-12)
+
+
+def config2_slowness(n, h, seed=2):
+    """r0 + a_eps on a 2D grid: r0 = 1 + 0.3 exp(-|x-(0.3,0.7)|^2/0.05) plus
+    32 seeded random Fourier modes (wavenumber in [32,128], direction and
+    phase uniform, amplitude N(0, 0.02)), floored at 0.2."""
+    x, y = _coords(n, h)
+    rng = np.random.default_rng(seed)
+    kmag = rng.uniform(32.0, 128.0, 32)
+    ang = rng.uniform(0.0, 2 * np.pi, 32)
+    phi = rng.uniform(0.0, 2 * np.pi, 32)
+    amp = rng.normal(0.0, 0.02, 32)
+    r0 = 1.0 + 0.3 * np.exp(-((x - 0.3) ** 2 + (y - 0.7) ** 2) / 0.05)
+    a = np.zeros_like(x)
+    for m in range(32):
+        a += amp[m] * np.cos(2 * np.pi * kmag[m] * (x * np.cos(ang[m]) + y * np.sin(ang[m])) + phi[m])
+    return np.maximum(r0 + a, 0.2)
+
+
+def config2(n_side: int = 1025, S: int = 64, M: int = 16) -> Problem:
+    """1025^2, h = 1/1024, 16x16 subdomains (S = 64), H = 1/64 (M = 16);
+    multiscale random-Fourier slowness; source = the whole left edge x = 0
+    with g = 0; theta = 0.5."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    r = config2_slowness(n, h)
+    nodes = [(0, j) for j in range(n_side)]
+    gi, gv = _gamma(n, nodes, np.zeros(n_side))
+    return Problem(f"c2_{n_side}sq_S{S}_M{M}", n, h, r, gi, gv, S=S, M=M, theta=0.5, tol=1e-12)
+
+
+def config3(n_side: int = 257, S: int = 32, M: int = 8) -> Problem:
+    """257^3, h = 1/256, 8^3 subdomains (S = 32), H = 1/32 (M = 8).
+    r = (1 + 0.4 prod_i sin(2 pi x_i / eps)) * exp(0.1 z_b), eps = 1/32, with
+    z_b a seeded N(0,1) draw per checkerboard block of side 1/16 (16 fine
+    cells at n = 257).  Sources: node (64,64,64) with g = 0, and the off-node
+    point (0.75, 0.6, 0.5) represented by its two nearest nodes along y with
+    g = r(x0) * distance (the paper fixes values "on or near" the boundary)."""
+    n = (n_side, n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    x, y, z = _coords(n, h)
+    eps = 1.0 / 32
+    rng = np.random.default_rng(3)
+    nb = 16
+    zb = rng.normal(0.0, 1.0, (nb, nb, nb))  # [bx][by][bz]
+    cell = max(1, (n_side - 1) // 16)
+    bi = np.minimum(np.arange(n_side) // cell, nb - 1)
+    # field shape is (nz, ny, nx): index zb[bx, by, bz]
+    blk = zb[bi[None, None, :], bi[None, :, None], bi[:, None, None]]
+    r = (1.0 + 0.4 * np.sin(2 * np.pi * x / eps) * np.sin(2 * np.pi * y / eps)
+         * np.sin(2 * np.pi * z / eps)) * np.exp(0.1 * blk)
+    x0 = (0.75, 0.6, 0.5)
+    i0 = int(round(x0[0] * (n_side - 1)))
+    k0 = int(round(x0[2] * (n_side - 1)))
+    yf = x0[1] * (n_side - 1)
+    jlo = int(math.floor(yf))
+    bxi = min(int(x0[0] * (n_side - 1)) // cell, nb - 1)
+    byi = min(int(x0[1] * (n_side - 1)) // cell, nb - 1)
+    bzi = min(int(x0[2] * (n_side - 1)) // cell, nb - 1)
+    r_x0 = (1.0 + 0.4 * math.sin(2 * math.pi * x0[0] / eps) * math.sin(2 * math.pi * x0[1] / eps)
+            * math.sin(2 * math.pi * x0[2] / eps)) * math.exp(0.1 * zb[bxi, byi, bzi])
+    c = n_side // 4
+    nodes = [(c, c, c), (i0, jlo, k0), (i0, jlo + 1, k0)]
+    vals = [0.0, r_x0 * (yf - jlo) * h, r_x0 * (jlo + 1 - yf) * h]
+    gi, gv = _gamma(n, nodes, vals)
+    return Problem(f"c3_{n_side}cube_S{S}_M{M}", n, h, r, gi, gv, S=S, M=M, theta=0.5, tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# small seeded cases for parity tests
+# ---------------------------------------------------------------------------
+
+def random_media(n, h, seed, kind="fourier"):
+    """A smooth positive random medium on the grid (float64)."""
+    rng = np.random.default_rng(seed)
+    xs = _coords(n, h)
+    if kind == "const":
+        return np.full(tuple(n[::-1]), float(rng.uniform(0.5, 2.0)))
+    if kind == "blocks":
+        nb = int(rng.integers(2, 6))
+        vals = rng.choice([1.0, 2.0], size=(nb,) * len(n))
+        idx = [np.minimum((c * nb).astype(np.int64), nb - 1) for c in xs]
+        return vals[tuple(idx)]
+    r = np.ones(tuple(n[::-1]))
+    for _ in range(6):
+        k = rng.uniform(1.0, 8.0, len(n))
+        ph = rng.uniform(0, 2 * np.pi)
+        amp = rng.uniform(0.05, 0.2)
+        arg = sum(k[a] * 2 * np.pi * xs[a] for a in range(len(n))) + ph
+        r = r + amp * np.sin(arg)
+    return np.maximum(r, 0.2)
+
+
+def random_problem(seed: int, n, S: int, M: int, n_src: int = 1,
+                   kind: str = "fourier", edge: Optional[int] = None,
+                   theta: float = 0.5) -> Problem:
+    """A seeded small problem: random smooth (or blocky / constant) medium,
+    n_src random node sources with g = 0, or a whole domain edge when
+    `edge` is given (axis index; the x_axis = 0 face)."""
+    n = tuple(int(v) for v in n)
+    h = 1.0 / (n[0] - 1)
+    r = random_media(n, h, seed, kind)
+    rng = np.random.default_rng(seed + 1000)
+    if edge is not None:
+        grid = np.indices(n[::-1]).reshape(len(n), -1)[::-1].T  # (i, j[, k])
+        nodes = [tuple(c) for c in grid if c[edge] == 0]
+        vals = np.zeros(len(nodes))
+    else:
+        nodes = [tuple(int(rng.integers(0, m)) for m in n) for _ in range(n_src)]
+        vals = rng.uniform(0.0, 0.05, n_src)
+    gi, gv = _gamma(n, nodes, vals)
+    return Problem(f"rand{seed}", n, h, r, gi, gv, S=S, M=M, theta=theta, tol=1e-12)
+
+
+def paper_r1(n_side: int, S: int, M: int) -> Problem:
+    """r^1 = 1 + .99 sin(2 pi x) sin(2 pi y) with a source at the origin
+    (Section 5.1 medium; source placement is ours)."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    x, y = _coords(n, h)
+    r = 1.0 + 0.99 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    gi, gv = _gamma(n, [(0, 0)], [0.0])
+    return Problem(f"r1_{n_side}", n, h, r, gi, gv, S=S, M=M)
+
+
+def paper_r2(n_side: int, S: int, M: int) -> Problem:
+    """r^2 = 1 + .5 sin(20 pi x) sin(20 pi y) with a source at the origin."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    x, y = _coords(n, h)
+    r = 1.0 + 0.5 * np.sin(20 * np.pi * x) * np.sin(20 * np.pi * y)
+    gi, gv = _gamma(n, [(0, 0)], [0.0])
+    return Problem(f"r2_{n_side}", n, h, r, gi, gv, S=S, M=M)
+
+
+def paper_r4(n_side: int, S: int, M: int) -> Problem:
+    """Fast obstacle r^4: r = 0.01 on [0.26,0.27] x [0,0.6], 1 elsewhere;
+    source (0,0) (Section 5.2)."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    x, y = _coords(n, h)
+    r = np.ones_like(x)
+    inside = (x >= 0.26 - 1e-12) & (x <= 0.27 + 1e-12) & (y <= 0.6 + 1e-12)
+    r[inside] = 0.01
+    gi, gv = _gamma(n, [(0, 0)], [0.0])
+    return Problem(f"r4_{n_side}", n, h, r, gi, gv, S=S, M=M)
+
+
+def model_strip(N: int, M: int) -> Problem:
+    """The model problem of Section 4: Omega = [0,1] x [0,H], r = 1,
+    Gamma = bottom and left edges, g = sqrt(x^2 + y^2); H = 1/N, h = 1/(NM).
+    The subdomains are the coarse cells (S = M)."""
+    n = (N * M + 1, M + 1)
+    h = 1.0 / (N * M)
+    r = np.ones((n[1], n[0]))
+    nodes, vals = [], []
+    for i in range(n[0]):
+        nodes.append((i, 0))
+        vals.append(i * h)
+    for j in range(1, n[1]):
+        nodes.append((0, j))
+        vals.append(j * h)
+    gi, gv = _gamma(n, nodes, vals)
+    return Problem(f"strip_N{N}_M{M}", n, h, r, gi, gv, S=M, M=M)
+
+
+CONFIGS = {"c1": config1, "c2": config2, "c3": config3}

@@ -1,0 +1,171 @@
+"""Pins for the oracle's fast sweeping method (Sec. 1.1): initialisation,
+the 2^d orderings of the loop nest and the update u = min(u, u~).
+
+It is checked against what the mathematics fixes: closed forms on grid
+axes, the paper's discrete equations (eq. godonuv with its one-sided rule
+on boundary nodes) evaluated directly from the output, an independent fast
+marching solve of the same discrete system, and invariants (u >= min g,
+values never increase from sweep to sweep, causality, mirror symmetry)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_04198_amd import workloads as W
+
+EPS = np.finfo(np.float64).eps
+
+
+def seq_sum(step, count):
+    """((step + step) + step) + ... in float64, count terms."""
+    s = 0.0
+    out = [0.0]
+    for _ in range(count):
+        s = s + step
+        out.append(s)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_point_source_constant_medium_axis_values(d):
+    n = (33,) * d if d == 2 else (17,) * d
+    h = 1.0 / (n[0] - 1)
+    r0 = 1.3
+    r = np.full(n[::-1], r0)
+    c = tuple(m // 2 for m in n)
+    gi = np.array([W.linear_index(n, *c)])
+    u, _ = oracle.fsm(n, h, r, gi, [0.0])
+    U = u.reshape(n[::-1])
+    step = r0 * h
+    ref = seq_sum(step, n[0] - 1 - c[0])
+    # along +x from the source every update is one-sided: u = sum of r*h
+    if d == 2:
+        line = U[c[1], c[0]:]
+    else:
+        line = U[c[2], c[1], c[0]:]
+    assert np.array_equal(line, ref[: len(line)])
+
+
+def test_edge_source_constant_medium_rows():
+    n = (41, 23)
+    h = 1.0 / 40
+    r0 = 0.7
+    r = np.full(n[::-1], r0)
+    nodes = [(0, j) for j in range(n[1])]
+    gi = np.array(sorted(W.linear_index(n, *c) for c in nodes))
+    u, w = oracle.fsm(n, h, r, gi, np.zeros(len(gi)))
+    U = u.reshape(n[::-1])
+    ref = seq_sum(r0 * h, n[0] - 1)
+    for j in range(n[1]):
+        assert np.allclose(U[j], ref, rtol=0, atol=4 * EPS * ref[-1])
+    # the flow is along +x everywhere off the source
+    assert np.all(w[0].reshape(n[::-1])[:, 1:] == 1)
+
+
+def godunov_residual(u, n, h, r, fixed):
+    """Evaluate eq. godonuv at every non-fixed node from the solution:
+    sqrt(max(a+, b-)^2 + max(c+, d-)^2 [+ z terms]) - r, with a = D_x^- u,
+    b = D_x^+ u, ..., and the one-sided forms on boundary nodes."""
+    d = len(n)
+    U = u.reshape(n[::-1])
+    tot = np.zeros_like(U)
+    for a in range(d):
+        ax = d - 1 - a  # numpy axis of grid axis a
+        Um = np.full_like(U, np.nan)
+        Up = np.full_like(U, np.nan)
+        sl = [slice(None)] * d
+        sl2 = [slice(None)] * d
+        sl[ax] = slice(1, None)
+        sl2[ax] = slice(None, -1)
+        Dm = np.full_like(U, -np.inf)   # D^- u (absent at the low boundary)
+        Dp = np.full_like(U, np.inf)    # D^+ u (absent at the high boundary)
+        Dm[tuple(sl)] = (U[tuple(sl)] - U[tuple(sl2)]) / h
+        Dp[tuple(sl2)] = (U[tuple(sl)] - U[tuple(sl2)]) / h
+        with np.errstate(invalid="ignore"):
+            term = np.maximum(np.maximum(Dm, 0.0), np.maximum(-Dp, 0.0))
+        tot = tot + term * term
+    res = np.sqrt(tot) - r
+    res = res.reshape(-1)
+    res[fixed] = 0.0
+    return res
+
+
+@pytest.mark.parametrize("d,seed", [(2, 0), (2, 1), (2, 2), (3, 3), (3, 4)])
+def test_solution_satisfies_discrete_equations(d, seed):
+    n = (37, 29) if d == 2 else (13, 11, 9)
+    p = W.random_problem(seed, n, 1, 1, n_src=3)
+    u, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    assert np.all(np.isfinite(u))
+    res = godunov_residual(u, p.n, p.h, p.r, p.gamma_idx)
+    assert np.max(np.abs(res)) <= 1e-9 * np.max(p.r)
+
+
+@pytest.mark.parametrize("d,seed,kind", [(2, 10, "fourier"), (2, 11, "blocks"), (2, 12, "const"),
+                                         (3, 13, "fourier"), (3, 14, "blocks")])
+def test_matches_fast_marching(d, seed, kind):
+    n = (41, 35) if d == 2 else (15, 13, 11)
+    p = W.random_problem(seed, n, 1, 1, n_src=2, kind=kind)
+    u, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    uf = oracle.fmm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    assert np.max(np.abs(u - uf)) <= 4 * EPS * np.max(u)
+
+
+def test_invariants_monotone_sweeps_bounds_causality():
+    p = W.random_problem(21, (31, 27), 1, 1, n_src=2, kind="blocks")
+    prev = None
+    for k in range(1, 13):
+        u, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, max_sweeps=k)
+        if prev is not None:
+            assert np.all(u <= prev)
+        prev = u
+    u, w = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    assert np.all(u >= p.gamma_val.min())
+    assert np.array_equal(u[p.gamma_idx], p.gamma_val)
+    # causality: the neighbour a wind points at is strictly smaller
+    n = p.n
+    U = u.reshape(n[::-1])
+    Wx = w[0].reshape(n[::-1])
+    Wy = w[1].reshape(n[::-1])
+    jj, ii = np.nonzero(Wx == 1)
+    assert np.all(U[jj, ii - 1] < U[jj, ii])
+    jj, ii = np.nonzero(Wx == -1)
+    assert np.all(U[jj, ii + 1] < U[jj, ii])
+    jj, ii = np.nonzero(Wy == 1)
+    assert np.all(U[jj - 1, ii] < U[jj, ii])
+    jj, ii = np.nonzero(Wy == -1)
+    assert np.all(U[jj + 1, ii] < U[jj, ii])
+
+
+def test_mirror_symmetry():
+    n = (33, 33)
+    h = 1.0 / 32
+    x = np.arange(33) * h
+    r = 1 + 0.4 * np.cos(2 * np.pi * x)[None, :] * np.cos(2 * np.pi * x)[:, None]
+    gi = np.array([W.linear_index(n, 16, 16)])
+    u, _ = oracle.fsm(n, h, r, gi, [0.0])
+    U = u.reshape(33, 33)
+    tol = 8 * EPS * U.max()
+    assert np.max(np.abs(U - U[:, ::-1])) <= tol
+    assert np.max(np.abs(U - U[::-1, :])) <= tol
+    assert np.max(np.abs(U - U.T)) <= tol
+
+
+def test_fp32_build_close_to_fp64():
+    p = W.random_problem(31, (65, 65), 1, 1, n_src=2)
+    u64, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    u32, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, dtype=np.float32)
+    assert np.max(np.abs(u32.astype(np.float64) - u64)) <= 2e-5 * u64.max()
+
+
+def test_argument_errors():
+    n = (9, 9)
+    r = np.ones((9, 9))
+    with pytest.raises(ValueError):
+        oracle.fsm(n, 0.125, -r, [0], [0.0])
+    with pytest.raises(ValueError):
+        oracle.fsm(n, 0.125, r, [5, 3], [0.0, 0.0])   # not sorted
+    with pytest.raises(ValueError):
+        oracle.fsm(n, 0.125, r, [81], [0.0])          # out of range
+    bad = r.copy()
+    bad[3, 3] = np.nan
+    with pytest.raises(ValueError):
+        oracle.fsm(n, 0.125, bad, [0], [0.0])
