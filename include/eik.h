@@ -1,0 +1,170 @@
+/*
+ * eik.h -- C ABI of the MI355X (gfx950) two-scale domain-decomposition
+ * Eikonal solver (Martin & Tsai, "A multiscale domain decomposition
+ * algorithm for boundary value problems for Eikonal equations",
+ * arXiv 1805.04198).
+ *
+ * Problem (Sec. 1, eq. eikonal; Sec. 3.2, eqs. 2Deq/2Dbc):
+ *     |grad u(x)| = r(x) in Omega = [0,1]^d,   u = g on Gamma,
+ * discretised on a uniform grid by the Godunov upwind scheme (Sec. 1.1,
+ * eq. godonuv).  r is the slowness r_eps = r0 + a_eps sampled at the nodes.
+ *
+ * Conventions shared by every entry point
+ *   - Layout: node (i,j[,k]) lives at linear index i + n0*(j + n1*k); x is the
+ *     fastest axis.  All arrays are DEVICE pointers owned by the caller; the
+ *     library never frees them and keeps no reference after the call returns.
+ *   - Calls are ordered on the given HIP stream (NULL = the null stream).  An
+ *     entry point returns after its work is complete (it synchronises that
+ *     stream), so outputs and the host-side stats are ready on return.
+ *   - Winds (the paper's w and W, Secs. 3.1-3.2) are int8 codes, two bits per
+ *     axis: bits 0-1 = x, 2-3 = y, 4-5 = z; each field 0 = no component,
+ *     1 = +1, 3 = -1.  A +1 component means the flow arrives from the minus
+ *     side (the upwind neighbour has the smaller index).
+ *   - Every call returns an eik_status.  Nothing throws.  On an error the
+ *     outputs are unspecified unless stated otherwise; eik_last_error()
+ *     returns a message for the calling thread.
+ *   - Workspace is allocated by the library on first use on a device and
+ *     reused (grown when a larger problem arrives) until eik_release().
+ *     Calls that overlap on one device from different host threads are
+ *     serialised by the library.
+ */
+#ifndef EIK_H
+#define EIK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t eik_status;
+#define EIK_OK 0
+#define EIK_ERR_ARG (-1)          /* bad argument: r <= 0 or not finite, Gamma unsorted or out of range, theta outside [0,1], NULL pointer */
+#define EIK_ERR_SHAPE (-2)        /* (n-1) % S != 0, S % M != 0, M < 2, extents too small */
+#define EIK_ERR_NOCONV (-3)       /* max_iter reached without max|U^{k+1}-U^k| < tol; outputs and stats ARE written */
+#define EIK_ERR_HIP (-4)          /* a HIP runtime call failed */
+#define EIK_ERR_UNSUPPORTED (-5)  /* valid problem outside what this build implements (see eik_last_error) */
+#define EIK_ERR_NONFINITE (-6)    /* the residual became NaN */
+
+typedef enum { EIK_F32 = 0, EIK_F64 = 1 } eik_dtype;
+
+/* The grid: d = 2 (or 3), n[a] nodes along axis a (n[a] >= 2; unused axes
+ * ignored), spacing h > 0, and the element type of every real array passed
+ * with it. */
+typedef struct {
+    int32_t dim;
+    int32_t dtype; /* eik_dtype */
+    int64_t n[3];
+    double h;
+} eik_grid;
+
+/* The boundary set Gamma (Sec. 1.1, "Initialization"): `count` node indices
+ * (device, int64, strictly increasing, each in [0, N)) and their values g
+ * (device, grid dtype, finite).  count may be 0. */
+typedef struct {
+    int64_t count;
+    const int64_t* idx;
+    const void* g;
+} eik_gamma;
+
+/* Optional per-iteration snapshots for debugging and parity tests: full-grid
+ * device arrays (NaN / 0 off the coarse skeleton) of the LAST iteration's
+ * reconciled fine values u^k and winds w^k (Sec. 3.2, Alg. fineupdate) and
+ * of its corrected coarse values before the causal sweep (Alg.
+ * 2Dweightedupdate).  Any member may be NULL. */
+typedef struct {
+    void* uk;
+    int8_t* wk;
+    void* U_pre_causal;
+} eik_dd_debug;
+
+/* Options of the domain-decomposition iteration (Sec. 3.2). */
+typedef struct {
+    int32_t S;          /* subdomain side in fine cells; (n[a]-1) % S == 0 */
+    int32_t M;          /* coarse spacing H/h in fine cells; S % M == 0, M >= 2 */
+    double theta;       /* parareal weight theta in [0,1] (Sec. 2, eq. wtdparasimp) */
+    double tol;         /* stop when max |U^{k+1} - U^k| over the coarse nodes < tol (or == 0) */
+    int32_t max_iter;   /* cap on DD iterations (0: only Step 1) */
+    int32_t max_fine_sweeps;   /* cap on FSM sweeps per subdomain per iteration (>= 1) */
+    int32_t max_coarse_sweeps; /* cap on sweeps per coarse lattice in Steps 1 and 4 (>= 1) */
+    int32_t reserved;
+    const void* U_init;        /* optional resume state (device, full grid, grid dtype): U^k ... */
+    const int8_t* W_init;      /* ... and W^k codes; both NULL = run Step 1 */
+    const eik_dd_debug* debug; /* optional snapshots, NULL = none */
+} eik_dd_opts;
+
+/* Host-side statistics.  residual_history (host, may be NULL) receives
+ * max|U^{k+1}-U^k| of up to history_cap iterations. */
+typedef struct {
+    int32_t iterations;      /* DD iterations run */
+    int32_t converged;       /* 1 if the residual went below tol */
+    int64_t fine_updates;    /* local solves evaluated in Step 3: sum over subdomains of (non-Gamma nodes) x (sweeps) */
+    int64_t coarse_updates;  /* the same for the coarse lattices in Steps 1 and 4 */
+    int64_t sweeps;          /* eik_solve: sweeps run */
+    double final_residual;
+    double* residual_history;
+    int32_t history_cap;
+    float ms_total;          /* device time of the whole call */
+    float ms_fine;           /* device time in Step 3 (subdomain FSM) */
+    float ms_coarse;         /* device time in Steps 1 and 4 and the causal sweeps */
+} eik_stats;
+
+/* eik_solve -- the fast sweeping method on the whole fine grid (Sec. 1.1:
+ * Gamma nodes fixed at g, all others start at +inf; Gauss-Seidel sweeps in
+ * the 2^d orderings of the paper's loop nest with u = min(u, u~), eq.
+ * FSMupdate), stopped after the first sweep that changes no value or after
+ * max_sweeps.  This is the "overall fine solution" u^f of Secs. 4-5.
+ *   r        device, N elements of grid dtype, > 0 and finite
+ *   u_out    device, N elements of grid dtype (must not alias r)
+ *   wind_out device, N int8 wind codes, or NULL
+ *   stats    host, or NULL (fields iterations/converged/sweeps/ms_total)
+ * Returns EIK_ERR_NOCONV (outputs written) if max_sweeps was reached. */
+eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma,
+                     int32_t max_sweeps, void* u_out, int8_t* wind_out, eik_stats* stats,
+                     void* hip_stream);
+
+/* eik_dd_solve -- the two-scale DD iteration of Sec. 3.2:
+ *   Step 1  FSM on every shifted coarse lattice with Alg. update2D, then the
+ *           causal sweep (Alg. causalsweep2D) -> U^0, W^0 (skipped when
+ *           opts->U_init / W_init are given);
+ *   Step 2  subdomain boundary data from (U^k, W^k) (inflow test W . n > 0);
+ *   Step 3  FSM on every subdomain with Alg. fineupdate2D, then the
+ *           reconciliation of Alg. fineupdate at the coarse nodes -> u^k, w^k;
+ *   Step 4  Alg. 2Dweightedupdate sweeps on every lattice, then the causal
+ *           sweep -> U^{k+1}, W^{k+1};
+ * repeated until max|U^{k+1} - U^k| < tol.
+ *   r      device, N elements, > 0 and finite
+ *   u_out  device, N: the subdomain solutions of the last Step 3 patched
+ *          together (coarse nodes take u^k); NaN if max_iter == 0
+ *   U_out  device, N or NULL: U of the last iterate, NaN off the skeleton
+ *   W_out  device, N int8 codes or NULL: W of the last iterate
+ * Resume: passing (U_out, W_out) of a run as opts->U_init/W_init continues
+ * it exactly (the iteration reads nothing else).
+ * This build: d = 2, subdomain side S+1 <= 65 nodes and lattice extents
+ * (n-1)/M + 1 <= 65 (else EIK_ERR_UNSUPPORTED). */
+eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma,
+                        const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
+                        eik_stats* stats, void* hip_stream);
+
+/* eik_adjoint -- gradient of a loss of the converged travel times with
+ * respect to the slowness, by the transposed upwind system swept in reverse
+ * causal order.  Not part of the paper; declared for the differentiation
+ * workload and not implemented in this build: returns EIK_ERR_UNSUPPORTED. */
+eik_status eik_adjoint(const eik_grid* grid, const void* r, const eik_gamma* gamma,
+                       const void* u, const int8_t* wind, const void* dL_du, void* dL_dr_out,
+                       void* hip_stream);
+
+/* Message for the last non-OK status returned to the calling thread. */
+const char* eik_last_error(void);
+
+/* Frees the workspace held on every device.  Returns EIK_OK. */
+eik_status eik_release(void);
+
+/* Library version string. */
+const char* eik_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIK_H */

@@ -1,0 +1,217 @@
+"""MI355X-native two-scale domain-decomposition Eikonal solver.
+
+Python binding of libeik.so (HIP, gfx950): argument marshalling only.  Every
+step of the solve runs in the library's kernels; PyTorch provides device
+memory and the current stream.  Importing the package does not load the
+library; the first call does, and raises if it is missing (build it with
+``python -m paper_1805_04198_amd.build`` or ``__graft_entry__.build()``).
+
+Method: Martin & Tsai, arXiv 1805.04198 (Sec. 1.1 FSM, Sec. 3.2 DD).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libeik.so")
+
+EIK_OK, EIK_ERR_ARG, EIK_ERR_SHAPE, EIK_ERR_NOCONV = 0, -1, -2, -3
+EIK_ERR_HIP, EIK_ERR_UNSUPPORTED, EIK_ERR_NONFINITE = -4, -5, -6
+EIK_F32, EIK_F64 = 0, 1
+STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "ERR_HIP",
+                -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE"}
+
+# exported symbols of include/eik.h
+SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_adjoint", "eik_last_error", "eik_release",
+           "eik_version")
+
+
+class EikError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("h", ctypes.c_double)]
+
+
+class Gamma(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("idx", ctypes.c_void_p), ("g", ctypes.c_void_p)]
+
+
+class DDDebug(ctypes.Structure):
+    _fields_ = [("uk", ctypes.c_void_p), ("wk", ctypes.c_void_p), ("U_pre_causal", ctypes.c_void_p)]
+
+
+class DDOpts(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("M", ctypes.c_int32), ("theta", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("max_fine_sweeps", ctypes.c_int32), ("max_coarse_sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("U_init", ctypes.c_void_p),
+                ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug))]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("fine_updates", ctypes.c_int64), ("coarse_updates", ctypes.c_int64),
+                ("sweeps", ctypes.c_int64), ("final_residual", ctypes.c_double),
+                ("residual_history", ctypes.POINTER(ctypes.c_double)),
+                ("history_cap", ctypes.c_int32), ("ms_total", ctypes.c_float),
+                ("ms_fine", ctypes.c_float), ("ms_coarse", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load libeik.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libeik.so not found at {p}: build it with "
+                           "`python -m paper_1805_04198_amd.build`")
+    L = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    L.eik_solve.restype = ctypes.c_int32
+    L.eik_solve.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma), ctypes.c_int32, vp,
+                            vp, ctypes.POINTER(Stats), vp]
+    L.eik_dd_solve.restype = ctypes.c_int32
+    L.eik_dd_solve.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
+                               ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
+    L.eik_adjoint.restype = ctypes.c_int32
+    L.eik_adjoint.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma), vp, vp, vp, vp, vp]
+    L.eik_last_error.restype = ctypes.c_char_p
+    L.eik_release.restype = ctypes.c_int32
+    L.eik_version.restype = ctypes.c_char_p
+    if path is None:
+        _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(L, st):
+    if st != EIK_OK and st != EIK_ERR_NOCONV:
+        raise EikError(st, L.eik_last_error().decode())
+    return st
+
+
+def _grid(r, h):
+    torch = _torch()
+    if not r.is_cuda:
+        raise ValueError("r must be a device tensor")
+    if r.dtype not in (torch.float32, torch.float64):
+        raise ValueError("r must be float32 or float64")
+    g = Grid()
+    g.dim = r.dim()
+    g.dtype = EIK_F32 if r.dtype == torch.float32 else EIK_F64
+    shape = list(r.shape)[::-1]  # x fastest
+    for a in range(3):
+        g.n[a] = shape[a] if a < len(shape) else 1
+    g.h = float(h)
+    return g
+
+
+def _gamma(idx, val, r):
+    torch = _torch()
+    gm = Gamma()
+    idx = idx.to(device=r.device, dtype=torch.int64).contiguous()
+    val = val.to(device=r.device, dtype=r.dtype).contiguous()
+    gm.count = idx.numel()
+    gm.idx = idx.data_ptr() if idx.numel() else None
+    gm.g = val.data_ptr() if val.numel() else None
+    return gm, (idx, val)
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def solve(r, gamma_idx, gamma_val, h, max_sweeps: int = 100000, with_wind: bool = False):
+    """eik_solve: FSM on the whole fine grid (the overall fine solution u^f).
+    Returns (u, wind codes or None, stats dict)."""
+    torch = _torch()
+    L = load_library()
+    r = r.contiguous()
+    g = _grid(r, h)
+    gm, keep = _gamma(gamma_idx, gamma_val, r)
+    u = torch.empty_like(r)
+    w = torch.empty(r.shape, dtype=torch.int8, device=r.device) if with_wind else None
+    st = Stats()
+    status = L.eik_solve(ctypes.byref(g), r.data_ptr(), ctypes.byref(gm), int(max_sweeps),
+                         u.data_ptr(), w.data_ptr() if w is not None else None, ctypes.byref(st),
+                         _stream())
+    _check(L, status)
+    info = {"status": status, "converged": bool(st.converged), "sweeps": int(st.sweeps),
+            "updates": int(st.fine_updates), "ms": float(st.ms_total)}
+    return u, w, info
+
+
+def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol: float = 1e-12,
+             max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
+             max_coarse_sweeps: int = 256, U_init=None, W_init=None, debug: bool = False,
+             history_cap: int = 4096):
+    """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
+    with the patched fine solution u, coarse values U (NaN off the skeleton),
+    coarse wind codes W, counters and timings; with debug=True also the last
+    iteration's u^k, w^k and pre-causal-sweep U."""
+    torch = _torch()
+    L = load_library()
+    r = r.contiguous()
+    g = _grid(r, h)
+    gm, keep = _gamma(gamma_idx, gamma_val, r)
+    if max_iter is None:
+        max_iter = 4 * (int(g.n[0]) - 1) // M + 16
+    u = torch.empty_like(r)
+    U = torch.empty_like(r)
+    W = torch.empty(r.shape, dtype=torch.int8, device=r.device)
+    o = DDOpts()
+    o.S, o.M, o.theta, o.tol = int(S), int(M), float(theta), float(tol)
+    o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps)
+    if U_init is not None:
+        U_init = U_init.to(device=r.device, dtype=r.dtype).contiguous()
+        W_init = W_init.to(device=r.device, dtype=torch.int8).contiguous()
+        o.U_init, o.W_init = U_init.data_ptr(), W_init.data_ptr()
+    dbg = None
+    if debug:
+        dbg_t = {"uk": torch.empty_like(r), "wk": torch.empty(r.shape, dtype=torch.int8, device=r.device),
+                 "Upre": torch.empty_like(r)}
+        dbg = DDDebug(dbg_t["uk"].data_ptr(), dbg_t["wk"].data_ptr(), dbg_t["Upre"].data_ptr())
+        o.debug = ctypes.pointer(dbg)
+    hist = (ctypes.c_double * max(1, history_cap))()
+    st = Stats()
+    st.residual_history = hist
+    st.history_cap = history_cap
+    status = L.eik_dd_solve(ctypes.byref(g), r.data_ptr(), ctypes.byref(gm), ctypes.byref(o),
+                            u.data_ptr(), U.data_ptr(), W.data_ptr(), ctypes.byref(st), _stream())
+    _check(L, status)
+    it = int(st.iterations)
+    out = {"u": u, "U": U, "W": W, "status": status, "iterations": it,
+           "converged": bool(st.converged), "fine_updates": int(st.fine_updates),
+           "coarse_updates": int(st.coarse_updates), "residuals": list(hist[: min(it, history_cap)]),
+           "ms_total": float(st.ms_total), "ms_fine": float(st.ms_fine),
+           "ms_coarse": float(st.ms_coarse)}
+    if debug:
+        out.update(dbg_t)
+    return out
+
+
+def decode_winds(codes, d: int):
+    """Wind codes (2 bits per axis, see include/eik.h) -> per-axis int8
+    components in {-1, 0, +1}, shape (d, N)."""
+    import numpy as np
+    c = np.asarray(codes).astype(np.uint8).reshape(-1)
+    out = np.zeros((d, c.size), dtype=np.int8)
+    for a in range(d):
+        f = (c >> (2 * a)) & 3
+        out[a] = np.where(f == 3, -1, f).astype(np.int8)
+    return out

@@ -1,0 +1,476 @@
+// Host runtime and C ABI of the MI355X two-scale DD Eikonal solver
+// (Martin & Tsai, arXiv 1805.04198).  See include/eik.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/eik.h"
+#include "kernels2d.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+eik_status fail(eik_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+eik_status fail(eik_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(EIK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kLdsBytes = 160 * 1024;
+
+// Per-device workspace: one device buffer grown on demand, plus pinned host
+// words for the per-iteration readback.  Calls on one device are serialised.
+struct Workspace {
+  std::mutex mu;
+  void* dev = nullptr;
+  size_t bytes = 0;
+  unsigned long long* host = nullptr;  // pinned: 8 words
+};
+Workspace g_ws[kMaxDevices];
+
+eik_status ws_get(int dev, size_t need, void** out, unsigned long long** host) {
+  Workspace& w = g_ws[dev];
+  if (w.bytes < need) {
+    if (w.dev) HIPCHK(hipFree(w.dev));
+    w.dev = nullptr;
+    w.bytes = 0;
+    HIPCHK(hipMalloc(&w.dev, need));
+    w.bytes = need;
+  }
+  if (!w.host) HIPCHK(hipHostMalloc((void**)&w.host, 8 * sizeof(unsigned long long), hipHostMallocDefault));
+  *out = w.dev;
+  *host = w.host;
+  return EIK_OK;
+}
+
+// carve aligned sub-buffers out of the workspace
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename U>
+  U* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    U* p = reinterpret_cast<U*>(base + off);
+    off += n * sizeof(U);
+    return p;
+  }
+};
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename K>
+eik_status allow_lds(K kernel, size_t bytes) {
+  if (bytes > 64 * 1024)
+    HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return EIK_OK;
+}
+
+template <typename T>
+eik_status validate(const T* r, int64_t N, const eik_gamma* gam, unsigned int* dflag,
+                    unsigned long long* host, hipStream_t s) {
+  HIPCHK(hipMemsetAsync(dflag, 0, sizeof(unsigned int), s));
+  const int64_t n = std::max<int64_t>(N, gam->count);
+  hipLaunchKernelGGL(eik::k_validate<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, r, N, gam->idx,
+                     (const T*)gam->g, gam->count, dflag);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(host, dflag, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  unsigned int bad = *(unsigned int*)host;
+  if (bad & 1) return fail(EIK_ERR_ARG, "r must be > 0 and finite at every node");
+  if (bad & 2) return fail(EIK_ERR_ARG, "Gamma indices must be strictly increasing and in [0, N)");
+  if (bad & 4) return fail(EIK_ERR_ARG, "Gamma values must be finite");
+  return EIK_OK;
+}
+
+template <typename T>
+T* as(const void* p) { return (T*)p; }
+
+// ---------------------------------------------------------------------------
+// eik_dd_solve, d = 2
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t ldsB) {
+  const int nC = (A.NI + 1) * (A.NJ + 1);
+  const int nH = A.NI * (A.NJ + 1);
+  const int nV = (A.NI + 1) * A.NJ;
+  for (int dir = 0; dir < 4; ++dir) {
+    const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
+    hipLaunchKernelGGL(eik::k_causal_a<T>, dim3(nblocks(nC + nH + nV, 256)), dim3(256), 0, s, A, U, W,
+                       sx, sy);
+    hipLaunchKernelGGL(eik::k_causal_b<T>, dim3(1), dim3(1024), ldsB, s, A, U, sx, sy);
+    hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nblocks(nH + nV, 256)), dim3(256), 0, s, A, U, sx, sy);
+  }
+}
+
+template <typename T>
+eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, const eik_dd_opts* o,
+                      void* u_outv, void* U_outv, int8_t* W_out, eik_stats* st, hipStream_t s) {
+  const int n0 = (int)G->n[0], n1 = (int)G->n[1];
+  const int S = o->S, M = o->M;
+  if (M < 2 || S < M || S % M != 0) return fail(EIK_ERR_SHAPE, "need M >= 2 and S a multiple of M (S=%d M=%d)", S, M);
+  if ((n0 - 1) % S != 0 || (n1 - 1) % S != 0)
+    return fail(EIK_ERR_SHAPE, "(n-1) must be a multiple of S on every axis");
+  if (S + 1 > eik::kMaxL) return fail(EIK_ERR_UNSUPPORTED, "subdomain side S+1 = %d > %d nodes", S + 1, eik::kMaxL);
+  const int NI = (n0 - 1) / M, NJ = (n1 - 1) / M;
+  if (NI + 1 > eik::kMaxL || NJ + 1 > eik::kMaxL)
+    return fail(EIK_ERR_UNSUPPORTED, "coarse lattice extent > %d nodes", eik::kMaxL);
+  if (!(o->theta >= 0.0 && o->theta <= 1.0)) return fail(EIK_ERR_ARG, "theta must lie in [0,1]");
+  if (o->max_iter < 0 || o->max_fine_sweeps < 1 || o->max_coarse_sweeps < 1)
+    return fail(EIK_ERR_ARG, "max_iter >= 0, max_fine_sweeps >= 1, max_coarse_sweeps >= 1");
+  if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
+  const size_t szT = sizeof(T);
+  const int L = S + 1;
+  const size_t lds_tile = eik::halo_count(L, L) * (2 * szT + 2);
+  const size_t lds_lat = eik::halo_count(NI + 1, NJ + 1) * (4 * szT + 2);
+  const int nC = (NI + 1) * (NJ + 1);
+  const size_t lds_cb = nC * (2 * szT + 1) + 16;
+  if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cb > kLdsBytes)
+    return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this build");
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+
+  const int64_t N = (int64_t)n0 * n1;
+  const int P0 = (n0 - 1) / S, P1 = (n1 - 1) / S;
+  const int ntile = P0 * P1;
+  const int nH = NI * (NJ + 1), nV = (NI + 1) * NJ;
+  size_t need = 0;
+  need += 7 * (N * szT + 256);           // gfull U Un uk cwork + spare
+  need += 6 * (N + 256);                 // W Wn wk cflag
+  need += 2 * (N * 8 + 256);             // near keys
+  need += ntile * 4 * L * (szT + 1) + 512;
+  need += nC * (szT + 1) + (nH + nV) * (szT + 1) + 2048;
+  need += 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::DD2<T> A;
+  A.n0 = n0; A.n1 = n1; A.S = S; A.M = M; A.P0 = P0; A.P1 = P1; A.NI = NI; A.NJ = NJ;
+  A.hT = (T)G->h;
+  A.HT = (T)((double)M * G->h);
+  A.theta = (T)o->theta;
+  A.max_fine_sweeps = o->max_fine_sweeps;
+  A.max_coarse_sweeps = o->max_coarse_sweeps;
+  A.r = as<T>(rv);
+  A.gidx = gam->idx;
+  A.gval = as<T>(gam->g);
+  A.ng = gam->count;
+  T* gfull = cv.take<T>(N);
+  A.gfull = gfull;
+  A.U = cv.take<T>(N);
+  A.Un = cv.take<T>(N);
+  A.uk = cv.take<T>(N);
+  A.cwork = cv.take<T>(N);
+  A.W = cv.take<uint8_t>(N);
+  A.Wn = cv.take<uint8_t>(N);
+  A.wk = cv.take<uint8_t>(N);
+  A.cflag = cv.take<uint8_t>(N);
+  A.near_key = cv.take<unsigned long long>(N);
+  A.near_win = cv.take<long long>(N);
+  A.edge_u = cv.take<T>((size_t)ntile * 4 * L);
+  A.edge_w = cv.take<uint8_t>((size_t)ntile * 4 * L);
+  A.corner_v = cv.take<T>(nC);
+  A.corner_f = cv.take<uint8_t>(nC);
+  A.hseg_p = cv.take<T>(std::max(nH, 1));
+  A.hseg_l = cv.take<uint8_t>(std::max(nH, 1));
+  A.vseg_p = cv.take<T>(std::max(nV, 1));
+  A.vseg_l = cv.take<uint8_t>(std::max(nV, 1));
+  A.counters = cv.take<unsigned long long>(4);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  A.u_out = as<T>(u_outv);
+
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_tile<T>, lds_tile)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_init<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_correct<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal_b<T>, lds_cb)) != EIK_OK) return e;
+
+  hipEvent_t ev[4];
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  HIPCHK(hipEventRecord(ev[0], s));
+
+  const T nanT = (T)NAN;
+  const int bs = 256;
+  HIPCHK(hipMemsetAsync(A.counters, 0, 4 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, nanT, N);
+  if (gam->count > 0)
+    hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
+                       gam->idx, as<T>(gam->g), gam->count);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.u_out, nanT, N);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.uk, nanT, N);
+  HIPCHK(hipMemsetAsync(A.wk, 0, N, s));
+  HIPCHK(hipGetLastError());
+
+  const int nlat = 2 * M - 1;
+  float ms_fine = 0.f, ms_coarse = 0.f;
+  if (o->U_init) {
+    hipLaunchKernelGGL(eik::k_import_U<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, as<T>(o->U_init), A.U);
+    HIPCHK(hipMemcpyAsync(A.W, o->W_init, N, hipMemcpyDeviceToDevice, s));
+  } else {
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.U, nanT, N);
+    HIPCHK(hipMemsetAsync(A.W, 0, N, s));
+    HIPCHK(hipMemsetAsync(A.near_key, 0xff, N * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(eik::k_fill<long long>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.near_win,
+                       (long long)0x7fffffffffffffffll, N);
+    const int64_t W2 = 2 * M - 1;
+    const int64_t npair = gam->count * W2 * W2;
+    if (npair > 0) {
+      hipLaunchKernelGGL(eik::k_near_a<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
+      hipLaunchKernelGGL(eik::k_near_b<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
+    }
+    hipLaunchKernelGGL(eik::k_lattice_init<T>, dim3(nlat), dim3(eik::kWave), lds_lat, s, A);
+    causal_sweep(A, A.U, A.W, s, lds_cb);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.Un, nanT, N);
+  HIPCHK(hipMemsetAsync(A.Wn, 0, N, s));
+
+  const eik_dd_debug* dbg = o->debug;
+  int it = 0, conv = 0;
+  double last = 0.0;
+  const int64_t nres = (int64_t)(NJ + 1) * n0 + (int64_t)(NI + 1) * n1;
+  for (int k = 0; k < o->max_iter; ++k) {
+    HIPCHK(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kWave), lds_tile, s, A);
+    HIPCHK(hipEventRecord(ev[2], s));
+    const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
+    if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
+    hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kWave), lds_lat, s, A);
+    if (dbg && dbg->U_pre_causal)
+      HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
+    causal_sweep(A, A.Un, A.Wn, s, lds_cb);
+    HIPCHK(hipMemsetAsync(&A.counters[2], 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(eik::k_residual<T>, dim3(nblocks(nres, bs)), dim3(bs), 0, s, A);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float a = 0.f, b = 0.f;
+    HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[3]));
+    ms_fine += a;
+    ms_coarse += b;
+    unsigned long long bits = host[0];
+    double delta;
+    std::memcpy(&delta, &bits, sizeof delta);
+    std::swap(A.U, A.Un);
+    std::swap(A.W, A.Wn);
+    it = k + 1;
+    last = delta;
+    if (st && st->residual_history && k < st->history_cap) st->residual_history[k] = delta;
+    if (std::isnan(delta)) return fail(EIK_ERR_NONFINITE, "residual is NaN");
+    if (delta < o->tol || delta == 0.0) {
+      conv = 1;
+      break;
+    }
+  }
+  if (U_outv) hipLaunchKernelGGL(eik::k_export_U<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, A.U, as<T>(U_outv));
+  if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
+  if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
+  if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(host, A.counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(ev[3], s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  if (st) {
+    float tot = 0.f;
+    HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[3]));
+    st->iterations = it;
+    st->converged = conv;
+    st->fine_updates = (int64_t)host[0];
+    st->coarse_updates = (int64_t)host[1];
+    st->sweeps = 0;
+    st->final_residual = last;
+    st->ms_total = tot;
+    st->ms_fine = ms_fine;
+    st->ms_coarse = tot - ms_fine;
+    (void)ms_coarse;
+  }
+  if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
+  return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// eik_solve, d = 2
+// ---------------------------------------------------------------------------
+
+template <typename T>
+eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int32_t max_sweeps,
+                   void* u_outv, int8_t* wind_out, eik_stats* st, hipStream_t s) {
+  const int n0 = (int)G->n[0], n1 = (int)G->n[1];
+  const int64_t N = (int64_t)n0 * n1;
+  if (max_sweeps < 1) return fail(EIK_ERR_ARG, "max_sweeps must be >= 1");
+  auto side = [](int n) { int nb = (n + eik::kMaxL - 1) / eik::kMaxL; return (n + nb - 1) / nb; };
+  const int B = std::max(side(n0), side(n1));
+  const int BX = (n0 + B - 1) / B, BY = (n1 + B - 1) / B;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  const size_t szT = sizeof(T);
+  size_t need = N * szT + 256 + (wind_out ? 0 : N + 256) + 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::GS2<T> A;
+  A.n0 = n0; A.n1 = n1; A.B = B; A.BX = BX; A.BY = BY;
+  A.hT = (T)G->h;
+  A.r = as<T>(rv);
+  T* gfull = cv.take<T>(N);
+  A.gfull = gfull;
+  A.u = as<T>(u_outv);
+  A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(N);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  A.changed = dflag + 1;
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  const size_t lds = eik::halo_count(B, B) * (2 * szT + 2);
+  if ((e = allow_lds(eik::k_grid_sweep<T>, lds)) != EIK_OK) return e;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  const int bs = 256;
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, (T)NAN, N);
+  if (gam->count > 0)
+    hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
+                       gam->idx, as<T>(gam->g), gam->count);
+  hipLaunchKernelGGL(eik::k_grid_init<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  HIPCHK(hipGetLastError());
+  int sw = 0, conv = 0;
+  while (sw < max_sweeps) {
+    const int dir = sw & 3;
+    const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
+    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
+    for (int d = 0; d <= BX + BY - 2; ++d) {
+      const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kWave), lds, s, A, sx, sy, d);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++sw;
+    if (*(unsigned int*)host == 0) {
+      conv = 1;
+      break;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    st->iterations = 0;
+    st->converged = conv;
+    st->sweeps = sw;
+    st->fine_updates = (int64_t)sw * (N - gam->count);
+    st->coarse_updates = 0;
+    st->final_residual = 0.0;
+    st->ms_total = ms;
+    st->ms_fine = ms;
+    st->ms_coarse = 0.f;
+  }
+  if (!conv) return fail(EIK_ERR_NOCONV, "FSM not stationary after %d sweeps", sw);
+  return EIK_OK;
+}
+
+eik_status check_common(const eik_grid* G, const void* r, const eik_gamma* gam, const void* out) {
+  if (!G || !r || !gam || !out) return fail(EIK_ERR_ARG, "NULL argument");
+  if (G->dim != 2) {
+    if (G->dim == 3) return fail(EIK_ERR_UNSUPPORTED, "d = 3 is not implemented in this build");
+    return fail(EIK_ERR_ARG, "dim must be 2 or 3");
+  }
+  if (G->dtype != EIK_F32 && G->dtype != EIK_F64) return fail(EIK_ERR_ARG, "dtype must be EIK_F32 or EIK_F64");
+  if (G->n[0] < 2 || G->n[1] < 2) return fail(EIK_ERR_SHAPE, "need at least 2 nodes per axis");
+  if ((int64_t)G->n[0] * G->n[1] >= (int64_t)1 << 31) return fail(EIK_ERR_UNSUPPORTED, "grid too large for 32-bit indexing");
+  if (!(G->h > 0) || !std::isfinite(G->h)) return fail(EIK_ERR_ARG, "h must be positive and finite");
+  if (gam->count < 0 || (gam->count > 0 && (!gam->idx || !gam->g))) return fail(EIK_ERR_ARG, "bad Gamma");
+  if (r == out) return fail(EIK_ERR_ARG, "u_out must not alias r");
+  return EIK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma, int32_t max_sweeps,
+                     void* u_out, int8_t* wind_out, eik_stats* stats, void* hip_stream) {
+  eik_status e = check_common(grid, r, gamma, u_out);
+  if (e != EIK_OK) return e;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
+  return solve_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
+}
+
+eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma, const eik_dd_opts* opts,
+                        void* u_out, void* U_out, int8_t* W_out, eik_stats* stats, void* hip_stream) {
+  eik_status e = check_common(grid, r, gamma, u_out);
+  if (e != EIK_OK) return e;
+  if (!opts) return fail(EIK_ERR_ARG, "NULL opts");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dtype == EIK_F32)
+    return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+  return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+}
+
+eik_status eik_adjoint(const eik_grid*, const void*, const eik_gamma*, const void*, const int8_t*,
+                       const void*, void*, void*) {
+  return fail(EIK_ERR_UNSUPPORTED, "eik_adjoint is not implemented in this build");
+}
+
+const char* eik_last_error(void) { return g_err.c_str(); }
+
+eik_status eik_release(void) {
+  for (int d = 0; d < kMaxDevices; ++d) {
+    std::lock_guard<std::mutex> lock(g_ws[d].mu);
+    if (g_ws[d].dev) {
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(d);
+      (void)hipFree(g_ws[d].dev);
+      if (g_ws[d].host) (void)hipHostFree(g_ws[d].host);
+      (void)hipSetDevice(cur);
+      g_ws[d].dev = nullptr;
+      g_ws[d].host = nullptr;
+      g_ws[d].bytes = 0;
+    }
+  }
+  return EIK_OK;
+}
+
+const char* eik_version(void) { return "eik-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,943 @@
+// Device code of the 2D domain-decomposition Eikonal solver for gfx950.
+//
+// Method: Martin & Tsai, arXiv 1805.04198, Sec. 3.2.  Every step here has a
+// counterpart in the CPU reference that is checked value-by-value against it;
+// the arithmetic of the local solve follows one fixed evaluation order (no FMA
+// contraction: the library is built with -ffp-contract=off) so that the two
+// agree bit for bit:
+//     rd = r * Delta;  d = a - b;  t = rd*rd;  t = t + t;  t = t - d*d;
+//     two-sided (|d| < rd):  u = ((a + b) + sqrt(t)) * 0.5
+//     one-sided          :  u = min(a, b) + rd
+//
+// Layout: node (i, j) at i + n0*j.  Winds are 2-bit-per-axis codes (see
+// include/eik.h).  Subdomains ("tiles") and coarse lattices are swept by one
+// 64-lane wave each with the whole grid resident in LDS: lane = row in sweep
+// order, and at step t lane j updates column t - j, i.e. the anti-diagonal
+// (hyperplane) order, which gives exactly the values of the paper's
+// lexicographic Gauss-Seidel sweep because a node only reads neighbours on the
+// previous (already updated) and next (not yet updated) anti-diagonals.
+// A 65th row (tiles of 64 cells) rides on lane 0 one step late.
+//
+// LDS grids carry a one-node halo ring: interior node (i, j) of an L0 x L1
+// box sits at (j+1)*SP + (i+1).  The ring holds +inf (no neighbour: the
+// one-sided rule on a box boundary) or, for the whole-grid sweep, the
+// neighbouring values across the box edge; it is never updated.  SP is even,
+// so neighbouring lanes (address step SP-1 or SP+1) hit different banks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eik {
+
+constexpr int kWave = 64;
+constexpr int kMaxL = 65;  // nodes per axis of a tile / lattice held in LDS
+
+template <typename T> __device__ __forceinline__ T pinf();
+template <> __device__ __forceinline__ float pinf<float>() { return __builtin_huge_valf(); }
+template <> __device__ __forceinline__ double pinf<double>() { return __builtin_huge_val(); }
+
+__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ bool disnan(float x) { return x != x; }
+__device__ __forceinline__ bool disnan(double x) { return x != x; }
+template <typename T> __device__ __forceinline__ bool dfinite(T x) { return dabs(x) < pinf<T>(); }
+
+// ---- wind codes ----
+__device__ __forceinline__ int wx_of(uint8_t c) { int v = c & 3; return v == 3 ? -1 : v; }
+__device__ __forceinline__ int wy_of(uint8_t c) { int v = (c >> 2) & 3; return v == 3 ? -1 : v; }
+__device__ __forceinline__ uint8_t wenc(int wx, int wy) { return (uint8_t)((wx & 3) | ((wy & 3) << 2)); }
+
+// Local solve of the Godunov scheme (eq. godonuv) in the closed form of the
+// coarse solver C_H (Sec. 3.2).  a, b: smaller neighbour per axis.
+template <typename T>
+__device__ __forceinline__ T godunov2(T a, T b, T rd, bool& two) {
+  T d = a - b;
+  two = dabs(d) < rd;
+  if (two) {
+    T t = rd * rd;
+    t = t + t;
+    t = t - d * d;
+    return ((a + b) + dsqrt(t)) * T(0.5);
+  }
+  return (a < b) ? (a + rd) : (b + rd);
+}
+
+// Compiler-level ordering point between consecutive wavefront steps: every
+// lane's LDS write of step t must be issued before any lane's LDS read of step
+// t+1.  One wave executes its LDS instructions in order, so no hardware
+// barrier is needed.
+__device__ __forceinline__ void step_fence() {
+  __builtin_amdgcn_wave_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// One directional Gauss-Seidel sweep over an L0 x L1 grid in LDS (row stride
+// SP) in anti-diagonal order.  sx, sy: sweep signs.  Returns true in lanes
+// that changed a value.
+template <typename Rule>
+__device__ __forceinline__ bool wave_sweep(Rule& R, int L0, int L1, int sx, int sy) {
+  const int lane = threadIdx.x;
+  bool changed = false;
+  const bool extra = L1 > kWave;  // 65th row on lane 0, one step late
+  const int nsteps = L0 + L1 - 1 + (extra ? 1 : 0);
+  for (int t = 0; t < nsteps; ++t) {
+    int jq = lane, iq = t - lane;
+    if (extra && lane == 0 && t > kWave) {
+      jq = kWave;
+      iq = t - kWave - 1;
+    }
+    if (jq < L1 && iq >= 0 && iq < L0) {
+      const int i = sx > 0 ? iq : L0 - 1 - iq;
+      const int j = sy > 0 ? jq : L1 - 1 - jq;
+      changed |= R.update(i, j);
+    }
+    step_fence();
+  }
+  return changed;
+}
+
+// Sweep in the 2^d orders of the paper's loop nest ((-,-), (-,+), (+,-),
+// (+,+), x outermost) until a whole sweep changes nothing, at most max_sweeps.
+template <typename Rule>
+__device__ int wave_fsm(Rule& R, int L0, int L1, int max_sweeps) {
+  int s = 0;
+  while (s < max_sweeps) {
+    const int dir = s & 3;
+    const int sx = (dir & 2) ? 1 : -1;
+    const int sy = (dir & 1) ? 1 : -1;
+    bool ch = wave_sweep(R, L0, L1, sx, sy);
+    ++s;
+    if (!__any(ch)) break;
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Per-node rules
+// ---------------------------------------------------------------------------
+
+// Fine update (Alg. fineupdate2D with flow-direction winds; eq. FSMupdate).
+template <typename T>
+struct FineRule {
+  T* u;
+  uint8_t* w;
+  const T* rd;
+  const uint8_t* fixed;
+  int L0, L1, SP;
+  __device__ __forceinline__ bool update(int i, int j) {
+    const int x = (j + 1) * SP + (i + 1);
+    if (fixed[x]) return false;
+    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+    T a, b;
+    int wx, wy;
+    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
+    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
+    bool two;
+    T ut = godunov2(a, b, rd[x], two);
+    if (ut < u[x]) {
+      u[x] = ut;
+      w[x] = two ? wenc(wx, wy) : (a < b ? wenc(wx, 0) : wenc(0, wy));
+      return true;
+    }
+    return false;
+  }
+};
+
+// Coarse update of Step 1 (Alg. update2D, with the FSM minimum).
+template <typename T>
+struct CoarseInitRule {
+  T* u;
+  uint8_t* w;
+  const T* rd;
+  const uint8_t* fixed;
+  int L0, L1, SP;
+  __device__ __forceinline__ bool update(int i, int j) {
+    const int x = (j + 1) * SP + (i + 1);
+    if (fixed[x]) return false;
+    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+    T a, b;
+    int wx, wy;
+    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
+    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
+    bool two;
+    T ut = godunov2(a, b, rd[x], two);
+    if (ut < u[x]) {
+      u[x] = ut;
+      w[x] = (ut < b) ? wenc(wx, 0) : ((ut < a) ? wenc(0, wy) : wenc(wx, wy));
+      return true;
+    }
+    return false;
+  }
+};
+
+// Step 4 (Alg. 2Dweightedupdate): U = u^k + theta*(U~ - C^k) when the winds
+// w^k, W^k and W~ agree along every normal axis of the node's coarse line and
+// U~, C^k are finite; U = u^k otherwise.  Direct assignment, no minimum.
+// flags: bit0 = Gamma (fixed), bit1 = x is a normal axis, bit2 = y is.
+// wk: low nibble = w^k code, high nibble = W^k code.
+template <typename T>
+struct CorrectRule {
+  T* u;
+  const T* uk;
+  const T* ck;
+  const T* rd;
+  const uint8_t* wk;
+  const uint8_t* flags;
+  T theta;
+  int L0, L1, SP;
+  __device__ __forceinline__ bool update(int i, int j) {
+    const int x = (j + 1) * SP + (i + 1);
+    const uint8_t f = flags[x];
+    if (f & 1) return false;
+    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+    T a, b;
+    int wx, wy;
+    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
+    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
+    bool two;
+    T ut = godunov2(a, b, rd[x], two);
+    int tx, ty;  // W~
+    if (ut < b) { tx = wx; ty = 0; } else if (ut < a) { tx = 0; ty = wy; } else { tx = wx; ty = wy; }
+    const uint8_t c = wk[x];
+    bool cond = true;
+    if (f & 2) {
+      int p = wx_of(c & 15), q = wx_of(c >> 4);
+      bool le = p <= 0 && q <= 0 && tx <= 0, ge = p >= 0 && q >= 0 && tx >= 0;
+      cond = cond && (le || ge);
+    }
+    if (f & 4) {
+      int p = wy_of(c & 15), q = wy_of(c >> 4);
+      bool le = p <= 0 && q <= 0 && ty <= 0, ge = p >= 0 && q >= 0 && ty >= 0;
+      cond = cond && (le || ge);
+    }
+    const T ckx = ck[x];
+    T v;
+    if (cond && dfinite(ut) && dfinite(ckx))
+      v = uk[x] + theta * (ut - ckx);
+    else
+      v = uk[x];
+    if (v != u[x]) {
+      u[x] = v;
+      return true;
+    }
+    return false;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Kernel arguments
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct DD2 {
+  int n0, n1;        // nodes per axis
+  int S, M;          // subdomain side, coarse spacing (fine cells)
+  int P0, P1;        // subdomains per axis
+  int NI, NJ;        // coarse cells per axis
+  T hT, HT, theta;
+  int max_fine_sweeps, max_coarse_sweeps;
+  const T* r;
+  const T* gfull;      // Gamma value per node, NaN if not a Gamma node
+  const int64_t* gidx; // sorted Gamma indices
+  const T* gval;
+  int64_t ng;
+  T* U;               // coarse values (full grid, skeleton used)
+  uint8_t* W;
+  T* Un;
+  uint8_t* Wn;
+  T* uk;
+  uint8_t* wk;
+  T* u_out;
+  T* edge_u;          // [tile][4][S+1]
+  uint8_t* edge_w;
+  T* cwork;           // causal sweep scratch (full grid)
+  uint8_t* cflag;     // causal sweep scratch (full grid)
+  T* corner_v;        // (NI+1)(NJ+1)
+  uint8_t* corner_f;
+  T* hseg_p;          // NI*(NJ+1) segment end values
+  uint8_t* hseg_l;
+  T* vseg_p;          // (NI+1)*NJ
+  uint8_t* vseg_l;
+  unsigned long long* near_key;  // Step 1 nearest-Gamma keys (full grid)
+  long long* near_win;
+  unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits
+};
+
+__device__ __forceinline__ bool is_iface(int c, int S, int n) { return (c % S == 0) && c > 0 && c < n - 1; }
+
+// order-preserving map of a real onto unsigned 64-bit keys
+__device__ __forceinline__ unsigned long long okey(double v) {
+  unsigned long long b = __double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ unsigned long long okey(float v) { return okey((double)v); }
+__device__ __forceinline__ double okey_dec(unsigned long long k) {
+  unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return __longlong_as_double(b);
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scatter_gamma(T* gfull, const int64_t* gidx, const T* gval, int64_t ng) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < ng) gfull[gidx[i]] = gval[i];
+}
+
+// r > 0 and finite everywhere; Gamma sorted, in range, finite.  bad[0] != 0 on failure.
+template <typename T>
+__global__ void k_validate(const T* r, int64_t N, const int64_t* gidx, const T* gval, int64_t ng,
+                           unsigned int* bad) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) {
+    T v = r[i];
+    if (!(v > T(0)) || !dfinite(v)) atomicOr(bad, 1u);
+  }
+  if (i < ng) {
+    int64_t g = gidx[i];
+    if (g < 0 || g >= N) atomicOr(bad, 2u);
+    if (i > 0 && !(gidx[i - 1] < g)) atomicOr(bad, 2u);
+    if (!dfinite(gval[i])) atomicOr(bad, 4u);
+  }
+}
+
+// Step 1 initialisation near Gamma: every coarse node X within max-norm
+// distance < H (M cells) of a Gamma node x_g gets the candidate
+// g + r_X * (h * sqrt(|X - x_g|^2 / h^2)); the smallest wins, ties to the
+// first Gamma node.  Pass A keeps the smallest value, pass B its first index.
+template <typename T>
+__device__ __forceinline__ bool near_candidate(const DD2<T>& A, int64_t gi, int off, int& X, T& v) {
+  const int W2 = 2 * A.M - 1;
+  const int dx = off % W2 - (A.M - 1), dy = off / W2 - (A.M - 1);
+  const int64_t g = A.gidx[gi];
+  const int gxi = (int)(g % A.n0), gyi = (int)(g / A.n0);
+  const int xi = gxi + dx, yi = gyi + dy;
+  if (xi < 0 || xi >= A.n0 || yi < 0 || yi >= A.n1) return false;
+  if (xi % A.M != 0 && yi % A.M != 0) return false;  // not a coarse node
+  X = xi + A.n0 * yi;
+  const int d2 = dx * dx + dy * dy;
+  T sq = dsqrt((T)d2);
+  T dist = A.hT * sq;
+  v = A.gval[gi] + A.r[X] * dist;
+  return true;
+}
+
+template <typename T>
+__global__ void k_near_a(DD2<T> A) {
+  const int W2 = 2 * A.M - 1;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= A.ng * W2 * W2) return;
+  int X;
+  T v;
+  if (near_candidate(A, t / (W2 * W2), (int)(t % (W2 * W2)), X, v)) atomicMin(&A.near_key[X], okey(v));
+}
+
+template <typename T>
+__global__ void k_near_b(DD2<T> A) {
+  const int W2 = 2 * A.M - 1;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= A.ng * W2 * W2) return;
+  int X;
+  T v;
+  const int64_t gi = t / (W2 * W2);
+  if (near_candidate(A, gi, (int)(t % (W2 * W2)), X, v))
+    if (okey(v) == A.near_key[X]) atomicMin(&A.near_win[X], (long long)gi);
+}
+
+// ---------------------------------------------------------------------------
+// LDS boxes
+// ---------------------------------------------------------------------------
+
+__host__ __device__ __forceinline__ int halo_stride(int L0) { return (L0 + 3) & ~1; }
+__host__ __device__ __forceinline__ int halo_count(int L0, int L1) { return halo_stride(L0) * (L1 + 2); }
+
+// ---------------------------------------------------------------------------
+// lattices (Steps 1 and 4)
+// ---------------------------------------------------------------------------
+
+// lattice q: 0 -> offset (0,0); 1..M-1 -> (q,0); M..2M-2 -> (0, q-M+1)
+__device__ __forceinline__ void lattice_offset(int q, int M, int& o0, int& o1) {
+  if (q == 0) { o0 = 0; o1 = 0; }
+  else if (q < M) { o0 = q; o1 = 0; }
+  else { o0 = 0; o1 = q - M + 1; }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int o0, o1;
+  lattice_offset(blockIdx.x, A.M, o0, o1);
+  const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
+  const int SP = halo_stride(L0);
+  const int cnt = halo_count(L0, L1);
+  T* u = (T*)smem;
+  T* rd = u + cnt;
+  uint8_t* w = (uint8_t*)(rd + cnt);
+  uint8_t* fx = w + cnt;
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); fx[k] = 1; w[k] = 0; }
+  step_fence();
+  int nfree = 0;
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
+    const int X = xi + A.n0 * yi;
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    rd[x] = A.r[X] * A.HT;
+    const T g = A.gfull[X];
+    if (!disnan(g)) {
+      u[x] = g; w[x] = 0; fx[x] = 1;
+    } else if (A.near_win[X] != 0x7fffffffffffffffll) {
+      u[x] = (T)okey_dec(A.near_key[X]);
+      const int64_t gg = A.gidx[A.near_win[X]];
+      const int dx = xi - (int)(gg % A.n0), dy = yi - (int)(gg / A.n0);
+      w[x] = wenc((dx > 0) - (dx < 0), (dy > 0) - (dy < 0));
+      fx[x] = 1;
+    } else {
+      u[x] = pinf<T>(); w[x] = 0; fx[x] = 0;
+      ++nfree;
+    }
+  }
+  step_fence();
+  CoarseInitRule<T> R{u, w, rd, fx, L0, L1, SP};
+  const int ns = wave_fsm(R, L0, L1, A.max_coarse_sweeps);
+  step_fence();
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    A.U[X] = u[x];
+    A.W[X] = w[x];
+  }
+  for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)nfree * (unsigned long long)ns);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int o0, o1;
+  lattice_offset(blockIdx.x, A.M, o0, o1);
+  const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
+  const int SP = halo_stride(L0);
+  const int cnt = halo_count(L0, L1);
+  T* u = (T*)smem;
+  T* uk = u + cnt;
+  T* ck = uk + cnt;
+  T* rd = ck + cnt;
+  uint8_t* wk = (uint8_t*)(rd + cnt);
+  uint8_t* fl = wk + cnt;
+  const T inf = pinf<T>();
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = inf; fl[k] = 1; }
+  step_fence();
+  int nfree = 0;
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
+    const int X = xi + A.n0 * yi;
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    u[x] = A.U[X];  // U^k, used for C^k first
+    uk[x] = A.uk[X];
+    rd[x] = A.r[X] * A.HT;
+    wk[x] = (uint8_t)((A.wk[X] & 15) | ((A.W[X] & 15) << 4));
+    const bool gam = !disnan(A.gfull[X]);
+    fl[x] = (uint8_t)((gam ? 1 : 0) | ((xi % A.M == 0) ? 2 : 0) | ((yi % A.M == 0) ? 4 : 0));
+    if (!gam) ++nfree;
+  }
+  step_fence();
+  // C^k = C_H(nbrs^H(U^k)) once per node (Jacobi)
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+    T a = xm < xp ? xm : xp;
+    T b = ym < yp ? ym : yp;
+    bool two;
+    ck[x] = godunov2(a, b, rd[x], two);
+  }
+  step_fence();
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    if (fl[x] & 1) {
+      const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+      u[x] = A.gfull[X];
+    } else {
+      u[x] = inf;
+    }
+  }
+  step_fence();
+  CorrectRule<T> R{u, uk, ck, rd, wk, fl, A.theta, L0, L1, SP};
+  const int ns = wave_fsm(R, L0, L1, A.max_coarse_sweeps);
+  step_fence();
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+    const int x = (p1 + 1) * SP + (p0 + 1);
+    A.Un[X] = u[x];
+    A.Wn[X] = (fl[x] & 1) ? (uint8_t)0 : (uint8_t)(wk[x] & 15);
+  }
+  for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)nfree * (unsigned long long)ns);
+}
+
+// ---------------------------------------------------------------------------
+// Steps 2 and 3: one wave per subdomain
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int I = blockIdx.x % A.P0, J = blockIdx.x / A.P0;
+  const int L = A.S + 1;
+  const int SP = halo_stride(L);
+  const int cnt = halo_count(L, L);
+  T* u = (T*)smem;
+  T* rd = u + cnt;
+  uint8_t* w = (uint8_t*)(rd + cnt);
+  uint8_t* fx = w + cnt;
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); fx[k] = 1; w[k] = 0; }
+  step_fence();
+  const int bi = I * A.S, bj = J * A.S;
+  int nfree = 0;
+  for (int k = threadIdx.x; k < L * L; k += kWave) {
+    const int li = k % L, lj = k / L;
+    const int xi = bi + li, yi = bj + lj;
+    const int X = xi + A.n0 * yi;
+    const int x = (lj + 1) * SP + (li + 1);
+    rd[x] = A.r[X] * A.hT;
+    const T g = A.gfull[X];
+    if (!disnan(g)) {
+      u[x] = g; w[x] = 0; fx[x] = 1;
+      continue;
+    }
+    ++nfree;
+    fx[x] = 0;
+    // Step 2: a subdomain-boundary node on an interface is inflow if the
+    // coarse wind points into the subdomain; it starts at U with wind W and,
+    // like every non-Gamma node, still takes the FSM minimum.
+    bool inflow = false;
+    uint8_t Wc = 0;
+    const bool bx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
+    const bool by = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
+    if (bx || by) {
+      Wc = A.W[X];
+      if (bx && ((li == 0 && wx_of(Wc) > 0) || (li == A.S && wx_of(Wc) < 0))) inflow = true;
+      if (by && ((lj == 0 && wy_of(Wc) > 0) || (lj == A.S && wy_of(Wc) < 0))) inflow = true;
+    }
+    if (inflow) {
+      u[x] = A.U[X];
+      w[x] = Wc;
+    } else {
+      u[x] = pinf<T>();
+      w[x] = 0;
+    }
+  }
+  step_fence();
+  FineRule<T> R{u, w, rd, fx, L, L, SP};
+  const int ns = wave_fsm(R, L, L, A.max_fine_sweeps);
+  step_fence();
+  const int tile = blockIdx.x;
+  for (int k = threadIdx.x; k < L * L; k += kWave) {
+    const int li = k % L, lj = k / L;
+    const int xi = bi + li, yi = bj + lj;
+    const int X = xi + A.n0 * yi;
+    const int x = (lj + 1) * SP + (li + 1);
+    const T v = u[x];
+    const uint8_t c = w[x];
+    const bool ifx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
+    const bool ify = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
+    if (!ifx && !ify) {
+      A.u_out[X] = v;
+      if (xi % A.M == 0 || yi % A.M == 0) {
+        A.uk[X] = v;
+        A.wk[X] = c;
+      }
+    }
+    if (li == 0) { A.edge_u[(tile * 4 + 0) * L + lj] = v; A.edge_w[(tile * 4 + 0) * L + lj] = c; }
+    if (li == A.S) { A.edge_u[(tile * 4 + 1) * L + lj] = v; A.edge_w[(tile * 4 + 1) * L + lj] = c; }
+    if (lj == 0) { A.edge_u[(tile * 4 + 2) * L + li] = v; A.edge_w[(tile * 4 + 2) * L + li] = c; }
+    if (lj == A.S) { A.edge_u[(tile * 4 + 3) * L + li] = v; A.edge_w[(tile * 4 + 3) * L + li] = c; }
+  }
+  for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
+  if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)nfree * (unsigned long long)ns);
+}
+
+// ---------------------------------------------------------------------------
+// eik_solve: one directional sweep of the whole grid, boxes in wavefront order
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct GS2 {
+  int n0, n1;
+  int B;            // box side (nodes)
+  int BX, BY;       // boxes per axis
+  T hT;
+  const T* r;
+  const T* gfull;
+  T* u;
+  uint8_t* w;
+  unsigned int* changed;
+};
+
+// Boxes with (I' + J') == diag in sweep order.  Box (I, J) reads its halo
+// from global memory: the upwind neighbours were finished by the previous
+// diagonals, the downwind ones are untouched, so the sweep of the whole grid
+// is the paper's serial Gauss-Seidel sweep exactly.
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int sx, int sy, int diag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int q0 = max(0, diag - (A.BY - 1));
+  const int Iq = q0 + (int)blockIdx.x;
+  const int Jq = diag - Iq;
+  if (Iq >= A.BX || Jq < 0) return;
+  const int I = sx > 0 ? Iq : A.BX - 1 - Iq;
+  const int J = sy > 0 ? Jq : A.BY - 1 - Jq;
+  const int bi = I * A.B, bj = J * A.B;
+  const int L0 = min(A.B, A.n0 - bi), L1 = min(A.B, A.n1 - bj);
+  const int SP = halo_stride(L0);
+  const int cnt = halo_count(L0, L1);
+  T* u = (T*)smem;
+  T* rd = u + cnt;
+  uint8_t* w = (uint8_t*)(rd + cnt);
+  uint8_t* fx = w + cnt;
+  const T inf = pinf<T>();
+  for (int k = threadIdx.x; k < cnt; k += kWave) {
+    const int hi = k % SP - 1, hj = k / SP - 1;
+    const int xi = bi + hi, yi = bj + hj;
+    const bool inside = hi >= 0 && hi < L0 && hj >= 0 && hj < L1;
+    const bool ring = !inside && hi >= -1 && hi <= L0 && hj >= -1 && hj <= L1 &&
+                      ((hi >= 0 && hi < L0) || (hj >= 0 && hj < L1));
+    T v = inf;
+    uint8_t f = 1;
+    uint8_t c = 0;
+    if (inside) {
+      const int X = xi + A.n0 * yi;
+      v = A.u[X];
+      c = A.w[X];
+      rd[k] = A.r[X] * A.hT;
+      f = disnan(A.gfull[X]) ? 0 : 1;
+    } else if (ring && xi >= 0 && xi < A.n0 && yi >= 0 && yi < A.n1) {
+      v = A.u[xi + A.n0 * yi];
+    }
+    u[k] = v;
+    w[k] = c;
+    fx[k] = f;
+  }
+  step_fence();
+  FineRule<T> R{u, w, rd, fx, L0, L1, SP};
+  bool ch = wave_sweep(R, L0, L1, sx, sy);
+  step_fence();
+  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+    const int li = k % L0, lj = k / L0;
+    const int X = (bi + li) + A.n0 * (bj + lj);
+    const int x = (lj + 1) * SP + (li + 1);
+    A.u[X] = u[x];
+    A.w[X] = w[x];
+  }
+  if (__any(ch) && threadIdx.x == 0) atomicOr(A.changed, 1u);
+}
+
+template <typename T>
+__global__ void k_grid_init(GS2<T> A) {
+  const int64_t N = (int64_t)A.n0 * A.n1;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const T g = A.gfull[t];
+  A.u[t] = disnan(g) ? pinf<T>() : g;
+  A.w[t] = 0;
+}
+
+// Reconciliation (Alg. fineupdate, per interface axis) at every interface
+// node.  Threads: (P0-1) vertical interface lines x n1 nodes, then (P1-1)
+// horizontal lines x n0 nodes (crossings are done by the vertical pass).
+template <typename T>
+__global__ void k_reconcile(DD2<T> A) {
+  const int64_t nv = (int64_t)(A.P0 - 1) * A.n1;
+  const int64_t nh = (int64_t)(A.P1 - 1) * A.n0;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int xi, yi;
+  if (t < nv) {
+    xi = (int)(t / A.n1 + 1) * A.S;
+    yi = (int)(t % A.n1);
+  } else if (t < nv + nh) {
+    const int64_t s = t - nv;
+    yi = (int)(s / A.n0 + 1) * A.S;
+    xi = (int)(s % A.n0);
+    if (is_iface(xi, A.S, A.n0)) return;  // done by the vertical pass
+  } else {
+    return;
+  }
+  const int L = A.S + 1;
+  const bool ifx = is_iface(xi, A.S, A.n0), ify = is_iface(yi, A.S, A.n1);
+  int tx[2], ty[2], nx, ny;
+  if (ifx) { tx[0] = xi / A.S - 1; tx[1] = xi / A.S; nx = 2; }
+  else { tx[0] = min(xi / A.S, A.P0 - 1); nx = 1; }
+  if (ify) { ty[0] = yi / A.S - 1; ty[1] = yi / A.S; ny = 2; }
+  else { ty[0] = min(yi / A.S, A.P1 - 1); ny = 1; }
+  T cu[4];
+  uint8_t cw[4];
+  int sdx[4], sdy[4];
+  int nc = 0;
+  for (int a = 0; a < nx; ++a)
+    for (int b = 0; b < ny; ++b) {
+      const int tile = tx[a] + A.P0 * ty[b];
+      const int li = xi - tx[a] * A.S, lj = yi - ty[b] * A.S;
+      int e;
+      if (li == 0) e = (tile * 4 + 0) * L + lj;
+      else if (li == A.S) e = (tile * 4 + 1) * L + lj;
+      else if (lj == 0) e = (tile * 4 + 2) * L + li;
+      else e = (tile * 4 + 3) * L + li;
+      cu[nc] = A.edge_u[e];
+      cw[nc] = A.edge_w[e];
+      sdx[nc] = a;
+      sdy[nc] = b;
+      ++nc;
+    }
+  const int X = xi + A.n0 * yi;
+  const uint8_t Wk = A.W[X];
+  const T inf = pinf<T>();
+  bool keep[4];
+  int nf = 0;
+  for (int c = 0; c < nc; ++c) { keep[c] = cu[c] < inf; nf += keep[c]; }
+  if (nf == 0)
+    for (int c = 0; c < nc; ++c) keep[c] = true;
+  // allowed sides per interface axis: bit0 = minus, bit1 = plus
+  int alx = 3, aly = 3;
+  if (ifx) {
+    bool le = wx_of(Wk) <= 0, ge = wx_of(Wk) >= 0;
+    for (int c = 0; c < nc; ++c)
+      if (keep[c]) { le = le && wx_of(cw[c]) <= 0; ge = ge && wx_of(cw[c]) >= 0; }
+    if (le) alx = 2; else if (ge) alx = 1;
+  }
+  if (ify) {
+    bool le = wy_of(Wk) <= 0, ge = wy_of(Wk) >= 0;
+    for (int c = 0; c < nc; ++c)
+      if (keep[c]) { le = le && wy_of(cw[c]) <= 0; ge = ge && wy_of(cw[c]) >= 0; }
+    if (le) aly = 2; else if (ge) aly = 1;
+  }
+  int best = -1;
+  for (int c = 0; c < nc; ++c) {
+    if (!keep[c]) continue;
+    if (ifx && !((alx >> sdx[c]) & 1)) continue;
+    if (ify && !((aly >> sdy[c]) & 1)) continue;
+    if (best < 0 || cu[c] < cu[best]) best = c;
+  }
+  if (best < 0)
+    for (int c = 0; c < nc; ++c)
+      if (keep[c] && (best < 0 || cu[c] < cu[best])) best = c;
+  A.uk[X] = cu[best];
+  A.wk[X] = cw[best];
+  A.u_out[X] = cu[best];
+}
+
+// ---------------------------------------------------------------------------
+// causal sweep (Alg. causalsweep2D), one direction = three kernels
+//
+// In sweep direction (sx, sy) a coarse node X with wind component W_e = s_e
+// (flow along the sweep) is raised to the NEW value of its upwind fine
+// neighbour X - s_e e, and with W_e = -s_e to the OLD value of X + s_e e.
+// Both are maxima, so the result is: V(X) = max(U(X), old successors), then
+// U_new(X) = max(V(X), U_new of every linked predecessor).  Between corners
+// the links form chains (segments of M-1 nodes); corners join the
+// horizontal and vertical chains.  Phase A: V and the chain prefix maxima
+// per segment; phase B: the corner recurrence on the coarse grid in
+// anti-diagonal order; phase C: fill the segments from their start corner.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T vmax(T a, T b) { return a < b ? b : a; }
+
+template <typename T>
+__global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) {
+  const int nC = (A.NI + 1) * (A.NJ + 1);
+  const int nH = A.NI * (A.NJ + 1);
+  const int nV = (A.NI + 1) * A.NJ;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = A.M;
+  if (t < nC) {
+    const int I = t % (A.NI + 1), J = t / (A.NI + 1);
+    const int xi = I * M, yi = J * M;
+    const int X = xi + A.n0 * yi;
+    T v = U[X];
+    uint8_t f = 0;
+    if (disnan(A.gfull[X])) {
+      const uint8_t c = W[X];
+      const int ex = wx_of(c), ey = wy_of(c);
+      const int nxi = xi + sx, nyi = yi + sy;
+      if (ex == -sx && nxi >= 0 && nxi < A.n0) v = vmax(v, U[X + sx]);
+      if (ey == -sy && nyi >= 0 && nyi < A.n1) v = vmax(v, U[X + sy * A.n0]);
+      const int pxi = xi - sx, pyi = yi - sy;
+      if (ex == sx && pxi >= 0 && pxi < A.n0) f |= 1;
+      if (ey == sy && pyi >= 0 && pyi < A.n1) f |= 2;
+    }
+    A.corner_v[t] = v;
+    A.corner_f[t] = f;
+    return;
+  }
+  int s = t - nC;
+  bool horiz;
+  int I, J;
+  if (s < nH) { horiz = true; I = s % A.NI; J = s / A.NI; }
+  else if (s < nH + nV) { s -= nH; horiz = false; I = s % (A.NI + 1); J = s / (A.NI + 1); }
+  else return;
+  const int sg = horiz ? sx : sy;
+  const int stride = horiz ? 1 : A.n0;
+  const int base = (I * M) + A.n0 * (J * M);  // corner (I, J)
+  T P = T(0);
+  bool L = true;
+  for (int q = 1; q < M; ++q) {
+    const int off = sg > 0 ? q : M - q;
+    const int X = base + off * stride;
+    T v = U[X];
+    bool link = false;
+    if (disnan(A.gfull[X])) {
+      const uint8_t c = W[X];
+      const int e = horiz ? wx_of(c) : wy_of(c);
+      if (e == -sg) v = vmax(v, U[X + sg * stride]);
+      link = (e == sg);
+    }
+    P = (link && q > 1) ? vmax(v, P) : v;
+    L = L && link;
+    A.cwork[X] = P;
+    A.cflag[X] = L ? 1 : 0;
+  }
+  if (horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
+  else { A.vseg_p[s] = P; A.vseg_l[s] = L ? 1 : 0; }
+}
+
+// one workgroup; corner values in LDS
+template <typename T>
+__global__ __launch_bounds__(1024) void k_causal_b(DD2<T> A, T* U, int sx, int sy) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int CI = A.NI + 1, CJ = A.NJ + 1;
+  const int nC = CI * CJ;
+  T* cu = (T*)smem;   // result
+  T* cb = cu + nC;    // B(C)
+  uint8_t* ca = (uint8_t*)(cb + nC);  // alpha bits
+  for (int t = threadIdx.x; t < nC; t += blockDim.x) {
+    const int I = t % CI, J = t / CI;
+    T b = A.corner_v[t];
+    const uint8_t f = A.corner_f[t];
+    uint8_t al = 0;
+    if (f & 1) {
+      const int hs = (sx > 0 ? I - 1 : I) + A.NI * J;  // incoming horizontal segment
+      b = vmax(b, A.hseg_p[hs]);
+      if (A.hseg_l[hs]) al |= 1;
+    }
+    if (f & 2) {
+      const int vs = I + CI * (sy > 0 ? J - 1 : J);
+      b = vmax(b, A.vseg_p[vs]);
+      if (A.vseg_l[vs]) al |= 2;
+    }
+    cb[t] = b;
+    ca[t] = al;
+  }
+  __syncthreads();
+  for (int d = 0; d <= A.NI + A.NJ; ++d) {
+    for (int Iq = threadIdx.x; Iq < CI; Iq += blockDim.x) {
+      const int Jq = d - Iq;
+      if (Jq < 0 || Jq >= CJ) continue;
+      const int I = sx > 0 ? Iq : A.NI - Iq;
+      const int J = sy > 0 ? Jq : A.NJ - Jq;
+      const int t = I + CI * J;
+      T v = cb[t];
+      const uint8_t al = ca[t];
+      if (al & 1) v = vmax(v, cu[(I - sx) + CI * J]);
+      if (al & 2) v = vmax(v, cu[I + CI * (J - sy)]);
+      cu[t] = v;
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < nC; t += blockDim.x) {
+    const int I = t % CI, J = t / CI;
+    U[(I * A.M) + A.n0 * (J * A.M)] = cu[t];
+  }
+}
+
+template <typename T>
+__global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
+  const int nH = A.NI * (A.NJ + 1);
+  const int nV = (A.NI + 1) * A.NJ;
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  bool horiz;
+  int I, J;
+  if (s < nH) { horiz = true; I = s % A.NI; J = s / A.NI; }
+  else if (s < nH + nV) { s -= nH; horiz = false; I = s % (A.NI + 1); J = s / (A.NI + 1); }
+  else return;
+  const int M = A.M;
+  const int sg = horiz ? sx : sy;
+  const int stride = horiz ? 1 : A.n0;
+  const int base = (I * M) + A.n0 * (J * M);
+  const int start = sg > 0 ? base : base + M * stride;
+  const T cs = U[start];
+  for (int q = 1; q < M; ++q) {
+    const int X = base + q * stride;
+    const T P = A.cwork[X];
+    U[X] = A.cflag[X] ? vmax(P, cs) : P;
+  }
+}
+
+// max |Un - U| over the skeleton, |inf - inf| = 0, NaN counts as +inf.
+template <typename T>
+__global__ void k_residual(DD2<T> A) {
+  const int64_t nh = (int64_t)(A.NJ + 1) * A.n0;
+  const int64_t nv = (int64_t)(A.NI + 1) * A.n1;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double dv = 0.0;
+  if (t < nh) {
+    const int X = (int)(t % A.n0) + A.n0 * ((int)(t / A.n0) * A.M);
+    const T a = A.Un[X], b = A.U[X];
+    if (!(a == b)) dv = (double)dabs(a - b);
+    if (disnan(dv)) dv = __builtin_huge_val();
+  } else if (t < nh + nv) {
+    const int64_t s = t - nh;
+    const int X = (int)(s / A.n1) * A.M + A.n0 * (int)(s % A.n1);
+    const T a = A.Un[X], b = A.U[X];
+    if (!(a == b)) dv = (double)dabs(a - b);
+    if (disnan(dv)) dv = __builtin_huge_val();
+  }
+  // wave max, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    double v = __shfl_xor(dv, o);
+    dv = dv < v ? v : dv;
+  }
+  if ((threadIdx.x & 63) == 0 && dv > 0.0)
+    atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(dv));
+}
+
+// U_out: U on the skeleton, NaN elsewhere
+template <typename T>
+__global__ void k_export_U(DD2<T> A, const T* U, T* out) {
+  const int64_t N = (int64_t)A.n0 * A.n1;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int xi = (int)(t % A.n0), yi = (int)(t / A.n0);
+  out[t] = (xi % A.M == 0 || yi % A.M == 0) ? U[t] : T(__builtin_nan(""));
+}
+
+template <typename T>
+__global__ void k_import_U(DD2<T> A, const T* Uin, T* U) {
+  const int64_t N = (int64_t)A.n0 * A.n1;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int xi = (int)(t % A.n0), yi = (int)(t / A.n0);
+  U[t] = (xi % A.M == 0 || yi % A.M == 0) ? Uin[t] : T(__builtin_nan(""));
+}
+
+}  // namespace eik

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Bar: the kernels evaluate the same expressions in the same order as the
+oracle (no FMA contraction, correctly rounded sqrt), visit nodes in an order
+with the same Gauss-Seidel dependencies (anti-diagonal = lexicographic), and
+take every discrete decision (winds, branches, stopping) on the same values,
+so fp64 results must be bit-identical to the fp64 oracle and fp32 results
+bit-identical to the fp32 build of the oracle.  Converged fp32 results are
+also held to the stated tolerance 2e-5 * max u against the fp64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_04198_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1805_04198_amd as E  # noqa: E402
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def gpu_inputs(p, dtype):
+    r = dev(p.r.astype(dtype), dtype)
+    gi = torch.from_numpy(p.gamma_idx.astype(np.int64)).cuda()
+    gv = dev(p.gamma_val.astype(dtype), dtype)
+    return r, gi, gv
+
+
+def same(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return a.shape == b.shape and np.array_equal(a, b, equal_nan=True)
+
+
+def show_diff(name, g, o):
+    g = np.asarray(g).reshape(-1)
+    o = np.asarray(o).reshape(-1)
+    bad = np.nonzero(~((g == o) | (np.isnan(g) & np.isnan(o))))[0] if g.dtype.kind == "f" else np.nonzero(g != o)[0]
+    return f"{name}: {len(bad)} mismatches, first {bad[:5]} gpu={g[bad[:5]]} oracle={o[bad[:5]]}"
+
+
+# ---------------------------------------------------------------------------
+# eik_solve (the overall fine solution)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", [
+    dict(seed=1, n=(33, 33), nsrc=1, kind="fourier"),
+    dict(seed=2, n=(70, 45), nsrc=3, kind="blocks"),      # ragged boxes
+    dict(seed=3, n=(131, 97), nsrc=2, kind="fourier"),
+    dict(seed=4, n=(65, 65), nsrc=0, kind="const", edge=0),
+    dict(seed=5, n=(2, 40), nsrc=1, kind="const"),
+])
+def test_solve_bitwise(case, dtype):
+    p = W.random_problem(case["seed"], case["n"], 1, 1, n_src=case["nsrc"] or 1,
+                         kind=case["kind"], edge=case.get("edge"))
+    print(f"solve case={case} dtype={np.dtype(dtype).name}", flush=True)
+    r, gi, gv = gpu_inputs(p, dtype)
+    u, w, info = E.solve(r, gi, gv, p.h, with_wind=True)
+    uo, wo, io = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, dtype=dtype, with_info=True)
+    ug = u.cpu().numpy().reshape(-1)
+    assert same(ug, uo), show_diff("u", ug, uo)
+    assert info["sweeps"] == io["sweeps"]
+    wg = E.decode_winds(w.cpu().numpy(), 2)
+    assert same(wg, wo), show_diff("w", wg, wo)
+
+
+def test_solve_no_gamma_is_all_inf():
+    p = W.random_problem(6, (40, 40), 1, 1)
+    r = dev(p.r, np.float64)
+    u, _, info = E.solve(r, torch.zeros(0, dtype=torch.int64).cuda(), torch.zeros(0, dtype=torch.float64).cuda(), p.h)
+    assert torch.all(torch.isinf(u)) and info["sweeps"] == 1
+
+
+# ---------------------------------------------------------------------------
+# eik_dd_solve: iterate-by-iterate against the oracle
+# ---------------------------------------------------------------------------
+
+DD_CASES = [
+    dict(seed=10, n=(33, 33), S=8, M=8, nsrc=1, kind="fourier", theta=0.5),
+    dict(seed=11, n=(49, 33), S=16, M=8, nsrc=2, kind="fourier", theta=0.3),
+    dict(seed=12, n=(65, 65), S=32, M=8, nsrc=1, kind="blocks", theta=0.25),
+    dict(seed=13, n=(41, 81), S=8, M=4, nsrc=3, kind="const", theta=0.7),
+    dict(seed=14, n=(65, 65), S=64, M=16, nsrc=1, kind="fourier", theta=0.5),   # one subdomain
+    dict(seed=15, n=(129, 65), S=64, M=16, nsrc=0, kind="fourier", theta=0.5, edge=0),  # 65-node tiles
+    dict(seed=16, n=(33, 65), S=16, M=2, nsrc=2, kind="blocks", theta=0.0),
+]
+
+
+def run_pair(p, dtype, theta, max_iter, tol=0.0):
+    r, gi, gv = gpu_inputs(p, dtype)
+    G = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=theta, tol=tol, max_iter=max_iter, debug=True)
+    O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=tol,
+                  max_iter=max_iter, dtype=dtype)
+    return G, O
+
+
+def compare(G, O, d=2, check_debug=True):
+    U = G["U"].cpu().numpy().reshape(-1)
+    assert same(U, O["U"]), show_diff("U", U, O["U"])
+    Wg = E.decode_winds(G["W"].cpu().numpy(), d)
+    assert same(Wg, O["W"]), show_diff("W", Wg, O["W"])
+    if O["iterations"] > 0:
+        u = G["u"].cpu().numpy().reshape(-1)
+        assert same(u, O["u"]), show_diff("u", u, O["u"])
+        if check_debug:
+            uk = G["uk"].cpu().numpy().reshape(-1)
+            m = ~np.isnan(O["U"])
+            assert same(uk[m], O["uk"][m]), show_diff("uk", uk[m], O["uk"][m])
+            wk = E.decode_winds(G["wk"].cpu().numpy(), d)
+            assert same(wk[:, m], O["wk"][:, m]), show_diff("wk", wk[:, m], O["wk"][:, m])
+            up = G["Upre"].cpu().numpy().reshape(-1)
+            assert same(up[m], O["Upre"][m]), show_diff("Upre", up[m], O["Upre"][m])
+    assert G["iterations"] == O["iterations"]
+    assert G["fine_updates"] == O["fine_updates"]
+    assert G["coarse_updates"] == O["coarse_updates"]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("ci", range(len(DD_CASES)))
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_dd_iterates_bitwise(ci, k, dtype):
+    c = DD_CASES[ci]
+    p = W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=c["nsrc"] or 1, kind=c["kind"],
+                         edge=c.get("edge"))
+    print(f"dd case={c} k={k} dtype={np.dtype(dtype).name}", flush=True)
+    G, O = run_pair(p, dtype, c["theta"], k)
+    compare(G, O)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_config1_to_convergence(dtype):
+    p = W.config1()
+    tol = 1e-12 if dtype == np.float64 else 1e-6
+    print(f"config1 converge dtype={np.dtype(dtype).name}", flush=True)
+    G, O = run_pair(p, dtype, 0.25, 200, tol=tol)
+    assert O["converged"] and G["converged"]
+    compare(G, O)
+    uf, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    u = G["u"].cpu().numpy().reshape(-1).astype(np.float64)
+    bound = (1e-10 if dtype == np.float64 else 2e-5) * np.max(uf)
+    assert np.max(np.abs(u - uf)) <= bound
+
+
+def test_config1_theta_half_iterates():
+    p = W.config1()
+    print("config1 theta=0.5 12 iterations", flush=True)
+    G, O = run_pair(p, np.float64, 0.5, 12)
+    compare(G, O)
+    assert np.allclose(G["residuals"], O["residuals"], rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_config2_full_size_first_iterations(dtype):
+    p = W.config2()
+    print(f"config2 full size 2 iterations dtype={np.dtype(dtype).name}", flush=True)
+    G, O = run_pair(p, dtype, 0.25, 2)
+    compare(G, O)
+
+
+def test_dd_resume_matches_uninterrupted():
+    p = W.random_problem(20, (65, 65), 16, 8, n_src=2)
+    r, gi, gv = gpu_inputs(p, np.float64)
+    full = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=6)
+    part = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=4)
+    rest = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=2,
+                      U_init=part["U"], W_init=part["W"])
+    assert torch.equal(torch.nan_to_num(full["U"], nan=-1.0), torch.nan_to_num(rest["U"], nan=-1.0))
+    assert torch.equal(full["W"], rest["W"])
+    assert torch.equal(full["u"], rest["u"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(S=12, M=8), E.EIK_ERR_SHAPE),
+    (dict(S=16, M=1), E.EIK_ERR_SHAPE),
+    (dict(theta=1.5), E.EIK_ERR_ARG),
+    (dict(S=128, M=16), E.EIK_ERR_UNSUPPORTED),
+])
+def test_dd_error_paths(kw, status):
+    p = W.random_problem(21, (129, 129), 16, 8)
+    r, gi, gv = gpu_inputs(p, np.float64)
+    args = dict(S=p.S, M=p.M, theta=0.5)
+    args.update(kw)
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve(r, gi, gv, p.h, args["S"], args["M"], theta=args["theta"], max_iter=2)
+    assert ei.value.status == status
+
+
+def test_bad_slowness_is_rejected():
+    p = W.random_problem(22, (33, 33), 8, 4)
+    rr = p.r.copy()
+    rr[5, 7] = -1.0
+    r = dev(rr, np.float64)
+    gi = torch.from_numpy(p.gamma_idx).cuda()
+    gv = dev(p.gamma_val, np.float64)
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve(r, gi, gv, p.h, 8, 4, max_iter=1)
+    assert ei.value.status == E.EIK_ERR_ARG
+    with pytest.raises(E.EikError):
+        E.solve(r, gi, gv, p.h)
