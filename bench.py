@@ -1,0 +1,156 @@
+"""Benchmark: the two-scale DD Eikonal solve on MI355X.
+
+One step = one eik_dd_solve to convergence on the config-2 workload (2D
+1025^2, h = 1/1024, 16x16 subdomains S = 64, H = 1/64 (M = 16), seeded
+random-Fourier multiscale slowness, source = left edge), i.e. one pass of the
+whole hot path: Step 1, then Steps 2-4 and the causal sweep every iteration
+until max|U^{k+1}-U^k| < tol.  Inputs are resident in HBM before timing.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
+
+Prints one JSON line.  value = fine-grid Godunov updates per second over the
+whole solve (Step 3 local solves / wall time of the solves); ms_per_step is
+the DD time-to-solution.  The roofline object describes the dominant kernel,
+the subdomain sweep of Step 3, timed with HIP events on its own stream inside
+the library.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point operations of one local solve (eq. godonuv in
+# closed form, two-sided branch): 2 neighbour-minimum compares, a - b,
+# |a - b| < r h, (rh)^2, doubling, (a-b)^2, subtraction, a + b, sqrt, add,
+# halving, and the FSM minimum compare.
+OPS_PER_UPDATE = 13
+# Non-FMA vector issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3 T lane-ops/s (the published 157.3 TFLOP/s fp32 counts an FMA as two
+# flops and packed fp32 as two lanes; 78.6 TFLOP/s fp64 counts the FMA).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--theta", type=float, default=0.25)
+    ap.add_argument("--n", type=int, default=1025)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=8)
+    return ap.parse_args()
+
+
+def cpu_baseline(p, theta, iters):
+    """The oracle as it stands (serial C, fp64), on a bounded sample of the
+    same workload: Step 1 plus the first `iters` DD iterations."""
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=0.0,
+                  max_iter=iters, dtype=np.float64)
+    dt = time.perf_counter() - t0
+    return {"value": R["fine_updates"] / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{p.name}: Step 1 + first {iters} DD iterations, fp64 serial oracle, "
+                      f"{R['fine_updates']} fine updates in {dt:.2f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); the DD "
+              "path would shard subdomains across GPUs with one skeleton exchange per "
+              "iteration, which is not built.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1805_04198_amd as E
+    from paper_1805_04198_amd import workloads as W
+
+    dt = np.float32 if a.dtype == "f32" else np.float64
+    tdt = torch.float32 if a.dtype == "f32" else torch.float64
+    tol = 1e-6 if a.dtype == "f32" else 1e-12
+    p = W.config2(a.n)
+    dev = torch.device("cuda:0")
+    r = torch.from_numpy(p.r.astype(dt)).to(dev)
+    gi = torch.from_numpy(p.gamma_idx).to(dev)
+    gv = torch.from_numpy(p.gamma_val.astype(dt)).to(dev)
+    kw = dict(theta=a.theta, tol=tol, max_iter=400)
+
+    for _ in range(a.warmup):
+        E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for _ in range(a.steps):
+        outs.append(E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    last = outs[-1]
+    fine = sum(o["fine_updates"] for o in outs)
+    iters = sum(o["iterations"] for o in outs)
+    ms_fine = sum(o["ms_fine"] for o in outs)
+    ms_step = wall * 1e3 / a.steps
+    value = fine / wall
+    # dominant kernel: the Step 3 subdomain sweep, one launch per iteration
+    upd_per_launch = fine / iters
+    ms_per_launch = ms_fine / iters
+    achieved = upd_per_launch * OPS_PER_UPDATE / (ms_per_launch * 1e-3) / 1e12
+
+    # error against the fp64 oracle's overall fine solution u^f (the fixed
+    # point the iteration converges to)
+    import oracle
+    uf, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    u = last["u"].double().cpu().numpy().reshape(-1)
+    err = float(np.max(np.abs(u - uf)) / np.max(uf))
+
+    line = {
+        "metric": "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"config 2: 2D {p.n[0]}x{p.n[1]}, h=1/{p.n[0]-1}, {p.n[0]//p.S}x{p.n[1]//p.S} "
+                               f"subdomains (S={p.S}), H=1/{(p.n[0]-1)//p.M} (M={p.M}), random-Fourier "
+                               f"multiscale slowness (seed 2), left-edge source, theta={a.theta}, tol={tol}",
+                   "global_batch": 1, "seq_len": None, "parallelism": "none"},
+        "time_to_solution_ms": ms_step,
+        "iterations": last["iterations"],
+        "converged": last["converged"],
+        "fine_updates_per_solve": last["fine_updates"],
+        "coarse_updates_per_solve": last["coarse_updates"],
+        "rel_err_vs_fp64_oracle_uf": err,
+        "gate": 2e-5 if a.dtype == "f32" else 1e-10,
+        "ms_fine_per_solve": last["ms_fine"],
+        "ms_coarse_per_solve": last["ms_coarse"],
+        "roofline": {"bound": "alu", "kernel": "k_tile (Step 3 subdomain FSM)",
+                     "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s",
+                     "frac": achieved / ALU_PEAK_TOPS, "traffic": None,
+                     "per_launch": {"updates": upd_per_launch, "ms": ms_per_launch,
+                                    "ops_per_update": OPS_PER_UPDATE}},
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, a.theta, a.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -132,7 +132,7 @@ def fmm(n, h, r, gidx, gval, dtype=np.float64):
 
 
 def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.float64,
-       max_fine_sweeps=256, max_coarse_sweeps=256, U_init=None, W_init=None, hist_cap=4096):
+       max_fine_sweeps=256, max_coarse_sweeps=32, U_init=None, W_init=None, hist_cap=4096):
     """The DD iteration of Sec. 3.2.  Returns a dict with the patched fine
     solution u, coarse values U (NaN off the skeleton), coarse winds W (d, N),
     the last iteration's reconciled fine values uk / winds wk, the last

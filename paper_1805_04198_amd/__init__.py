@@ -158,7 +158,7 @@ def solve(r, gamma_idx, gamma_val, h, max_sweeps: int = 100000, with_wind: bool 
 
 def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol: float = 1e-12,
              max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
-             max_coarse_sweeps: int = 256, U_init=None, W_init=None, debug: bool = False,
+             max_coarse_sweeps: int = 32, U_init=None, W_init=None, debug: bool = False,
              history_cap: int = 4096):
     """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
     with the patched fine solution u, coarse values U (NaN off the skeleton),

@@ -142,8 +142,9 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
   const size_t szT = sizeof(T);
   const int L = S + 1;
-  const size_t lds_tile = eik::halo_count(L, L) * (2 * szT + 2);
-  const size_t lds_lat = eik::halo_count(NI + 1, NJ + 1) * (4 * szT + 2);
+  const size_t lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
+  const size_t lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT),
+                                  eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
   const int nC = (NI + 1) * (NJ + 1);
   const size_t lds_cb = nC * (2 * szT + 1) + 16;
   if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cb > kLdsBytes)
@@ -355,7 +356,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.changed = dflag + 1;
   if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
-  const size_t lds = eik::halo_count(B, B) * (2 * szT + 2);
+  const size_t lds = eik::box_bytes(eik::halo_count(B, B), 2, 1, szT);
   if ((e = allow_lds(eik::k_grid_sweep<T>, lds)) != EIK_OK) return e;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -371,11 +372,10 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
   int sw = 0, conv = 0;
   while (sw < max_sweeps) {
     const int dir = sw & 3;
-    const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
     HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
     for (int d = 0; d <= BX + BY - 2; ++d) {
       const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
-      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kWave), lds, s, A, sx, sy, d);
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kWave), lds, s, A, dir, d);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));

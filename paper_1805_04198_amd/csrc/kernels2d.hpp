@@ -32,6 +32,11 @@ namespace eik {
 
 constexpr int kWave = 64;
 constexpr int kMaxL = 65;  // nodes per axis of a tile / lattice held in LDS
+// Every LDS array of a box is surrounded by kGuard spare elements: reads of
+// idle lanes may fall there, and stores that must not land anywhere go to
+// index kDummy (inside the leading guard band).
+constexpr int kGuard = 72;
+constexpr int kDummy = -kGuard;
 
 template <typename T> __device__ __forceinline__ T pinf();
 template <> __device__ __forceinline__ float pinf<float>() { return __builtin_huge_valf(); }
@@ -65,50 +70,137 @@ __device__ __forceinline__ T godunov2(T a, T b, T rd, bool& two) {
   return (a < b) ? (a + rd) : (b + rd);
 }
 
-// Compiler-level ordering point between consecutive wavefront steps: every
-// lane's LDS write of step t must be issued before any lane's LDS read of step
-// t+1.  One wave executes its LDS instructions in order, so no hardware
-// barrier is needed.
+// Compiler-level ordering point between sweeps: every LDS write of one sweep
+// is issued before any LDS read of the next.  One wave executes its LDS
+// instructions in order, so no hardware barrier is needed.
 __device__ __forceinline__ void step_fence() {
   __builtin_amdgcn_wave_barrier();
   __asm__ __volatile__("" ::: "memory");
 }
 
-// One directional Gauss-Seidel sweep over an L0 x L1 grid in LDS (row stride
-// SP) in anti-diagonal order.  sx, sy: sweep signs.  Returns true in lanes
-// that changed a value.
-template <typename Rule>
-__device__ __forceinline__ bool wave_sweep(Rule& R, int L0, int L1, int sx, int sy) {
+// Lane i receives lane i-1's value (lane 0 receives lane 63's): DPP wave_ror:1.
+__device__ __forceinline__ int dpp_ror1(int v) {
+  // every source lane exists under a rotation, so the old operand is unused
+  return __builtin_amdgcn_update_dpp(v, v, 0x13C, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float dpp_ror1(float v) {
+  return __builtin_bit_cast(float, dpp_ror1(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double dpp_ror1(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_ror1((int)(b & 0xffffffffll));
+  const int hi = dpp_ror1((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Smaller neighbour per axis with the flow-direction wind sign of its side
+// (ties take the plus side, as the strict '<' of the paper's algorithms).
+template <typename T>
+__device__ __forceinline__ void pick(T m, T p, T& v, int& w) {
+  const bool lt = m < p;
+  v = lt ? m : p;
+  w = lt ? 1 : -1;
+}
+
+// Godunov local solve, branch-free: both branches are evaluated with the same
+// expressions as above and one is selected (the sqrt of a negative argument
+// in the unused branch yields NaN and is discarded).
+template <typename T>
+__device__ __forceinline__ T godunov2_sel(T a, T b, T rd, bool& two) {
+  const T d = a - b;
+  two = dabs(d) < rd;
+  T t = rd * rd;
+  t = t + t;
+  t = t - d * d;
+  const T u2 = ((a + b) + dsqrt(t)) * T(0.5);
+  const T u1 = ((a < b) ? a : b) + rd;
+  return two ? u2 : u1;
+}
+
+// One directional Gauss-Seidel sweep (signs SX, SY) over an L0 x L1 box in
+// LDS, anti-diagonal order, one lane per row.  Dataflow per step t, lane j
+// (row j in sweep order, column i = t - j):
+//   upwind-x value : the lane's own result of step t-1 (register)
+//   upwind-y value : row j-1's result of step t-1, moved by DPP wave_ror:1
+//   self, downwind-x, downwind-y, r*Delta, halo values : LDS, loaded one step
+//                    ahead.  None of these locations is written during the
+//                    step that loads it (nodes of step t are on anti-diagonal
+//                    t; the loads are on t+1 and t+2, or halo), so no LDS
+//                    round trip lies on the dependency chain.
+// Row 64 (boxes of 65 rows) runs on lane 0 one step late, after row 0 is
+// done; it takes its upwind-y value from lane 63's result of two steps back.
+// Fixed nodes carry r*Delta = NaN, which makes the candidate NaN and leaves
+// them untouched.  The step is branch-free: a lane that is idle or does not
+// lower its node stores to a dummy LDS slot, and the address of a lane moves
+// by SX every step (reads of idle lanes land in the guard bands around each
+// LDS array).  Returns true in lanes that changed a value.
+template <int SX, int SY, typename Rule>
+__device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
+  using T = typename Rule::real;
+  using Pre = typename Rule::Pre;
   const int lane = threadIdx.x;
-  bool changed = false;
-  const bool extra = L1 > kWave;  // 65th row on lane 0, one step late
+  const bool extra = L1 > kWave;
   const int nsteps = L0 + L1 - 1 + (extra ? 1 : 0);
-  for (int t = 0; t < nsteps; ++t) {
-    int jq = lane, iq = t - lane;
-    if (extra && lane == 0 && t > kWave) {
-      jq = kWave;
-      iq = t - kWave - 1;
-    }
-    if (jq < L1 && iq >= 0 && iq < L0) {
-      const int i = sx > 0 ? iq : L0 - 1 - iq;
-      const int j = sy > 0 ? jq : L1 - 1 - jq;
-      changed |= R.update(i, j);
-    }
-    step_fence();
+  const int jA = min(max(SY > 0 ? lane : L1 - 1 - lane, 0), L1 - 1);
+  const int jB = SY > 0 ? kWave : L1 - 1 - kWave;
+  // LDS index of the lane's node at step t: x = x0 + SX * t
+  const int xA0 = (jA + 1) * SP + 1 + (SX > 0 ? -lane : L0 - 1 + lane);
+  const int xB0 = (jB + 1) * SP + 1 + (SX > 0 ? -(kWave + 1) : L0 - 1 + kWave + 1);
+  const bool laneB = extra && lane == 0;
+  const bool rowA = lane < L1;
+  T cur = pinf<T>(), cur_prev = pinf<T>();
+  bool changed = false;
+  int x = xA0;
+  Pre pa = R.template load<SX, SY>(x), pb;
+  // one step; p holds this step's operands, pn receives the next step's
+  auto step = [&](int t, const Pre& p, Pre& pn) {
+    const bool useB = laneB && t > kWave;
+    const int iq = t - (useB ? kWave + 1 : lane);
+    const bool act = (useB || rowA) && (unsigned)iq < (unsigned)L0;
+    const int x1 = ((laneB && t >= kWave) ? xB0 : xA0) + SX * (t + 1);
+    pn = R.template load<SX, SY>(x1);
+    // keep the loads at the top of the step, a whole step ahead of their use
+    __builtin_amdgcn_sched_barrier(0);
+    const T ex = (lane == kWave - 1) ? cur_prev : cur;
+    const T from_prev_row = dpp_ror1(ex);
+    const T yprev = (lane == 0 && !useB) ? p.hy : from_prev_row;
+    const T xprev = (iq == 0) ? p.hx : cur;
+    const T xm = SX > 0 ? xprev : p.xn, xp = SX > 0 ? p.xn : xprev;
+    const T ym = SY > 0 ? yprev : p.yn, yp = SY > 0 ? p.yn : yprev;
+    bool ch;
+    const T v = R.compute(xm, xp, ym, yp, p, x, act, ch);
+    cur_prev = cur;
+    cur = act ? v : cur;
+    changed = changed || ch;
+    x = x1;
+  };
+  // unrolled by two so that the prefetch buffers alternate without copies;
+  // a trailing step past the end is idle in every lane
+  for (int t = 0; t < nsteps; t += 2) {
+    step(t, pa, pb);
+    step(t + 1, pb, pa);
   }
   return changed;
+}
+
+template <typename Rule>
+__device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int dir) {
+  switch (dir) {
+    case 0: return sweep_dir<-1, -1>(R, L0, L1, SP);
+    case 1: return sweep_dir<-1, 1>(R, L0, L1, SP);
+    case 2: return sweep_dir<1, -1>(R, L0, L1, SP);
+    default: return sweep_dir<1, 1>(R, L0, L1, SP);
+  }
 }
 
 // Sweep in the 2^d orders of the paper's loop nest ((-,-), (-,+), (+,-),
 // (+,+), x outermost) until a whole sweep changes nothing, at most max_sweeps.
 template <typename Rule>
-__device__ int wave_fsm(Rule& R, int L0, int L1, int max_sweeps) {
+__device__ int wave_fsm(Rule& R, int L0, int L1, int SP, int max_sweeps) {
   int s = 0;
   while (s < max_sweeps) {
-    const int dir = s & 3;
-    const int sx = (dir & 2) ? 1 : -1;
-    const int sy = (dir & 1) ? 1 : -1;
-    bool ch = wave_sweep(R, L0, L1, sx, sy);
+    bool ch = sweep_any(R, L0, L1, SP, s & 3);
+    step_fence();
     ++s;
     if (!__any(ch)) break;
   }
@@ -116,114 +208,127 @@ __device__ int wave_fsm(Rule& R, int L0, int L1, int max_sweeps) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-node rules
+// Per-node rules.  load<SX,SY>(x) fetches the node's old value, its downwind
+// neighbours, the halo values that stand in for missing upwind neighbours and
+// its parameters; compute() returns the node's new value and performs the
+// LDS writes.
 // ---------------------------------------------------------------------------
 
-// Fine update (Alg. fineupdate2D with flow-direction winds; eq. FSMupdate).
 template <typename T>
-struct FineRule {
+struct PreFine {
+  T self, xn, yn, hx, hy, rd;
+};
+
+// Fine update (Alg. fineupdate2D with flow-direction winds; eq. FSMupdate).
+// Also the coarse update of Step 1 (Alg. update2D) when Coarse = true.
+template <typename T, bool Coarse>
+struct MinRule {
+  using real = T;
+  using Pre = PreFine<T>;
   T* u;
   uint8_t* w;
   const T* rd;
-  const uint8_t* fixed;
-  int L0, L1, SP;
-  __device__ __forceinline__ bool update(int i, int j) {
-    const int x = (j + 1) * SP + (i + 1);
-    if (fixed[x]) return false;
-    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+  int SP;
+  template <int SX, int SY>
+  __device__ __forceinline__ Pre load(int x) const {
+    Pre p;
+    p.self = u[x];
+    p.xn = u[x + SX];
+    p.yn = u[x + SY * SP];
+    p.hx = u[x - SX];
+    p.hy = u[x - SY * SP];
+    p.rd = rd[x];
+    return p;
+  }
+  __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
+                                      bool& ch) const {
     T a, b;
     int wx, wy;
-    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
-    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
+    pick(xm, xp, a, wx);
+    pick(ym, yp, b, wy);
     bool two;
-    T ut = godunov2(a, b, rd[x], two);
-    if (ut < u[x]) {
-      u[x] = ut;
-      w[x] = two ? wenc(wx, wy) : (a < b ? wenc(wx, 0) : wenc(0, wy));
-      return true;
+    const T ut = godunov2_sel(a, b, p.rd, two);
+    ch = act && (ut < p.self);
+    // axes that enter the wind: Alg. update2D (coarse) or Alg. fineupdate2D
+    bool useX, useY;
+    if (Coarse) {
+      useX = (ut < b) || !(ut < a);
+      useY = !(ut < b);
+    } else {
+      useX = two || (a < b);
+      useY = two || !(a < b);
     }
-    return false;
+    const uint8_t c = (uint8_t)((useX ? (wx & 3) : 0) | (useY ? ((wy & 3) << 2) : 0));
+    const int xs = ch ? x : kDummy;
+    u[xs] = ut;
+    w[xs] = c;
+    return ch ? ut : p.self;
   }
 };
 
-// Coarse update of Step 1 (Alg. update2D, with the FSM minimum).
 template <typename T>
-struct CoarseInitRule {
-  T* u;
-  uint8_t* w;
-  const T* rd;
-  const uint8_t* fixed;
-  int L0, L1, SP;
-  __device__ __forceinline__ bool update(int i, int j) {
-    const int x = (j + 1) * SP + (i + 1);
-    if (fixed[x]) return false;
-    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
-    T a, b;
-    int wx, wy;
-    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
-    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
-    bool two;
-    T ut = godunov2(a, b, rd[x], two);
-    if (ut < u[x]) {
-      u[x] = ut;
-      w[x] = (ut < b) ? wenc(wx, 0) : ((ut < a) ? wenc(0, wy) : wenc(wx, wy));
-      return true;
-    }
-    return false;
-  }
+struct PreCorr {
+  T self, xn, yn, hx, hy, rd, uk, ck;
+  uint8_t wk;
 };
 
 // Step 4 (Alg. 2Dweightedupdate): U = u^k + theta*(U~ - C^k) when the winds
 // w^k, W^k and W~ agree along every normal axis of the node's coarse line and
 // U~, C^k are finite; U = u^k otherwise.  Direct assignment, no minimum.
-// flags: bit0 = Gamma (fixed), bit1 = x is a normal axis, bit2 = y is.
-// wk: low nibble = w^k code, high nibble = W^k code.
+// Gamma nodes carry u^k = g and r*H = NaN, so they always keep g.
+// wk: low nibble = w^k code, high nibble = W^k code.  nx, ny: x / y is a
+// normal axis of every node of the lattice.
 template <typename T>
 struct CorrectRule {
+  using real = T;
+  using Pre = PreCorr<T>;
   T* u;
   const T* uk;
   const T* ck;
   const T* rd;
   const uint8_t* wk;
-  const uint8_t* flags;
   T theta;
-  int L0, L1, SP;
-  __device__ __forceinline__ bool update(int i, int j) {
-    const int x = (j + 1) * SP + (i + 1);
-    const uint8_t f = flags[x];
-    if (f & 1) return false;
-    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+  bool nx, ny;
+  int SP;
+  template <int SX, int SY>
+  __device__ __forceinline__ Pre load(int x) const {
+    Pre p;
+    p.self = u[x];
+    p.xn = u[x + SX];
+    p.yn = u[x + SY * SP];
+    p.hx = u[x - SX];
+    p.hy = u[x - SY * SP];
+    p.rd = rd[x];
+    p.uk = uk[x];
+    p.ck = ck[x];
+    p.wk = wk[x];
+    return p;
+  }
+  __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
+                                      bool& ch) const {
     T a, b;
     int wx, wy;
-    if (xm < xp) { a = xm; wx = 1; } else { a = xp; wx = -1; }
-    if (ym < yp) { b = ym; wy = 1; } else { b = yp; wy = -1; }
+    pick(xm, xp, a, wx);
+    pick(ym, yp, b, wy);
     bool two;
-    T ut = godunov2(a, b, rd[x], two);
-    int tx, ty;  // W~
-    if (ut < b) { tx = wx; ty = 0; } else if (ut < a) { tx = 0; ty = wy; } else { tx = wx; ty = wy; }
-    const uint8_t c = wk[x];
+    const T ut = godunov2_sel(a, b, p.rd, two);
+    const int tx = (ut < b) ? wx : ((ut < a) ? 0 : wx);  // W~ (Alg. update2D)
+    const int ty = (ut < b) ? 0 : wy;
+    const uint8_t c = p.wk;
     bool cond = true;
-    if (f & 2) {
-      int p = wx_of(c & 15), q = wx_of(c >> 4);
-      bool le = p <= 0 && q <= 0 && tx <= 0, ge = p >= 0 && q >= 0 && tx >= 0;
-      cond = cond && (le || ge);
+    if (nx) {
+      const int q = wx_of(c & 15), r = wx_of(c >> 4);
+      cond = cond && ((q <= 0 && r <= 0 && tx <= 0) || (q >= 0 && r >= 0 && tx >= 0));
     }
-    if (f & 4) {
-      int p = wy_of(c & 15), q = wy_of(c >> 4);
-      bool le = p <= 0 && q <= 0 && ty <= 0, ge = p >= 0 && q >= 0 && ty >= 0;
-      cond = cond && (le || ge);
+    if (ny) {
+      const int q = wy_of(c & 15), r = wy_of(c >> 4);
+      cond = cond && ((q <= 0 && r <= 0 && ty <= 0) || (q >= 0 && r >= 0 && ty >= 0));
     }
-    const T ckx = ck[x];
-    T v;
-    if (cond && dfinite(ut) && dfinite(ckx))
-      v = uk[x] + theta * (ut - ckx);
-    else
-      v = uk[x];
-    if (v != u[x]) {
-      u[x] = v;
-      return true;
-    }
-    return false;
+    const T corr = p.uk + theta * (ut - p.ck);
+    const T v = (cond && dfinite(ut) && dfinite(p.ck)) ? corr : p.uk;
+    ch = act && (v != p.self);
+    u[ch ? x : kDummy] = v;
+    return v;
   }
 };
 
@@ -366,6 +471,17 @@ __global__ void k_near_b(DD2<T> A) {
 
 __host__ __device__ __forceinline__ int halo_stride(int L0) { return (L0 + 3) & ~1; }
 __host__ __device__ __forceinline__ int halo_count(int L0, int L1) { return halo_stride(L0) * (L1 + 2); }
+// LDS bytes of a box with nreal real arrays and nbyte byte arrays (guards included)
+__host__ __device__ __forceinline__ size_t box_bytes(int cnt, int nreal, int nbyte, size_t szT) {
+  return (size_t)(cnt + 2 * kGuard) * (nreal * szT + nbyte);
+}
+// next array of n elements (plus guards) from the LDS cursor
+template <typename U>
+__device__ __forceinline__ U* carve(unsigned char*& cur, int n) {
+  U* a = reinterpret_cast<U*>(cur) + kGuard;
+  cur += (size_t)(n + 2 * kGuard) * sizeof(U);
+  return a;
+}
 
 // ---------------------------------------------------------------------------
 // lattices (Steps 1 and 4)
@@ -386,11 +502,12 @@ __global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
-  T* u = (T*)smem;
-  T* rd = u + cnt;
-  uint8_t* w = (uint8_t*)(rd + cnt);
-  uint8_t* fx = w + cnt;
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); fx[k] = 1; w[k] = 0; }
+  unsigned char* lc = smem;
+  T* u = carve<T>(lc, cnt);
+  T* rd = carve<T>(lc, cnt);
+  uint8_t* w = carve<uint8_t>(lc, cnt);
+  const T nan = T(__builtin_nan(""));
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
   step_fence();
   int nfree = 0;
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
@@ -398,24 +515,23 @@ __global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
     const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
     const int X = xi + A.n0 * yi;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    rd[x] = A.r[X] * A.HT;
     const T g = A.gfull[X];
     if (!disnan(g)) {
-      u[x] = g; w[x] = 0; fx[x] = 1;
+      u[x] = g; w[x] = 0; rd[x] = nan;
     } else if (A.near_win[X] != 0x7fffffffffffffffll) {
       u[x] = (T)okey_dec(A.near_key[X]);
       const int64_t gg = A.gidx[A.near_win[X]];
       const int dx = xi - (int)(gg % A.n0), dy = yi - (int)(gg / A.n0);
       w[x] = wenc((dx > 0) - (dx < 0), (dy > 0) - (dy < 0));
-      fx[x] = 1;
+      rd[x] = nan;
     } else {
-      u[x] = pinf<T>(); w[x] = 0; fx[x] = 0;
+      u[x] = pinf<T>(); w[x] = 0; rd[x] = A.r[X] * A.HT;
       ++nfree;
     }
   }
   step_fence();
-  CoarseInitRule<T> R{u, w, rd, fx, L0, L1, SP};
-  const int ns = wave_fsm(R, L0, L1, A.max_coarse_sweeps);
+  MinRule<T, true> R{u, w, rd, SP};
+  const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
   step_fence();
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
     const int p0 = k % L0, p1 = k / L0;
@@ -436,14 +552,15 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
-  T* u = (T*)smem;
-  T* uk = u + cnt;
-  T* ck = uk + cnt;
-  T* rd = ck + cnt;
-  uint8_t* wk = (uint8_t*)(rd + cnt);
-  uint8_t* fl = wk + cnt;
+  unsigned char* lc = smem;
+  T* u = carve<T>(lc, cnt);
+  T* uk = carve<T>(lc, cnt);
+  T* ck = carve<T>(lc, cnt);
+  T* rd = carve<T>(lc, cnt);
+  uint8_t* wk = carve<uint8_t>(lc, cnt);
   const T inf = pinf<T>();
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = inf; fl[k] = 1; }
+  const T nan = T(__builtin_nan(""));
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = inf; rd[k] = nan; uk[k] = inf; ck[k] = inf; wk[k] = 0; }
   step_fence();
   int nfree = 0;
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
@@ -452,11 +569,11 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
     const int X = xi + A.n0 * yi;
     const int x = (p1 + 1) * SP + (p0 + 1);
     u[x] = A.U[X];  // U^k, used for C^k first
-    uk[x] = A.uk[X];
+    const T g = A.gfull[X];
+    const bool gam = !disnan(g);
+    uk[x] = gam ? g : A.uk[X];
     rd[x] = A.r[X] * A.HT;
     wk[x] = (uint8_t)((A.wk[X] & 15) | ((A.W[X] & 15) << 4));
-    const bool gam = !disnan(A.gfull[X]);
-    fl[x] = (uint8_t)((gam ? 1 : 0) | ((xi % A.M == 0) ? 2 : 0) | ((yi % A.M == 0) ? 4 : 0));
     if (!gam) ++nfree;
   }
   step_fence();
@@ -464,33 +581,36 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
-    T a = xm < xp ? xm : xp;
-    T b = ym < yp ? ym : yp;
+    const T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
+    const T a = xm < xp ? xm : xp;
+    const T b = ym < yp ? ym : yp;
     bool two;
     ck[x] = godunov2(a, b, rd[x], two);
   }
   step_fence();
+  // start of Step 4: U = +inf, Gamma nodes at g (they keep it: r*H = NaN)
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    if (fl[x] & 1) {
-      const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
-      u[x] = A.gfull[X];
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+    const T g = A.gfull[X];
+    if (!disnan(g)) {
+      u[x] = g;
+      rd[x] = nan;
     } else {
       u[x] = inf;
     }
   }
   step_fence();
-  CorrectRule<T> R{u, uk, ck, rd, wk, fl, A.theta, L0, L1, SP};
-  const int ns = wave_fsm(R, L0, L1, A.max_coarse_sweeps);
+  CorrectRule<T> R{u, uk, ck, rd, wk, A.theta, o0 == 0, o1 == 0, SP};
+  const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
   step_fence();
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
     const int p0 = k % L0, p1 = k / L0;
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const int x = (p1 + 1) * SP + (p0 + 1);
     A.Un[X] = u[x];
-    A.Wn[X] = (fl[x] & 1) ? (uint8_t)0 : (uint8_t)(wk[x] & 15);
+    A.Wn[X] = disnan(A.gfull[X]) ? (uint8_t)(wk[x] & 15) : (uint8_t)0;
   }
   for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)nfree * (unsigned long long)ns);
@@ -507,11 +627,12 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
   const int L = A.S + 1;
   const int SP = halo_stride(L);
   const int cnt = halo_count(L, L);
-  T* u = (T*)smem;
-  T* rd = u + cnt;
-  uint8_t* w = (uint8_t*)(rd + cnt);
-  uint8_t* fx = w + cnt;
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); fx[k] = 1; w[k] = 0; }
+  unsigned char* lc = smem;
+  T* u = carve<T>(lc, cnt);
+  T* rd = carve<T>(lc, cnt);
+  uint8_t* w = carve<uint8_t>(lc, cnt);
+  const T nan = T(__builtin_nan(""));
+  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
   step_fence();
   const int bi = I * A.S, bj = J * A.S;
   int nfree = 0;
@@ -520,14 +641,13 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
     const int xi = bi + li, yi = bj + lj;
     const int X = xi + A.n0 * yi;
     const int x = (lj + 1) * SP + (li + 1);
-    rd[x] = A.r[X] * A.hT;
     const T g = A.gfull[X];
     if (!disnan(g)) {
-      u[x] = g; w[x] = 0; fx[x] = 1;
+      u[x] = g; w[x] = 0; rd[x] = nan;
       continue;
     }
     ++nfree;
-    fx[x] = 0;
+    rd[x] = A.r[X] * A.hT;
     // Step 2: a subdomain-boundary node on an interface is inflow if the
     // coarse wind points into the subdomain; it starts at U with wind W and,
     // like every non-Gamma node, still takes the FSM minimum.
@@ -549,8 +669,8 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
     }
   }
   step_fence();
-  FineRule<T> R{u, w, rd, fx, L, L, SP};
-  const int ns = wave_fsm(R, L, L, A.max_fine_sweeps);
+  MinRule<T, false> R{u, w, rd, SP};
+  const int ns = wave_fsm(R, L, L, SP, A.max_fine_sweeps);
   step_fence();
   const int tile = blockIdx.x;
   for (int k = threadIdx.x; k < L * L; k += kWave) {
@@ -600,8 +720,9 @@ struct GS2 {
 // diagonals, the downwind ones are untouched, so the sweep of the whole grid
 // is the paper's serial Gauss-Seidel sweep exactly.
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int sx, int sy, int diag) {
+__global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int dir, int diag) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int q0 = max(0, diag - (A.BY - 1));
   const int Iq = q0 + (int)blockIdx.x;
   const int Jq = diag - Iq;
@@ -612,36 +733,34 @@ __global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int sx, int sy, 
   const int L0 = min(A.B, A.n0 - bi), L1 = min(A.B, A.n1 - bj);
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
-  T* u = (T*)smem;
-  T* rd = u + cnt;
-  uint8_t* w = (uint8_t*)(rd + cnt);
-  uint8_t* fx = w + cnt;
+  unsigned char* lc = smem;
+  T* u = carve<T>(lc, cnt);
+  T* rd = carve<T>(lc, cnt);
+  uint8_t* w = carve<uint8_t>(lc, cnt);
   const T inf = pinf<T>();
+  const T nan = T(__builtin_nan(""));
   for (int k = threadIdx.x; k < cnt; k += kWave) {
     const int hi = k % SP - 1, hj = k / SP - 1;
     const int xi = bi + hi, yi = bj + hj;
     const bool inside = hi >= 0 && hi < L0 && hj >= 0 && hj < L1;
-    const bool ring = !inside && hi >= -1 && hi <= L0 && hj >= -1 && hj <= L1 &&
-                      ((hi >= 0 && hi < L0) || (hj >= 0 && hj < L1));
-    T v = inf;
-    uint8_t f = 1;
+    T v = inf, rv = nan;
     uint8_t c = 0;
     if (inside) {
       const int X = xi + A.n0 * yi;
       v = A.u[X];
       c = A.w[X];
-      rd[k] = A.r[X] * A.hT;
-      f = disnan(A.gfull[X]) ? 0 : 1;
-    } else if (ring && xi >= 0 && xi < A.n0 && yi >= 0 && yi < A.n1) {
+      if (disnan(A.gfull[X])) rv = A.r[X] * A.hT;
+    } else if (hi >= -1 && hi <= L0 && hj >= -1 && hj <= L1 && xi >= 0 && xi < A.n0 && yi >= 0 &&
+               yi < A.n1) {
       v = A.u[xi + A.n0 * yi];
     }
     u[k] = v;
     w[k] = c;
-    fx[k] = f;
+    rd[k] = rv;
   }
   step_fence();
-  FineRule<T> R{u, w, rd, fx, L0, L1, SP};
-  bool ch = wave_sweep(R, L0, L1, sx, sy);
+  MinRule<T, false> R{u, w, rd, SP};
+  const bool ch = sweep_any(R, L0, L1, SP, dir);
   step_fence();
   for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
     const int li = k % L0, lj = k / L0;
