@@ -106,7 +106,9 @@ typedef struct {
     int32_t history_cap;
     float ms_total;          /* device time of the whole call */
     float ms_fine;           /* device time in Step 3 (subdomain FSM) */
-    float ms_coarse;         /* device time in Steps 1 and 4 and the causal sweeps */
+    float ms_coarse;         /* device time in everything else (Steps 1, 2, 4, causal sweeps, residuals) */
+    float ms_correct;        /* device time of the Step 4 lattice sweeps (incl. the reconciliation) */
+    float ms_causal;         /* device time of the causal sweeps after Step 4 and the residuals */
 } eik_stats;
 
 /* eik_solve -- the fast sweeping method on the whole fine grid (Sec. 1.1:

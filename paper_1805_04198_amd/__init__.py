@@ -61,7 +61,8 @@ class Stats(ctypes.Structure):
                 ("sweeps", ctypes.c_int64), ("final_residual", ctypes.c_double),
                 ("residual_history", ctypes.POINTER(ctypes.c_double)),
                 ("history_cap", ctypes.c_int32), ("ms_total", ctypes.c_float),
-                ("ms_fine", ctypes.c_float), ("ms_coarse", ctypes.c_float)]
+                ("ms_fine", ctypes.c_float), ("ms_coarse", ctypes.c_float),
+                ("ms_correct", ctypes.c_float), ("ms_causal", ctypes.c_float)]
 
 
 _lib = None
@@ -73,6 +74,9 @@ def load_library(path: Optional[str] = None):
     if _lib is not None and path is None:
         return _lib
     p = path or LIB_PATH
+    # torch provides the device memory and streams; load its HIP runtime first
+    # so that the library binds to the same runtime instance
+    _torch()
     if not os.path.exists(p):
         raise RuntimeError(f"libeik.so not found at {p}: build it with "
                            "`python -m paper_1805_04198_amd.build`")
@@ -199,7 +203,8 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
            "converged": bool(st.converged), "fine_updates": int(st.fine_updates),
            "coarse_updates": int(st.coarse_updates), "residuals": list(hist[: min(it, history_cap)]),
            "ms_total": float(st.ms_total), "ms_fine": float(st.ms_fine),
-           "ms_coarse": float(st.ms_coarse)}
+           "ms_coarse": float(st.ms_coarse), "ms_correct": float(st.ms_correct),
+           "ms_causal": float(st.ms_causal)}
     if debug:
         out.update(dbg_t)
     return out

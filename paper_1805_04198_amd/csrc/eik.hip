@@ -119,7 +119,7 @@ void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t 
     const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
     hipLaunchKernelGGL(eik::k_causal_a<T>, dim3(nblocks(nC + nH + nV, 256)), dim3(256), 0, s, A, U, W,
                        sx, sy);
-    hipLaunchKernelGGL(eik::k_causal_b<T>, dim3(1), dim3(1024), ldsB, s, A, U, sx, sy);
+    hipLaunchKernelGGL(eik::k_causal_b<T>, dim3(1), dim3(eik::kBlock), ldsB, s, A, U, dir);
     hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nblocks(nH + nV, 256)), dim3(256), 0, s, A, U, sx, sy);
   }
 }
@@ -146,7 +146,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const size_t lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT),
                                   eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
   const int nC = (NI + 1) * (NJ + 1);
-  const size_t lds_cb = nC * (2 * szT + 1) + 16;
+  const size_t lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
   if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cb > kLdsBytes)
     return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this build");
 
@@ -212,11 +212,11 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if ((e = allow_lds(eik::k_lattice_correct<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_causal_b<T>, lds_cb)) != EIK_OK) return e;
 
-  hipEvent_t ev[4];
+  hipEvent_t ev[6];
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
   struct EvGuard {
     hipEvent_t* e;
-    ~EvGuard() { for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]); }
+    ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
   } evg{ev};
   HIPCHK(hipEventRecord(ev[0], s));
 
@@ -233,7 +233,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   HIPCHK(hipGetLastError());
 
   const int nlat = 2 * M - 1;
-  float ms_fine = 0.f, ms_coarse = 0.f;
+  float ms_fine = 0.f, ms_correct = 0.f, ms_causal = 0.f;
   if (o->U_init) {
     hipLaunchKernelGGL(eik::k_import_U<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, as<T>(o->U_init), A.U);
     HIPCHK(hipMemcpyAsync(A.W, o->W_init, N, hipMemcpyDeviceToDevice, s));
@@ -249,7 +249,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
       hipLaunchKernelGGL(eik::k_near_a<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
       hipLaunchKernelGGL(eik::k_near_b<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
     }
-    hipLaunchKernelGGL(eik::k_lattice_init<T>, dim3(nlat), dim3(eik::kWave), lds_lat, s, A);
+    hipLaunchKernelGGL(eik::k_lattice_init<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
     causal_sweep(A, A.U, A.W, s, lds_cb);
     HIPCHK(hipGetLastError());
   }
@@ -262,11 +262,12 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const int64_t nres = (int64_t)(NJ + 1) * n0 + (int64_t)(NI + 1) * n1;
   for (int k = 0; k < o->max_iter; ++k) {
     HIPCHK(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kWave), lds_tile, s, A);
+    hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
     HIPCHK(hipEventRecord(ev[2], s));
     const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
     if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
-    hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kWave), lds_lat, s, A);
+    hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
+    HIPCHK(hipEventRecord(ev[4], s));
     if (dbg && dbg->U_pre_causal)
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
     causal_sweep(A, A.Un, A.Wn, s, lds_cb);
@@ -276,11 +277,13 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    float a = 0.f, b = 0.f;
+    float a = 0.f, b = 0.f, c = 0.f;
     HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
-    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[3]));
+    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[4]));
+    HIPCHK(hipEventElapsedTime(&c, ev[4], ev[3]));
     ms_fine += a;
-    ms_coarse += b;
+    ms_correct += b;
+    ms_causal += c;
     unsigned long long bits = host[0];
     double delta;
     std::memcpy(&delta, &bits, sizeof delta);
@@ -315,7 +318,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     st->ms_total = tot;
     st->ms_fine = ms_fine;
     st->ms_coarse = tot - ms_fine;
-    (void)ms_coarse;
+    st->ms_correct = ms_correct;
+    st->ms_causal = ms_causal;
   }
   if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
   return EIK_OK;
@@ -375,7 +379,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
     HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
     for (int d = 0; d <= BX + BY - 2; ++d) {
       const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
-      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kWave), lds, s, A, dir, d);
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kBlock), lds, s, A, dir, d);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
@@ -402,6 +406,8 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
     st->ms_total = ms;
     st->ms_fine = ms;
     st->ms_coarse = 0.f;
+    st->ms_correct = 0.f;
+    st->ms_causal = 0.f;
   }
   if (!conv) return fail(EIK_ERR_NOCONV, "FSM not stationary after %d sweeps", sw);
   return EIK_OK;

@@ -31,18 +31,40 @@
 namespace eik {
 
 constexpr int kWave = 64;
+// Box kernels run one workgroup of kBlock threads: all of them stage the box
+// between HBM and LDS, wave 0 alone sweeps it.
+constexpr int kBlock = 256;
 constexpr int kMaxL = 65;  // nodes per axis of a tile / lattice held in LDS
 // Every LDS array of a box is surrounded by kGuard spare elements: reads of
 // idle lanes may fall there, and stores that must not land anywhere go to
-// index kDummy (inside the leading guard band).
+// the lane's own slot kDummy + lane in the leading guard band (distinct
+// addresses, so the discarded stores do not serialise on one bank).
 constexpr int kGuard = 72;
 constexpr int kDummy = -kGuard;
+__device__ __forceinline__ int dummy_slot() { return kDummy + (int)threadIdx.x; }
 
 template <typename T> __device__ __forceinline__ T pinf();
 template <> __device__ __forceinline__ float pinf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double pinf<double>() { return __builtin_huge_val(); }
 
-__device__ __forceinline__ float dsqrt(float x) { return __builtin_sqrtf(x); }
+// Correctly rounded single-precision square root for arguments >= 2^-96
+// (the local solve's t = 2(r Delta)^2 - (a-b)^2 is far above that): the
+// hardware v_sqrt_f32 result s is within one ulp, and Tuckerman's rounding
+// test with the adjacent products decides between pred(s), s and succ(s):
+// x - pred(s)*s <= 0 means sqrt(x) lies below the lower midpoint, and
+// x - succ(s)*s > 0 that it lies above the upper one (the residuals are
+// multiples of ulp^2/2, so no value falls strictly between 0 and the true
+// midpoint gap).  Other arguments (negative, NaN: the discarded branch) give
+// an unspecified value.
+__device__ __forceinline__ float dsqrt(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sm = __builtin_bit_cast(float, __builtin_bit_cast(int, s) - 1);
+  const float sp = __builtin_bit_cast(float, __builtin_bit_cast(int, s) + 1);
+  const float rm = __builtin_fmaf(-sm, s, x);
+  const float rp = __builtin_fmaf(-sp, s, x);
+  const float t = (rm <= 0.0f) ? sm : s;
+  return (rp > 0.0f) ? sp : t;
+}
 __device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
 __device__ __forceinline__ float dabs(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
@@ -134,21 +156,21 @@ __device__ __forceinline__ T godunov2_sel(T a, T b, T rd, bool& two) {
 // lower its node stores to a dummy LDS slot, and the address of a lane moves
 // by SX every step (reads of idle lanes land in the guard bands around each
 // LDS array).  Returns true in lanes that changed a value.
-template <int SX, int SY, typename Rule>
+template <int SX, int SY, bool EXTRA, typename Rule>
 __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
   using T = typename Rule::real;
   using Pre = typename Rule::Pre;
+  const T inf = pinf<T>();
   const int lane = threadIdx.x;
-  const bool extra = L1 > kWave;
-  const int nsteps = L0 + L1 - 1 + (extra ? 1 : 0);
+  const int nsteps = L0 + L1 - 1 + (EXTRA ? 1 : 0);
   const int jA = min(max(SY > 0 ? lane : L1 - 1 - lane, 0), L1 - 1);
   const int jB = SY > 0 ? kWave : L1 - 1 - kWave;
   // LDS index of the lane's node at step t: x = x0 + SX * t
   const int xA0 = (jA + 1) * SP + 1 + (SX > 0 ? -lane : L0 - 1 + lane);
   const int xB0 = (jB + 1) * SP + 1 + (SX > 0 ? -(kWave + 1) : L0 - 1 + kWave + 1);
-  const bool laneB = extra && lane == 0;
+  const bool laneB = EXTRA && lane == 0;
   const bool rowA = lane < L1;
-  T cur = pinf<T>(), cur_prev = pinf<T>();
+  T cur = inf, cur_prev = inf;
   bool changed = false;
   int x = xA0;
   Pre pa = R.template load<SX, SY>(x), pb;
@@ -161,15 +183,23 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
     pn = R.template load<SX, SY>(x1);
     // keep the loads at the top of the step, a whole step ahead of their use
     __builtin_amdgcn_sched_barrier(0);
-    const T ex = (lane == kWave - 1) ? cur_prev : cur;
+    const T ex = (EXTRA && lane == kWave - 1) ? cur_prev : cur;
     const T from_prev_row = dpp_ror1(ex);
-    const T yprev = (lane == 0 && !useB) ? p.hy : from_prev_row;
-    const T xprev = (iq == 0) ? p.hx : cur;
+    T yprev, xprev;
+    if (Rule::kHalo) {
+      yprev = (lane == 0 && !useB) ? p.hy : from_prev_row;
+      xprev = (iq == 0) ? p.hx : cur;
+    } else {
+      // the halo is +inf: the first row has no upwind-y neighbour, and a
+      // lane's cur is +inf until its row starts (the delayed row restarts)
+      yprev = (lane == 0 && !useB) ? inf : from_prev_row;
+      xprev = (EXTRA && laneB && t == kWave + 1) ? inf : cur;
+    }
     const T xm = SX > 0 ? xprev : p.xn, xp = SX > 0 ? p.xn : xprev;
     const T ym = SY > 0 ? yprev : p.yn, yp = SY > 0 ? p.yn : yprev;
     bool ch;
-    const T v = R.compute(xm, xp, ym, yp, p, x, act, ch);
-    cur_prev = cur;
+    const T v = R.template compute<SX, SY>(xm, xp, ym, yp, p, x, act, ch);
+    if (EXTRA) cur_prev = cur;
     cur = act ? v : cur;
     changed = changed || ch;
     x = x1;
@@ -183,13 +213,18 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
   return changed;
 }
 
+template <int SX, int SY, typename Rule>
+__device__ __forceinline__ bool sweep_dir2(Rule& R, int L0, int L1, int SP) {
+  return (L1 > kWave) ? sweep_dir<SX, SY, true>(R, L0, L1, SP) : sweep_dir<SX, SY, false>(R, L0, L1, SP);
+}
+
 template <typename Rule>
 __device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int dir) {
   switch (dir) {
-    case 0: return sweep_dir<-1, -1>(R, L0, L1, SP);
-    case 1: return sweep_dir<-1, 1>(R, L0, L1, SP);
-    case 2: return sweep_dir<1, -1>(R, L0, L1, SP);
-    default: return sweep_dir<1, 1>(R, L0, L1, SP);
+    case 0: return sweep_dir2<-1, -1>(R, L0, L1, SP);
+    case 1: return sweep_dir2<-1, 1>(R, L0, L1, SP);
+    case 2: return sweep_dir2<1, -1>(R, L0, L1, SP);
+    default: return sweep_dir2<1, 1>(R, L0, L1, SP);
   }
 }
 
@@ -221,10 +256,11 @@ struct PreFine {
 
 // Fine update (Alg. fineupdate2D with flow-direction winds; eq. FSMupdate).
 // Also the coarse update of Step 1 (Alg. update2D) when Coarse = true.
-template <typename T, bool Coarse>
+template <typename T, bool Coarse, bool Halo>
 struct MinRule {
   using real = T;
   using Pre = PreFine<T>;
+  static constexpr bool kHalo = Halo;
   T* u;
   uint8_t* w;
   const T* rd;
@@ -235,11 +271,14 @@ struct MinRule {
     p.self = u[x];
     p.xn = u[x + SX];
     p.yn = u[x + SY * SP];
-    p.hx = u[x - SX];
-    p.hy = u[x - SY * SP];
+    if (Halo) {
+      p.hx = u[x - SX];
+      p.hy = u[x - SY * SP];
+    }
     p.rd = rd[x];
     return p;
   }
+  template <int SX, int SY>
   __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
                                       bool& ch) const {
     T a, b;
@@ -259,7 +298,7 @@ struct MinRule {
       useY = two || !(a < b);
     }
     const uint8_t c = (uint8_t)((useX ? (wx & 3) : 0) | (useY ? ((wy & 3) << 2) : 0));
-    const int xs = ch ? x : kDummy;
+    const int xs = ch ? x : dummy_slot();
     u[xs] = ut;
     w[xs] = c;
     return ch ? ut : p.self;
@@ -269,26 +308,39 @@ struct MinRule {
 template <typename T>
 struct PreCorr {
   T self, xn, yn, hx, hy, rd, uk, ck;
-  uint8_t wk;
+  uint8_t m;
 };
+
+// Step 4 condition mask of a node (Alg. 2Dweightedupdate): bits 0-2 say
+// which values -1, 0, +1 of the x component of W~ let the weighted update
+// through (all of w^k, W^k, W~ having x components <= 0, or all >= 0; all
+// three values when x is not a normal axis of the node's coarse line),
+// bits 3-5 the same for y, bit 6 that C^k is finite.
+__device__ __forceinline__ uint8_t corr_mask(uint8_t wk, uint8_t Wk, bool nx, bool ny, bool ck_finite) {
+  auto axis = [](int q, int r, bool normal) -> int {
+    if (!normal) return 7;
+    const bool le = q <= 0 && r <= 0, ge = q >= 0 && r >= 0;
+    return (le ? 1 : 0) | ((le || ge) ? 2 : 0) | (ge ? 4 : 0);
+  };
+  return (uint8_t)(axis(wx_of(wk), wx_of(Wk), nx) | (axis(wy_of(wk), wy_of(Wk), ny) << 3) |
+                   (ck_finite ? 64 : 0));
+}
 
 // Step 4 (Alg. 2Dweightedupdate): U = u^k + theta*(U~ - C^k) when the winds
 // w^k, W^k and W~ agree along every normal axis of the node's coarse line and
 // U~, C^k are finite; U = u^k otherwise.  Direct assignment, no minimum.
 // Gamma nodes carry u^k = g and r*H = NaN, so they always keep g.
-// wk: low nibble = w^k code, high nibble = W^k code.  nx, ny: x / y is a
-// normal axis of every node of the lattice.
 template <typename T>
 struct CorrectRule {
   using real = T;
   using Pre = PreCorr<T>;
+  static constexpr bool kHalo = false;
   T* u;
   const T* uk;
   const T* ck;
   const T* rd;
-  const uint8_t* wk;
+  const uint8_t* mk;
   T theta;
-  bool nx, ny;
   int SP;
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
@@ -296,14 +348,13 @@ struct CorrectRule {
     p.self = u[x];
     p.xn = u[x + SX];
     p.yn = u[x + SY * SP];
-    p.hx = u[x - SX];
-    p.hy = u[x - SY * SP];
     p.rd = rd[x];
     p.uk = uk[x];
     p.ck = ck[x];
-    p.wk = wk[x];
+    p.m = mk[x];
     return p;
   }
+  template <int SX, int SY>
   __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
                                       bool& ch) const {
     T a, b;
@@ -312,22 +363,16 @@ struct CorrectRule {
     pick(ym, yp, b, wy);
     bool two;
     const T ut = godunov2_sel(a, b, p.rd, two);
-    const int tx = (ut < b) ? wx : ((ut < a) ? 0 : wx);  // W~ (Alg. update2D)
-    const int ty = (ut < b) ? 0 : wy;
-    const uint8_t c = p.wk;
-    bool cond = true;
-    if (nx) {
-      const int q = wx_of(c & 15), r = wx_of(c >> 4);
-      cond = cond && ((q <= 0 && r <= 0 && tx <= 0) || (q >= 0 && r >= 0 && tx >= 0));
-    }
-    if (ny) {
-      const int q = wy_of(c & 15), r = wy_of(c >> 4);
-      cond = cond && ((q <= 0 && r <= 0 && ty <= 0) || (q >= 0 && r >= 0 && ty >= 0));
-    }
+    // W~ of Alg. update2D: U~ < b -> (Wx, 0); else U~ < a -> (0, Wy); else both
+    const bool lb = ut < b, la = ut < a;
+    const int tx = (!lb && la) ? 0 : wx;
+    const int ty = lb ? 0 : wy;
+    const unsigned m = p.m;
+    const bool cond = ((m >> (tx + 1)) & 1u) && ((m >> (ty + 4)) & 1u) && (m & 64u) && dfinite(ut);
     const T corr = p.uk + theta * (ut - p.ck);
-    const T v = (cond && dfinite(ut) && dfinite(p.ck)) ? corr : p.uk;
+    const T v = cond ? corr : p.uk;
     ch = act && (v != p.self);
-    u[ch ? x : kDummy] = v;
+    u[ch ? x : dummy_slot()] = v;
     return v;
   }
 };
@@ -495,7 +540,7 @@ __device__ __forceinline__ void lattice_offset(int q, int M, int& o0, int& o1) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
+__global__ __launch_bounds__(kBlock) void k_lattice_init(DD2<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   int o0, o1;
   lattice_offset(blockIdx.x, A.M, o0, o1);
@@ -507,10 +552,10 @@ __global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
   T* rd = carve<T>(lc, cnt);
   uint8_t* w = carve<uint8_t>(lc, cnt);
   const T nan = T(__builtin_nan(""));
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
-  step_fence();
+  for (int k = threadIdx.x; k < cnt; k += kBlock) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
+  __syncthreads();
   int nfree = 0;
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
     const int X = xi + A.n0 * yi;
@@ -529,11 +574,17 @@ __global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
       ++nfree;
     }
   }
-  step_fence();
-  MinRule<T, true> R{u, w, rd, SP};
-  const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
-  step_fence();
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  __syncthreads();
+  __shared__ int sh_ns, sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    MinRule<T, true, false> R{u, w, rd, SP};
+    const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+    if (threadIdx.x == 0) sh_ns = ns;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const int x = (p1 + 1) * SP + (p0 + 1);
@@ -541,11 +592,13 @@ __global__ __launch_bounds__(kWave) void k_lattice_init(DD2<T> A) {
     A.W[X] = w[x];
   }
   for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
-  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)nfree * (unsigned long long)ns);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
+__global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   int o0, o1;
   lattice_offset(blockIdx.x, A.M, o0, o1);
@@ -557,13 +610,14 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
   T* uk = carve<T>(lc, cnt);
   T* ck = carve<T>(lc, cnt);
   T* rd = carve<T>(lc, cnt);
-  uint8_t* wk = carve<uint8_t>(lc, cnt);
+  uint8_t* mk = carve<uint8_t>(lc, cnt);
   const T inf = pinf<T>();
   const T nan = T(__builtin_nan(""));
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = inf; rd[k] = nan; uk[k] = inf; ck[k] = inf; wk[k] = 0; }
-  step_fence();
+  const bool nx = o0 == 0, ny = o1 == 0;  // normal axes shared by the whole lattice
+  for (int k = threadIdx.x; k < cnt; k += kBlock) { u[k] = inf; rd[k] = nan; uk[k] = inf; ck[k] = inf; mk[k] = 0; }
+  __syncthreads();
   int nfree = 0;
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
     const int X = xi + A.n0 * yi;
@@ -573,23 +627,25 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
     const bool gam = !disnan(g);
     uk[x] = gam ? g : A.uk[X];
     rd[x] = A.r[X] * A.HT;
-    wk[x] = (uint8_t)((A.wk[X] & 15) | ((A.W[X] & 15) << 4));
     if (!gam) ++nfree;
   }
-  step_fence();
-  // C^k = C_H(nbrs^H(U^k)) once per node (Jacobi)
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  __syncthreads();
+  // C^k = C_H(nbrs^H(U^k)) once per node (Jacobi), and the condition masks
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const T xm = u[x - 1], xp = u[x + 1], ym = u[x - SP], yp = u[x + SP];
     const T a = xm < xp ? xm : xp;
     const T b = ym < yp ? ym : yp;
     bool two;
-    ck[x] = godunov2(a, b, rd[x], two);
+    const T c = godunov2(a, b, rd[x], two);
+    ck[x] = c;
+    mk[x] = corr_mask(A.wk[X], A.W[X], nx, ny, dfinite(c));
   }
-  step_fence();
+  __syncthreads();
   // start of Step 4: U = +inf, Gamma nodes at g (they keep it: r*H = NaN)
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
@@ -601,19 +657,27 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
       u[x] = inf;
     }
   }
-  step_fence();
-  CorrectRule<T> R{u, uk, ck, rd, wk, A.theta, o0 == 0, o1 == 0, SP};
-  const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
-  step_fence();
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  __syncthreads();
+  __shared__ int sh_ns, sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    CorrectRule<T> R{u, uk, ck, rd, mk, A.theta, SP};
+    const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+    if (threadIdx.x == 0) sh_ns = ns;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const int x = (p1 + 1) * SP + (p0 + 1);
     A.Un[X] = u[x];
-    A.Wn[X] = disnan(A.gfull[X]) ? (uint8_t)(wk[x] & 15) : (uint8_t)0;
+    A.Wn[X] = disnan(A.gfull[X]) ? A.wk[X] : (uint8_t)0;
   }
   for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
-  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)nfree * (unsigned long long)ns);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
 
 // ---------------------------------------------------------------------------
@@ -621,7 +685,7 @@ __global__ __launch_bounds__(kWave) void k_lattice_correct(DD2<T> A) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
+__global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int I = blockIdx.x % A.P0, J = blockIdx.x / A.P0;
   const int L = A.S + 1;
@@ -632,11 +696,11 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
   T* rd = carve<T>(lc, cnt);
   uint8_t* w = carve<uint8_t>(lc, cnt);
   const T nan = T(__builtin_nan(""));
-  for (int k = threadIdx.x; k < cnt; k += kWave) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
-  step_fence();
+  for (int k = threadIdx.x; k < cnt; k += kBlock) { u[k] = pinf<T>(); rd[k] = nan; w[k] = 0; }
+  __syncthreads();
   const int bi = I * A.S, bj = J * A.S;
   int nfree = 0;
-  for (int k = threadIdx.x; k < L * L; k += kWave) {
+  for (int k = threadIdx.x; k < L * L; k += kBlock) {
     const int li = k % L, lj = k / L;
     const int xi = bi + li, yi = bj + lj;
     const int X = xi + A.n0 * yi;
@@ -668,12 +732,18 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
       w[x] = 0;
     }
   }
-  step_fence();
-  MinRule<T, false> R{u, w, rd, SP};
-  const int ns = wave_fsm(R, L, L, SP, A.max_fine_sweeps);
-  step_fence();
+  __syncthreads();
+  __shared__ int sh_ns, sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    MinRule<T, false, false> R{u, w, rd, SP};
+    const int ns = wave_fsm(R, L, L, SP, A.max_fine_sweeps);
+    if (threadIdx.x == 0) sh_ns = ns;
+  }
+  __syncthreads();
   const int tile = blockIdx.x;
-  for (int k = threadIdx.x; k < L * L; k += kWave) {
+  for (int k = threadIdx.x; k < L * L; k += kBlock) {
     const int li = k % L, lj = k / L;
     const int xi = bi + li, yi = bj + lj;
     const int X = xi + A.n0 * yi;
@@ -695,7 +765,9 @@ __global__ __launch_bounds__(kWave) void k_tile(DD2<T> A) {
     if (lj == A.S) { A.edge_u[(tile * 4 + 3) * L + li] = v; A.edge_w[(tile * 4 + 3) * L + li] = c; }
   }
   for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
-  if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)nfree * (unsigned long long)ns);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +792,7 @@ struct GS2 {
 // diagonals, the downwind ones are untouched, so the sweep of the whole grid
 // is the paper's serial Gauss-Seidel sweep exactly.
 template <typename T>
-__global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int dir, int diag) {
+__global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int diag) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int q0 = max(0, diag - (A.BY - 1));
@@ -739,7 +811,7 @@ __global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int dir, int dia
   uint8_t* w = carve<uint8_t>(lc, cnt);
   const T inf = pinf<T>();
   const T nan = T(__builtin_nan(""));
-  for (int k = threadIdx.x; k < cnt; k += kWave) {
+  for (int k = threadIdx.x; k < cnt; k += kBlock) {
     const int hi = k % SP - 1, hj = k / SP - 1;
     const int xi = bi + hi, yi = bj + hj;
     const bool inside = hi >= 0 && hi < L0 && hj >= 0 && hj < L1;
@@ -758,18 +830,24 @@ __global__ __launch_bounds__(kWave) void k_grid_sweep(GS2<T> A, int dir, int dia
     w[k] = c;
     rd[k] = rv;
   }
-  step_fence();
-  MinRule<T, false> R{u, w, rd, SP};
-  const bool ch = sweep_any(R, L0, L1, SP, dir);
-  step_fence();
-  for (int k = threadIdx.x; k < L0 * L1; k += kWave) {
+  __syncthreads();
+  __shared__ int sh_ch;
+  if (threadIdx.x == 0) sh_ch = 0;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    MinRule<T, false, true> R{u, w, rd, SP};
+    const bool ch = sweep_any(R, L0, L1, SP, dir);
+    if (__any(ch) && threadIdx.x == 0) sh_ch = 1;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int li = k % L0, lj = k / L0;
     const int X = (bi + li) + A.n0 * (bj + lj);
     const int x = (lj + 1) * SP + (li + 1);
     A.u[X] = u[x];
     A.w[X] = w[x];
   }
-  if (__any(ch) && threadIdx.x == 0) atomicOr(A.changed, 1u);
+  if (threadIdx.x == 0 && sh_ch) atomicOr(A.changed, 1u);
 }
 
 template <typename T>
@@ -920,36 +998,98 @@ __global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) {
   const int base = (I * M) + A.n0 * (J * M);  // corner (I, J)
   T P = T(0);
   bool L = true;
-  for (int q = 1; q < M; ++q) {
-    const int off = sg > 0 ? q : M - q;
-    const int X = base + off * stride;
-    T v = U[X];
-    bool link = false;
-    if (disnan(A.gfull[X])) {
-      const uint8_t c = W[X];
-      const int e = horiz ? wx_of(c) : wy_of(c);
-      if (e == -sg) v = vmax(v, U[X + sg * stride]);
-      link = (e == sg);
+  // the segment's M-1 nodes in sweep order, in chunks whose loads are
+  // independent of the running maximum
+  constexpr int C = 8;
+  for (int q0 = 1; q0 < M; q0 += C) {
+    T v[C], nx[C];
+    uint8_t wc[C];
+    bool gm[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int q = min(q0 + k, M - 1);
+      const int off = sg > 0 ? q : M - q;
+      const int X = base + off * stride;
+      v[k] = U[X];
+      nx[k] = U[X + sg * stride];
+      wc[k] = W[X];
+      gm[k] = !disnan(A.gfull[X]);
     }
-    P = (link && q > 1) ? vmax(v, P) : v;
-    L = L && link;
-    A.cwork[X] = P;
-    A.cflag[X] = L ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int q = q0 + k;
+      if (q >= M) break;
+      const int off = sg > 0 ? q : M - q;
+      const int X = base + off * stride;
+      T vv = v[k];
+      bool link = false;
+      if (!gm[k]) {
+        const int e = horiz ? wx_of(wc[k]) : wy_of(wc[k]);
+        if (e == -sg) vv = vmax(vv, nx[k]);
+        link = (e == sg);
+      }
+      P = (link && q > 1) ? vmax(vv, P) : vv;
+      L = L && link;
+      A.cwork[X] = P;
+      A.cflag[X] = L ? 1 : 0;
+    }
   }
   if (horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
   else { A.vseg_p[s] = P; A.vseg_l[s] = L ? 1 : 0; }
 }
 
-// one workgroup; corner values in LDS
+// The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
+// on the coarse grid of corners, swept by one wave like a subdomain: the
+// predecessors in sweep order arrive as the engine's upwind-x (register) and
+// upwind-y (DPP) values.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_causal_b(DD2<T> A, T* U, int sx, int sy) {
+struct PreCausal {
+  T self, xn, yn, hx, hy, b;
+  uint8_t a;
+};
+
+template <typename T>
+struct CausalRule {
+  using real = T;
+  using Pre = PreCausal<T>;
+  static constexpr bool kHalo = false;
+  T* cu;
+  const T* cb;
+  const uint8_t* ca;
+  template <int SX, int SY>
+  __device__ __forceinline__ Pre load(int x) const {
+    Pre p;
+    p.b = cb[x];
+    p.a = ca[x];
+    p.xn = p.yn = p.self = p.hx = p.hy = T(0);
+    return p;
+  }
+  template <int SX, int SY>
+  __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
+                                      bool& ch) const {
+    const T px = SX > 0 ? xm : xp;  // predecessor along x in sweep order
+    const T py = SY > 0 ? ym : yp;
+    T v = p.b;
+    v = (p.a & 1) ? vmax(v, px) : v;
+    v = (p.a & 2) ? vmax(v, py) : v;
+    cu[act ? x : dummy_slot()] = v;
+    ch = false;
+    return v;
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_causal_b(DD2<T> A, T* U, int dir) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int CI = A.NI + 1, CJ = A.NJ + 1;
-  const int nC = CI * CJ;
-  T* cu = (T*)smem;   // result
-  T* cb = cu + nC;    // B(C)
-  uint8_t* ca = (uint8_t*)(cb + nC);  // alpha bits
-  for (int t = threadIdx.x; t < nC; t += blockDim.x) {
+  const int SP = halo_stride(CI);
+  const int cnt = halo_count(CI, CJ);
+  unsigned char* lc = smem;
+  T* cu = carve<T>(lc, cnt);
+  T* cb = carve<T>(lc, cnt);
+  uint8_t* ca = carve<uint8_t>(lc, cnt);
+  for (int t = threadIdx.x; t < CI * CJ; t += kBlock) {
     const int I = t % CI, J = t / CI;
     T b = A.corner_v[t];
     const uint8_t f = A.corner_f[t];
@@ -964,28 +1104,19 @@ __global__ __launch_bounds__(1024) void k_causal_b(DD2<T> A, T* U, int sx, int s
       b = vmax(b, A.vseg_p[vs]);
       if (A.vseg_l[vs]) al |= 2;
     }
-    cb[t] = b;
-    ca[t] = al;
+    const int x = (J + 1) * SP + (I + 1);
+    cb[x] = b;
+    ca[x] = al;
   }
   __syncthreads();
-  for (int d = 0; d <= A.NI + A.NJ; ++d) {
-    for (int Iq = threadIdx.x; Iq < CI; Iq += blockDim.x) {
-      const int Jq = d - Iq;
-      if (Jq < 0 || Jq >= CJ) continue;
-      const int I = sx > 0 ? Iq : A.NI - Iq;
-      const int J = sy > 0 ? Jq : A.NJ - Jq;
-      const int t = I + CI * J;
-      T v = cb[t];
-      const uint8_t al = ca[t];
-      if (al & 1) v = vmax(v, cu[(I - sx) + CI * J]);
-      if (al & 2) v = vmax(v, cu[I + CI * (J - sy)]);
-      cu[t] = v;
-    }
-    __syncthreads();
+  if (threadIdx.x < kWave) {
+    CausalRule<T> R{cu, cb, ca};
+    sweep_any(R, CI, CJ, SP, dir);
   }
-  for (int t = threadIdx.x; t < nC; t += blockDim.x) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < CI * CJ; t += kBlock) {
     const int I = t % CI, J = t / CI;
-    U[(I * A.M) + A.n0 * (J * A.M)] = cu[t];
+    U[(I * A.M) + A.n0 * (J * A.M)] = cu[(J + 1) * SP + (I + 1)];
   }
 }
 
@@ -1005,10 +1136,22 @@ __global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
   const int base = (I * M) + A.n0 * (J * M);
   const int start = sg > 0 ? base : base + M * stride;
   const T cs = U[start];
-  for (int q = 1; q < M; ++q) {
-    const int X = base + q * stride;
-    const T P = A.cwork[X];
-    U[X] = A.cflag[X] ? vmax(P, cs) : P;
+  constexpr int C = 8;
+  for (int q0 = 1; q0 < M; q0 += C) {
+    T P[C];
+    uint8_t F[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int X = base + min(q0 + k, M - 1) * stride;
+      P[k] = A.cwork[X];
+      F[k] = A.cflag[X];
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      if (q0 + k >= M) break;
+      const int X = base + (q0 + k) * stride;
+      U[X] = F[k] ? vmax(P[k], cs) : P[k];
+    }
   }
 }
 
