@@ -10,9 +10,11 @@ until max|U^{k+1}-U^k| < tol.  Inputs are resident in HBM before timing.
 
 Prints one JSON line.  value = fine-grid Godunov updates per second over the
 whole solve (Step 3 local solves / wall time of the solves); ms_per_step is
-the DD time-to-solution.  The roofline object describes the dominant kernel,
-the subdomain sweep of Step 3, timed with HIP events on its own stream inside
-the library.
+the DD time-to-solution.  The roofline object describes the dominant kernel
+(the Step 4 lattice correction or the Step 3 subdomain sweep, whichever takes
+longer per launch), timed with HIP events on the stream it runs on, inside
+the library; its traffic comes from the committed rocprofv3 counter summary
+while the kernel sources are unchanged.
 """
 from __future__ import annotations
 
@@ -49,7 +51,43 @@ def parse():
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (3 times), the "
+                         "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
     return ap.parse_args()
+
+
+def measured_traffic(kernel_prefix, dtype):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary (profiles/hbm_traffic_config2_<dtype>.md), or None when there is
+    none or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_config2_{dtype}.md")
+    if not os.path.exists(path):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1805_04198_amd", "csrc", f), "rb").read()
+                   for f in ("kernels2d.hpp", "eik.hip"))
+    h = hashlib.sha256(src).hexdigest()[:16]
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "traffic" and parts[1].startswith(kernel_prefix):
+            kv = dict(x.split("=") for x in parts[2:])
+            if kv["source_sha256_16"] != h:
+                return None
+            return {"bytes": int(kv["read_bytes"]) + int(kv["write_bytes"]),
+                    "read_bytes": int(kv["read_bytes"]), "write_bytes": int(kv["write_bytes"])}
+    return None
+
+
+def copy_calibration():
+    import torch
+    n = 64 * 1024 * 1024  # 256 MiB of float32
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
 
 
 def cpu_baseline(p, theta, iters):
@@ -69,6 +107,9 @@ def cpu_baseline(p, theta, iters):
 
 def main():
     a = parse()
+    if a.copy_calibration:
+        copy_calibration()
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); the DD "
               "path would shard subdomains across GPUs with one skeleton exchange per "
@@ -109,17 +150,21 @@ def main():
     init = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=a.theta, tol=tol, max_iter=0)
     corr_updates = sum(o["coarse_updates"] - init["coarse_updates"] for o in outs)
 
-    def kernel_line(name, updates, ms, ops):
+    def kernel_line(name, sym, updates, ms, ops):
         upl = updates / iters
         msl = ms / iters
         ach = upl * ops / (msl * 1e-3) / 1e12
+        tr = measured_traffic(f"eik::{sym}<{'float' if a.dtype == 'f32' else 'double'}>", a.dtype)
         return {"bound": "alu", "kernel": name, "achieved": ach, "peak": ALU_PEAK_TOPS,
-                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS,
+                "traffic": None if tr is None else tr["bytes"],
+                "traffic_detail": tr,
                 "per_launch": {"updates": upl, "ms": msl, "ops_per_update": ops}}
 
-    k_fine = kernel_line("k_tile (Step 3 subdomain FSM)", fine,
+    k_fine = kernel_line("k_tile (Step 3 subdomain FSM)", "k_tile", fine,
                          sum(o["ms_fine"] for o in outs), OPS_PER_UPDATE)
-    k_corr = kernel_line("k_lattice_correct (Step 4 weighted correction sweeps)", corr_updates,
+    k_corr = kernel_line("k_lattice_correct (Step 4 weighted correction sweeps)",
+                         "k_lattice_correct", corr_updates,
                          sum(o["ms_correct"] for o in outs), OPS_PER_CORRECTION)
     dominant, other = (k_corr, k_fine) if k_corr["per_launch"]["ms"] > k_fine["per_launch"]["ms"] \
         else (k_fine, k_corr)
