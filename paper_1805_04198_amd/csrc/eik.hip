@@ -13,6 +13,7 @@
 
 #include "../../include/eik.h"
 #include "kernels2d.hpp"
+#include "kernels3d.hpp"
 
 namespace {
 
@@ -326,6 +327,225 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
 }
 
 // ---------------------------------------------------------------------------
+// eik_dd_solve, d = 3
+// ---------------------------------------------------------------------------
+
+// number of coarse cells (in sweep coordinates) on anti-diagonal d
+static int cells_on_diag(const int CN[3], int d) {
+  int c = 0;
+  for (int i = std::max(0, d - (CN[1] - 1) - (CN[2] - 1)); i <= std::min(d, CN[0] - 1); ++i) {
+    const int r2 = d - i;
+    const int jlo = std::max(0, r2 - (CN[2] - 1)), jhi = std::min(r2, CN[1] - 1);
+    if (jhi >= jlo) c += jhi - jlo + 1;
+  }
+  return c;
+}
+
+template <typename T>
+void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
+  const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
+  const int ndiag = CN[0] + CN[1] + CN[2] - 2;
+  const size_t lds = (size_t)A.M * A.M * A.M * sizeof(T);
+  for (int dir = 0; dir < 8; ++dir)
+    for (int d = 0; d < ndiag; ++d) {
+      const int nc = cells_on_diag(CN, d);
+      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(nc), dim3(256), lds, s, A, U, W, dir, d);
+    }
+}
+
+template <typename T>
+eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, const eik_dd_opts* o,
+                       void* u_outv, void* U_outv, int8_t* W_out, eik_stats* st, hipStream_t s) {
+  int n[3];
+  for (int a = 0; a < 3; ++a) n[a] = (int)G->n[a];
+  const int S = o->S, M = o->M;
+  if (M < 2 || S < M || S % M != 0) return fail(EIK_ERR_SHAPE, "need M >= 2 and S a multiple of M (S=%d M=%d)", S, M);
+  for (int a = 0; a < 3; ++a)
+    if ((n[a] - 1) % S != 0) return fail(EIK_ERR_SHAPE, "(n-1) must be a multiple of S on every axis");
+  const size_t szT = sizeof(T);
+  const int L = S + 1;
+  int NC[3], P[3];
+  for (int a = 0; a < 3; ++a) { NC[a] = (n[a] - 1) / M; P[a] = (n[a] - 1) / S; }
+  const int Lmax = std::max(NC[0], std::max(NC[1], NC[2])) + 1;
+  if (L > eik::kMaxL3 || Lmax > eik::kMaxL3)
+    return fail(EIK_ERR_UNSUPPORTED, "3D boxes are limited to %d nodes per axis", eik::kMaxL3);
+  const size_t lds_tile = (size_t)L * L * L * szT;
+  const size_t lds_lat = (size_t)(NC[0] + 1) * (NC[1] + 1) * (NC[2] + 1) * szT;
+  const size_t lds_cell = (size_t)M * M * M * szT;
+  if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cell > kLdsBytes)
+    return fail(EIK_ERR_UNSUPPORTED, "3D box does not fit in LDS in this precision");
+  if (!(o->theta >= 0.0 && o->theta <= 1.0)) return fail(EIK_ERR_ARG, "theta must lie in [0,1]");
+  if (o->max_iter < 0 || o->max_fine_sweeps < 1 || o->max_coarse_sweeps < 1)
+    return fail(EIK_ERR_ARG, "max_iter >= 0, max_fine_sweeps >= 1, max_coarse_sweeps >= 1");
+  if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  const int ntile = P[0] * P[1] * P[2];
+  const int nlat = 3 * M * M - 3 * M + 1;
+  size_t need = 0;
+  need += 8 * (N * szT + 256);
+  need += 4 * (N + 256) + 2 * N + 256;
+  need += 2 * (N * 8 + 256);
+  need += (size_t)ntile * 6 * L * L * (szT + 1) + 512;
+  need += (size_t)ntile * L * L * L + 256;
+  need += 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::DD3<T> A;
+  for (int a = 0; a < 3; ++a) { A.n[a] = n[a]; A.P[a] = P[a]; A.NC[a] = NC[a]; }
+  A.S = S; A.M = M; A.nlat = nlat;
+  A.hT = (T)G->h;
+  A.HT = (T)((double)M * G->h);
+  A.theta = (T)o->theta;
+  A.max_fine_sweeps = o->max_fine_sweeps;
+  A.max_coarse_sweeps = o->max_coarse_sweeps;
+  A.r = as<T>(rv);
+  A.gidx = gam->idx;
+  A.gval = as<T>(gam->g);
+  A.ng = gam->count;
+  T* gfull = cv.take<T>(N);
+  A.gfull = gfull;
+  A.rdh = cv.take<T>(N);
+  A.rdH = cv.take<T>(N);
+  A.U = cv.take<T>(N);
+  A.Un = cv.take<T>(N);
+  A.uk = cv.take<T>(N);
+  A.ck = cv.take<T>(N);
+  A.W = cv.take<uint8_t>(N);
+  A.Wn = cv.take<uint8_t>(N);
+  A.wk = cv.take<uint8_t>(N);
+  A.mk = cv.take<uint16_t>(N);
+  A.near_key = cv.take<unsigned long long>(N);
+  A.near_win = cv.take<long long>(N);
+  A.face_u = cv.take<T>((size_t)ntile * 6 * L * L);
+  A.face_w = cv.take<uint8_t>((size_t)ntile * 6 * L * L);
+  A.tile_w = cv.take<uint8_t>((size_t)ntile * L * L * L);
+  A.cvals = nullptr;
+  A.counters = cv.take<unsigned long long>(4);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  A.u_out = as<T>(u_outv);
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_tile3<T>, lds_tile)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_init3<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_correct3<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal3<T>, lds_cell)) != EIK_OK) return e;
+
+  hipEvent_t ev[6];
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  HIPCHK(hipEventRecord(ev[0], s));
+  const T nanT = (T)NAN;
+  const int bs = 256;
+  HIPCHK(hipMemsetAsync(A.counters, 0, 4 * sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, nanT, N);
+  if (gam->count > 0)
+    hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
+                       gam->idx, as<T>(gam->g), gam->count);
+  hipLaunchKernelGGL(eik::k_rd3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.u_out, nanT, N);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.uk, nanT, N);
+  HIPCHK(hipMemsetAsync(A.wk, 0, N, s));
+  HIPCHK(hipGetLastError());
+  float ms_fine = 0.f, ms_correct = 0.f, ms_causal = 0.f;
+  if (o->U_init) {
+    hipLaunchKernelGGL(eik::k_skel3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, as<T>(o->U_init), A.U);
+    HIPCHK(hipMemcpyAsync(A.W, o->W_init, N, hipMemcpyDeviceToDevice, s));
+  } else {
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.U, nanT, N);
+    HIPCHK(hipMemsetAsync(A.W, 0, N, s));
+    HIPCHK(hipMemsetAsync(A.near_key, 0xff, N * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(eik::k_fill<long long>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.near_win,
+                       (long long)0x7fffffffffffffffll, N);
+    const int64_t W2 = 2 * M - 1;
+    const int64_t npair = gam->count * W2 * W2 * W2;
+    if (npair > 0) {
+      hipLaunchKernelGGL(eik::k_near3_a<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
+      hipLaunchKernelGGL(eik::k_near3_b<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
+    }
+    hipLaunchKernelGGL(eik::k_lattice_init3<T>, dim3(nlat), dim3(eik::kBlock3), lds_lat, s, A);
+    causal_sweep3(A, A.U, A.W, s);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.Un, nanT, N);
+  HIPCHK(hipMemsetAsync(A.Wn, 0, N, s));
+  const eik_dd_debug* dbg = o->debug;
+  int it = 0, conv = 0;
+  double last = 0.0;
+  for (int k = 0; k < o->max_iter; ++k) {
+    HIPCHK(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(eik::k_tile3<T>, dim3(ntile), dim3(eik::kBlock3), lds_tile, s, A);
+    HIPCHK(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL(eik::k_reconcile3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+    hipLaunchKernelGGL(eik::k_ck3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+    hipLaunchKernelGGL(eik::k_lattice_correct3<T>, dim3(nlat), dim3(eik::kBlock3), lds_lat, s, A);
+    HIPCHK(hipEventRecord(ev[4], s));
+    if (dbg && dbg->U_pre_causal)
+      HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
+    causal_sweep3(A, A.Un, A.Wn, s);
+    HIPCHK(hipMemsetAsync(&A.counters[2], 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(eik::k_residual3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float a = 0.f, b = 0.f, c = 0.f;
+    HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[4]));
+    HIPCHK(hipEventElapsedTime(&c, ev[4], ev[3]));
+    ms_fine += a;
+    ms_correct += b;
+    ms_causal += c;
+    unsigned long long bits = host[0];
+    double delta;
+    std::memcpy(&delta, &bits, sizeof delta);
+    std::swap(A.U, A.Un);
+    std::swap(A.W, A.Wn);
+    it = k + 1;
+    last = delta;
+    if (st && st->residual_history && k < st->history_cap) st->residual_history[k] = delta;
+    if (std::isnan(delta)) return fail(EIK_ERR_NONFINITE, "residual is NaN");
+    if (delta < o->tol || delta == 0.0) {
+      conv = 1;
+      break;
+    }
+  }
+  if (U_outv) hipLaunchKernelGGL(eik::k_skel3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, A.U, as<T>(U_outv));
+  if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
+  if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
+  if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(host, A.counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(ev[3], s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  if (st) {
+    float tot = 0.f;
+    HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[3]));
+    st->iterations = it;
+    st->converged = conv;
+    st->fine_updates = (int64_t)host[0];
+    st->coarse_updates = (int64_t)host[1];
+    st->sweeps = 0;
+    st->final_residual = last;
+    st->ms_total = tot;
+    st->ms_fine = ms_fine;
+    st->ms_coarse = tot - ms_fine;
+    st->ms_correct = ms_correct;
+    st->ms_causal = ms_causal;
+  }
+  if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
+  return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
 // eik_solve, d = 2
 // ---------------------------------------------------------------------------
 
@@ -415,13 +635,14 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
 
 eik_status check_common(const eik_grid* G, const void* r, const eik_gamma* gam, const void* out) {
   if (!G || !r || !gam || !out) return fail(EIK_ERR_ARG, "NULL argument");
-  if (G->dim != 2) {
-    if (G->dim == 3) return fail(EIK_ERR_UNSUPPORTED, "d = 3 is not implemented in this build");
-    return fail(EIK_ERR_ARG, "dim must be 2 or 3");
-  }
+  if (G->dim != 2 && G->dim != 3) return fail(EIK_ERR_ARG, "dim must be 2 or 3");
   if (G->dtype != EIK_F32 && G->dtype != EIK_F64) return fail(EIK_ERR_ARG, "dtype must be EIK_F32 or EIK_F64");
-  if (G->n[0] < 2 || G->n[1] < 2) return fail(EIK_ERR_SHAPE, "need at least 2 nodes per axis");
-  if ((int64_t)G->n[0] * G->n[1] >= (int64_t)1 << 31) return fail(EIK_ERR_UNSUPPORTED, "grid too large for 32-bit indexing");
+  int64_t N = 1;
+  for (int a = 0; a < G->dim; ++a) {
+    if (G->n[a] < 2) return fail(EIK_ERR_SHAPE, "need at least 2 nodes per axis");
+    N *= G->n[a];
+  }
+  if (N >= (int64_t)1 << 31) return fail(EIK_ERR_UNSUPPORTED, "grid too large for 32-bit indexing");
   if (!(G->h > 0) || !std::isfinite(G->h)) return fail(EIK_ERR_ARG, "h must be positive and finite");
   if (gam->count < 0 || (gam->count > 0 && (!gam->idx || !gam->g))) return fail(EIK_ERR_ARG, "bad Gamma");
   if (r == out) return fail(EIK_ERR_ARG, "u_out must not alias r");
@@ -436,6 +657,7 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
                      void* u_out, int8_t* wind_out, eik_stats* stats, void* hip_stream) {
   eik_status e = check_common(grid, r, gamma, u_out);
   if (e != EIK_OK) return e;
+  if (grid->dim == 3) return fail(EIK_ERR_UNSUPPORTED, "eik_solve: d = 3 is not implemented in this build");
   hipStream_t s = (hipStream_t)hip_stream;
   if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
   return solve_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
@@ -447,6 +669,10 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
   if (e != EIK_OK) return e;
   if (!opts) return fail(EIK_ERR_ARG, "NULL opts");
   hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dim == 3) {
+    if (grid->dtype == EIK_F32) return dd_solve3_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+    return dd_solve3_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+  }
   if (grid->dtype == EIK_F32)
     return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
   return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);

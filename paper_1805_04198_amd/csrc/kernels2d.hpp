@@ -1165,13 +1165,13 @@ __global__ void k_residual(DD2<T> A) {
   if (t < nh) {
     const int X = (int)(t % A.n0) + A.n0 * ((int)(t / A.n0) * A.M);
     const T a = A.Un[X], b = A.U[X];
-    if (!(a == b)) dv = (double)dabs(a - b);
+    if (!(a == b)) dv = dabs((double)a - (double)b);
     if (disnan(dv)) dv = __builtin_huge_val();
   } else if (t < nh + nv) {
     const int64_t s = t - nh;
     const int X = (int)(s / A.n1) * A.M + A.n0 * (int)(s % A.n1);
     const T a = A.Un[X], b = A.U[X];
-    if (!(a == b)) dv = (double)dabs(a - b);
+    if (!(a == b)) dv = dabs((double)a - (double)b);
     if (disnan(dv)) dv = __builtin_huge_val();
   }
   // wave max, then one atomic per wave

@@ -1,0 +1,774 @@
+// Device code of the 3D domain-decomposition Eikonal solver for gfx950.
+//
+// The paper writes the method in 2D and states that it generalises (Sec. 3,
+// Sec. 1.1: 2^d sweeps); this file carries every step to d = 3 with the same
+// per-axis rules as the CPU reference:
+//   local solve  : the minima of the three axes sorted ascending (stable in
+//                  axis order); one-sided u = a1 + rd, then the two-sided root
+//                  if a2 is below it, then the three-sided root if a3 is below
+//                  the two-sided one (t3 = 3 rd^2 - sum of squared pairwise
+//                  differences, clamped at 0; u = ((a1+a2)+a3 + sqrt t3) / 3)
+//   fine wind    : the axes used by the final root (Alg. fineupdate2D)
+//   coarse wind  : an axis enters unless U~ lies below its neighbour minimum
+//                  (the tests of Alg. update2D taken per axis)
+// Layout: node (i, j, k) at i + n0*(j + n1*k).
+//
+// A box (subdomain or lattice, <= 34 nodes per axis in fp32) is swept by one
+// workgroup with its values in LDS: thread p owns x-pencils (j, k); at step t
+// of a sweep pencil (j, k) (in sweep order) updates node i = t - j - k, so the
+// nodes of hyperplane t are updated between two barriers.  A node reads only
+// hyperplanes t-1 (updated) and t+1 (not yet updated), so the result is the
+// paper's lexicographic Gauss-Seidel sweep value for value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels2d.hpp"
+
+namespace eik {
+
+constexpr int kBlock3 = 1024;
+constexpr int kMaxL3 = 34;  // nodes per axis of a 3D box held in LDS (fp32)
+
+
+__device__ __forceinline__ int w_of(uint8_t c, int a) { int v = (c >> (2 * a)) & 3; return v == 3 ? -1 : v; }
+__device__ __forceinline__ uint8_t wenc3(int wx, int wy, int wz) {
+  return (uint8_t)((wx & 3) | ((wy & 3) << 2) | ((wz & 3) << 4));
+}
+
+// 3D local solve.  m: per-axis neighbour minima; ws: their wind signs.
+// Coarse = false: fine wind, true: coarse wind.  Returns u~ and the wind code.
+template <typename T, bool Coarse>
+__device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd, uint8_t& code) {
+  int p0 = 0, p1 = 1, p2 = 2;
+  // stable insertion sort of the three axes by value
+  if (m[p1] < m[p0]) { const int t = p0; p0 = p1; p1 = t; }
+  if (m[p2] < m[p1]) {
+    int t = p1; p1 = p2; p2 = t;
+    if (m[p1] < m[p0]) { t = p0; p0 = p1; p1 = t; }
+  }
+  const T a1 = m[p0], a2 = m[p1], a3 = m[p2];
+  T ut;
+  int used;
+  const T d12 = a1 - a2;
+  if (!(dabs(d12) < rd)) {
+    ut = a1 + rd;
+    used = 1;
+  } else {
+    T t = rd * rd;
+    t = t + t;
+    t = t - d12 * d12;
+    const T u2 = ((a1 + a2) + dsqrt(t)) * T(0.5);
+    if (!(a3 < u2)) {
+      ut = u2;
+      used = 2;
+    } else {
+      const T d13 = a1 - a3, d23 = a2 - a3;
+      T q = rd * rd;
+      q = (q + q) + q;
+      q = q - ((d12 * d12 + d13 * d13) + d23 * d23);
+      if (q < T(0)) q = T(0);
+      ut = (((a1 + a2) + a3) + dsqrt(q)) / T(3);
+      used = 3;
+    }
+  }
+  int w[3] = {0, 0, 0};
+  if (!Coarse) {
+    w[p0] = ws[p0];
+    if (used >= 2) w[p1] = ws[p1];
+    if (used >= 3) w[p2] = ws[p2];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = (ut < m[a]) ? 0 : ws[a];
+  }
+  code = wenc3(w[0], w[1], w[2]);
+  return ut;
+}
+
+// ---------------------------------------------------------------------------
+// arguments
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct DD3 {
+  int n[3];          // nodes per axis
+  int S, M;          // subdomain side, coarse spacing (fine cells)
+  int P[3];          // subdomains per axis
+  int NC[3];         // coarse cells per axis ((n-1)/M)
+  int nlat;          // lattices: offsets in [0,M)^3 with a zero component
+  T hT, HT, theta;
+  int max_fine_sweeps, max_coarse_sweeps;
+  const T* r;
+  const T* gfull;     // Gamma value per node, NaN if not Gamma
+  const int64_t* gidx;
+  const T* gval;
+  int64_t ng;
+  T* rdh;             // r*h, NaN at Gamma nodes
+  T* rdH;             // r*H, NaN at Gamma nodes
+  T* U;
+  uint8_t* W;
+  T* Un;
+  uint8_t* Wn;
+  T* uk;
+  uint8_t* wk;
+  T* ck;              // C^k (full grid, coarse nodes used)
+  uint16_t* mk;       // Step 4 condition masks
+  T* u_out;
+  T* face_u;          // [tile][6][(S+1)^2]
+  uint8_t* face_w;
+  uint8_t* tile_w;    // [tile][(S+1)^3] winds of the subdomain sweep
+  T* cvals;           // causal sweep scratch: V per coarse node (full grid)
+  unsigned long long* near_key;
+  long long* near_win;
+  unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits
+};
+
+__device__ __forceinline__ int64_t idx3(const int (&n)[3], int i, int j, int k) {
+  return (int64_t)i + (int64_t)n[0] * ((int64_t)j + (int64_t)n[1] * k);
+}
+
+__device__ __forceinline__ bool coarse3(int i, int j, int k, int M) {
+  return (i % M == 0) || (j % M == 0) || (k % M == 0);
+}
+
+// lattice q -> offset: first all with o0 = 0 (M^2), then o0 > 0 and o1 = 0
+// (M(M-1)), then o0 > 0, o1 > 0, o2 = 0 ((M-1)^2)
+__device__ __forceinline__ void lattice_offset3(int q, int M, int& o0, int& o1, int& o2) {
+  if (q < M * M) { o0 = 0; o1 = q % M; o2 = q / M; return; }
+  q -= M * M;
+  if (q < (M - 1) * M) { o0 = 1 + q % (M - 1); o1 = 0; o2 = q / (M - 1); return; }
+  q -= (M - 1) * M;
+  o0 = 1 + q % (M - 1);
+  o1 = 1 + q / (M - 1);
+  o2 = 0;
+}
+
+// ---------------------------------------------------------------------------
+// the 3D box sweep engine
+// ---------------------------------------------------------------------------
+
+// One directional sweep over an L0 x L1 x L2 box in LDS (index i + L0*(j +
+// L1*k)); returns true (block-wide) if any value changed.
+template <typename Rule>
+__device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir) {
+  const int sx = (dir & 4) ? 1 : -1, sy = (dir & 2) ? 1 : -1, sz = (dir & 1) ? 1 : -1;
+  const int nsteps = L0 + L1 + L2 - 2;
+  const int np = L1 * L2;
+  int changed = 0;
+  for (int t = 0; t < nsteps; ++t) {
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+      const int jq = p % L1, kq = p / L1;
+      const int iq = t - jq - kq;
+      if (iq < 0 || iq >= L0) continue;
+      const int i = sx > 0 ? iq : L0 - 1 - iq;
+      const int j = sy > 0 ? jq : L1 - 1 - jq;
+      const int k = sz > 0 ? kq : L2 - 1 - kq;
+      changed |= R.update(i, j, k) ? 1 : 0;
+    }
+    __syncthreads();
+  }
+  return __syncthreads_or(changed) != 0;
+}
+
+// 2^d orders of the loop nest (x outermost, z innermost) until a sweep
+// changes nothing, at most max_sweeps.
+template <typename Rule>
+__device__ int fsm3(Rule& R, int L0, int L1, int L2, int max_sweeps) {
+  int s = 0;
+  while (s < max_sweeps) {
+    const bool ch = sweep3(R, L0, L1, L2, s & 7);
+    ++s;
+    if (!ch) break;
+  }
+  return s;
+}
+
+// neighbour minima of box node x=(i,j,k); missing neighbours are +inf
+template <typename T>
+__device__ __forceinline__ void gather3(const T* u, int L0, int L1, int L2, int i, int j, int k, T (&m)[3],
+                                        int (&ws)[3]) {
+  const T inf = pinf<T>();
+  const int x = i + L0 * (j + L1 * k);
+  const int st[3] = {1, L0, L0 * L1};
+  const int c[3] = {i, j, k};
+  const int L[3] = {L0, L1, L2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T lo = c[a] > 0 ? u[x - st[a]] : inf;
+    const T hi = c[a] < L[a] - 1 ? u[x + st[a]] : inf;
+    const bool lt = lo < hi;
+    m[a] = lt ? lo : hi;
+    ws[a] = lt ? 1 : -1;
+  }
+}
+
+// Minimum-update rule (fine, Alg. fineupdate2D generalised; or Step 1 coarse,
+// Alg. update2D generalised).  rd: global r*Delta at the node (NaN = fixed);
+// wind codes go to a global per-box array when a value is lowered.
+template <typename T, bool Coarse>
+struct MinRule3 {
+  T* u;
+  int L0, L1, L2;
+  const T* rd_g;       // global array of r*Delta
+  uint8_t* w_g;        // global wind array of the box nodes
+  int64_t base;        // global index of box node (0,0,0)
+  int gs[3];           // global strides of the box axes
+  int64_t wbase;       // index of box node (0,0,0) in w_g
+  int ws_[3];          // strides of the box axes in w_g
+  __device__ __forceinline__ bool update(int i, int j, int k) const {
+    const T rd = rd_g[base + (int64_t)i * gs[0] + (int64_t)j * gs[1] + (int64_t)k * gs[2]];
+    if (disnan(rd)) return false;
+    T m[3];
+    int ws[3];
+    gather3(u, L0, L1, L2, i, j, k, m, ws);
+    uint8_t code;
+    const T ut = godunov3<T, Coarse>(m, ws, rd, code);
+    const int x = i + L0 * (j + L1 * k);
+    if (ut < u[x]) {
+      u[x] = ut;
+      w_g[wbase + (int64_t)i * ws_[0] + (int64_t)j * ws_[1] + (int64_t)k * ws_[2]] = code;
+      return true;
+    }
+    return false;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+
+// r*h and r*H with NaN at Gamma nodes
+template <typename T>
+__global__ void k_rd3(DD3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const bool g = !disnan(A.gfull[t]);
+  const T nan = T(__builtin_nan(""));
+  A.rdh[t] = g ? nan : A.r[t] * A.hT;
+  A.rdH[t] = g ? nan : A.r[t] * A.HT;
+}
+
+template <typename T>
+__device__ __forceinline__ bool near_candidate3(const DD3<T>& A, int64_t gi, int off, int64_t& X, T& v) {
+  const int W2 = 2 * A.M - 1;
+  const int dx = off % W2 - (A.M - 1), dy = (off / W2) % W2 - (A.M - 1), dz = off / (W2 * W2) - (A.M - 1);
+  const int64_t g = A.gidx[gi];
+  const int gx = (int)(g % A.n[0]), gy = (int)((g / A.n[0]) % A.n[1]), gz = (int)(g / ((int64_t)A.n[0] * A.n[1]));
+  const int xi = gx + dx, yi = gy + dy, zi = gz + dz;
+  if (xi < 0 || xi >= A.n[0] || yi < 0 || yi >= A.n[1] || zi < 0 || zi >= A.n[2]) return false;
+  if (!coarse3(xi, yi, zi, A.M)) return false;
+  X = idx3(A.n, xi, yi, zi);
+  const int d2 = dx * dx + dy * dy + dz * dz;
+  const T sq = dsqrt((T)d2);
+  const T dist = A.hT * sq;
+  v = A.gval[gi] + A.r[X] * dist;
+  return true;
+}
+
+template <typename T>
+__global__ void k_near3_a(DD3<T> A) {
+  const int W2 = 2 * A.M - 1, W3 = W2 * W2 * W2;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= A.ng * W3) return;
+  int64_t X;
+  T v;
+  if (near_candidate3(A, t / W3, (int)(t % W3), X, v)) atomicMin(&A.near_key[X], okey(v));
+}
+
+template <typename T>
+__global__ void k_near3_b(DD3<T> A) {
+  const int W2 = 2 * A.M - 1, W3 = W2 * W2 * W2;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= A.ng * W3) return;
+  int64_t X;
+  T v;
+  const int64_t gi = t / W3;
+  if (near_candidate3(A, gi, (int)(t % W3), X, v))
+    if (okey(v) == A.near_key[X]) atomicMin(&A.near_win[X], (long long)gi);
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 on every lattice
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock3) void k_lattice_init3(DD3<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int o[3];
+  lattice_offset3(blockIdx.x, A.M, o[0], o[1], o[2]);
+  int L[3];
+  for (int a = 0; a < 3; ++a) L[a] = (A.n[a] - 1 - o[a]) / A.M + 1;
+  const int cnt = L[0] * L[1] * L[2];
+  T* u = (T*)smem;
+  __shared__ int sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  const int64_t base = idx3(A.n, o[0], o[1], o[2]);
+  const int gs[3] = {A.M, A.M * A.n[0], A.M * A.n[0] * A.n[1]};
+  int nfree = 0;
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    const int xi = o[0] + p0 * A.M, yi = o[1] + p1 * A.M, zi = o[2] + p2 * A.M;
+    const int64_t X = idx3(A.n, xi, yi, zi);
+    const T g = A.gfull[X];
+    if (!disnan(g)) {
+      u[x] = g;
+      A.W[X] = 0;
+    } else if (A.near_win[X] != 0x7fffffffffffffffll) {
+      u[x] = (T)okey_dec(A.near_key[X]);
+      const int64_t gg = A.gidx[A.near_win[X]];
+      const int gx = (int)(gg % A.n[0]), gy = (int)((gg / A.n[0]) % A.n[1]),
+                gz = (int)(gg / ((int64_t)A.n[0] * A.n[1]));
+      const int dx = xi - gx, dy = yi - gy, dz = zi - gz;
+      A.W[X] = wenc3((dx > 0) - (dx < 0), (dy > 0) - (dy < 0), (dz > 0) - (dz < 0));
+    } else {
+      u[x] = pinf<T>();
+      A.W[X] = 0;
+      ++nfree;
+    }
+  }
+  __syncthreads();
+  // nodes fixed by Gamma or by the near-Gamma initialisation are not updated
+  struct Rule {
+    T* u;
+    int L0, L1, L2;
+    const T* gfull;
+    const long long* near_win;
+    const T* rdH;
+    uint8_t* W;
+    int64_t base;
+    int gs0, gs1, gs2;
+    __device__ bool update(int i, int j, int k) const {
+      const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
+      if (!disnan(gfull[X]) || near_win[X] != 0x7fffffffffffffffll) return false;
+      T m[3];
+      int ws[3];
+      gather3(u, L0, L1, L2, i, j, k, m, ws);
+      uint8_t code;
+      const T ut = godunov3<T, true>(m, ws, rdH[X], code);
+      const int x = i + L0 * (j + L1 * k);
+      if (ut < u[x]) {
+        u[x] = ut;
+        W[X] = code;
+        return true;
+      }
+      return false;
+    }
+  } R{u, L[0], L[1], L[2], A.gfull, A.near_win, A.rdH, A.W, base, gs[0], gs[1], gs[2]};
+  const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    A.U[base + (int64_t)p0 * gs[0] + (int64_t)p1 * gs[1] + (int64_t)p2 * gs[2]] = u[x];
+  }
+  for (int of = 32; of > 0; of >>= 1) nfree += __shfl_xor(nfree, of);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)ns);
+}
+
+// ---------------------------------------------------------------------------
+// Steps 2 and 3
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool iface3(int c, int S, int n) { return (c % S == 0) && c > 0 && c < n - 1; }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock3) void k_tile3(DD3<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int L = A.S + 1;
+  const int tile = blockIdx.x;
+  const int T0 = tile % A.P[0], T1 = (tile / A.P[0]) % A.P[1], T2 = tile / (A.P[0] * A.P[1]);
+  const int b0 = T0 * A.S, b1 = T1 * A.S, b2 = T2 * A.S;
+  const int cnt = L * L * L;
+  T* u = (T*)smem;
+  __shared__ int sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  uint8_t* tw = A.tile_w + (int64_t)tile * cnt;
+  int nfree = 0;
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int li = x % L, lj = (x / L) % L, lk = x / (L * L);
+    const int c[3] = {b0 + li, b1 + lj, b2 + lk};
+    const int lc[3] = {li, lj, lk};
+    const int64_t X = idx3(A.n, c[0], c[1], c[2]);
+    const T g = A.gfull[X];
+    T v = pinf<T>();
+    uint8_t wc = 0;
+    if (!disnan(g)) {
+      v = g;
+    } else {
+      ++nfree;
+      bool inflow = false;
+      uint8_t Wc = 0;
+      bool onif = false;
+      for (int a = 0; a < 3; ++a) onif = onif || ((lc[a] == 0 || lc[a] == A.S) && iface3(c[a], A.S, A.n[a]));
+      if (onif) {
+        Wc = A.W[X];
+        for (int a = 0; a < 3; ++a) {
+          if (!iface3(c[a], A.S, A.n[a])) continue;
+          const int we = w_of(Wc, a);
+          if ((lc[a] == 0 && we > 0) || (lc[a] == A.S && we < 0)) inflow = true;
+        }
+      }
+      if (inflow) {
+        v = A.U[X];
+        wc = Wc;
+      }
+    }
+    u[x] = v;
+    tw[x] = wc;
+  }
+  __syncthreads();
+  MinRule3<T, false> R;
+  R.u = u; R.L0 = L; R.L1 = L; R.L2 = L;
+  R.rd_g = A.rdh;
+  R.w_g = tw;
+  R.base = idx3(A.n, b0, b1, b2);
+  R.gs[0] = 1; R.gs[1] = A.n[0]; R.gs[2] = A.n[0] * A.n[1];
+  R.wbase = 0;
+  R.ws_[0] = 1; R.ws_[1] = L; R.ws_[2] = L * L;
+  const int ns = fsm3(R, L, L, L, A.max_fine_sweeps);
+  const int F = L * L;
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int li = x % L, lj = (x / L) % L, lk = x / (L * L);
+    const int c[3] = {b0 + li, b1 + lj, b2 + lk};
+    const int lc[3] = {li, lj, lk};
+    const int64_t X = idx3(A.n, c[0], c[1], c[2]);
+    const T v = u[x];
+    const uint8_t wc = tw[x];
+    bool onif = false;
+    for (int a = 0; a < 3; ++a) onif = onif || ((lc[a] == 0 || lc[a] == A.S) && iface3(c[a], A.S, A.n[a]));
+    if (!onif) {
+      A.u_out[X] = v;
+      if (coarse3(c[0], c[1], c[2], A.M)) {
+        A.uk[X] = v;
+        A.wk[X] = wc;
+      }
+    }
+    // faces: 0/1 = x low/high (index lj + L*lk), 2/3 = y (li + L*lk), 4/5 = z (li + L*lj)
+    const int64_t fb = (int64_t)tile * 6 * F;
+    if (li == 0) { A.face_u[fb + 0 * F + lj + L * lk] = v; A.face_w[fb + 0 * F + lj + L * lk] = wc; }
+    if (li == A.S) { A.face_u[fb + 1 * F + lj + L * lk] = v; A.face_w[fb + 1 * F + lj + L * lk] = wc; }
+    if (lj == 0) { A.face_u[fb + 2 * F + li + L * lk] = v; A.face_w[fb + 2 * F + li + L * lk] = wc; }
+    if (lj == A.S) { A.face_u[fb + 3 * F + li + L * lk] = v; A.face_w[fb + 3 * F + li + L * lk] = wc; }
+    if (lk == 0) { A.face_u[fb + 4 * F + li + L * lj] = v; A.face_w[fb + 4 * F + li + L * lj] = wc; }
+    if (lk == A.S) { A.face_u[fb + 5 * F + li + L * lj] = v; A.face_w[fb + 5 * F + li + L * lj] = wc; }
+  }
+  for (int of = 32; of > 0; of >>= 1) nfree += __shfl_xor(nfree, of);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)ns);
+}
+
+// Reconciliation at every interface node (up to 8 candidates: the subdomains
+// containing the node, x slowest, minus side first).
+template <typename T>
+__global__ void k_reconcile3(DD3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int c[3] = {(int)(t % A.n[0]), (int)((t / A.n[0]) % A.n[1]), (int)(t / ((int64_t)A.n[0] * A.n[1]))};
+  bool ifa[3];
+  bool any = false;
+  for (int a = 0; a < 3; ++a) { ifa[a] = iface3(c[a], A.S, A.n[a]); any = any || ifa[a]; }
+  if (!any) return;
+  const int L = A.S + 1, F = L * L;
+  int tl[3][2], ns[3];
+  for (int a = 0; a < 3; ++a) {
+    if (ifa[a]) { tl[a][0] = c[a] / A.S - 1; tl[a][1] = c[a] / A.S; ns[a] = 2; }
+    else { tl[a][0] = min(c[a] / A.S, A.P[a] - 1); tl[a][1] = tl[a][0]; ns[a] = 1; }
+  }
+  T cu[8];
+  uint8_t cw[8];
+  int sd[8][3];
+  int nc = 0;
+  for (int x0 = 0; x0 < ns[0]; ++x0)
+    for (int x1 = 0; x1 < ns[1]; ++x1)
+      for (int x2 = 0; x2 < ns[2]; ++x2) {
+        const int T0 = tl[0][x0], T1 = tl[1][x1], T2 = tl[2][x2];
+        const int tile = T0 + A.P[0] * (T1 + A.P[1] * T2);
+        const int l0 = c[0] - T0 * A.S, l1 = c[1] - T1 * A.S, l2 = c[2] - T2 * A.S;
+        int f, q;
+        if (l0 == 0) { f = 0; q = l1 + L * l2; }
+        else if (l0 == A.S) { f = 1; q = l1 + L * l2; }
+        else if (l1 == 0) { f = 2; q = l0 + L * l2; }
+        else if (l1 == A.S) { f = 3; q = l0 + L * l2; }
+        else if (l2 == 0) { f = 4; q = l0 + L * l1; }
+        else { f = 5; q = l0 + L * l1; }
+        const int64_t e = ((int64_t)tile * 6 + f) * F + q;
+        cu[nc] = A.face_u[e];
+        cw[nc] = A.face_w[e];
+        sd[nc][0] = x0; sd[nc][1] = x1; sd[nc][2] = x2;
+        ++nc;
+      }
+  const uint8_t Wk = A.W[t];
+  const T inf = pinf<T>();
+  bool keep[8];
+  int nf = 0;
+  for (int q = 0; q < nc; ++q) { keep[q] = cu[q] < inf; nf += keep[q]; }
+  if (nf == 0)
+    for (int q = 0; q < nc; ++q) keep[q] = true;
+  int allow[3] = {3, 3, 3};
+  for (int a = 0; a < 3; ++a) {
+    if (!ifa[a]) continue;
+    bool le = w_of(Wk, a) <= 0, ge = w_of(Wk, a) >= 0;
+    for (int q = 0; q < nc; ++q)
+      if (keep[q]) { le = le && w_of(cw[q], a) <= 0; ge = ge && w_of(cw[q], a) >= 0; }
+    if (le) allow[a] = 2; else if (ge) allow[a] = 1;
+  }
+  int best = -1;
+  for (int q = 0; q < nc; ++q) {
+    if (!keep[q]) continue;
+    bool ok = true;
+    for (int a = 0; a < 3; ++a)
+      if (ifa[a] && !((allow[a] >> sd[q][a]) & 1)) ok = false;
+    if (!ok) continue;
+    if (best < 0 || cu[q] < cu[best]) best = q;
+  }
+  if (best < 0)
+    for (int q = 0; q < nc; ++q)
+      if (keep[q] && (best < 0 || cu[q] < cu[best])) best = q;
+  A.u_out[t] = cu[best];
+  if (coarse3(c[0], c[1], c[2], A.M)) {
+    A.uk[t] = cu[best];
+    A.wk[t] = cw[best];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 4
+// ---------------------------------------------------------------------------
+
+// C^k = C_H(nbrs^H(U^k)) at every coarse node and the condition mask:
+// bits 3a..3a+2 = allowed values -1, 0, +1 of component a of W~ (all three
+// when a is not a normal axis of the node), bit 9 = C^k finite.
+template <typename T>
+__global__ void k_ck3(DD3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int c[3] = {(int)(t % A.n[0]), (int)((t / A.n[0]) % A.n[1]), (int)(t / ((int64_t)A.n[0] * A.n[1]))};
+  if (!coarse3(c[0], c[1], c[2], A.M)) return;
+  const T inf = pinf<T>();
+  const int64_t st[3] = {A.M, (int64_t)A.M * A.n[0], (int64_t)A.M * A.n[0] * A.n[1]};
+  T m[3];
+  int ws[3];
+  for (int a = 0; a < 3; ++a) {
+    const T lo = c[a] - A.M >= 0 ? A.U[t - st[a]] : inf;
+    const T hi = c[a] + A.M <= A.n[a] - 1 ? A.U[t + st[a]] : inf;
+    const bool lt = lo < hi;
+    m[a] = lt ? lo : hi;
+    ws[a] = lt ? 1 : -1;
+  }
+  uint8_t code;
+  const T rd = A.r[t] * A.HT;
+  const T v = godunov3<T, true>(m, ws, rd, code);
+  A.ck[t] = v;
+  const uint8_t wk = A.wk[t], Wk = A.W[t];
+  uint16_t mask = dfinite(v) ? (uint16_t)512 : (uint16_t)0;
+  for (int a = 0; a < 3; ++a) {
+    int bits = 7;
+    if (c[a] % A.M == 0) {
+      const int q = w_of(wk, a), r = w_of(Wk, a);
+      const bool le = q <= 0 && r <= 0, ge = q >= 0 && r >= 0;
+      bits = (le ? 1 : 0) | ((le || ge) ? 2 : 0) | (ge ? 4 : 0);
+    }
+    mask |= (uint16_t)(bits << (3 * a));
+  }
+  A.mk[t] = mask;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int o[3];
+  lattice_offset3(blockIdx.x, A.M, o[0], o[1], o[2]);
+  int L[3];
+  for (int a = 0; a < 3; ++a) L[a] = (A.n[a] - 1 - o[a]) / A.M + 1;
+  const int cnt = L[0] * L[1] * L[2];
+  T* u = (T*)smem;
+  __shared__ int sh_free;
+  if (threadIdx.x == 0) sh_free = 0;
+  const int64_t base = idx3(A.n, o[0], o[1], o[2]);
+  const int gs[3] = {A.M, A.M * A.n[0], A.M * A.n[0] * A.n[1]};
+  int nfree = 0;
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    const int64_t X = base + (int64_t)p0 * gs[0] + (int64_t)p1 * gs[1] + (int64_t)p2 * gs[2];
+    const T g = A.gfull[X];
+    if (!disnan(g)) u[x] = g; else { u[x] = pinf<T>(); ++nfree; }
+  }
+  __syncthreads();
+  struct Rule {
+    T* u;
+    int L0, L1, L2;
+    const T* gfull;
+    const T* rdH;
+    const uint16_t* mk;
+    const T* uk;
+    const T* ck;
+    T theta;
+    int64_t base;
+    int gs0, gs1, gs2;
+    __device__ bool update(int i, int j, int k) const {
+      const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
+      if (!disnan(gfull[X])) return false;
+      T m[3];
+      int ws[3];
+      gather3(u, L0, L1, L2, i, j, k, m, ws);
+      uint8_t code;
+      const T ut = godunov3<T, true>(m, ws, rdH[X], code);
+      const unsigned mask = mk[X];
+      bool cond = dfinite(ut) && (mask & 512u);
+      for (int a = 0; a < 3; ++a) cond = cond && ((mask >> (3 * a + w_of(code, a) + 1)) & 1u);
+      const T ukx = uk[X];
+      const T v = cond ? ukx + theta * (ut - ck[X]) : ukx;
+      const int x = i + L0 * (j + L1 * k);
+      if (v != u[x]) {
+        u[x] = v;
+        return true;
+      }
+      return false;
+    }
+  } R{u, L[0], L[1], L[2], A.gfull, A.rdH, A.mk, A.uk, A.ck, A.theta, base, gs[0], gs[1], gs[2]};
+  const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    const int64_t X = base + (int64_t)p0 * gs[0] + (int64_t)p1 * gs[1] + (int64_t)p2 * gs[2];
+    A.Un[X] = u[x];
+    A.Wn[X] = disnan(A.gfull[X]) ? A.wk[X] : (uint8_t)0;
+  }
+  for (int of = 32; of > 0; of >>= 1) nfree += __shfl_xor(nfree, of);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)ns);
+}
+
+// ---------------------------------------------------------------------------
+// causal sweep: coarse-cell wavefront
+//
+// Cell (I, J, K) owns the coarse nodes with coordinates in [IM, IM+M) x
+// [JM, JM+M) x [KM, KM+M) (its three low faces).  In sweep direction s a node
+// X takes V(X) = max(U(X), old U(X + s_e e) for the axes where W_e = -s_e),
+// then U_new(X) = max(V(X), U_new(X - s_e e) for the axes where W_e = s_e),
+// each comparison only with a coarse fine neighbour.  A link X - s_e e lies
+// in the same cell or in an upwind cell, so cells are processed one coarse
+// anti-diagonal per launch and, inside a cell, node levels a'+b'+c' in order.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* W, int dir, int diag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
+  const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
+  // blockIdx.x enumerates the cells (in sweep coordinates) with I'+J'+K' = diag
+  int rem = blockIdx.x;
+  int Iq = -1, Jq = -1, Kq = -1;
+  for (int i = max(0, diag - (CN[1] - 1) - (CN[2] - 1)); i <= min(diag, CN[0] - 1); ++i) {
+    const int r2 = diag - i;
+    const int jlo = max(0, r2 - (CN[2] - 1)), jhi = min(r2, CN[1] - 1);
+    const int cntj = jhi - jlo + 1;
+    if (cntj <= 0) continue;
+    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; break; }
+    rem -= cntj;
+  }
+  if (Iq < 0) return;
+  const int C[3] = {s[0] > 0 ? Iq : CN[0] - 1 - Iq, s[1] > 0 ? Jq : CN[1] - 1 - Jq, s[2] > 0 ? Kq : CN[2] - 1 - Kq};
+  const int M = A.M;
+  int E[3];  // cell extent along each axis (the last cell holds the far boundary plane only)
+  for (int a = 0; a < 3; ++a) E[a] = min(M, A.n[a] - C[a] * M);
+  T* val = (T*)smem;  // E0*E1*E2 values, local index a + E0*(b + E1*c)
+  const int cnt = E[0] * E[1] * E[2];
+  const int64_t st[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
+  // V for the owned nodes (old values)
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
+    if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
+    const int c[3] = {C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2]};
+    const int64_t X = idx3(A.n, c[0], c[1], c[2]);
+    T v = U[X];
+    if (disnan(A.gfull[X])) {
+      const uint8_t wc = W[X];
+      for (int a = 0; a < 3; ++a) {
+        if (w_of(wc, a) != -s[a]) continue;
+        int cn[3] = {c[0], c[1], c[2]};
+        cn[a] += s[a];
+        if (cn[a] < 0 || cn[a] >= A.n[a] || !coarse3(cn[0], cn[1], cn[2], M)) continue;
+        v = vmax(v, U[X + s[a] * st[a]]);
+      }
+    }
+    val[x] = v;
+  }
+  __syncthreads();
+  const int nlev = (E[0] - 1) + (E[1] - 1) + (E[2] - 1);
+  for (int lev = 0; lev <= nlev; ++lev) {
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+      const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
+      if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
+      int lq = 0;
+      for (int a = 0; a < 3; ++a) lq += s[a] > 0 ? l[a] : E[a] - 1 - l[a];
+      if (lq != lev) continue;
+      const int c[3] = {C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2]};
+      const int64_t X = idx3(A.n, c[0], c[1], c[2]);
+      if (!disnan(A.gfull[X])) continue;
+      const uint8_t wc = W[X];
+      T v = val[x];
+      for (int a = 0; a < 3; ++a) {
+        if (w_of(wc, a) != s[a]) continue;
+        int cn[3] = {c[0], c[1], c[2]};
+        cn[a] -= s[a];
+        if (cn[a] < 0 || cn[a] >= A.n[a] || !coarse3(cn[0], cn[1], cn[2], M)) continue;
+        const int la = l[a] - s[a];
+        T pv;
+        if (la >= 0 && la < E[a]) {
+          int ll[3] = {l[0], l[1], l[2]};
+          ll[a] = la;
+          pv = val[ll[0] + E[0] * (ll[1] + E[1] * ll[2])];
+        } else {
+          pv = U[X - s[a] * st[a]];  // finished by an upwind cell
+        }
+        v = vmax(v, pv);
+      }
+      val[x] = v;
+    }
+    __syncthreads();
+  }
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
+    if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
+    U[idx3(A.n, C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2])] = val[x];
+  }
+}
+
+// max |Un - U| over the coarse nodes
+template <typename T>
+__global__ void k_residual3(DD3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double dv = 0.0;
+  if (t < N) {
+    const int c0 = (int)(t % A.n[0]), c1 = (int)((t / A.n[0]) % A.n[1]), c2 = (int)(t / ((int64_t)A.n[0] * A.n[1]));
+    if (coarse3(c0, c1, c2, A.M)) {
+      const T a = A.Un[t], b = A.U[t];
+      if (!(a == b)) dv = dabs((double)a - (double)b);
+      if (disnan(dv)) dv = __builtin_huge_val();
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(dv, o);
+    dv = dv < v ? v : dv;
+  }
+  if ((threadIdx.x & 63) == 0 && dv > 0.0)
+    atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(dv));
+}
+
+template <typename T>
+__global__ void k_skel3(DD3<T> A, const T* src, T* dst) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int c0 = (int)(t % A.n[0]), c1 = (int)((t / A.n[0]) % A.n[1]), c2 = (int)(t / ((int64_t)A.n[0] * A.n[1]));
+  dst[t] = coarse3(c0, c1, c2, A.M) ? src[t] : T(__builtin_nan(""));
+}
+
+}  // namespace eik

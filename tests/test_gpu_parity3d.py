@@ -1,0 +1,163 @@
+"""GPU parity in three dimensions: eik_dd_solve with d = 3 through the C ABI
+against the CPU oracle on the same seeded inputs.
+
+The 3D kernels evaluate the oracle's expressions in the oracle's order (no
+FMA contraction, correctly rounded sqrt and division), sweep boxes by
+hyperplanes i+j+k = t (the same Gauss-Seidel dependencies as the
+lexicographic loop nest) and run the causal sweep as a coarse-cell wavefront
+with the same read-before/read-after pattern, so every iterate must be
+bit-identical to the oracle built in the same precision."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_04198_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1805_04198_amd as E  # noqa: E402
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def gpu_inputs(p, dtype):
+    r = dev(p.r.astype(dtype), dtype)
+    gi = torch.from_numpy(p.gamma_idx.astype(np.int64)).cuda()
+    gv = dev(p.gamma_val.astype(dtype), dtype)
+    return r, gi, gv
+
+
+def same(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return a.shape == b.shape and np.array_equal(a, b, equal_nan=True)
+
+
+def show_diff(name, g, o):
+    g = np.asarray(g).reshape(-1)
+    o = np.asarray(o).reshape(-1)
+    if g.dtype.kind == "f":
+        bad = np.nonzero(~((g == o) | (np.isnan(g) & np.isnan(o))))[0]
+    else:
+        bad = np.nonzero(g != o)[0]
+    return f"{name}: {len(bad)} mismatches, first {bad[:5]} gpu={g[bad[:5]]} oracle={o[bad[:5]]}"
+
+
+def run_pair(p, dtype, theta, max_iter, tol=0.0):
+    r, gi, gv = gpu_inputs(p, dtype)
+    G = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=theta, tol=tol, max_iter=max_iter, debug=True)
+    O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=tol,
+                  max_iter=max_iter, dtype=dtype)
+    return G, O
+
+
+def compare(G, O):
+    U = G["U"].cpu().numpy().reshape(-1)
+    assert same(U, O["U"]), show_diff("U", U, O["U"])
+    Wg = E.decode_winds(G["W"].cpu().numpy(), 3)
+    assert same(Wg, O["W"]), show_diff("W", Wg, O["W"])
+    if O["iterations"] > 0:
+        m = ~np.isnan(O["U"])
+        uk = G["uk"].cpu().numpy().reshape(-1)
+        assert same(uk[m], O["uk"][m]), show_diff("uk", uk[m], O["uk"][m])
+        wk = E.decode_winds(G["wk"].cpu().numpy(), 3)
+        assert same(wk[:, m], O["wk"][:, m]), show_diff("wk", wk[:, m], O["wk"][:, m])
+        up = G["Upre"].cpu().numpy().reshape(-1)
+        assert same(up[m], O["Upre"][m]), show_diff("Upre", up[m], O["Upre"][m])
+        u = G["u"].cpu().numpy().reshape(-1)
+        assert same(u, O["u"]), show_diff("u", u, O["u"])
+    assert G["iterations"] == O["iterations"]
+    assert G["fine_updates"] == O["fine_updates"]
+    assert G["coarse_updates"] == O["coarse_updates"]
+
+
+# n is (nx, ny, nz); the arrays are shaped (nz, ny, nx)
+DD3_CASES = [
+    dict(seed=30, n=(17, 17, 17), S=8, M=4, nsrc=1, kind="fourier", theta=0.5),
+    dict(seed=31, n=(25, 17, 33), S=8, M=4, nsrc=2, kind="blocks", theta=0.3),   # ragged tile counts
+    dict(seed=32, n=(33, 33, 33), S=16, M=8, nsrc=3, kind="const", theta=0.25),
+    dict(seed=33, n=(33, 33, 33), S=32, M=8, nsrc=1, kind="fourier", theta=0.5),  # one 33^3 subdomain
+    dict(seed=34, n=(17, 33, 17), S=16, M=2, nsrc=2, kind="fourier", theta=0.0),  # 7 lattices
+    dict(seed=35, n=(17, 17, 17), S=8, M=4, nsrc=0, kind="blocks", theta=0.5, edge=0),
+    dict(seed=36, n=(9, 9, 41), S=8, M=8, nsrc=1, kind="fourier", theta=0.7),   # a column of tiles
+]
+
+
+def lds_fits(c, dtype):
+    L = c["S"] + 1
+    Lat = max((v - 1) // c["M"] for v in c["n"]) + 1
+    return max(L, Lat) <= 34 and max(L, Lat) ** 3 * np.dtype(dtype).itemsize <= 160 * 1024
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("ci", range(len(DD3_CASES)))
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_dd3_iterates_bitwise(ci, k, dtype):
+    c = DD3_CASES[ci]
+    p = W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=c["nsrc"] or 1, kind=c["kind"],
+                         edge=c.get("edge"))
+    print(f"dd3 case={c} k={k} dtype={np.dtype(dtype).name}", flush=True)
+    if not lds_fits(c, dtype):
+        r, gi, gv = gpu_inputs(p, dtype)
+        with pytest.raises(E.EikError) as ei:
+            E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=c["theta"], tol=0.0, max_iter=k)
+        assert ei.value.status == E.EIK_ERR_UNSUPPORTED
+        return
+    G, O = run_pair(p, dtype, c["theta"], k)
+    compare(G, O)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_dd3_to_convergence(dtype):
+    p = W.random_problem(40, (33, 33, 33), 16, 8, n_src=2, kind="fourier")
+    tol = 1e-6 if dtype == np.float32 else 1e-12
+    print(f"dd3 converge dtype={np.dtype(dtype).name}", flush=True)
+    G, O = run_pair(p, dtype, 0.25, 200, tol=tol)
+    assert O["converged"] and G["converged"]
+    compare(G, O)
+    assert np.array_equal(G["residuals"], O["residuals"])
+    # the converged DD solution against the fp64 overall fine solution u^f,
+    # at the stated gate (1e-10 max u in fp64, 2e-5 max u in fp32)
+    uf, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
+    u = G["u"].cpu().numpy().reshape(-1).astype(np.float64)
+    bound = (1e-10 if dtype == np.float64 else 2e-5) * np.max(uf)
+    assert np.max(np.abs(u - uf)) <= bound
+
+
+def test_dd3_resume_matches_uninterrupted():
+    p = W.random_problem(41, (17, 17, 17), 8, 4, n_src=2)
+    r, gi, gv = gpu_inputs(p, np.float64)
+    full = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=5)
+    part = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=3)
+    rest = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.3, tol=0.0, max_iter=2,
+                      U_init=part["U"], W_init=part["W"])
+    assert torch.equal(torch.nan_to_num(full["U"], nan=-1.0), torch.nan_to_num(rest["U"], nan=-1.0))
+    assert torch.equal(full["W"], rest["W"])
+    assert torch.equal(full["u"], rest["u"])
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(S=12, M=4), E.EIK_ERR_SHAPE),
+    (dict(S=16, M=1), E.EIK_ERR_SHAPE),
+    (dict(theta=-0.5), E.EIK_ERR_ARG),
+    (dict(S=64, M=8), E.EIK_ERR_UNSUPPORTED),    # 65^3 subdomain does not fit in LDS
+])
+def test_dd3_error_paths(kw, status):
+    p = W.random_problem(42, (65, 65, 65), 16, 8)
+    r, gi, gv = gpu_inputs(p, np.float32)
+    args = dict(S=p.S, M=p.M, theta=0.5)
+    args.update(kw)
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve(r, gi, gv, p.h, args["S"], args["M"], theta=args["theta"], max_iter=1)
+    assert ei.value.status == status
+
+
+def test_solve3_is_unsupported():
+    p = W.random_problem(43, (9, 9, 9), 8, 4)
+    r, gi, gv = gpu_inputs(p, np.float64)
+    with pytest.raises(E.EikError) as ei:
+        E.solve(r, gi, gv, p.h)
+    assert ei.value.status == E.EIK_ERR_UNSUPPORTED

@@ -109,8 +109,11 @@ def test_planar_front_is_exact_from_the_start():
     r = np.ones((65, 65))
     gi = np.array(sorted(W.linear_index(n, 0, j) for j in range(65)))
     uf, _ = oracle.fsm(n, h, r, gi, np.zeros(65))
+    # Step 4 sweeps run to stationarity here (no cap): the pin is about the
+    # method, and at theta = 0.9 a capped Step 4 stops before its fixed point
     for theta in (0.0, 0.5, 0.9):
-        R = oracle.dd(n, h, r, gi, np.zeros(65), 16, 8, theta=theta, tol=1e-14, max_iter=10)
+        R = oracle.dd(n, h, r, gi, np.zeros(65), 16, 8, theta=theta, tol=1e-14, max_iter=10,
+                      max_coarse_sweeps=1000)
         assert R["converged"] and R["iterations"] == 1
         assert np.max(np.abs(R["u"] - uf)) <= 4 * EPS
 
