@@ -345,7 +345,7 @@ template <typename T>
 void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
   const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
   const int ndiag = CN[0] + CN[1] + CN[2] - 2;
-  const size_t lds = (size_t)A.M * A.M * A.M * sizeof(T);
+  const size_t lds = eik::causal3_lds<T>(A.M);
   for (int dir = 0; dir < 8; ++dir)
     for (int d = 0; d < ndiag; ++d) {
       const int nc = cells_on_diag(CN, d);
@@ -371,7 +371,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     return fail(EIK_ERR_UNSUPPORTED, "3D boxes are limited to %d nodes per axis", eik::kMaxL3);
   const size_t lds_tile = (size_t)L * L * L * szT;
   const size_t lds_lat = (size_t)(NC[0] + 1) * (NC[1] + 1) * (NC[2] + 1) * szT;
-  const size_t lds_cell = (size_t)M * M * M * szT;
+  const size_t lds_cell = eik::causal3_lds<T>(M);
   if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cell > kLdsBytes)
     return fail(EIK_ERR_UNSUPPORTED, "3D box does not fit in LDS in this precision");
   if (!(o->theta >= 0.0 && o->theta <= 1.0)) return fail(EIK_ERR_ARG, "theta must lie in [0,1]");
@@ -492,7 +492,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
     causal_sweep3(A, A.Un, A.Wn, s);
     HIPCHK(hipMemsetAsync(&A.counters[2], 0, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(eik::k_residual3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+    hipLaunchKernelGGL(eik::k_residual3<T>, dim3(std::min(nblocks(N, bs), 2048u)), dim3(bs), 0, s, A);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -542,6 +542,101 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     st->ms_causal = ms_causal;
   }
   if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
+  return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// eik_solve, d = 3
+// ---------------------------------------------------------------------------
+
+template <typename T>
+eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int32_t max_sweeps,
+                    void* u_outv, int8_t* wind_out, eik_stats* st, hipStream_t s) {
+  int n[3];
+  for (int a = 0; a < 3; ++a) n[a] = (int)G->n[a];
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  if (max_sweeps < 1) return fail(EIK_ERR_ARG, "max_sweeps must be >= 1");
+  const size_t szT = sizeof(T);
+  // largest box side that fits in LDS, then even box sides per axis
+  int Bmax = eik::kMaxL3;
+  while ((size_t)Bmax * Bmax * Bmax * szT > kLdsBytes) --Bmax;
+  int B = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int nb = (n[a] + Bmax - 1) / Bmax;
+    B = std::max(B, (n[a] + nb - 1) / nb);
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  size_t need = N * szT + 256 + (wind_out ? 0 : N + 256) + 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::GS3<T> A;
+  for (int a = 0; a < 3; ++a) { A.n[a] = n[a]; A.nb[a] = (n[a] + B - 1) / B; }
+  A.B = B;
+  A.hT = (T)G->h;
+  A.r = as<T>(rv);
+  T* gfull = cv.take<T>(N);
+  A.gfull = gfull;
+  A.u = as<T>(u_outv);
+  A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(N);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  A.changed = dflag + 1;
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  const size_t lds = (size_t)B * B * B * szT;
+  if ((e = allow_lds(eik::k_grid_sweep3<T>, lds)) != EIK_OK) return e;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  const int bs = 256;
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, (T)NAN, N);
+  if (gam->count > 0)
+    hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
+                       gam->idx, as<T>(gam->g), gam->count);
+  hipLaunchKernelGGL(eik::k_grid_init3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  HIPCHK(hipGetLastError());
+  const int ndiag = A.nb[0] + A.nb[1] + A.nb[2] - 2;
+  int sw = 0, conv = 0;
+  while (sw < max_sweeps) {
+    const int dir = sw & 7;
+    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
+    for (int d = 0; d < ndiag; ++d)
+      hipLaunchKernelGGL(eik::k_grid_sweep3<T>, dim3(cells_on_diag(A.nb, d)), dim3(eik::kBlock3), lds, s, A,
+                         dir, d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++sw;
+    if (*(unsigned int*)host == 0) {
+      conv = 1;
+      break;
+    }
+  }
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    st->iterations = 0;
+    st->converged = conv;
+    st->sweeps = sw;
+    st->fine_updates = (int64_t)sw * (N - gam->count);
+    st->coarse_updates = 0;
+    st->final_residual = 0.0;
+    st->ms_total = ms;
+    st->ms_fine = ms;
+    st->ms_coarse = 0.f;
+    st->ms_correct = 0.f;
+    st->ms_causal = 0.f;
+  }
+  if (!conv) return fail(EIK_ERR_NOCONV, "no stationary sweep within %d sweeps", max_sweeps);
   return EIK_OK;
 }
 
@@ -657,8 +752,11 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
                      void* u_out, int8_t* wind_out, eik_stats* stats, void* hip_stream) {
   eik_status e = check_common(grid, r, gamma, u_out);
   if (e != EIK_OK) return e;
-  if (grid->dim == 3) return fail(EIK_ERR_UNSUPPORTED, "eik_solve: d = 3 is not implemented in this build");
   hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dim == 3) {
+    if (grid->dtype == EIK_F32) return solve3_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
+    return solve3_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
+  }
   if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
   return solve_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
 }

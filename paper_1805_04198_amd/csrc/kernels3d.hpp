@@ -29,7 +29,10 @@
 namespace eik {
 
 constexpr int kBlock3 = 1024;
-constexpr int kMaxL3 = 34;  // nodes per axis of a 3D box held in LDS (fp32)
+// nodes per axis of a 3D box held in LDS (fp32); sweep3 relies on kMaxL3^2 <=
+// 2 * kBlock3 (at most two pencils per thread)
+constexpr int kMaxL3 = 34;
+static_assert(kMaxL3 * kMaxL3 <= 2 * kBlock3, "sweep3 gives each thread at most two pencils");
 
 
 __device__ __forceinline__ int w_of(uint8_t c, int a) { int v = (c >> (2 * a)) & 3; return v == 3 ? -1 : v; }
@@ -149,24 +152,48 @@ __device__ __forceinline__ void lattice_offset3(int q, int M, int& o0, int& o1, 
 // ---------------------------------------------------------------------------
 
 // One directional sweep over an L0 x L1 x L2 box in LDS (index i + L0*(j +
-// L1*k)); returns true (block-wide) if any value changed.
+// L1*k)); returns true (block-wide) if any value changed.  A thread owns at
+// most two pencils (L1*L2 <= 2*blockDim); the read-only inputs of the node a
+// pencil reaches at step t+1 (Rule::load) are fetched before the update of
+// step t, so their global-memory latency overlaps a step.
 template <typename Rule>
 __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir) {
+  using In = typename Rule::In;
   const int sx = (dir & 4) ? 1 : -1, sy = (dir & 2) ? 1 : -1, sz = (dir & 1) ? 1 : -1;
   const int nsteps = L0 + L1 + L2 - 2;
   const int np = L1 * L2;
+  int jq[2], kq[2], jj[2], kk[2];
+  bool has[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int p = threadIdx.x + q * blockDim.x;
+    has[q] = p < np;
+    jq[q] = has[q] ? p % L1 : 0;
+    kq[q] = has[q] ? p / L1 : 0;
+    jj[q] = sy > 0 ? jq[q] : L1 - 1 - jq[q];
+    kk[q] = sz > 0 ? kq[q] : L2 - 1 - kq[q];
+  }
+  In cur[2], nxt[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int iq = -jq[q] - kq[q];
+    if (has[q] && iq >= 0 && iq < L0) cur[q] = R.load(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q]);
+  }
   int changed = 0;
   for (int t = 0; t < nsteps; ++t) {
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-      const int jq = p % L1, kq = p / L1;
-      const int iq = t - jq - kq;
-      if (iq < 0 || iq >= L0) continue;
-      const int i = sx > 0 ? iq : L0 - 1 - iq;
-      const int j = sy > 0 ? jq : L1 - 1 - jq;
-      const int k = sz > 0 ? kq : L2 - 1 - kq;
-      changed |= R.update(i, j, k) ? 1 : 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int iq = t + 1 - jq[q] - kq[q];
+      if (has[q] && iq >= 0 && iq < L0) nxt[q] = R.load(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int iq = t - jq[q] - kq[q];
+      if (has[q] && iq >= 0 && iq < L0) changed |= R.update(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q], cur[q]) ? 1 : 0;
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) cur[q] = nxt[q];
   }
   return __syncthreads_or(changed) != 0;
 }
@@ -216,8 +243,14 @@ struct MinRule3 {
   int gs[3];           // global strides of the box axes
   int64_t wbase;       // index of box node (0,0,0) in w_g
   int ws_[3];          // strides of the box axes in w_g
-  __device__ __forceinline__ bool update(int i, int j, int k) const {
-    const T rd = rd_g[base + (int64_t)i * gs[0] + (int64_t)j * gs[1] + (int64_t)k * gs[2]];
+  struct In {
+    T rd;
+  };
+  __device__ __forceinline__ In load(int i, int j, int k) const {
+    return In{rd_g[base + (int64_t)i * gs[0] + (int64_t)j * gs[1] + (int64_t)k * gs[2]]};
+  }
+  __device__ __forceinline__ bool update(int i, int j, int k, const In& in) const {
+    const T rd = in.rd;
     if (disnan(rd)) return false;
     T m[3];
     int ws[3];
@@ -339,14 +372,22 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_init3(DD3<T> A) {
     uint8_t* W;
     int64_t base;
     int gs0, gs1, gs2;
-    __device__ bool update(int i, int j, int k) const {
+    struct In {
+      T rd;  // NaN: the node is fixed
+    };
+    __device__ In load(int i, int j, int k) const {
       const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
-      if (!disnan(gfull[X]) || near_win[X] != 0x7fffffffffffffffll) return false;
+      const bool fixed = !disnan(gfull[X]) || near_win[X] != 0x7fffffffffffffffll;
+      return In{fixed ? T(__builtin_nan("")) : rdH[X]};
+    }
+    __device__ bool update(int i, int j, int k, const In& in) const {
+      const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
+      if (disnan(in.rd)) return false;
       T m[3];
       int ws[3];
       gather3(u, L0, L1, L2, i, j, k, m, ws);
       uint8_t code;
-      const T ut = godunov3<T, true>(m, ws, rdH[X], code);
+      const T ut = godunov3<T, true>(m, ws, in.rd, code);
       const int x = i + L0 * (j + L1 * k);
       if (ut < u[x]) {
         u[x] = ut;
@@ -610,19 +651,27 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
     T theta;
     int64_t base;
     int gs0, gs1, gs2;
-    __device__ bool update(int i, int j, int k) const {
+    struct In {
+      T rd;   // NaN at Gamma nodes
+      T ukx, ckx;
+      unsigned mask;
+    };
+    __device__ In load(int i, int j, int k) const {
       const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
-      if (!disnan(gfull[X])) return false;
+      return In{rdH[X], uk[X], ck[X], (unsigned)mk[X]};
+    }
+    __device__ bool update(int i, int j, int k, const In& in) const {
+      if (disnan(in.rd)) return false;
       T m[3];
       int ws[3];
       gather3(u, L0, L1, L2, i, j, k, m, ws);
       uint8_t code;
-      const T ut = godunov3<T, true>(m, ws, rdH[X], code);
-      const unsigned mask = mk[X];
+      const T ut = godunov3<T, true>(m, ws, in.rd, code);
+      const unsigned mask = in.mask;
       bool cond = dfinite(ut) && (mask & 512u);
       for (int a = 0; a < 3; ++a) cond = cond && ((mask >> (3 * a + w_of(code, a) + 1)) & 1u);
-      const T ukx = uk[X];
-      const T v = cond ? ukx + theta * (ut - ck[X]) : ukx;
+      const T ukx = in.ukx;
+      const T v = cond ? ukx + theta * (ut - in.ckx) : ukx;
       const int x = i + L0 * (j + L1 * k);
       if (v != u[x]) {
         u[x] = v;
@@ -653,8 +702,32 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
 // then U_new(X) = max(V(X), U_new(X - s_e e) for the axes where W_e = s_e),
 // each comparison only with a coarse fine neighbour.  A link X - s_e e lies
 // in the same cell or in an upwind cell, so cells are processed one coarse
-// anti-diagonal per launch and, inside a cell, node levels a'+b'+c' in order.
+// anti-diagonal per launch.  Links into upwind cells read final values and
+// are folded into V; the links inside the cell are resolved level by level
+// (a'+b'+c' in sweep order) in LDS.  max is exact, so any order that
+// respects the links gives the serial sweep's values.
 // ---------------------------------------------------------------------------
+
+// owned node q of a cell with extents E -> local coordinates: first the face
+// l0 = 0 (E1*E2), then l0 > 0, l1 = 0 ((E0-1)*E2), then l0 > 0, l1 > 0,
+// l2 = 0 ((E0-1)*(E1-1))
+__device__ __forceinline__ void owned_coords(int q, const int (&E)[3], int (&l)[3]) {
+  const int fa = E[1] * E[2], fb = (E[0] - 1) * E[2];
+  if (q < fa) { l[0] = 0; l[1] = q % E[1]; l[2] = q / E[1]; return; }
+  q -= fa;
+  if (q < fb) { l[0] = 1 + q % (E[0] - 1); l[1] = 0; l[2] = q / (E[0] - 1); return; }
+  q -= fb;
+  l[0] = 1 + q % (E[0] - 1);
+  l[1] = 1 + q / (E[0] - 1);
+  l[2] = 0;
+}
+
+__device__ __forceinline__ int owned_index(const int (&l)[3], const int (&E)[3]) {
+  const int fa = E[1] * E[2], fb = (E[0] - 1) * E[2];
+  if (l[0] == 0) return l[1] + E[1] * l[2];
+  if (l[1] == 0) return fa + (l[0] - 1) + (E[0] - 1) * l[2];
+  return fa + fb + (l[0] - 1) + (E[0] - 1) * (l[1] - 1);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* W, int dir, int diag) {
@@ -677,89 +750,103 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
   const int M = A.M;
   int E[3];  // cell extent along each axis (the last cell holds the far boundary plane only)
   for (int a = 0; a < 3; ++a) E[a] = min(M, A.n[a] - C[a] * M);
-  T* val = (T*)smem;  // E0*E1*E2 values, local index a + E0*(b + E1*c)
-  const int cnt = E[0] * E[1] * E[2];
+  const int nown = E[1] * E[2] + (E[0] - 1) * E[2] + (E[0] - 1) * (E[1] - 1);
+  const int cap = 3 * M * M;
+  T* val = (T*)smem;                                   // value per owned node
+  short* pred = (short*)(val + cap);                   // in-cell link per axis, -1 = none
+  uint8_t* lvl = (uint8_t*)(pred + 3 * cap);           // level, 255 = not updated (Gamma)
   const int64_t st[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
-  // V for the owned nodes (old values)
-  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-    const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
-    if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
+  for (int q = threadIdx.x; q < nown; q += blockDim.x) {
+    int l[3];
+    owned_coords(q, E, l);
     const int c[3] = {C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2]};
     const int64_t X = idx3(A.n, c[0], c[1], c[2]);
     T v = U[X];
+    uint8_t lv = 255;
+    short pr[3] = {-1, -1, -1};
     if (disnan(A.gfull[X])) {
       const uint8_t wc = W[X];
       for (int a = 0; a < 3; ++a) {
-        if (w_of(wc, a) != -s[a]) continue;
+        const int wa = w_of(wc, a);
+        if (wa == 0) continue;
+        // old value downwind (W_a = -s_a) or new value upwind (W_a = s_a)
         int cn[3] = {c[0], c[1], c[2]};
-        cn[a] += s[a];
+        cn[a] -= wa;
         if (cn[a] < 0 || cn[a] >= A.n[a] || !coarse3(cn[0], cn[1], cn[2], M)) continue;
-        v = vmax(v, U[X + s[a] * st[a]]);
+        const int la = l[a] - wa;
+        if (wa == s[a] && la >= 0 && la < E[a]) {
+          int ll[3] = {l[0], l[1], l[2]};
+          ll[a] = la;
+          pr[a] = (short)owned_index(ll, E);
+        } else {
+          v = vmax(v, U[X - wa * st[a]]);
+        }
       }
+      int lq = 0;
+      for (int a = 0; a < 3; ++a) lq += s[a] > 0 ? l[a] : E[a] - 1 - l[a];
+      lv = (uint8_t)lq;
     }
-    val[x] = v;
+    val[q] = v;
+    lvl[q] = lv;
+    for (int a = 0; a < 3; ++a) pred[3 * q + a] = pr[a];
   }
   __syncthreads();
   const int nlev = (E[0] - 1) + (E[1] - 1) + (E[2] - 1);
-  for (int lev = 0; lev <= nlev; ++lev) {
-    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-      const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
-      if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
-      int lq = 0;
-      for (int a = 0; a < 3; ++a) lq += s[a] > 0 ? l[a] : E[a] - 1 - l[a];
-      if (lq != lev) continue;
-      const int c[3] = {C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2]};
-      const int64_t X = idx3(A.n, c[0], c[1], c[2]);
-      if (!disnan(A.gfull[X])) continue;
-      const uint8_t wc = W[X];
-      T v = val[x];
+  // level 0 has no in-cell link
+  for (int lev = 1; lev <= nlev; ++lev) {
+    for (int q = threadIdx.x; q < nown; q += blockDim.x) {
+      if (lvl[q] != lev) continue;
+      T v = val[q];
       for (int a = 0; a < 3; ++a) {
-        if (w_of(wc, a) != s[a]) continue;
-        int cn[3] = {c[0], c[1], c[2]};
-        cn[a] -= s[a];
-        if (cn[a] < 0 || cn[a] >= A.n[a] || !coarse3(cn[0], cn[1], cn[2], M)) continue;
-        const int la = l[a] - s[a];
-        T pv;
-        if (la >= 0 && la < E[a]) {
-          int ll[3] = {l[0], l[1], l[2]};
-          ll[a] = la;
-          pv = val[ll[0] + E[0] * (ll[1] + E[1] * ll[2])];
-        } else {
-          pv = U[X - s[a] * st[a]];  // finished by an upwind cell
-        }
-        v = vmax(v, pv);
+        const int pq = pred[3 * q + a];
+        if (pq >= 0) v = vmax(v, val[pq]);
       }
-      val[x] = v;
+      val[q] = v;
     }
     __syncthreads();
   }
-  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
-    const int l[3] = {x % E[0], (x / E[0]) % E[1], x / (E[0] * E[1])};
-    if (l[0] != 0 && l[1] != 0 && l[2] != 0) continue;
-    U[idx3(A.n, C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2])] = val[x];
+  for (int q = threadIdx.x; q < nown; q += blockDim.x) {
+    int l[3];
+    owned_coords(q, E, l);
+    U[idx3(A.n, C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2])] = val[q];
   }
 }
 
-// max |Un - U| over the coarse nodes
+// LDS bytes of k_causal3 for coarse spacing M
 template <typename T>
-__global__ void k_residual3(DD3<T> A) {
+inline size_t causal3_lds(int M) {
+  const size_t cap = (size_t)3 * M * M;
+  return cap * sizeof(T) + 3 * cap * sizeof(short) + cap;
+}
+
+// max |Un - U| over the coarse nodes: grid-stride loop, block maximum, one
+// atomic per block
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual3(DD3<T> A) {
   const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double dv = 0.0;
-  if (t < N) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < N; t += (int64_t)gridDim.x * blockDim.x) {
     const int c0 = (int)(t % A.n[0]), c1 = (int)((t / A.n[0]) % A.n[1]), c2 = (int)(t / ((int64_t)A.n[0] * A.n[1]));
     if (coarse3(c0, c1, c2, A.M)) {
       const T a = A.Un[t], b = A.U[t];
-      if (!(a == b)) dv = dabs((double)a - (double)b);
-      if (disnan(dv)) dv = __builtin_huge_val();
+      double d = 0.0;
+      if (!(a == b)) d = dabs((double)a - (double)b);
+      if (disnan(d)) d = __builtin_huge_val();
+      dv = dv < d ? d : dv;
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
     const double v = __shfl_xor(dv, o);
     dv = dv < v ? v : dv;
   }
-  if ((threadIdx.x & 63) == 0 && dv > 0.0)
-    atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(dv));
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dv;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = m < part[q] ? part[q] : m;
+    if (m > 0.0) atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 template <typename T>
@@ -769,6 +856,128 @@ __global__ void k_skel3(DD3<T> A, const T* src, T* dst) {
   if (t >= N) return;
   const int c0 = (int)(t % A.n[0]), c1 = (int)((t / A.n[0]) % A.n[1]), c2 = (int)(t / ((int64_t)A.n[0] * A.n[1]));
   dst[t] = coarse3(c0, c1, c2, A.M) ? src[t] : T(__builtin_nan(""));
+}
+
+// ---------------------------------------------------------------------------
+// eik_solve, d = 3: the fast sweeping method on the whole grid with the
+// serial sweep's values.  The grid is cut into boxes of at most B^3 nodes;
+// in each directional sweep the boxes are taken one box-diagonal per launch
+// in sweep order, each box swept by one workgroup in LDS with the same
+// hyperplane engine.  Neighbours across a box face are read from global
+// memory: the upwind box finished earlier in this sweep and the downwind box
+// has not started, which is what the lexicographic loop nest sees.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct GS3 {
+  int n[3];
+  int B;           // box side
+  int nb[3];       // boxes per axis
+  T hT;
+  const T* r;
+  const T* gfull;  // Gamma value per node, NaN if not Gamma
+  T* u;
+  uint8_t* w;
+  unsigned int* changed;
+};
+
+template <typename T>
+__global__ void k_grid_init3(GS3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const T g = A.gfull[t];
+  A.u[t] = disnan(g) ? pinf<T>() : g;
+  A.w[t] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int diag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
+  int rem = blockIdx.x;
+  int Iq = -1, Jq = -1, Kq = -1;
+  for (int i = max(0, diag - (A.nb[1] - 1) - (A.nb[2] - 1)); i <= min(diag, A.nb[0] - 1); ++i) {
+    const int r2 = diag - i;
+    const int jlo = max(0, r2 - (A.nb[2] - 1)), jhi = min(r2, A.nb[1] - 1);
+    const int cntj = jhi - jlo + 1;
+    if (cntj <= 0) continue;
+    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; break; }
+    rem -= cntj;
+  }
+  if (Iq < 0) return;
+  const int Tb[3] = {s[0] > 0 ? Iq : A.nb[0] - 1 - Iq, s[1] > 0 ? Jq : A.nb[1] - 1 - Jq,
+                     s[2] > 0 ? Kq : A.nb[2] - 1 - Kq};
+  int o[3], L[3];
+  for (int a = 0; a < 3; ++a) {
+    o[a] = Tb[a] * A.B;
+    L[a] = min(A.B, A.n[a] - o[a]);
+  }
+  const int cnt = L[0] * L[1] * L[2];
+  T* u = (T*)smem;
+  const int64_t base = idx3(A.n, o[0], o[1], o[2]);
+  const int64_t gs1 = A.n[0], gs2 = (int64_t)A.n[0] * A.n[1];
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    u[x] = A.u[base + p0 + p1 * gs1 + p2 * gs2];
+  }
+  __syncthreads();
+  struct Rule {
+    T* u;
+    int L0, L1, L2;
+    const T* ug;
+    const T* gfull;
+    const T* r;
+    uint8_t* w;
+    T hT;
+    int64_t base, gs1, gs2;
+    int lo0, lo1, lo2;   // box has a neighbour box on the minus side
+    int hi0, hi1, hi2;   // ... on the plus side
+    struct In {
+      T rd;  // NaN at Gamma nodes
+    };
+    __device__ In load(int i, int j, int k) const {
+      const int64_t X = base + i + j * gs1 + k * gs2;
+      return In{disnan(gfull[X]) ? r[X] * hT : T(__builtin_nan(""))};
+    }
+    __device__ bool update(int i, int j, int k, const In& in) const {
+      const int64_t X = base + i + j * gs1 + k * gs2;
+      if (disnan(in.rd)) return false;
+      const T inf = pinf<T>();
+      const int x = i + L0 * (j + L1 * k);
+      const int c[3] = {i, j, k};
+      const int L[3] = {L0, L1, L2};
+      const int st[3] = {1, L0, L0 * L1};
+      const int64_t gst[3] = {1, gs1, gs2};
+      const int lo_nb[3] = {lo0, lo1, lo2}, hi_nb[3] = {hi0, hi1, hi2};
+      T m[3];
+      int ws[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T lo = c[a] > 0 ? u[x - st[a]] : (lo_nb[a] ? ug[X - gst[a]] : inf);
+        const T hi = c[a] < L[a] - 1 ? u[x + st[a]] : (hi_nb[a] ? ug[X + gst[a]] : inf);
+        const bool lt = lo < hi;
+        m[a] = lt ? lo : hi;
+        ws[a] = lt ? 1 : -1;
+      }
+      uint8_t code;
+      const T ut = godunov3<T, false>(m, ws, in.rd, code);
+      if (ut < u[x]) {
+        u[x] = ut;
+        w[X] = code;
+        return true;
+      }
+      return false;
+    }
+  } R{u, L[0], L[1], L[2], A.u, A.gfull, A.r, A.w, A.hT, base, gs1, gs2,
+      o[0] > 0, o[1] > 0, o[2] > 0,
+      o[0] + L[0] < A.n[0], o[1] + L[1] < A.n[1], o[2] + L[2] < A.n[2]};
+  const bool ch = sweep3(R, L[0], L[1], L[2], dir);
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    A.u[base + p0 + p1 * gs1 + p2 * gs2] = u[x];
+  }
+  if (ch && threadIdx.x == 0) atomicOr(A.changed, 1u);
 }
 
 }  // namespace eik

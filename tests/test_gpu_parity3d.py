@@ -155,9 +155,32 @@ def test_dd3_error_paths(kw, status):
     assert ei.value.status == status
 
 
-def test_solve3_is_unsupported():
-    p = W.random_problem(43, (9, 9, 9), 8, 4)
-    r, gi, gv = gpu_inputs(p, np.float64)
-    with pytest.raises(E.EikError) as ei:
-        E.solve(r, gi, gv, p.h)
-    assert ei.value.status == E.EIK_ERR_UNSUPPORTED
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("case", [
+    dict(seed=50, n=(17, 17, 17), nsrc=1, kind="fourier"),
+    dict(seed=51, n=(40, 23, 35), nsrc=3, kind="blocks"),     # ragged boxes
+    dict(seed=52, n=(70, 36, 30), nsrc=2, kind="fourier"),    # several boxes per axis in fp32 and fp64
+    dict(seed=53, n=(2, 9, 40), nsrc=1, kind="const"),
+    dict(seed=54, n=(20, 20, 20), nsrc=0, kind="const", edge=2),
+])
+def test_solve3_bitwise(case, dtype):
+    p = W.random_problem(case["seed"], case["n"], 1, 1, n_src=case["nsrc"] or 1, kind=case["kind"],
+                         edge=case.get("edge"))
+    print(f"solve3 case={case} dtype={np.dtype(dtype).name}", flush=True)
+    r, gi, gv = gpu_inputs(p, dtype)
+    u, w, info = E.solve(r, gi, gv, p.h, with_wind=True)
+    uo, wo, io = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, dtype=dtype, with_info=True)
+    ug = u.cpu().numpy().reshape(-1)
+    assert same(ug, uo), show_diff("u", ug, uo)
+    assert info["sweeps"] == io["sweeps"]
+    wg = E.decode_winds(w.cpu().numpy(), 3)
+    assert same(wg, wo), show_diff("w", wg, wo)
+
+
+def test_config3_full_size_first_iteration():
+    """257^3, S = 32, M = 8, fp32: Step 1 and one DD iteration, every array
+    bit-identical to the fp32 oracle."""
+    p = W.config3()
+    print("config3 full size 1 iteration fp32", flush=True)
+    G, O = run_pair(p, np.float32, 0.1, 1)
+    compare(G, O)
