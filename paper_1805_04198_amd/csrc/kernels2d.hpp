@@ -139,6 +139,14 @@ __device__ __forceinline__ T godunov2_sel(T a, T b, T rd, bool& two) {
   return two ? u2 : u1;
 }
 
+// Sweep-order columns of the nodes a lane changed during a sweep (min and
+// max over both rows of lane 0 in a 65-row box), and whether lane 0 changed
+// a node of row 64.
+struct StepSpan {
+  int cmin = 0x7fffffff, cmax = -1;
+  bool rowB = false;
+};
+
 // One directional Gauss-Seidel sweep (signs SX, SY) over an L0 x L1 box in
 // LDS, anti-diagonal order, one lane per row.  Dataflow per step t, lane j
 // (row j in sweep order, column i = t - j):
@@ -155,9 +163,16 @@ __device__ __forceinline__ T godunov2_sel(T a, T b, T rd, bool& two) {
 // them untouched.  The step is branch-free: a lane that is idle or does not
 // lower its node stores to a dummy LDS slot, and the address of a lane moves
 // by SX every step (reads of idle lanes land in the guard bands around each
-// LDS array).  Returns true in lanes that changed a value.
+// LDS array).
+//
+// The sweep may start at step t0 > 0 and end early: the caller guarantees
+// that no node before step t0 can change (the registers that carry values
+// from step to step are then loaded from LDS), and the sweep stops after a
+// step pair at or beyond tmax in which no lane changed a value.  span
+// receives the steps at which each lane changed values.  Returns true in
+// lanes that changed a value.
 template <int SX, int SY, bool EXTRA, typename Rule>
-__device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
+__device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t0, int tmax, StepSpan& span) {
   using T = typename Rule::real;
   using Pre = typename Rule::Pre;
   const T inf = pinf<T>();
@@ -170,9 +185,26 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
   const int xB0 = (jB + 1) * SP + 1 + (SX > 0 ? -(kWave + 1) : L0 - 1 + kWave + 1);
   const bool laneB = EXTRA && lane == 0;
   const bool rowA = lane < L1;
+  auto x_at = [&](int t) { return ((laneB && t > kWave) ? xB0 : xA0) + SX * t; };
+  // the lane's value after step t: its node's value, +inf before its row starts
+  auto value_at = [&](int t) -> T {
+    const bool useB = laneB && t > kWave;
+    const int iq = t - (useB ? kWave + 1 : lane);
+    const bool ok = t >= 0 && (useB || rowA) && (unsigned)iq < (unsigned)L0;
+    const T v = R.value(ok ? x_at(t) : dummy_slot());
+    return ok ? v : inf;
+  };
+  // t0 and tmax are the same in every lane; keep them in scalar registers
+  t0 = __builtin_amdgcn_readfirstlane(t0);
+  tmax = __builtin_amdgcn_readfirstlane(tmax);
   T cur = inf, cur_prev = inf;
+  if (t0 > 0) {
+    cur = value_at(t0 - 1);
+    if (EXTRA) cur_prev = value_at(t0 - 2);
+  }
   bool changed = false;
-  int x = xA0;
+  unsigned long long recent = 0;
+  int x = x_at(t0);
   Pre pa = R.template load<SX, SY>(x), pb;
   // one step; p holds this step's operands, pn receives the next step's
   auto step = [&](int t, const Pre& p, Pre& pn) {
@@ -202,20 +234,98 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP) {
     if (EXTRA) cur_prev = cur;
     cur = act ? v : cur;
     changed = changed || ch;
+    recent |= __ballot(ch);
+    span.cmin = min(span.cmin, ch ? iq : 0x7fffffff);
+    span.cmax = max(span.cmax, ch ? iq : -1);
+    if (EXTRA) span.rowB = span.rowB || (ch && useB);
     x = x1;
   };
   // unrolled by two so that the prefetch buffers alternate without copies;
-  // a trailing step past the end is idle in every lane
-  for (int t = 0; t < nsteps; t += 2) {
+  // a trailing step past the end is idle in every lane.  Up to tmax the
+  // steps run unconditionally; after that the sweep ends with the first step
+  // pair that changes nothing.
+  int t = t0;
+  for (; t + 1 < tmax && t < nsteps; t += 2) {
     step(t, pa, pb);
     step(t + 1, pb, pa);
+  }
+  for (; t < nsteps; t += 2) {
+    recent = 0;
+    step(t, pa, pb);
+    step(t + 1, pb, pa);
+    if (recent == 0) break;
   }
   return changed;
 }
 
+// Axis-aligned box of nodes [i0, i1] x [j0, j1] in box coordinates (i0 > i1:
+// empty).
+struct NodeBox {
+  int i0, i1, j0, j1;
+};
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+// A sweep restricted to what can change.  P holds every node that may change
+// in this sweep without an upwind change inside the sweep (a node whose
+// neighbours kept their values since its last evaluation computes the same
+// candidate again and cannot change).  The sweep starts at the first step
+// that reaches P and runs at least to the last; changes propagate within
+// the sweep until a step pair changes nothing.  On return P holds the nodes
+// next to a change (a superset of those evaluated before a neighbour
+// changed), empty if nothing changed.
+template <int SX, int SY, bool EXTRA, typename Rule>
+__device__ __forceinline__ bool sweep_box(Rule& R, int L0, int L1, int SP, NodeBox& P) {
+  // sweep-order coordinates of the box corners
+  const int qi0 = SX > 0 ? P.i0 : L0 - 1 - P.i1, qi1 = SX > 0 ? P.i1 : L0 - 1 - P.i0;
+  const int qj0 = SY > 0 ? P.j0 : L1 - 1 - P.j1, qj1 = SY > 0 ? P.j1 : L1 - 1 - P.j0;
+  const int t0 = qi0 + qj0;
+  const int tmax = qi1 + qj1 + (EXTRA ? 1 : 0);  // row 64 runs one step late
+  StepSpan sp;
+  const bool ch = sweep_dir<SX, SY, EXTRA>(R, L0, L1, SP, t0, tmax, sp);
+  // changed nodes in sweep-order coordinates
+  const int lane = threadIdx.x;
+  // rows: the lanes that changed a value (lane 0 stands for row 0 even if
+  // only its row 64 changed, which only widens the box), plus row 64
+  const unsigned long long rows = __ballot(ch);
+  const bool rowB = EXTRA && __any(sp.rowB);
+  const int ci0 = wave_min(sp.cmin), ci1 = wave_max(sp.cmax);
+  if (rows == 0) {
+    P.i0 = 1; P.i1 = 0; P.j0 = 1; P.j1 = 0;
+    return ch;
+  }
+  const int cj0 = __builtin_ctzll(rows);
+  const int cj1 = rowB ? kWave : 63 - __builtin_clzll(rows);
+  // back to box coordinates, grown by one node and clipped
+  const int i0 = SX > 0 ? ci0 : L0 - 1 - ci1, i1 = SX > 0 ? ci1 : L0 - 1 - ci0;
+  const int j0 = SY > 0 ? cj0 : L1 - 1 - cj1, j1 = SY > 0 ? cj1 : L1 - 1 - cj0;
+  P.i0 = __builtin_amdgcn_readfirstlane(max(i0 - 1, 0));
+  P.i1 = __builtin_amdgcn_readfirstlane(min(i1 + 1, L0 - 1));
+  P.j0 = max(j0 - 1, 0);
+  P.j1 = min(j1 + 1, L1 - 1);
+  return ch;
+}
+
+template <int SX, int SY, typename Rule>
+__device__ __forceinline__ bool sweep_box2(Rule& R, int L0, int L1, int SP, NodeBox& P) {
+  return (L1 > kWave) ? sweep_box<SX, SY, true>(R, L0, L1, SP, P) : sweep_box<SX, SY, false>(R, L0, L1, SP, P);
+}
+
+// One full directional sweep (used by the whole-grid FSM, one sweep per
+// launch).
 template <int SX, int SY, typename Rule>
 __device__ __forceinline__ bool sweep_dir2(Rule& R, int L0, int L1, int SP) {
-  return (L1 > kWave) ? sweep_dir<SX, SY, true>(R, L0, L1, SP) : sweep_dir<SX, SY, false>(R, L0, L1, SP);
+  StepSpan sp;
+  const int n = L0 + L1;
+  return (L1 > kWave) ? sweep_dir<SX, SY, true>(R, L0, L1, SP, 0, n, sp)
+                      : sweep_dir<SX, SY, false>(R, L0, L1, SP, 0, n, sp);
 }
 
 template <typename Rule>
@@ -229,12 +339,22 @@ __device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int d
 }
 
 // Sweep in the 2^d orders of the paper's loop nest ((-,-), (-,+), (+,-),
-// (+,+), x outermost) until a whole sweep changes nothing, at most max_sweeps.
+// (+,+), x outermost) until a whole sweep changes nothing, at most
+// max_sweeps.  Every node starts out as possibly changing; afterwards each
+// sweep covers only the steps that can change a value (sweep_box), which
+// gives the full sweeps' values, winds and sweep count.
 template <typename Rule>
 __device__ int wave_fsm(Rule& R, int L0, int L1, int SP, int max_sweeps) {
+  NodeBox P{0, L0 - 1, 0, L1 - 1};
   int s = 0;
   while (s < max_sweeps) {
-    bool ch = sweep_any(R, L0, L1, SP, s & 3);
+    bool ch;
+    switch (s & 3) {
+      case 0: ch = sweep_box2<-1, -1>(R, L0, L1, SP, P); break;
+      case 1: ch = sweep_box2<-1, 1>(R, L0, L1, SP, P); break;
+      case 2: ch = sweep_box2<1, -1>(R, L0, L1, SP, P); break;
+      default: ch = sweep_box2<1, 1>(R, L0, L1, SP, P); break;
+    }
     step_fence();
     ++s;
     if (!__any(ch)) break;
@@ -265,6 +385,7 @@ struct MinRule {
   uint8_t* w;
   const T* rd;
   int SP;
+  __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
     Pre p;
@@ -342,6 +463,7 @@ struct CorrectRule {
   const uint8_t* mk;
   T theta;
   int SP;
+  __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
     Pre p;
@@ -1056,6 +1178,7 @@ struct CausalRule {
   T* cu;
   const T* cb;
   const uint8_t* ca;
+  __device__ __forceinline__ T value(int x) const { return cu[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
     Pre p;
