@@ -78,6 +78,32 @@ typedef struct {
     void* U_pre_causal;
 } eik_dd_debug;
 
+/* Weight of the Step 4 correction U = u^k + theta (U~ - C^k) at a node
+ * (Sec. 3.2 lets theta vary per node and iteration; Sec. 4.2 estimates it):
+ *   EIK_THETA_CONSTANT   opts->theta everywhere.
+ *   EIK_THETA_ESTIMATE   eq. secthetaest: t = (u^k - u^{k-1}) / (omega-weighted
+ *                        mean of the increments C_H(U^{k+1-s}) - C_H(U^{k-s}),
+ *                        s = 0, 1, 2; the s = 0 one is U~ - C^k), evaluated as
+ *                        num / ((w0 d0 + (w1 d1 + w2 d2)) / ((w0 + w1) + w2)),
+ *                        then eq. thetaest: [s t + (1 - s) delta t]^+ with
+ *                        s = 1 / (1 + e^{(t - x0)/gamma}).  opts->theta is used
+ *                        until C^{k-2} exists (the first two iterations of a
+ *                        call, also after a resume) and where a term is not
+ *                        finite or the denominator is 0.
+ *   EIK_THETA_REFERENCE  M-bar of Sec. 4.2 minus a margin: (u_ref - u^k) /
+ *                        (U~ - C^k) - margin, clamped at 0 (Sec. 5.4 uses
+ *                        u_ref = u^f and margin 0.001); opts->theta where not
+ *                        defined.
+ *   EIK_THETA_FIELD      theta_ref holds theta per node.
+ * The weight is computed in double from the grid-dtype values; e^x there is
+ * a fixed sequence of double operations (Cody-Waite reduction, Taylor series
+ * to degree 13), so results do not depend on the math library.  Only
+ * the node where the correction applies uses it. */
+#define EIK_THETA_CONSTANT 0
+#define EIK_THETA_ESTIMATE 1
+#define EIK_THETA_REFERENCE 2
+#define EIK_THETA_FIELD 3
+
 /* Options of the domain-decomposition iteration (Sec. 3.2). */
 typedef struct {
     int32_t S;          /* subdomain side in fine cells; (n[a]-1) % S == 0 */
@@ -87,10 +113,14 @@ typedef struct {
     int32_t max_iter;   /* cap on DD iterations (0: only Step 1) */
     int32_t max_fine_sweeps;   /* cap on FSM sweeps per subdomain per iteration (>= 1) */
     int32_t max_coarse_sweeps; /* cap on sweeps per coarse lattice in Steps 1 and 4 (>= 1) */
-    int32_t reserved;
+    int32_t theta_mode;        /* EIK_THETA_*; 0 = constant */
     const void* U_init;        /* optional resume state (device, full grid, grid dtype): U^k ... */
     const int8_t* W_init;      /* ... and W^k codes; both NULL = run Step 1 */
     const eik_dd_debug* debug; /* optional snapshots, NULL = none */
+    const void* theta_ref;     /* device, N, grid dtype: u_ref (REFERENCE) or theta (FIELD); else unused */
+    double theta_params[7];    /* gamma, delta, x0, omega0, omega1, omega2, margin (ESTIMATE and
+                                * REFERENCE; the paper's values are 0.75, 0.01, 0.9, -, -, -, 0.001;
+                                * the omegas are not stated there) */
 } eik_dd_opts;
 
 /* Host-side statistics.  residual_history (host, may be NULL) receives
@@ -142,8 +172,11 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
  *   W_out  device, N int8 codes or NULL: W of the last iterate
  * Resume: passing (U_out, W_out) of a run as opts->U_init/W_init continues
  * it exactly (the iteration reads nothing else).
- * This build: d = 2, subdomain side S+1 <= 65 nodes and lattice extents
- * (n-1)/M + 1 <= 65 (else EIK_ERR_UNSUPPORTED). */
+ * This build: d = 2 with subdomain side S+1 <= 65 nodes and lattice extents
+ * (n-1)/M + 1 <= 65; d = 3 with S+1 <= 34 and (n-1)/M + 1 <= 34 and the box
+ * in 160 KB of LDS ((S+1)^3 values of the grid dtype); with a non-constant
+ * theta_mode in 2D, a 65-node lattice fits only in fp32 (else
+ * EIK_ERR_UNSUPPORTED). */
 eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma,
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);

@@ -69,7 +69,14 @@ def lib():
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp,
                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
-                          vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+                          vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                          ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+            f = getattr(L, "eikref_exp_cw" + sfx)
+            f.restype = ctypes.c_double
+            f.argtypes = [ctypes.c_double]
+            f = getattr(L, "eikref_theta_damped" + sfx)
+            f.restype = ctypes.c_double
+            f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double]
             f = getattr(L, "eikref_local" + sfx)
             f.restype = ctypes.c_int
             rt = ctypes.c_float if sfx == "_f32" else ctypes.c_double
@@ -131,12 +138,24 @@ def fmm(n, h, r, gidx, gval, dtype=np.float64):
     return u
 
 
+THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
+# gamma, delta, x0 of eq. thetaest (Sec. 4.2 figure) and the omega weights
+# of eq. secthetaest (unstated in the paper: equal weights), margin of the
+# reference weight M-bar - 0.001 (Sec. 5.4)
+THETA_PARAMS = (0.75, 0.01, 0.9, 1.0, 1.0, 1.0, 0.001)
+
+
 def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.float64,
-       max_fine_sweeps=256, max_coarse_sweeps=32, U_init=None, W_init=None, hist_cap=4096):
+       max_fine_sweeps=256, max_coarse_sweeps=32, U_init=None, W_init=None, hist_cap=4096,
+       theta_mode="constant", theta_params=THETA_PARAMS, theta_ref=None):
     """The DD iteration of Sec. 3.2.  Returns a dict with the patched fine
     solution u, coarse values U (NaN off the skeleton), coarse winds W (d, N),
     the last iteration's reconciled fine values uk / winds wk, the last
-    corrected U before its causal sweep (Upre), and the counters."""
+    corrected U before its causal sweep (Upre), and the counters.
+    theta_mode selects the Step 4 weight (see theta_node in eikref.c):
+    "constant", "estimate" (eqs. secthetaest, thetaest), "reference"
+    (M-bar minus a margin, theta_ref = u^f) or "field" (theta_ref = theta
+    per node)."""
     d = len(n)
     n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
     N = int(np.prod(n))
@@ -152,11 +171,16 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
     hist = np.zeros(max(1, hist_cap), dtype=np.float64)
     Ui = None if U_init is None else np.ascontiguousarray(np.asarray(U_init, dtype=dtype).reshape(-1))
     Wi = None if W_init is None else np.ascontiguousarray(np.asarray(W_init, dtype=np.int8).reshape(-1))
+    mode = THETA_MODES[theta_mode]
+    tpar = np.ascontiguousarray(np.asarray(theta_params, dtype=np.float64))
+    assert tpar.shape == (7,)
+    tref = None if theta_ref is None else np.ascontiguousarray(np.asarray(theta_ref, dtype=dtype).reshape(-1))
     st = getattr(lib(), "eikref_dd" + _sfx(dtype))(
         d, _i64(n64), float(h), _p(r), len(gidx), _i64(gidx), _p(gval), int(S), int(M),
         float(theta), float(tol), int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps),
         _p(Ui), _p(Wi), _p(u), _p(U), _p(W), _p(uk), _p(wk), _p(Upre), _i64(info),
-        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(hist_cap))
+        hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(hist_cap), int(mode),
+        tpar.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(tref))
     if st not in (0, -3):
         raise ValueError(f"eikref_dd: {STATUS.get(st, st)}")
     it = int(info[0])
@@ -164,6 +188,16 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
             "Upre": Upre, "iterations": it, "converged": bool(info[1]),
             "fine_updates": int(info[2]), "coarse_updates": int(info[3]),
             "status": int(info[4]), "residuals": hist[: min(it, hist_cap)].copy()}
+
+
+def exp_cw(x):
+    """The oracle's fixed-sequence e^x (Cody-Waite reduction + Taylor)."""
+    return lib().eikref_exp_cw_f64(float(x))
+
+
+def theta_damped(tb, gamma=0.75, delta=0.01, x0=0.9):
+    """eq. thetaest applied to an estimate tb."""
+    return lib().eikref_theta_damped_f64(float(tb), float(gamma), float(delta), float(x0))
 
 
 def local(m, ws, rd, rule=0, dtype=np.float64):

@@ -36,6 +36,10 @@
  *                       Alg. fineupdate2D, then Alg. fineupdate), Step 4
  *                       (Alg. 2Dweightedupdate sweeps, then the causal sweep),
  *                       repeated until max|U^{k+1}-U^k| < tol.
+ *   theta_node       -- the weight of the Step 4 correction at one node:
+ *                       constant, the estimate of eqs. secthetaest and
+ *                       thetaest (Sec. 4.2), the reference weight M-bar
+ *                       minus a margin (Sec. 5.4), or a caller field.
  */
 #include <math.h>
 #include <stdint.h>
@@ -502,6 +506,13 @@ typedef struct {
     const real* r;
     unsigned char* isg;   /* Gamma flag per node */
     real* gv;             /* Gamma data per node */
+    /* weight of the Step 4 correction (theta_node) */
+    int theta_mode;       /* 0 constant, 1 estimate, 2 reference, 3 field */
+    double tpar[7];       /* gamma, delta, x0, omega0, omega1, omega2, margin */
+    const real* tref;     /* mode 2: u^f per node; mode 3: theta per node */
+    const real* ukm1;     /* u^{k-1} per node, or NULL before there is one */
+    const real* ckm1;     /* C^{k-1} per node, or NULL */
+    const real* ckm2;     /* C^{k-2} per node, or NULL */
 } ddp;
 
 static void node_coords(const ddp* D, int64_t x, int64_t c[3]) {
@@ -806,6 +817,96 @@ static void reconcile_node(int d, const cand* cs, int nc, const int* iface, cons
     for (int e = 0; e < d; e++) wk[e] = cs[best].w[e];
 }
 
+/* ---- the weight theta of the Step 4 correction ----
+ *
+ * exp_cw: e^x in double by Cody and Waite's range reduction (x = n ln2 + r,
+ * |r| <= ln2/2, with ln2 split into a high part exact in 32 bits and a low
+ * correction, the split used by fdlibm) and the Taylor series of e^r to
+ * r^13 in Horner form.  The logistic damping below needs e^x only to a few
+ * ulp; the point of writing it out is that every step is a fixed sequence
+ * of IEEE double operations.  Arguments below -700 give 0 (then 1 + e^x
+ * rounds to 1 anyway), arguments from 709.78 on give +inf. */
+static double exp_cw(double x) {
+    if (x != x) return x;
+    if (x >= 709.78) return INFINITY;
+    if (x < -700.0) return 0.0;
+    const double inv_ln2 = 0x1.71547652b82fep0;
+    const double ln2_hi = 0x1.62e42feep-1;
+    const double ln2_lo = 0x1.a39ef35793c76p-33;
+    double n = floor(x * inv_ln2 + 0.5);
+    double r = (x - n * ln2_hi) - n * ln2_lo;
+    double p = 1.0 / 6227020800.0;       /* 1/13! */
+    p = p * r + 1.0 / 479001600.0;       /* 1/12! */
+    p = p * r + 1.0 / 39916800.0;        /* 1/11! */
+    p = p * r + 1.0 / 3628800.0;         /* 1/10! */
+    p = p * r + 1.0 / 362880.0;          /* 1/9! */
+    p = p * r + 1.0 / 40320.0;           /* 1/8! */
+    p = p * r + 1.0 / 5040.0;            /* 1/7! */
+    p = p * r + 1.0 / 720.0;             /* 1/6! */
+    p = p * r + 1.0 / 120.0;             /* 1/5! */
+    p = p * r + 1.0 / 24.0;              /* 1/4! */
+    p = p * r + 1.0 / 6.0;               /* 1/3! */
+    p = p * r + 0.5;                     /* 1/2! */
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)n);
+}
+
+/* the damped weight of eq. thetaest: [s(t) t + (1 - s(t)) delta t]^+ with
+ * the logistic s(t) = 1 / (1 + e^{(t - x0)/gamma}) */
+static double theta_damped(double tb, double gamma, double delta, double x0) {
+    double e = exp_cw((tb - x0) / gamma);
+    double sg = 1.0 / (1.0 + e);
+    double th = sg * tb + (1.0 - sg) * (delta * tb);
+    return th > 0.0 ? th : 0.0;
+}
+
+/* Weight at coarse node X given the current lattice candidate Ut (U~, the
+ * coarse solver on the current neighbours, i.e. C_H(nbrs(U^{k+1}))) and
+ * C^k = C_H(nbrs(U^k)).  All in double from the working-precision values.
+ *  mode 0: the constant theta.
+ *  mode 1: eq. secthetaest with the estimate's numerator u^k - u^{k-1} and
+ *          the omega-weighted mean of the last three coarse increments
+ *          C_H(U^{k+1-s}) - C_H(U^{k-s}), s = 0, 1, 2 (the s = 0 increment
+ *          is U~ - C^k, the others come from earlier iterations), then
+ *          eq. thetaest.  Evaluated as t = num / ((w0 d0 + (w1 d1 + w2 d2))
+ *          / (w0 + w1 + w2)).  Until C^{k-2} exists, or when a term is not
+ *          finite or the denominator is 0, the constant theta is used.
+ *  mode 2: M-bar of Sec. 4.2 at this iteration, (u^f - u^k) / (U~ - C^k),
+ *          minus a margin (the paper uses 0.001), clamped at 0; the
+ *          constant theta where it is not defined.
+ *  mode 3: a caller-supplied theta per node. */
+static double theta_node(const ddp* D, int64_t X, real Ut, real Ck, real ukX, double theta) {
+    const double* q = D->tpar;
+    if (D->theta_mode == 1) {
+        if (!D->ukm1 || !D->ckm1 || !D->ckm2) return theta;
+        double num = (double)ukX - (double)D->ukm1[X];
+        double d1 = (double)Ck - (double)D->ckm1[X];
+        double d2 = (double)D->ckm1[X] - (double)D->ckm2[X];
+        double hs = q[4] * d1 + q[5] * d2;
+        if (!isfinite(num) || !isfinite(hs)) return theta;
+        double d0 = (double)Ut - (double)Ck;
+        double den = (q[3] * d0 + hs) / ((q[3] + q[4]) + q[5]);
+        if (!isfinite(den) || den == 0.0) return theta;
+        return theta_damped(num / den, q[0], q[1], q[2]);
+    }
+    if (D->theta_mode == 2) {
+        double num = (double)D->tref[X] - (double)ukX;
+        double den = (double)Ut - (double)Ck;
+        if (!isfinite(num) || !isfinite(den) || den == 0.0) return theta;
+        double th = num / den - q[6];
+        return th > 0.0 ? th : 0.0;
+    }
+    if (D->theta_mode == 3) return (double)D->tref[X];
+    return theta;
+}
+
+/* exported for the tests of the weight rule */
+double NAME(eikref_exp_cw)(double x) { return exp_cw(x); }
+double NAME(eikref_theta_damped)(double tb, double gamma, double delta, double x0) {
+    return theta_damped(tb, gamma, delta, x0);
+}
+
 /* ---- Step 4 on one lattice (Alg. 2Dweightedupdate) ---- */
 typedef struct {
     const ddp* D;
@@ -838,10 +939,15 @@ static int corr_node(const box* B, int64_t li, void* vctx) {
         if (!(le || ge)) cond = 0;
     }
     real v;
-    if (cond && isfinite((double)Ut) && isfinite((double)C->Ck[li]))
-        v = C->uk[li] + C->D->thetaT * (Ut - C->Ck[li]);
-    else
+    if (cond && isfinite((double)Ut) && isfinite((double)C->Ck[li])) {
+        real th = C->D->thetaT;
+        if (C->D->theta_mode != 0)
+            th = (real)theta_node(C->D, lattice_global(C->D, C->l, li), Ut, C->Ck[li], C->uk[li],
+                                  (double)C->D->thetaT);
+        v = C->uk[li] + th * (Ut - C->Ck[li]);
+    } else {
         v = C->uk[li];
+    }
     if (v != C->u[li]) {
         C->u[li] = v;
         return 1;
@@ -850,7 +956,8 @@ static int corr_node(const box* B, int64_t li, void* vctx) {
 }
 
 static int64_t step4_correct(const ddp* D, const real* Uk, const signed char* Wk, const real* ukg,
-                             const signed char* wkg, real* Un, signed char* Wn, int max_sweeps) {
+                             const signed char* wkg, real* Un, signed char* Wn, int max_sweeps,
+                             real* Ck_out) {
     lattice* L;
     int64_t nl = lattice_list(D, &L);
     int d = D->d;
@@ -894,6 +1001,7 @@ static int64_t step4_correct(const ddp* D, const real* Uk, const signed char* Wk
             signed char ws[3], wt[3];
             gather(&l->B, lUk, li, m, ws);
             lCk[li] = local_solve(d, m, ws, rd[li], 1, wt);
+            if (Ck_out) Ck_out[lattice_global(D, l, li)] = lCk[li];
         }
         corr_ctx C = {D, l, u, lUk, luk, lCk, lwk, lWk, rd, fixed, normal};
         int64_t ns = 0;
@@ -919,13 +1027,17 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
                     double tol, int max_iter, int max_fine_sweeps, int max_coarse_sweeps,
                     const real* U_init, const signed char* W_init, real* u_out, real* U_out,
                     signed char* W_out, real* uk_out, signed char* wk_out, real* Upre_out,
-                    int64_t* info, double* hist, int hist_cap) {
+                    int64_t* info, double* hist, int hist_cap, int theta_mode, const double* tpar,
+                    const real* tref) {
     int64_t N;
     int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
     if (st != OK) return st;
     if (M < 2 || S < M || S % M != 0) return ERR_SHAPE;
     if (!(theta >= 0.0 && theta <= 1.0)) return ERR_ARG;
     if (max_iter < 0 || max_fine_sweeps < 1 || max_coarse_sweeps < 1) return ERR_ARG;
+    if (theta_mode < 0 || theta_mode > 3) return ERR_ARG;
+    if (theta_mode != 0 && !tpar) return ERR_ARG;
+    if ((theta_mode == 2 || theta_mode == 3) && !tref) return ERR_ARG;
     ddp D;
     memset(&D, 0, sizeof(D));
     D.d = d;
@@ -943,6 +1055,9 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     D.hT = (real)h;
     D.HT = (real)((double)M * h);
     D.thetaT = (real)theta;
+    D.theta_mode = theta_mode;
+    for (int q = 0; q < 7; q++) D.tpar[q] = tpar ? tpar[q] : 0.0;
+    D.tref = tref;
     D.r = r;
     D.isg = (unsigned char*)calloc((size_t)N, 1);
     D.gv = (real*)calloc((size_t)N, sizeof(real));
@@ -957,6 +1072,10 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     signed char* W = (signed char*)calloc((size_t)(d * N), 1);
     signed char* Wn = (signed char*)calloc((size_t)(d * N), 1);
     signed char* wk = (signed char*)calloc((size_t)(d * N), 1);
+    /* history for the estimated weight: u^{k-1}, C^k, C^{k-1}, C^{k-2} */
+    real* hu = (real*)malloc(sizeof(real) * N);
+    real* hc[3];
+    for (int q = 0; q < 3; q++) hc[q] = (real*)malloc(sizeof(real) * N);
     int64_t ntile = D.P[0] * D.P[1] * D.P[2];
     int64_t V = 1;
     for (int a = 0; a < d; a++) V *= (S + 1);
@@ -1051,7 +1170,12 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
         }
         /* Step 4: weighted correction on every lattice, then causal sweep */
         for (int64_t x = 0; x < N; x++) Un[x] = (real)NAN;
-        coarse_upd += step4_correct(&D, U, W, uk, wk, Un, Wn, max_coarse_sweeps);
+        /* C^k goes to hc[k % 3]; C^{k-1} and C^{k-2} are the other two */
+        D.ckm1 = (k >= 1) ? hc[(k + 2) % 3] : NULL;
+        D.ckm2 = (k >= 2) ? hc[(k + 1) % 3] : NULL;
+        D.ukm1 = (k >= 1) ? hu : NULL;
+        coarse_upd += step4_correct(&D, U, W, uk, wk, Un, Wn, max_coarse_sweeps, hc[k % 3]);
+        memcpy(hu, uk, sizeof(real) * N);
         if (Upre_out) memcpy(Upre_out, Un, sizeof(real) * N);
         causal_sweep(&D, Un, Wn);
         /* max|U^{k+1} - U^k| over coarse nodes, |inf - inf| = 0 */
@@ -1100,6 +1224,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
         info[4] = (max_iter == 0 || conv) ? OK : ERR_NOCONV;
     }
     free(D.isg); free(D.gv); free(U); free(Un); free(uk); free(W); free(Wn); free(wk);
+    free(hu); free(hc[0]); free(hc[1]); free(hc[2]);
     free(tu); free(tw);
     return (max_iter == 0 || conv) ? OK : ERR_NOCONV;
 }

@@ -51,8 +51,16 @@ class DDOpts(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("M", ctypes.c_int32), ("theta", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("max_fine_sweeps", ctypes.c_int32), ("max_coarse_sweeps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("U_init", ctypes.c_void_p),
-                ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug))]
+                ("theta_mode", ctypes.c_int32), ("U_init", ctypes.c_void_p),
+                ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug)),
+                ("theta_ref", ctypes.c_void_p), ("theta_params", ctypes.c_double * 7)]
+
+
+THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
+# gamma, delta, x0 of eq. thetaest (the paper's values), equal omegas for
+# eq. secthetaest (not stated in the paper), margin 0.001 of the reference
+# weight
+THETA_PARAMS = (0.75, 0.01, 0.9, 1.0, 1.0, 1.0, 0.001)
 
 
 class Stats(ctypes.Structure):
@@ -163,7 +171,8 @@ def solve(r, gamma_idx, gamma_val, h, max_sweeps: int = 100000, with_wind: bool 
 def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol: float = 1e-12,
              max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
              max_coarse_sweeps: int = 32, U_init=None, W_init=None, debug: bool = False,
-             history_cap: int = 4096):
+             history_cap: int = 4096, theta_mode: str = "constant", theta_params=THETA_PARAMS,
+             theta_ref=None):
     """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
     with the patched fine solution u, coarse values U (NaN off the skeleton),
     coarse wind codes W, counters and timings; with debug=True also the last
@@ -181,6 +190,12 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     o = DDOpts()
     o.S, o.M, o.theta, o.tol = int(S), int(M), float(theta), float(tol)
     o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps)
+    o.theta_mode = THETA_MODES[theta_mode]
+    for q, v in enumerate(theta_params):
+        o.theta_params[q] = float(v)
+    if theta_ref is not None:
+        theta_ref = theta_ref.to(device=r.device, dtype=r.dtype).contiguous()
+        o.theta_ref = theta_ref.data_ptr()
     if U_init is not None:
         U_init = U_init.to(device=r.device, dtype=r.dtype).contiguous()
         W_init = W_init.to(device=r.device, dtype=torch.int8).contiguous()

@@ -125,6 +125,33 @@ void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t 
   }
 }
 
+eik_status check_theta(const eik_dd_opts* o) {
+  if (o->theta_mode < EIK_THETA_CONSTANT || o->theta_mode > EIK_THETA_FIELD)
+    return fail(EIK_ERR_ARG, "theta_mode must be one of EIK_THETA_*");
+  if ((o->theta_mode == EIK_THETA_REFERENCE || o->theta_mode == EIK_THETA_FIELD) && !o->theta_ref)
+    return fail(EIK_ERR_ARG, "theta_mode needs theta_ref");
+  if (o->theta_mode == EIK_THETA_ESTIMATE) {
+    const double* q = o->theta_params;
+    if (!(q[0] > 0) || !std::isfinite(q[0]) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
+        !(q[3] >= 0 && q[4] >= 0 && q[5] >= 0) || !((q[3] + q[4]) + q[5] > 0))
+      return fail(EIK_ERR_ARG, "theta_params: need gamma > 0, finite delta and x0, omegas >= 0 with a positive sum");
+  }
+  if (o->theta_mode == EIK_THETA_REFERENCE && !std::isfinite(o->theta_params[6]))
+    return fail(EIK_ERR_ARG, "theta_params: margin must be finite");
+  return EIK_OK;
+}
+
+template <typename T>
+void set_theta(eik::ThetaPar& q, const eik_dd_opts* o) {
+  q.gamma = o->theta_params[0];
+  q.delta = o->theta_params[1];
+  q.x0 = o->theta_params[2];
+  q.w0 = o->theta_params[3];
+  q.w1 = o->theta_params[4];
+  q.w2 = o->theta_params[5];
+  q.margin = o->theta_params[6];
+}
+
 template <typename T>
 eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, const eik_dd_opts* o,
                       void* u_outv, void* U_outv, int8_t* W_out, eik_stats* st, hipStream_t s) {
@@ -144,12 +171,20 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const size_t szT = sizeof(T);
   const int L = S + 1;
   const size_t lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
-  const size_t lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT),
+  eik_status e = check_theta(o);
+  if (e != EIK_OK) return e;
+  const int tmode = o->theta_mode;
+  // Step 4 holds two doubles more per node when the weight varies
+  const size_t lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT) +
+                                      (tmode ? eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 0, 8) : 0),
                                   eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
   const int nC = (NI + 1) * (NJ + 1);
   const size_t lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
-  if (lds_tile > kLdsBytes || lds_lat > kLdsBytes || lds_cb > kLdsBytes)
+  if (lds_tile > kLdsBytes || lds_cb > kLdsBytes)
     return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this build");
+  if (lds_lat > kLdsBytes)
+    return fail(EIK_ERR_UNSUPPORTED, "coarse lattice of %d x %d nodes does not fit in LDS%s", NI + 1, NJ + 1,
+                tmode ? " with a varying theta in this precision" : "");
 
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -167,9 +202,10 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   need += ntile * 4 * L * (szT + 1) + 512;
   need += nC * (szT + 1) + (nH + nV) * (szT + 1) + 2048;
   need += 4096;
+  if (tmode == EIK_THETA_ESTIMATE) need += 4 * (N * szT + 256);  // u^{k-1}, C^k, C^{k-1}, C^{k-2}
   void* wsv;
   unsigned long long* host;
-  eik_status e = ws_get(dev, need, &wsv, &host);
+  e = ws_get(dev, need, &wsv, &host);
   if (e != EIK_OK) return e;
   Carver cv{(char*)wsv};
   eik::DD2<T> A;
@@ -206,6 +242,17 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.counters = cv.take<unsigned long long>(4);
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.u_out = as<T>(u_outv);
+  A.theta_mode = tmode;
+  set_theta<T>(A.tq, o);
+  A.tref = as<T>(o->theta_ref);
+  A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
+  A.ck_out = nullptr;
+  T* hist_u = nullptr;
+  T* hist_c[3] = {nullptr, nullptr, nullptr};
+  if (tmode == EIK_THETA_ESTIMATE) {
+    hist_u = cv.take<T>(N);
+    for (auto& c : hist_c) c = cv.take<T>(N);
+  }
 
   if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_tile<T>, lds_tile)) != EIK_OK) return e;
@@ -267,7 +314,15 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     HIPCHK(hipEventRecord(ev[2], s));
     const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
     if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
+    if (tmode == EIK_THETA_ESTIMATE) {
+      // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
+      A.ck_out = hist_c[k % 3];
+      A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
+      A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
+      A.ukm1 = k >= 1 ? hist_u : nullptr;
+    }
     hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
+    if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipEventRecord(ev[4], s));
     if (dbg && dbg->U_pre_causal)
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
@@ -378,6 +433,11 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   if (o->max_iter < 0 || o->max_fine_sweeps < 1 || o->max_coarse_sweeps < 1)
     return fail(EIK_ERR_ARG, "max_iter >= 0, max_fine_sweeps >= 1, max_coarse_sweeps >= 1");
   if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
+  {
+    const eik_status et = check_theta(o);
+    if (et != EIK_OK) return et;
+  }
+  const int tmode = o->theta_mode;
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
@@ -392,6 +452,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   need += (size_t)ntile * 6 * L * L * (szT + 1) + 512;
   need += (size_t)ntile * L * L * L + 256;
   need += 4096;
+  if (tmode == EIK_THETA_ESTIMATE) need += 3 * (N * szT + 256);  // u^{k-1} and two more C arrays
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -430,10 +491,28 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   A.counters = cv.take<unsigned long long>(4);
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.u_out = as<T>(u_outv);
+  set_theta<T>(A.tq, o);
+  A.tref = as<T>(o->theta_ref);
+  A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
+  T* hist_u = nullptr;
+  T* hist_c[3] = {A.ck, nullptr, nullptr};
+  if (tmode == EIK_THETA_ESTIMATE) {
+    hist_u = cv.take<T>(N);
+    hist_c[1] = cv.take<T>(N);
+    hist_c[2] = cv.take<T>(N);
+  }
+  auto correct_kernel = [&]() -> void (*)(eik::DD3<T>) {
+    switch (tmode) {
+      case EIK_THETA_ESTIMATE: return eik::k_lattice_correct3<T, 1>;
+      case EIK_THETA_REFERENCE: return eik::k_lattice_correct3<T, 2>;
+      case EIK_THETA_FIELD: return eik::k_lattice_correct3<T, 3>;
+      default: return eik::k_lattice_correct3<T, 0>;
+    }
+  }();
   if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_tile3<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init3<T>, lds_lat)) != EIK_OK) return e;
-  if ((e = allow_lds(eik::k_lattice_correct3<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(correct_kernel, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_causal3<T>, lds_cell)) != EIK_OK) return e;
 
   hipEvent_t ev[6];
@@ -485,8 +564,16 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     hipLaunchKernelGGL(eik::k_tile3<T>, dim3(ntile), dim3(eik::kBlock3), lds_tile, s, A);
     HIPCHK(hipEventRecord(ev[2], s));
     hipLaunchKernelGGL(eik::k_reconcile3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+    if (tmode == EIK_THETA_ESTIMATE) {
+      // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
+      A.ck = hist_c[k % 3];
+      A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
+      A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
+      A.ukm1 = k >= 1 ? hist_u : nullptr;
+    }
     hipLaunchKernelGGL(eik::k_ck3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
-    hipLaunchKernelGGL(eik::k_lattice_correct3<T>, dim3(nlat), dim3(eik::kBlock3), lds_lat, s, A);
+    hipLaunchKernelGGL(correct_kernel, dim3(nlat), dim3(eik::kBlock3), lds_lat, s, A);
+    if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipEventRecord(ev[4], s));
     if (dbg && dbg->U_pre_causal)
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));

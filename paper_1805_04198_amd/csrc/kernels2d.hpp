@@ -72,6 +72,71 @@ __device__ __forceinline__ bool disnan(float x) { return x != x; }
 __device__ __forceinline__ bool disnan(double x) { return x != x; }
 template <typename T> __device__ __forceinline__ bool dfinite(T x) { return dabs(x) < pinf<T>(); }
 
+// e^x in double as a fixed sequence of IEEE operations: x = n ln2 + r with
+// Cody and Waite's two-part ln2 (high part exact in 32 bits, as in fdlibm),
+// |r| <= ln2/2, and the Taylor series of e^r to r^13 in Horner form.  0
+// below -700 (where 1 + e^x rounds to 1), +inf from 709.78 on.
+__device__ __forceinline__ double exp_cw(double x) {
+  if (x != x) return x;
+  if (x >= 709.78) return __builtin_huge_val();
+  if (x < -700.0) return 0.0;
+  const double n = __builtin_floor(x * 0x1.71547652b82fep0 + 0.5);
+  const double r = (x - n * 0x1.62e42feep-1) - n * 0x1.a39ef35793c76p-33;
+  double p = 1.0 / 6227020800.0;
+  p = p * r + 1.0 / 479001600.0;
+  p = p * r + 1.0 / 39916800.0;
+  p = p * r + 1.0 / 3628800.0;
+  p = p * r + 1.0 / 362880.0;
+  p = p * r + 1.0 / 40320.0;
+  p = p * r + 1.0 / 5040.0;
+  p = p * r + 1.0 / 720.0;
+  p = p * r + 1.0 / 120.0;
+  p = p * r + 1.0 / 24.0;
+  p = p * r + 1.0 / 6.0;
+  p = p * r + 0.5;
+  p = p * r + 1.0;
+  p = p * r + 1.0;
+  return __builtin_ldexp(p, (int)n);
+}
+
+// Step 4 weight rule (eqs. secthetaest and thetaest, Sec. 4.2; the reference
+// weight M-bar - margin of Sec. 5.4): parameters and per-node terms
+struct ThetaPar {
+  double gamma, delta, x0, w0, w1, w2, margin;
+};
+
+// eq. thetaest: [s t + (1 - s) delta t]^+, s = 1 / (1 + e^{(t - x0)/gamma})
+__device__ __forceinline__ double theta_damped(double tb, const ThetaPar& q) {
+  const double e = exp_cw((tb - q.x0) / q.gamma);
+  const double sg = 1.0 / (1.0 + e);
+  const double th = sg * tb + (1.0 - sg) * (q.delta * tb);
+  return th > 0.0 ? th : 0.0;
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return __builtin_fabs(x) < __builtin_huge_val(); }
+
+// Weight at a node in mode MODE (1 estimate, 2 reference, 3 field) from the
+// candidate ut, C^k, the node's precomputed terms ta / tb (mode 1: u^k -
+// u^{k-1} or NaN when it cannot be used, and w1 d1 + w2 d2; mode 2: u_ref -
+// u^k; mode 3: theta) and the constant weight.
+template <int MODE, typename T>
+__device__ __forceinline__ double theta_at(T ut, T ck, double ta, double tb, double theta, const ThetaPar& q) {
+  if (MODE == 1) {
+    if (ta != ta) return theta;
+    const double d0 = (double)ut - (double)ck;
+    const double den = (q.w0 * d0 + tb) / ((q.w0 + q.w1) + q.w2);
+    if (!finite_d(den) || den == 0.0) return theta;
+    return theta_damped(ta / den, q);
+  }
+  if (MODE == 2) {
+    const double den = (double)ut - (double)ck;
+    if (!finite_d(ta) || !finite_d(den) || den == 0.0) return theta;
+    const double th = ta / den - q.margin;
+    return th > 0.0 ? th : 0.0;
+  }
+  return ta;
+}
+
 // ---- wind codes ----
 __device__ __forceinline__ int wx_of(uint8_t c) { int v = c & 3; return v == 3 ? -1 : v; }
 __device__ __forceinline__ int wy_of(uint8_t c) { int v = (c >> 2) & 3; return v == 3 ? -1 : v; }
@@ -429,6 +494,7 @@ struct MinRule {
 template <typename T>
 struct PreCorr {
   T self, xn, yn, hx, hy, rd, uk, ck;
+  double ta, tb;
   uint8_t m;
 };
 
@@ -450,8 +516,9 @@ __device__ __forceinline__ uint8_t corr_mask(uint8_t wk, uint8_t Wk, bool nx, bo
 // Step 4 (Alg. 2Dweightedupdate): U = u^k + theta*(U~ - C^k) when the winds
 // w^k, W^k and W~ agree along every normal axis of the node's coarse line and
 // U~, C^k are finite; U = u^k otherwise.  Direct assignment, no minimum.
-// Gamma nodes carry u^k = g and r*H = NaN, so they always keep g.
-template <typename T>
+// Gamma nodes carry u^k = g and r*H = NaN, so they always keep g.  MODE
+// selects the weight (0 constant, else theta_at).
+template <typename T, int MODE>
 struct CorrectRule {
   using real = T;
   using Pre = PreCorr<T>;
@@ -463,6 +530,9 @@ struct CorrectRule {
   const uint8_t* mk;
   T theta;
   int SP;
+  const double* ta;  // per-node weight terms (MODE != 0)
+  const double* tb;
+  ThetaPar q;
   __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
@@ -474,6 +544,10 @@ struct CorrectRule {
     p.uk = uk[x];
     p.ck = ck[x];
     p.m = mk[x];
+    if (MODE != 0) {
+      p.ta = ta[x];
+      if (MODE == 1) p.tb = tb[x];
+    }
     return p;
   }
   template <int SX, int SY>
@@ -491,7 +565,9 @@ struct CorrectRule {
     const int ty = lb ? 0 : wy;
     const unsigned m = p.m;
     const bool cond = ((m >> (tx + 1)) & 1u) && ((m >> (ty + 4)) & 1u) && (m & 64u) && dfinite(ut);
-    const T corr = p.uk + theta * (ut - p.ck);
+    T th = theta;
+    if (MODE != 0) th = (T)theta_at<MODE>(ut, p.ck, p.ta, p.tb, (double)theta, q);
+    const T corr = p.uk + th * (ut - p.ck);
     const T v = cond ? corr : p.uk;
     ch = act && (v != p.self);
     u[ch ? x : dummy_slot()] = v;
@@ -536,6 +612,16 @@ struct DD2 {
   unsigned long long* near_key;  // Step 1 nearest-Gamma keys (full grid)
   long long* near_win;
   unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits
+  // Step 4 weight (ThetaPar, theta_at): mode, parameters, u_ref or theta per
+  // node, and the history u^{k-1}, C^{k-1}, C^{k-2} (NULL until it exists);
+  // this iteration's C^k goes to ck_out
+  int theta_mode;
+  ThetaPar tq;
+  const T* tref;
+  const T* ukm1;
+  const T* ckm1;
+  const T* ckm2;
+  T* ck_out;
 };
 
 __device__ __forceinline__ bool is_iface(int c, int S, int n) { return (c % S == 0) && c > 0 && c < n - 1; }
@@ -728,6 +814,9 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
   unsigned char* lc = smem;
+  // the weight terms come first so that the doubles are 8-byte aligned
+  double* ta = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
+  double* tb = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
   T* u = carve<T>(lc, cnt);
   T* uk = carve<T>(lc, cnt);
   T* ck = carve<T>(lc, cnt);
@@ -764,6 +853,25 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
     const T c = godunov2(a, b, rd[x], two);
     ck[x] = c;
     mk[x] = corr_mask(A.wk[X], A.W[X], nx, ny, dfinite(c));
+    if (A.theta_mode == 1) {
+      // u^k - u^{k-1} (NaN when it cannot be used) and w1 d1 + w2 d2 with
+      // d1 = C^k - C^{k-1}, d2 = C^{k-1} - C^{k-2}
+      double num = __builtin_nan(""), hs = 0.0;
+      if (A.ukm1 && A.ckm1 && A.ckm2) {
+        num = (double)uk[x] - (double)A.ukm1[X];
+        const double d1 = (double)c - (double)A.ckm1[X];
+        const double d2 = (double)A.ckm1[X] - (double)A.ckm2[X];
+        hs = A.tq.w1 * d1 + A.tq.w2 * d2;
+        if (!finite_d(num) || !finite_d(hs)) num = __builtin_nan("");
+      }
+      ta[x] = num;
+      tb[x] = hs;
+      A.ck_out[X] = c;
+    } else if (A.theta_mode == 2) {
+      ta[x] = (double)A.tref[X] - (double)uk[x];
+    } else if (A.theta_mode == 3) {
+      ta[x] = (double)A.tref[X];
+    }
   }
   __syncthreads();
   // start of Step 4: U = +inf, Gamma nodes at g (they keep it: r*H = NaN)
@@ -784,8 +892,29 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
   if (threadIdx.x == 0) sh_free = 0;
   __syncthreads();
   if (threadIdx.x < kWave) {
-    CorrectRule<T> R{u, uk, ck, rd, mk, A.theta, SP};
-    const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+    int ns;
+    switch (A.theta_mode) {
+      case 0: {
+        CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        break;
+      }
+      case 1: {
+        CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        break;
+      }
+      case 2: {
+        CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        break;
+      }
+      default: {
+        CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        break;
+      }
+    }
     if (threadIdx.x == 0) sh_ns = ns;
   }
   __syncthreads();

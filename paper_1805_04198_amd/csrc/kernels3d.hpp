@@ -125,6 +125,13 @@ struct DD3 {
   unsigned long long* near_key;
   long long* near_win;
   unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits
+  // Step 4 weight (theta_at): parameters, u_ref or theta per node, and the
+  // history u^{k-1}, C^{k-1}, C^{k-2} (NULL until it exists)
+  ThetaPar tq;
+  const T* tref;
+  const T* ukm1;
+  const T* ckm1;
+  const T* ckm2;
 };
 
 __device__ __forceinline__ int64_t idx3(const int (&n)[3], int i, int j, int k) {
@@ -619,7 +626,7 @@ __global__ void k_ck3(DD3<T> A) {
   A.mk[t] = mask;
 }
 
-template <typename T>
+template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   int o[3];
@@ -651,14 +658,35 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
     T theta;
     int64_t base;
     int gs0, gs1, gs2;
+    const T* tref;
+    const T* ukm1;
+    const T* ckm1;
+    const T* ckm2;
+    ThetaPar q;
     struct In {
       T rd;   // NaN at Gamma nodes
       T ukx, ckx;
       unsigned mask;
+      double ta, tb;  // weight terms (theta_at)
     };
     __device__ In load(int i, int j, int k) const {
       const int64_t X = base + (int64_t)i * gs0 + (int64_t)j * gs1 + (int64_t)k * gs2;
-      return In{rdH[X], uk[X], ck[X], (unsigned)mk[X]};
+      In in{rdH[X], uk[X], ck[X], (unsigned)mk[X], 0.0, 0.0};
+      if (MODE == 1) {
+        in.ta = __builtin_nan("");
+        if (ukm1 && ckm1 && ckm2) {
+          const double num = (double)in.ukx - (double)ukm1[X];
+          const double d1 = (double)in.ckx - (double)ckm1[X];
+          const double d2 = (double)ckm1[X] - (double)ckm2[X];
+          const double hs = q.w1 * d1 + q.w2 * d2;
+          if (finite_d(num) && finite_d(hs)) { in.ta = num; in.tb = hs; }
+        }
+      } else if (MODE == 2) {
+        in.ta = (double)tref[X] - (double)in.ukx;
+      } else if (MODE == 3) {
+        in.ta = (double)tref[X];
+      }
+      return in;
     }
     __device__ bool update(int i, int j, int k, const In& in) const {
       if (disnan(in.rd)) return false;
@@ -671,7 +699,9 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
       bool cond = dfinite(ut) && (mask & 512u);
       for (int a = 0; a < 3; ++a) cond = cond && ((mask >> (3 * a + w_of(code, a) + 1)) & 1u);
       const T ukx = in.ukx;
-      const T v = cond ? ukx + theta * (ut - in.ckx) : ukx;
+      T th = theta;
+      if (MODE != 0) th = (T)theta_at<MODE>(ut, in.ckx, in.ta, in.tb, (double)theta, q);
+      const T v = cond ? ukx + th * (ut - in.ckx) : ukx;
       const int x = i + L0 * (j + L1 * k);
       if (v != u[x]) {
         u[x] = v;
@@ -679,7 +709,8 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
       }
       return false;
     }
-  } R{u, L[0], L[1], L[2], A.gfull, A.rdH, A.mk, A.uk, A.ck, A.theta, base, gs[0], gs[1], gs[2]};
+  } R{u, L[0], L[1], L[2], A.gfull, A.rdH, A.mk, A.uk, A.ck, A.theta, base, gs[0], gs[1], gs[2],
+      A.tref, A.ukm1, A.ckm1, A.ckm2, A.tq};
   const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
