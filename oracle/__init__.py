@@ -71,6 +71,10 @@ def lib():
                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
                           vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                           ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+            f = getattr(L, "eikref_adjoint" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int, i64p, vp, vp, vp, vp,
+                          vp, vp, i64p]
             f = getattr(L, "eikref_exp_cw" + sfx)
             f.restype = ctypes.c_double
             f.argtypes = [ctypes.c_double]
@@ -188,6 +192,34 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
             "Upre": Upre, "iterations": it, "converged": bool(info[1]),
             "fine_updates": int(info[2]), "coarse_updates": int(info[3]),
             "status": int(info[4]), "residuals": hist[: min(it, hist_cap)].copy()}
+
+
+def adjoint(n, h, r, gammas, u, seed, winds=None, dtype=np.float64):
+    """Travel-time gradient by the discrete adjoint of the converged upwind
+    system (see eikref_adjoint): a batch of problems on one slowness.
+    gammas: list of Gamma index arrays, one per problem; u, seed: (nb, N);
+    winds: (nb, d, N) axis components or None (recomputed from u).
+    Returns (dL/dr (N,), lambda (nb, N), passes)."""
+    d = len(n)
+    nb = len(gammas)
+    n64 = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+    N = int(np.prod(n))
+    r = np.ascontiguousarray(np.asarray(r, dtype=dtype).reshape(-1))
+    u = np.ascontiguousarray(np.asarray(u, dtype=dtype).reshape(nb, N))
+    seed = np.ascontiguousarray(np.asarray(seed, dtype=dtype).reshape(nb, N))
+    gl = [np.ascontiguousarray(np.asarray(g, dtype=np.int64)) for g in gammas]
+    gcount = np.array([len(g) for g in gl], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * nb)(*[g.ctypes.data for g in gl])
+    w = None if winds is None else np.ascontiguousarray(np.asarray(winds, dtype=np.int8).reshape(nb, d, N))
+    lam = np.empty((nb, N), dtype=dtype)
+    grad = np.empty(N, dtype=dtype)
+    info = np.zeros(1, dtype=np.int64)
+    st = getattr(lib(), "eikref_adjoint" + _sfx(dtype))(
+        d, _i64(n64), float(h), _p(r), nb, _i64(gcount), ctypes.cast(ptrs, ctypes.c_void_p), _p(u), _p(w),
+        _p(seed), _p(lam), _p(grad), _i64(info))
+    if st != 0:
+        raise ValueError(f"eikref_adjoint: {STATUS.get(st, st)}")
+    return grad, lam, int(info[0])
 
 
 def exp_cw(x):

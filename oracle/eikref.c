@@ -1243,3 +1243,163 @@ int NAME(eikref_local)(int d, const real* m, const signed char* ws, real rd, int
     *out = local_solve(d, mm, ww, rd, rule, wt);
     return OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Travel-time gradient: the adjoint of the converged Godunov system   */
+/* ------------------------------------------------------------------ */
+
+/* Not a step of the paper's method: the gradient of a loss of converged
+ * travel times with respect to the slowness, by the discrete adjoint of the
+ * upwind scheme (eq. godonuv).  At a free node x whose update used the axes
+ * A (the nonzero components of its fine wind, Alg. fineupdate2D), the local
+ * equation is sum_{a in A} (u - u_a)^2 = (r h)^2, u_a the upwind neighbour
+ * x - w_a e_a.  Differentiating:
+ *     du = sum_a c_a du_a + q dr,   S = sum_{a in A} (u - u_a),
+ *     c_a = (u - u_a) / S,   q = (r h) h / S
+ * (one axis: c = 1, q = h up to rounding).  Gamma nodes and unreached nodes
+ * carry no equation.  For a loss L with seed s = dL/du the adjoint field
+ * solves lambda(y) = s(y) + sum over downwind nodes x that use y of
+ * c(x -> y) lambda(x), and dL/dr(x) = lambda(x) q(x).  The system is
+ * triangular in the order of decreasing u (an upwind neighbour has a
+ * strictly smaller value), so it is solved by passes over the nodes in that
+ * order until a pass changes nothing.
+ *
+ * Each node evaluates lambda(y) = s(y) + acc with acc summed in the fixed
+ * order of the terms  pm_0 lambda(y - e_0), pp_0 lambda(y + e_0), pm_1 ...,
+ * pp_1 ... (pm_a: coefficient of the node y - e_a towards y, pp_a: of
+ * y + e_a; a term is exactly 0 where the coefficient is 0, i.e. where that
+ * neighbour does not use y or does not exist), starting from acc = the
+ * first term.
+ *
+ * Batch of nb problems on one grid and slowness (e.g. one per source): u,
+ * seed, lambda are nb stacked N-arrays, gammas[b] the boundary set of
+ * problem b; grad = sum over b in order of lambda_b q_b.  w (nb stacked
+ * d*N arrays of axis components, as from eikref_fsm) may be NULL: the winds
+ * are then recomputed from u with the fine rule.  info[0] = passes of the
+ * slowest problem. */
+typedef struct {
+    real u;
+    int64_t x;
+} ukey;
+
+static int cmp_desc(const void* A, const void* B) {
+    const ukey* a = (const ukey*)A;
+    const ukey* b = (const ukey*)B;
+    if (a->u > b->u) return -1;
+    if (a->u < b->u) return 1;
+    return (a->x < b->x) ? -1 : (a->x > b->x);
+}
+
+int NAME(eikref_adjoint)(int d, const int64_t* n, double h, const real* r, int nb,
+                         const int64_t* gcount, const int64_t* const* gidx, const real* u,
+                         const signed char* w, const real* seed, real* lam, real* grad,
+                         int64_t* info) {
+    if (d != 2 && d != 3) return ERR_ARG;
+    if (nb < 1) return ERR_ARG;
+    box B;
+    box_init(&B, d, n);
+    const int64_t N = B.cnt;
+    real hT = (real)h;
+    real* c = (real*)malloc(sizeof(real) * (size_t)(d * N));   /* c_a(x) */
+    signed char* wd = (signed char*)malloc((size_t)(d * N));  /* used winds */
+    real* q = (real*)malloc(sizeof(real) * (size_t)N);
+    unsigned char* fix = (unsigned char*)malloc((size_t)N);
+    ukey* ord = (ukey*)malloc(sizeof(ukey) * (size_t)N);
+    for (int64_t x = 0; x < N; x++) grad[x] = (real)0;
+    int64_t maxpass = 0;
+    for (int b = 0; b < nb; b++) {
+        const real* ub = u + (int64_t)b * N;
+        const real* sb = seed + (int64_t)b * N;
+        real* lb = lam + (int64_t)b * N;
+        memset(fix, 0, (size_t)N);
+        for (int64_t g = 0; g < gcount[b]; g++) {
+            int64_t X = gidx[b][g];
+            if (X < 0 || X >= N) {
+                free(c); free(wd); free(q); free(fix); free(ord);
+                return ERR_ARG;
+            }
+            fix[X] = 1;
+        }
+        /* coefficients of every node's own equation */
+        for (int64_t x = 0; x < N; x++) {
+            q[x] = (real)0;
+            for (int a = 0; a < d; a++) {
+                c[a * N + x] = (real)0;
+                wd[a * N + x] = 0;
+            }
+            if (fix[x] || !(ub[x] < RINF)) continue;
+            signed char wt[3] = {0, 0, 0};
+            if (w) {
+                for (int a = 0; a < d; a++) wt[a] = w[(int64_t)b * d * N + a * N + x];
+            } else {
+                real m[3];
+                signed char ws[3];
+                gather(&B, ub, x, m, ws);
+                local_solve(d, m, ws, r[x] * hT, 0, wt);
+            }
+            int64_t cx[3];
+            box_coords(&B, x, cx);
+            real S = (real)0;
+            int first = 1;
+            for (int a = 0; a < d; a++) {
+                if (wt[a] == 0) continue;
+                real ua = ub[x - wt[a] * B.st[a]];
+                S = first ? (ub[x] - ua) : (S + (ub[x] - ua));
+                first = 0;
+            }
+            if (first || !(S > (real)0)) continue;
+            for (int a = 0; a < d; a++) {
+                if (wt[a] == 0) continue;
+                real ua = ub[x - wt[a] * B.st[a]];
+                c[a * N + x] = (ub[x] - ua) / S;
+                wd[a * N + x] = wt[a];
+            }
+            q[x] = ((r[x] * hT) * hT) / S;
+        }
+        /* passes in the order of decreasing u until nothing changes */
+        for (int64_t x = 0; x < N; x++) {
+            ord[x].u = ub[x];
+            ord[x].x = x;
+            lb[x] = (real)0;
+        }
+        qsort(ord, (size_t)N, sizeof(ukey), cmp_desc);
+        int64_t pass = 0;
+        for (;;) {
+            int64_t changed = 0;
+            for (int64_t k = 0; k < N; k++) {
+                int64_t y = ord[k].x;
+                int64_t cy[3];
+                box_coords(&B, y, cy);
+                real acc = (real)0;
+                for (int a = 0; a < d; a++) {
+                    /* a term is c * lambda where the neighbour uses y, else 0 */
+                    real tm = (real)0, tp = (real)0;
+                    if (cy[a] > 0) {
+                        int64_t xm = y - B.st[a];
+                        real pm = (wd[a * N + xm] == -1) ? c[a * N + xm] : (real)0;
+                        if (pm != (real)0) tm = pm * lb[xm];
+                    }
+                    if (cy[a] < B.L[a] - 1) {
+                        int64_t xp = y + B.st[a];
+                        real pp = (wd[a * N + xp] == 1) ? c[a * N + xp] : (real)0;
+                        if (pp != (real)0) tp = pp * lb[xp];
+                    }
+                    acc = (a == 0) ? tm : acc + tm;
+                    acc = acc + tp;
+                }
+                real v = sb[y] + acc;
+                if (v != lb[y]) {
+                    lb[y] = v;
+                    changed++;
+                }
+            }
+            pass++;
+            if (!changed) break;
+        }
+        if (pass > maxpass) maxpass = pass;
+        for (int64_t x = 0; x < N; x++) grad[x] = grad[x] + lb[x] * q[x];
+    }
+    if (info) info[0] = maxpass;
+    free(c); free(wd); free(q); free(fix); free(ord);
+    return OK;
+}
