@@ -181,10 +181,35 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);
 
-/* eik_adjoint -- gradient of a loss of the converged travel times with
- * respect to the slowness, by the transposed upwind system swept in reverse
- * causal order.  Not part of the paper; declared for the differentiation
- * workload and not implemented in this build: returns EIK_ERR_UNSUPPORTED. */
+/* eik_adjoint_batch -- gradient of a loss L of converged travel times with
+ * respect to the slowness, for nb problems on one grid and slowness (e.g.
+ * one per source), by the discrete adjoint of the upwind scheme (eq.
+ * godonuv).  Not a step of the paper's method.  At a free node x whose
+ * converged update used the axes A (the nonzero components of its fine wind,
+ * Alg. fineupdate2D) with upwind neighbours u_a:
+ *     S = sum_{a in A} (u - u_a),  c_a = (u - u_a)/S,  q = (r h) h / S,
+ * so du = sum_a c_a du_a + q dr.  The adjoint field lambda solves
+ * lambda(y) = dL/du(y) + sum of c(x -> y) lambda(x) over the neighbours x
+ * that use y (terms in the order x-, x+, y- of y, y+ of y), found by
+ * Gauss-Seidel sweeps of the whole grid in the paper's four orders until a
+ * sweep changes nothing; dL/dr = sum over the batch, in order, of lambda q.
+ * Gamma nodes and unreached nodes (u = +inf) carry no equation.
+ *   gammas     host array of nb boundary sets (device pointers inside)
+ *   u          device, nb x N, grid dtype: converged solutions (eik_solve)
+ *   wind       device, nb x N wind codes from the same solves, or NULL:
+ *              recomputed from u with the fine rule
+ *   dL_du      device, nb x N, grid dtype
+ *   dL_dr_out  device, N, grid dtype (overwritten)
+ *   lambda_out device, nb x N, or NULL
+ *   stats      host or NULL: sweeps, ms_total
+ * Returns EIK_ERR_NOCONV if max_sweeps was reached.  This build: d = 2
+ * (d = 3 gives EIK_ERR_UNSUPPORTED). */
+eik_status eik_adjoint_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
+                             const void* u, const int8_t* wind, const void* dL_du, void* dL_dr_out,
+                             void* lambda_out, int32_t max_sweeps, eik_stats* stats, void* hip_stream);
+
+/* eik_adjoint -- eik_adjoint_batch for one problem (nb = 1, no lambda, no
+ * stats, sweep cap 100000). */
 eik_status eik_adjoint(const eik_grid* grid, const void* r, const eik_gamma* gamma,
                        const void* u, const int8_t* wind, const void* dL_du, void* dL_dr_out,
                        void* hip_stream);

@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "
                 -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE"}
 
 # exported symbols of include/eik.h
-SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_adjoint", "eik_last_error", "eik_release",
-           "eik_version")
+SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_adjoint", "eik_adjoint_batch", "eik_last_error",
+           "eik_release", "eik_version")
 
 
 class EikError(RuntimeError):
@@ -98,6 +98,9 @@ def load_library(path: Optional[str] = None):
                                ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
     L.eik_adjoint.restype = ctypes.c_int32
     L.eik_adjoint.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma), vp, vp, vp, vp, vp]
+    L.eik_adjoint_batch.restype = ctypes.c_int32
+    L.eik_adjoint_batch.argtypes = [ctypes.POINTER(Grid), vp, ctypes.c_int32, ctypes.POINTER(Gamma), vp, vp,
+                                    vp, vp, vp, ctypes.c_int32, ctypes.POINTER(Stats), vp]
     L.eik_last_error.restype = ctypes.c_char_p
     L.eik_release.restype = ctypes.c_int32
     L.eik_version.restype = ctypes.c_char_p
@@ -223,6 +226,82 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     if debug:
         out.update(dbg_t)
     return out
+
+
+def adjoint(r, gammas, u, dL_du, h, wind=None, max_sweeps: int = 100000, with_lambda: bool = False):
+    """eik_adjoint_batch: dL/dr for a batch of converged solutions on one
+    slowness.  gammas: list of (idx, val) device tensors, one per problem;
+    u, dL_du: (nb, *r.shape) device tensors of r's dtype; wind: (nb,
+    *r.shape) int8 codes from eik_solve or None.  Returns (dL/dr, lambda or
+    None, stats dict)."""
+    torch = _torch()
+    L = load_library()
+    r = r.contiguous()
+    g = _grid(r, h)
+    nb = len(gammas)
+    u = u.to(dtype=r.dtype).contiguous()
+    dL_du = dL_du.to(dtype=r.dtype).contiguous()
+    if u.shape != (nb,) + tuple(r.shape) or dL_du.shape != u.shape:
+        raise ValueError("u and dL_du must have shape (nb, *r.shape)")
+    gms = (Gamma * nb)()
+    keep = []
+    for b, (gi, gv) in enumerate(gammas):
+        gm, k = _gamma(gi, gv, r)
+        gms[b] = gm
+        keep.append(k)
+    if wind is not None:
+        wind = wind.to(dtype=torch.int8).contiguous()
+        if wind.shape != u.shape:
+            raise ValueError("wind must have shape (nb, *r.shape)")
+    grad = torch.empty_like(r)
+    lam = torch.empty_like(u) if with_lambda else None
+    st = Stats()
+    status = L.eik_adjoint_batch(ctypes.byref(g), r.data_ptr(), nb, gms, u.data_ptr(),
+                                 wind.data_ptr() if wind is not None else None, dL_du.data_ptr(),
+                                 grad.data_ptr(), lam.data_ptr() if lam is not None else None,
+                                 int(max_sweeps), ctypes.byref(st), _stream())
+    _check(L, status)
+    return grad, lam, {"status": status, "sweeps": int(st.sweeps), "converged": bool(st.converged),
+                       "ms": float(st.ms_total)}
+
+
+def _travel_times_function():
+    torch = _torch()
+
+    class TravelTimes(torch.autograd.Function):
+        """u_b = the converged fine travel times (eik_solve) from point source
+        b (g = 0 there), stacked; the backward pass is the batched adjoint."""
+
+        @staticmethod
+        def forward(ctx, r, h, sources):
+            us, ws, gams = [], [], []
+            for s_ in sources:
+                gi = torch.tensor([int(s_)], dtype=torch.int64, device=r.device)
+                gv = torch.zeros(1, dtype=r.dtype, device=r.device)
+                u, w, _ = solve(r, gi, gv, h, with_wind=True)
+                us.append(u)
+                ws.append(w)
+                gams.append((gi, gv))
+            U = torch.stack(us)
+            ctx.save_for_backward(r, U, torch.stack(ws))
+            ctx.h = h
+            ctx.gams = gams
+            return U
+
+        @staticmethod
+        def backward(ctx, dU):
+            r, U, Wd = ctx.saved_tensors
+            grad, _, _ = adjoint(r, ctx.gams, U, dU, ctx.h, wind=Wd)
+            return grad, None, None
+
+    return TravelTimes
+
+
+def travel_times(r, h, sources):
+    """Differentiable travel times from point sources (node indices) on the
+    slowness r: returns (len(sources), *r.shape); backward gives dL/dr by the
+    batched adjoint (eik_adjoint_batch)."""
+    return _travel_times_function().apply(r, h, list(sources))
 
 
 def decode_winds(codes, d: int):

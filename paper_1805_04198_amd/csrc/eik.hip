@@ -14,6 +14,7 @@
 #include "../../include/eik.h"
 #include "kernels2d.hpp"
 #include "kernels3d.hpp"
+#include "kernels_adj.hpp"
 
 namespace {
 
@@ -815,6 +816,113 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
   return EIK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// travel-time gradient (adjoint), d = 2
+// ---------------------------------------------------------------------------
+
+template <typename T>
+eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_gamma* gams, const void* uv,
+                     const int8_t* wind, const void* seedv, void* gradv, void* lamv, int32_t max_sweeps,
+                     eik_stats* st, hipStream_t s) {
+  const int n0 = (int)G->n[0], n1 = (int)G->n[1];
+  const int64_t N = (int64_t)n0 * n1;
+  const size_t szT = sizeof(T);
+  int Bmax = eik::kMaxL;
+  while (Bmax > 8 && eik::adj_box_bytes(Bmax, szT) > kLdsBytes) --Bmax;
+  auto side = [&](int n) { int k = (n + Bmax - 1) / Bmax; return (n + k - 1) / k; };
+  const int B = std::max(side(n0), side(n1));
+  const size_t lds = eik::adj_box_bytes(B, szT);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  const int64_t NB = (int64_t)nb * N;
+  size_t need = (size_t)NB * (1 + 1) + 2 * 256;           // fixed, wd
+  need += (size_t)NB * szT * (2 + 1 + 4) + 3 * 256;       // c, q, pc
+  if (!lamv) need += (size_t)NB * szT + 256;
+  need += 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::ADJ2<T> A;
+  A.n0 = n0; A.n1 = n1; A.nb = nb;
+  A.B = B; A.BX = (n0 + B - 1) / B; A.BY = (n1 + B - 1) / B;
+  A.hT = (T)G->h;
+  A.r = as<T>(rv);
+  A.u = as<T>(uv);
+  A.w = wind;
+  A.seed = as<T>(seedv);
+  A.fixed = cv.take<uint8_t>(NB);
+  A.wd = cv.take<uint8_t>(NB);
+  A.c = cv.take<T>(2 * NB);
+  A.q = cv.take<T>(NB);
+  A.pc = cv.take<T>(4 * NB);
+  A.lam = lamv ? as<T>(lamv) : cv.take<T>(NB);
+  A.grad = as<T>(gradv);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  A.changed = dflag + 1;
+  // the slowness and every boundary set are checked like the forward solve's
+  for (int b = 0; b < nb; ++b)
+    if ((e = validate<T>(A.r, N, &gams[b], dflag, host, s)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_adj_sweep<T>, lds)) != EIK_OK) return e;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } evg{e0, e1};
+  HIPCHK(hipEventRecord(e0, s));
+  const int bs = 256;
+  HIPCHK(hipMemsetAsync(A.fixed, 0, NB, s));
+  for (int b = 0; b < nb; ++b)
+    if (gams[b].count > 0)
+      hipLaunchKernelGGL(eik::k_adj_mark<T>, dim3(nblocks(gams[b].count, bs)), dim3(bs), 0, s,
+                         A.fixed + (int64_t)b * N, gams[b].idx, gams[b].count);
+  const dim3 gridN(nblocks(N, bs), nb);
+  hipLaunchKernelGGL(eik::k_adj_coef<T>, gridN, dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_adj_pull<T>, gridN, dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(NB, bs)), dim3(bs), 0, s, A.lam, T(0), NB);
+  HIPCHK(hipGetLastError());
+  int sw = 0, conv = 0;
+  while (sw < max_sweeps) {
+    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
+    for (int d = 0; d <= A.BX + A.BY - 2; ++d) {
+      const int q0 = std::max(0, d - (A.BY - 1)), q1 = std::min(d, A.BX - 1);
+      hipLaunchKernelGGL(eik::k_adj_sweep<T>, dim3(q1 - q0 + 1, nb), dim3(eik::kBlock), lds, s, A, sw & 3, d);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ++sw;
+    if (*(unsigned int*)host == 0) {
+      conv = 1;
+      break;
+    }
+  }
+  hipLaunchKernelGGL(eik::k_adj_grad<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  if (st) {
+    st->iterations = 0;
+    st->converged = conv;
+    st->sweeps = sw;
+    st->fine_updates = (int64_t)sw * NB;
+    st->coarse_updates = 0;
+    st->final_residual = 0.0;
+    st->ms_total = ms;
+    st->ms_fine = ms;
+    st->ms_coarse = st->ms_correct = st->ms_causal = 0.f;
+  }
+  if (!conv) return fail(EIK_ERR_NOCONV, "adjoint sweeps not stationary after %d sweeps", max_sweeps);
+  return EIK_OK;
+}
+
 eik_status check_common(const eik_grid* G, const void* r, const eik_gamma* gam, const void* out) {
   if (!G || !r || !gam || !out) return fail(EIK_ERR_ARG, "NULL argument");
   if (G->dim != 2 && G->dim != 3) return fail(EIK_ERR_ARG, "dim must be 2 or 3");
@@ -863,9 +971,29 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
   return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
 }
 
-eik_status eik_adjoint(const eik_grid*, const void*, const eik_gamma*, const void*, const int8_t*,
-                       const void*, void*, void*) {
-  return fail(EIK_ERR_UNSUPPORTED, "eik_adjoint is not implemented in this build");
+eik_status eik_adjoint_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
+                             const void* u, const int8_t* wind, const void* dL_du, void* dL_dr_out,
+                             void* lambda_out, int32_t max_sweeps, eik_stats* stats, void* hip_stream) {
+  if (!gammas || nb < 1) return fail(EIK_ERR_ARG, "need nb >= 1 boundary sets");
+  eik_status e = check_common(grid, r, &gammas[0], dL_dr_out);
+  if (e != EIK_OK) return e;
+  for (int b = 1; b < nb; ++b)
+    if (gammas[b].count < 0 || (gammas[b].count > 0 && (!gammas[b].idx || !gammas[b].g)))
+      return fail(EIK_ERR_ARG, "bad Gamma of problem %d", b);
+  if (!u || !dL_du) return fail(EIK_ERR_ARG, "NULL u or dL_du");
+  if (max_sweeps < 1) return fail(EIK_ERR_ARG, "max_sweeps must be >= 1");
+  if (dL_dr_out == u || dL_dr_out == dL_du || (lambda_out && (lambda_out == u || lambda_out == dL_du)))
+    return fail(EIK_ERR_ARG, "outputs must not alias inputs");
+  if (grid->dim != 2) return fail(EIK_ERR_UNSUPPORTED, "eik_adjoint: d = 3 is not implemented in this build");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dtype == EIK_F32)
+    return adjoint_t<float>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);
+  return adjoint_t<double>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);
+}
+
+eik_status eik_adjoint(const eik_grid* grid, const void* r, const eik_gamma* gamma, const void* u,
+                       const int8_t* wind, const void* dL_du, void* dL_dr_out, void* hip_stream) {
+  return eik_adjoint_batch(grid, r, 1, gamma, u, wind, dL_du, dL_dr_out, nullptr, 100000, nullptr, hip_stream);
 }
 
 const char* eik_last_error(void) { return g_err.c_str(); }

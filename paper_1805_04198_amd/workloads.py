@@ -262,4 +262,47 @@ def model_strip(N: int, M: int) -> Problem:
     return Problem(f"strip_N{N}_M{M}", n, h, r, gi, gv, S=M, M=M)
 
 
+@dataclasses.dataclass
+class GradProblem:
+    """The travel-time gradient workload: one slowness, many point sources,
+    receivers, and the perturbed slowness the target times come from."""
+
+    name: str
+    n: tuple
+    h: float
+    r: np.ndarray              # slowness, shape n[::-1]
+    r_perturbed: np.ndarray    # slowness of the synthetic observations
+    sources: list              # node indices (g = 0 at each, one problem per source)
+    receivers: np.ndarray      # node indices
+    targets: np.ndarray        # (len(sources), len(receivers)) stand-in targets, see config5_problem
+
+
+def config5_problem(n_side: int = 1025, n_src: int = 32, n_bumps: int = 8, seed: int = 5) -> GradProblem:
+    """Differentiation workload: 1025^2, the config-1 slowness (eps = 1/16),
+    32 distinct seeded top-edge sources, receivers at i = 2 + 4m on the
+    bottom edge (256 at n = 1025), and a perturbed slowness r + sum of
+    n_bumps Gaussian bumps 0.05 exp(-|x - c|^2 / (2 0.05^2)), centres
+    uniform in [0.1, 0.9]^2.  The observations are meant to be the travel
+    times through r_perturbed (the benchmark solves for them on the GPU);
+    `targets` holds a stand-in that needs no solver: straight-ray times
+    |x_r - x_s| times the mean of r_perturbed."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    x, y = _coords(n, h)
+    eps = 1.0 / 16
+    r = 1.0 + 0.5 * np.sin(2 * np.pi * x / eps) * np.sin(2 * np.pi * y / eps)
+    rng = np.random.default_rng(seed)
+    cols = np.sort(rng.choice(n_side, n_src, replace=False))
+    centres = rng.uniform(0.1, 0.9, (n_bumps, 2))
+    rp = r.copy()
+    for cx, cy in centres:
+        rp = rp + 0.05 * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * 0.05 ** 2))
+    sources = [linear_index(n, int(i), n_side - 1) for i in cols]
+    ri = np.arange(2, n_side - 1, 4)[:256]
+    receivers = np.array([linear_index(n, int(i), 0) for i in ri], dtype=np.int64)
+    mean_r = float(np.mean(rp))
+    targets = np.array([[mean_r * h * float(np.hypot(ri_ - si, n_side - 1)) for ri_ in ri] for si in cols])
+    return GradProblem(f"c5_{n_side}sq_{n_src}src", n, h, r, rp, sources, receivers, targets)
+
+
 CONFIGS = {"c1": config1, "c2": config2, "c3": config3}

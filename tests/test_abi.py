@@ -37,4 +37,5 @@ def test_null_arguments_are_rejected_without_touching_a_device():
     st = L.eik_dd_solve(None, None, None, None, None, None, None, None, None)
     assert st == E.EIK_ERR_ARG
     assert b"NULL" in L.eik_last_error()
-    assert L.eik_adjoint(None, None, None, None, None, None, None, None) == E.EIK_ERR_UNSUPPORTED
+    assert L.eik_adjoint(None, None, None, None, None, None, None, None) == E.EIK_ERR_ARG
+    assert L.eik_adjoint_batch(None, None, 0, None, None, None, None, None, None, 1, None, None) == E.EIK_ERR_ARG
