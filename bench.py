@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--theta", type=float, default=0.25)
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
