@@ -181,6 +181,27 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);
 
+/* eik_dd_solve_batch -- eik_dd_solve on nprob independent problems at once
+ * (d = 2, one dtype; the subdomains of Sec. 3.2 and the problems are all
+ * independent work): every DD step is one launch over the subdomains,
+ * lattices and causal-sweep segments of all problems that have not yet
+ * converged, and one readback per iteration serves all residuals.  Problem
+ * p stops like its own eik_dd_solve would (its tol / max_iter), and its
+ * outputs are exactly those of eik_dd_solve(grids[p], r[p], &gammas[p],
+ * &opts[p], u_out[p], U_out[p], W_out[p]).
+ *   grids, gammas, opts, stats  host arrays of nprob entries (opts[p].debug
+ *                               must be NULL); stats may be NULL; the
+ *                               device-time fields of every entry hold the
+ *                               batch's totals
+ *   r, u_out                    host arrays of nprob device pointers
+ *   U_out, W_out                host arrays of nprob device pointers (entries
+ *                               may be NULL) or NULL
+ * Returns EIK_ERR_NOCONV if any problem reached its max_iter (all outputs
+ * written). */
+eik_status eik_dd_solve_batch(int32_t nprob, const eik_grid* grids, const void* const* r,
+                              const eik_gamma* gammas, const eik_dd_opts* opts, void* const* u_out,
+                              void* const* U_out, int8_t* const* W_out, eik_stats* stats, void* hip_stream);
+
 /* eik_adjoint_batch -- gradient of a loss L of converged travel times with
  * respect to the slowness, for nb problems on one grid and slowness (e.g.
  * one per source), by the discrete adjoint of the upwind scheme (eq.

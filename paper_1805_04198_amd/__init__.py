@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "
                 -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE"}
 
 # exported symbols of include/eik.h
-SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_adjoint", "eik_adjoint_batch", "eik_last_error",
-           "eik_release", "eik_version")
+SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_dd_solve_batch", "eik_adjoint", "eik_adjoint_batch",
+           "eik_last_error", "eik_release", "eik_version")
 
 
 class EikError(RuntimeError):
@@ -96,6 +96,9 @@ def load_library(path: Optional[str] = None):
     L.eik_dd_solve.restype = ctypes.c_int32
     L.eik_dd_solve.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
                                ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
+    L.eik_dd_solve_batch.restype = ctypes.c_int32
+    L.eik_dd_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
+                                     ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
     L.eik_adjoint.restype = ctypes.c_int32
     L.eik_adjoint.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma), vp, vp, vp, vp, vp]
     L.eik_adjoint_batch.restype = ctypes.c_int32
@@ -226,6 +229,74 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     if debug:
         out.update(dbg_t)
     return out
+
+
+def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
+                   max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
+                   theta_refs=None, history_cap: int = 4096):
+    """eik_dd_solve_batch: the DD iteration on independent 2D problems at
+    once (every DD step is one launch over all problems that have not
+    converged).  rs: list of device slowness tensors (one dtype); gammas:
+    list of (idx, val); hs: list of spacings; S, M, theta, tol, max_iter,
+    theta_mode: one value for all or a list.  Returns a list of result dicts
+    as dd_solve, plus the batch's device time in each."""
+    torch = _torch()
+    L = load_library()
+    P = len(rs)
+    per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * P
+    hs, Ss, Ms, thetas, tols = per(hs), per(S), per(M), per(theta), per(tol)
+    iters, modes = per(max_iter), per(theta_mode)
+    refs = per(theta_refs) if theta_refs is not None else [None] * P
+    grids = (Grid * P)()
+    gms = (Gamma * P)()
+    opts = (DDOpts * P)()
+    stats = (Stats * P)()
+    rptr = (ctypes.c_void_p * P)()
+    uptr = (ctypes.c_void_p * P)()
+    Uptr = (ctypes.c_void_p * P)()
+    Wptr = (ctypes.c_void_p * P)()
+    keep, outs, hists = [], [], []
+    for p in range(P):
+        r = rs[p].contiguous()
+        keep.append(r)
+        grids[p] = _grid(r, hs[p])
+        gm, k = _gamma(gammas[p][0], gammas[p][1], r)
+        gms[p] = gm
+        keep.append(k)
+        mi = iters[p] if iters[p] is not None else 4 * (int(grids[p].n[0]) - 1) // Ms[p] + 16
+        o = opts[p]
+        o.S, o.M, o.theta, o.tol = int(Ss[p]), int(Ms[p]), float(thetas[p]), float(tols[p])
+        o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(mi), int(max_fine_sweeps), int(max_coarse_sweeps)
+        o.theta_mode = THETA_MODES[modes[p]]
+        for q_, v in enumerate(theta_params):
+            o.theta_params[q_] = float(v)
+        if refs[p] is not None:
+            tr = refs[p].to(device=r.device, dtype=r.dtype).contiguous()
+            keep.append(tr)
+            o.theta_ref = tr.data_ptr()
+        u = torch.empty_like(r)
+        U = torch.empty_like(r)
+        W = torch.empty(r.shape, dtype=torch.int8, device=r.device)
+        outs.append((u, U, W))
+        rptr[p], uptr[p], Uptr[p], Wptr[p] = r.data_ptr(), u.data_ptr(), U.data_ptr(), W.data_ptr()
+        h = (ctypes.c_double * max(1, history_cap))()
+        hists.append(h)
+        stats[p].residual_history = h
+        stats[p].history_cap = history_cap
+    status = L.eik_dd_solve_batch(P, grids, rptr, gms, opts, uptr, Uptr, Wptr, stats, _stream())
+    _check(L, status)
+    res = []
+    for p in range(P):
+        st = stats[p]
+        it = int(st.iterations)
+        u, U, W = outs[p]
+        res.append({"u": u, "U": U, "W": W, "status": status, "iterations": it,
+                    "converged": bool(st.converged), "fine_updates": int(st.fine_updates),
+                    "coarse_updates": int(st.coarse_updates),
+                    "residuals": list(hists[p][: min(it, history_cap)]), "ms_total": float(st.ms_total),
+                    "ms_fine": float(st.ms_fine), "ms_correct": float(st.ms_correct),
+                    "ms_causal": float(st.ms_causal)})
+    return res
 
 
 def adjoint(r, gammas, u, dL_du, h, wind=None, max_sweeps: int = 100000, with_lambda: bool = False):

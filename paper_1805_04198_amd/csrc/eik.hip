@@ -383,6 +383,397 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
 }
 
 // ---------------------------------------------------------------------------
+// eik_dd_solve_batch, d = 2: many independent problems, every DD step one
+// launch over the subdomains / lattices / segments of all active problems
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct BatchProb {
+  eik::DD2<T> A;
+  int ntile = 0, nlat = 0, nC = 0, nH = 0, nV = 0;
+  int64_t N = 0, nrec = 0, nres = 0, npair = 0;
+  size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
+  int tmode = 0;
+  T* hist_u = nullptr;
+  T* hist_c[3] = {nullptr, nullptr, nullptr};
+  T* gfull = nullptr;
+  bool active = true, conv = false, resumed = false;
+  int it = 0;
+  double last = 0.0;
+  unsigned long long* counters = nullptr;
+};
+
+// work table: (problem, block) for every block of every selected problem
+template <typename F>
+static void build_work(std::vector<int2>& out, int P, F blocks_of) {
+  out.clear();
+  for (int p = 0; p < P; ++p) {
+    const int64_t nb = blocks_of(p);
+    for (int64_t b = 0; b < nb; ++b) out.push_back(make_int2(p, (int)b));
+  }
+}
+
+template <typename T>
+eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, const eik_gamma* gam,
+                            const eik_dd_opts* o, void* const* u_out, void* const* U_out, int8_t* const* W_out,
+                            eik_stats* st, hipStream_t s) {
+  const size_t szT = sizeof(T);
+  const int bs = 256;
+  std::vector<BatchProb<T>> pr(P);
+  size_t need = 4096 + (size_t)P * (sizeof(eik::DD2<T>) + 4 * 8) + 512;
+  int64_t tot_tile = 0, tot_lat = 0, tot_rec = 0, tot_res = 0, tot_ca = 0, tot_cc = 0;
+  size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
+  for (int p = 0; p < P; ++p) {
+    const eik_dd_opts* op = &o[p];
+    BatchProb<T>& q = pr[p];
+    const int n0 = (int)G[p].n[0], n1 = (int)G[p].n[1];
+    const int S = op->S, M = op->M;
+    if (G[p].dim != 2) return fail(EIK_ERR_UNSUPPORTED, "batch: problem %d is not 2D", p);
+    if (G[p].dtype != G[0].dtype) return fail(EIK_ERR_ARG, "batch: all problems need the same dtype");
+    if (M < 2 || S < M || S % M != 0) return fail(EIK_ERR_SHAPE, "problem %d: need M >= 2 and S a multiple of M", p);
+    if ((n0 - 1) % S != 0 || (n1 - 1) % S != 0) return fail(EIK_ERR_SHAPE, "problem %d: (n-1) %% S != 0", p);
+    if (S + 1 > eik::kMaxL) return fail(EIK_ERR_UNSUPPORTED, "problem %d: S+1 > %d", p, eik::kMaxL);
+    const int NI = (n0 - 1) / M, NJ = (n1 - 1) / M;
+    if (NI + 1 > eik::kMaxL || NJ + 1 > eik::kMaxL)
+      return fail(EIK_ERR_UNSUPPORTED, "problem %d: coarse lattice extent > %d nodes", p, eik::kMaxL);
+    if (!(op->theta >= 0.0 && op->theta <= 1.0)) return fail(EIK_ERR_ARG, "problem %d: theta outside [0,1]", p);
+    if (op->max_iter < 0 || op->max_fine_sweeps < 1 || op->max_coarse_sweeps < 1)
+      return fail(EIK_ERR_ARG, "problem %d: bad iteration or sweep caps", p);
+    if ((op->U_init == nullptr) != (op->W_init == nullptr))
+      return fail(EIK_ERR_ARG, "problem %d: U_init and W_init go together", p);
+    if (op->debug) return fail(EIK_ERR_ARG, "problem %d: debug snapshots are not available in a batch", p);
+    eik_status e = check_theta(op);
+    if (e != EIK_OK) return e;
+    if (!rv[p] || !u_out[p] || rv[p] == u_out[p]) return fail(EIK_ERR_ARG, "problem %d: bad r / u_out", p);
+    q.tmode = op->theta_mode;
+    const int L = S + 1;
+    q.lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
+    q.lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT) +
+                             (q.tmode ? eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 0, 8) : 0),
+                         eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
+    q.lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
+    if (q.lds_tile > kLdsBytes || q.lds_lat > kLdsBytes || q.lds_cb > kLdsBytes)
+      return fail(EIK_ERR_UNSUPPORTED, "problem %d: LDS footprint too large", p);
+    lds_tile = std::max(lds_tile, q.lds_tile);
+    lds_lat = std::max(lds_lat, q.lds_lat);
+    lds_cb = std::max(lds_cb, q.lds_cb);
+    q.N = (int64_t)n0 * n1;
+    const int P0 = (n0 - 1) / S, P1 = (n1 - 1) / S;
+    q.ntile = P0 * P1;
+    q.nlat = 2 * M - 1;
+    q.nC = (NI + 1) * (NJ + 1);
+    q.nH = NI * (NJ + 1);
+    q.nV = (NI + 1) * NJ;
+    q.nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
+    q.nres = (int64_t)(NJ + 1) * n0 + (int64_t)(NI + 1) * n1;
+    q.npair = gam[p].count * (int64_t)(2 * M - 1) * (2 * M - 1);
+    q.resumed = op->U_init != nullptr;
+    size_t nd = 0;
+    nd += 7 * (q.N * szT + 256);
+    nd += 6 * (q.N + 256);
+    nd += 2 * (q.N * 8 + 256);
+    nd += (size_t)q.ntile * 4 * L * (szT + 1) + 512;
+    nd += q.nC * (szT + 1) + (q.nH + q.nV) * (szT + 1) + 2048;
+    if (q.tmode == EIK_THETA_ESTIMATE) nd += 4 * (q.N * szT + 256);
+    need += nd;
+    tot_tile += q.ntile;
+    tot_lat += q.nlat;
+    tot_rec += nblocks(q.nrec, bs);
+    tot_res += nblocks(q.nres, bs);
+    tot_ca += nblocks(q.nC + q.nH + q.nV, bs);
+    tot_cc += nblocks(q.nH + q.nV, bs);
+  }
+  int64_t tot_near = 0;
+  for (int p = 0; p < P; ++p) tot_near += nblocks(pr[p].npair, bs);
+  const int64_t tot_work = tot_tile + tot_lat + tot_rec + tot_res + tot_ca + tot_cc + P + tot_near;
+  need += (size_t)tot_work * sizeof(int2) + 8 * 256;
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::DD2<T>* d_desc = cv.take<eik::DD2<T>>(P);
+  unsigned long long* d_cnt = cv.take<unsigned long long>(4 * (size_t)P);
+  unsigned int* dflag = cv.take<unsigned int>(4);
+  // one device table per kind of launch, sized for all problems
+  int2* w_tile = cv.take<int2>(std::max<int64_t>(tot_tile, 1));
+  int2* w_lat = cv.take<int2>(std::max<int64_t>(tot_lat, 1));
+  int2* w_rec = cv.take<int2>(std::max<int64_t>(tot_rec, 1));
+  int2* w_res = cv.take<int2>(std::max<int64_t>(tot_res, 1));
+  int2* w_ca = cv.take<int2>(std::max<int64_t>(tot_ca, 1));
+  int2* w_cc = cv.take<int2>(std::max<int64_t>(tot_cc, 1));
+  int2* w_cb = cv.take<int2>(P);
+  int2* w_near = cv.take<int2>(std::max<int64_t>(tot_near, 1));
+  for (int p = 0; p < P; ++p) {
+    BatchProb<T>& q = pr[p];
+    const eik_dd_opts* op = &o[p];
+    eik::DD2<T>& A = q.A;
+    const int n0 = (int)G[p].n[0], n1 = (int)G[p].n[1];
+    const int S = op->S, M = op->M, L = S + 1;
+    const int64_t N = q.N;
+    A.n0 = n0; A.n1 = n1; A.S = S; A.M = M; A.P0 = (n0 - 1) / S; A.P1 = (n1 - 1) / S;
+    A.NI = (n0 - 1) / M; A.NJ = (n1 - 1) / M;
+    A.hT = (T)G[p].h;
+    A.HT = (T)((double)M * G[p].h);
+    A.theta = (T)op->theta;
+    A.max_fine_sweeps = op->max_fine_sweeps;
+    A.max_coarse_sweeps = op->max_coarse_sweeps;
+    A.r = as<T>(rv[p]);
+    A.gidx = gam[p].idx;
+    A.gval = as<T>(gam[p].g);
+    A.ng = gam[p].count;
+    q.gfull = cv.take<T>(N);
+    A.gfull = q.gfull;
+    A.U = cv.take<T>(N);
+    A.Un = cv.take<T>(N);
+    A.uk = cv.take<T>(N);
+    A.cwork = cv.take<T>(N);
+    A.W = cv.take<uint8_t>(N);
+    A.Wn = cv.take<uint8_t>(N);
+    A.wk = cv.take<uint8_t>(N);
+    A.cflag = cv.take<uint8_t>(N);
+    A.near_key = cv.take<unsigned long long>(N);
+    A.near_win = cv.take<long long>(N);
+    A.edge_u = cv.take<T>((size_t)q.ntile * 4 * L);
+    A.edge_w = cv.take<uint8_t>((size_t)q.ntile * 4 * L);
+    A.corner_v = cv.take<T>(q.nC);
+    A.corner_f = cv.take<uint8_t>(q.nC);
+    A.hseg_p = cv.take<T>(std::max(q.nH, 1));
+    A.hseg_l = cv.take<uint8_t>(std::max(q.nH, 1));
+    A.vseg_p = cv.take<T>(std::max(q.nV, 1));
+    A.vseg_l = cv.take<uint8_t>(std::max(q.nV, 1));
+    A.counters = d_cnt + 4 * (size_t)p;
+    A.u_out = as<T>(u_out[p]);
+    A.theta_mode = q.tmode;
+    set_theta<T>(A.tq, op);
+    A.tref = as<T>(op->theta_ref);
+    A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
+    A.ck_out = nullptr;
+    if (q.tmode == EIK_THETA_ESTIMATE) {
+      q.hist_u = cv.take<T>(N);
+      for (auto& c : q.hist_c) c = cv.take<T>(N);
+    }
+    if ((e = validate<T>(A.r, N, &gam[p], dflag, host, s)) != EIK_OK) return e;
+  }
+  if ((e = allow_lds(eik::k_tile_b<T>, lds_tile)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_init_b<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_lattice_correct_b<T>, lds_lat)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal_b_b<T>, lds_cb)) != EIK_OK) return e;
+
+  hipEvent_t ev[5];
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 5; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  HIPCHK(hipEventRecord(ev[0], s));
+  const T nanT = (T)NAN;
+  HIPCHK(hipMemsetAsync(d_cnt, 0, 4 * (size_t)P * sizeof(unsigned long long), s));
+  std::vector<eik::DD2<T>> hdesc(P);
+  auto upload_desc = [&]() -> eik_status {
+    for (int p = 0; p < P; ++p) hdesc[p] = pr[p].A;
+    HIPCHK(hipMemcpyAsync(d_desc, hdesc.data(), (size_t)P * sizeof(eik::DD2<T>), hipMemcpyHostToDevice, s));
+    return EIK_OK;
+  };
+  std::vector<int2> tab;
+  auto upload = [&](int2* dst, std::vector<int2>& v) -> eik_status {
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // the host vector is reused
+    return EIK_OK;
+  };
+  // per-problem set-up (as in the single solve)
+  for (int p = 0; p < P; ++p) {
+    eik::DD2<T>& A = pr[p].A;
+    const int64_t N = pr[p].N;
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, pr[p].gfull, nanT, N);
+    if (gam[p].count > 0)
+      hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam[p].count, bs)), dim3(bs), 0, s, pr[p].gfull,
+                         gam[p].idx, as<T>(gam[p].g), gam[p].count);
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.u_out, nanT, N);
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.uk, nanT, N);
+    HIPCHK(hipMemsetAsync(A.wk, 0, N, s));
+    if (pr[p].resumed) {
+      hipLaunchKernelGGL(eik::k_import_U<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, as<T>(o[p].U_init), A.U);
+      HIPCHK(hipMemcpyAsync(A.W, o[p].W_init, N, hipMemcpyDeviceToDevice, s));
+    } else {
+      hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.U, nanT, N);
+      HIPCHK(hipMemsetAsync(A.W, 0, N, s));
+      HIPCHK(hipMemsetAsync(A.near_key, 0xff, N * sizeof(unsigned long long), s));
+      hipLaunchKernelGGL(eik::k_fill<long long>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.near_win,
+                         (long long)0x7fffffffffffffffll, N);
+    }
+    hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.Un, nanT, N);
+    HIPCHK(hipMemsetAsync(A.Wn, 0, N, s));
+  }
+  HIPCHK(hipGetLastError());
+  if ((e = upload_desc()) != EIK_OK) return e;
+  // Step 1 for the problems that do not resume
+  auto fresh = [&](int p) { return !pr[p].resumed; };
+  build_work(tab, P, [&](int p) { return fresh(p) ? (int64_t)nblocks(pr[p].npair, bs) : 0; });
+  if (!tab.empty()) {
+    if ((e = upload(w_near, tab)) != EIK_OK) return e;
+    hipLaunchKernelGGL(eik::k_near_a_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
+    hipLaunchKernelGGL(eik::k_near_b_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
+  }
+  int64_t tot_cb_ = 0;
+  auto causal_batch = [&](int which) -> eik_status {
+    // tables for the selected problems are in w_ca, w_cb, w_cc (counts below)
+    for (int dir = 0; dir < 4; ++dir) {
+      const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
+      hipLaunchKernelGGL(eik::k_causal_a_b<T>, dim3((unsigned)tot_ca), dim3(bs), 0, s, d_desc, w_ca, which, sx, sy);
+      hipLaunchKernelGGL(eik::k_causal_b_b<T>, dim3((unsigned)tot_cb_), dim3(eik::kBlock), lds_cb, s, d_desc, w_cb,
+                         which, dir);
+      hipLaunchKernelGGL(eik::k_causal_c_b<T>, dim3((unsigned)tot_cc), dim3(bs), 0, s, d_desc, w_cc, which, sx, sy);
+    }
+    HIPCHK(hipGetLastError());
+    return EIK_OK;
+  };
+  auto set_tables = [&](auto sel) -> eik_status {
+    eik_status ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)pr[p].ntile : 0; });
+    tot_tile = (int64_t)tab.size();
+    if ((ee = upload(w_tile, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)pr[p].nlat : 0; });
+    tot_lat = (int64_t)tab.size();
+    if ((ee = upload(w_lat, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nrec, bs) : 0; });
+    tot_rec = (int64_t)tab.size();
+    if ((ee = upload(w_rec, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nres, bs) : 0; });
+    tot_res = (int64_t)tab.size();
+    if ((ee = upload(w_res, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nC + pr[p].nH + pr[p].nV, bs) : 0; });
+    tot_ca = (int64_t)tab.size();
+    if ((ee = upload(w_ca, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)1 : 0; });
+    tot_cb_ = (int64_t)tab.size();
+    if ((ee = upload(w_cb, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nH + pr[p].nV, bs) : 0; });
+    tot_cc = (int64_t)tab.size();
+    if ((ee = upload(w_cc, tab)) != EIK_OK) return ee;
+    return EIK_OK;
+  };
+  if ((e = set_tables(fresh)) != EIK_OK) return e;
+  if (tot_lat > 0) {
+    hipLaunchKernelGGL(eik::k_lattice_init_b<T>, dim3((unsigned)tot_lat), dim3(eik::kBlock), lds_lat, s, d_desc, w_lat);
+    if ((e = causal_batch(0)) != EIK_OK) return e;
+  }
+  // the DD iteration
+  int max_iter = 0;
+  for (int p = 0; p < P; ++p) {
+    max_iter = std::max(max_iter, o[p].max_iter);
+    pr[p].active = o[p].max_iter > 0;
+  }
+  auto is_active = [&](int p) { return pr[p].active; };
+  if ((e = set_tables(is_active)) != EIK_OK) return e;
+  std::vector<unsigned long long> hc(4 * (size_t)P);
+  float ms_fine = 0.f, ms_correct = 0.f, ms_causal = 0.f;
+  eik_status bad = EIK_OK;
+  for (int k = 0; k < max_iter && tot_tile > 0; ++k) {
+    for (int p = 0; p < P; ++p) {
+      BatchProb<T>& q = pr[p];
+      if (!q.active || q.tmode != EIK_THETA_ESTIMATE) continue;
+      q.A.ck_out = q.hist_c[k % 3];
+      q.A.ckm1 = k >= 1 ? q.hist_c[(k + 2) % 3] : nullptr;
+      q.A.ckm2 = k >= 2 ? q.hist_c[(k + 1) % 3] : nullptr;
+      q.A.ukm1 = k >= 1 ? q.hist_u : nullptr;
+    }
+    if ((e = upload_desc()) != EIK_OK) return e;
+    HIPCHK(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(eik::k_tile_b<T>, dim3((unsigned)tot_tile), dim3(eik::kBlock), lds_tile, s, d_desc, w_tile);
+    HIPCHK(hipEventRecord(ev[2], s));
+    if (tot_rec > 0)
+      hipLaunchKernelGGL(eik::k_reconcile_b<T>, dim3((unsigned)tot_rec), dim3(bs), 0, s, d_desc, w_rec);
+    hipLaunchKernelGGL(eik::k_lattice_correct_b<T>, dim3((unsigned)tot_lat), dim3(eik::kBlock), lds_lat, s, d_desc,
+                       w_lat);
+    for (int p = 0; p < P; ++p)
+      if (pr[p].active && pr[p].tmode == EIK_THETA_ESTIMATE)
+        HIPCHK(hipMemcpyAsync(pr[p].hist_u, pr[p].A.uk, pr[p].N * szT, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipEventRecord(ev[3], s));
+    if ((e = causal_batch(1)) != EIK_OK) return e;
+    // clear the residual word of every problem, then the residuals
+    HIPCHK(hipMemset2DAsync(d_cnt + 2, 4 * sizeof(unsigned long long), 0, sizeof(unsigned long long), P, s));
+    hipLaunchKernelGGL(eik::k_residual_b<T>, dim3((unsigned)tot_res), dim3(bs), 0, s, d_desc, w_res);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[4], s));
+    HIPCHK(hipMemcpyAsync(hc.data(), d_cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float a = 0.f, b = 0.f, c = 0.f;
+    HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[3]));
+    HIPCHK(hipEventElapsedTime(&c, ev[3], ev[4]));
+    ms_fine += a;
+    ms_correct += b;
+    ms_causal += c;
+    bool changed_set = false;
+    for (int p = 0; p < P; ++p) {
+      BatchProb<T>& q = pr[p];
+      if (!q.active) continue;
+      double delta;
+      std::memcpy(&delta, &hc[4 * (size_t)p + 2], sizeof delta);
+      std::swap(q.A.U, q.A.Un);
+      std::swap(q.A.W, q.A.Wn);
+      q.it = k + 1;
+      q.last = delta;
+      if (st && st[p].residual_history && k < st[p].history_cap) st[p].residual_history[k] = delta;
+      bool stop = false;
+      if (std::isnan(delta)) {
+        bad = fail(EIK_ERR_NONFINITE, "problem %d: residual is NaN", p);
+        stop = true;
+      } else if (delta < o[p].tol || delta == 0.0) {
+        q.conv = true;
+        stop = true;
+      } else if (q.it >= o[p].max_iter) {
+        stop = true;
+      }
+      if (stop) {
+        q.active = false;
+        changed_set = true;
+      }
+    }
+    if (changed_set && (e = set_tables(is_active)) != EIK_OK) return e;
+  }
+  // outputs
+  for (int p = 0; p < P; ++p) {
+    eik::DD2<T>& A = pr[p].A;
+    if (U_out && U_out[p])
+      hipLaunchKernelGGL(eik::k_export_U<T>, dim3(nblocks(pr[p].N, bs)), dim3(bs), 0, s, A, A.U, as<T>(U_out[p]));
+    if (W_out && W_out[p]) HIPCHK(hipMemcpyAsync(W_out[p], A.W, pr[p].N, hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipMemcpyAsync(hc.data(), d_cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(ev[4], s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  float tot = 0.f;
+  HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[4]));
+  bool all_conv = true;
+  for (int p = 0; p < P; ++p) {
+    const bool conv = pr[p].conv || o[p].max_iter == 0;
+    all_conv = all_conv && conv;
+    if (!st) continue;
+    st[p].iterations = pr[p].it;
+    st[p].converged = pr[p].conv ? 1 : 0;
+    st[p].fine_updates = (int64_t)hc[4 * (size_t)p + 0];
+    st[p].coarse_updates = (int64_t)hc[4 * (size_t)p + 1];
+    st[p].sweeps = 0;
+    st[p].final_residual = pr[p].last;
+    st[p].ms_total = tot;
+    st[p].ms_fine = ms_fine;
+    st[p].ms_coarse = tot - ms_fine;
+    st[p].ms_correct = ms_correct;
+    st[p].ms_causal = ms_causal;
+  }
+  if (bad != EIK_OK) return bad;
+  if (!all_conv) return fail(EIK_ERR_NOCONV, "some problems did not converge within max_iter");
+  return EIK_OK;
+}
+
+// ---------------------------------------------------------------------------
 // eik_dd_solve, d = 3
 // ---------------------------------------------------------------------------
 
@@ -969,6 +1360,20 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
   if (grid->dtype == EIK_F32)
     return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
   return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+}
+
+eik_status eik_dd_solve_batch(int32_t nprob, const eik_grid* grids, const void* const* r, const eik_gamma* gammas,
+                              const eik_dd_opts* opts, void* const* u_out, void* const* U_out, int8_t* const* W_out,
+                              eik_stats* stats, void* hip_stream) {
+  if (nprob < 1 || !grids || !r || !gammas || !opts || !u_out) return fail(EIK_ERR_ARG, "NULL argument or nprob < 1");
+  for (int p = 0; p < nprob; ++p) {
+    eik_status e = check_common(&grids[p], r[p], &gammas[p], u_out[p]);
+    if (e != EIK_OK) return e;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grids[0].dtype == EIK_F32)
+    return dd_solve_batch_t<float>(nprob, grids, r, gammas, opts, u_out, U_out, W_out, stats, s);
+  return dd_solve_batch_t<double>(nprob, grids, r, gammas, opts, u_out, U_out, W_out, stats, s);
 }
 
 eik_status eik_adjoint_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,

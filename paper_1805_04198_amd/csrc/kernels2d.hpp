@@ -697,19 +697,28 @@ __device__ __forceinline__ bool near_candidate(const DD2<T>& A, int64_t gi, int 
 }
 
 template <typename T>
-__global__ void k_near_a(DD2<T> A) {
+__device__ __forceinline__ void near_a_body(const DD2<T>& A, int bx) {
   const int W2 = 2 * A.M - 1;
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
   if (t >= A.ng * W2 * W2) return;
   int X;
   T v;
   if (near_candidate(A, t / (W2 * W2), (int)(t % (W2 * W2)), X, v)) atomicMin(&A.near_key[X], okey(v));
 }
+template <typename T>
+__global__ void k_near_a(DD2<T> A) { near_a_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ void k_near_a_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  near_a_body(A, w.y);
+}
+
 
 template <typename T>
-__global__ void k_near_b(DD2<T> A) {
+__device__ __forceinline__ void near_b_body(const DD2<T>& A, int bx) {
   const int W2 = 2 * A.M - 1;
-  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
   if (t >= A.ng * W2 * W2) return;
   int X;
   T v;
@@ -717,6 +726,15 @@ __global__ void k_near_b(DD2<T> A) {
   if (near_candidate(A, gi, (int)(t % (W2 * W2)), X, v))
     if (okey(v) == A.near_key[X]) atomicMin(&A.near_win[X], (long long)gi);
 }
+template <typename T>
+__global__ void k_near_b(DD2<T> A) { near_b_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ void k_near_b_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  near_b_body(A, w.y);
+}
+
 
 // ---------------------------------------------------------------------------
 // LDS boxes
@@ -748,10 +766,10 @@ __device__ __forceinline__ void lattice_offset(int q, int M, int& o0, int& o1) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lattice_init(DD2<T> A) {
+__device__ __forceinline__ void lattice_init_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   int o0, o1;
-  lattice_offset(blockIdx.x, A.M, o0, o1);
+  lattice_offset(bx, A.M, o0, o1);
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
@@ -804,12 +822,21 @@ __global__ __launch_bounds__(kBlock) void k_lattice_init(DD2<T> A) {
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lattice_init(DD2<T> A) { lattice_init_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lattice_init_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  lattice_init_body(A, w.y);
+}
+
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
+__device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   int o0, o1;
-  lattice_offset(blockIdx.x, A.M, o0, o1);
+  lattice_offset(bx, A.M, o0, o1);
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
@@ -930,15 +957,24 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) {
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) { lattice_correct_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  lattice_correct_body(A, w.y);
+}
+
 
 // ---------------------------------------------------------------------------
 // Steps 2 and 3: one wave per subdomain
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) {
+__device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int I = blockIdx.x % A.P0, J = blockIdx.x / A.P0;
+  const int I = bx % A.P0, J = bx / A.P0;
   const int L = A.S + 1;
   const int SP = halo_stride(L);
   const int cnt = halo_count(L, L);
@@ -993,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) {
     if (threadIdx.x == 0) sh_ns = ns;
   }
   __syncthreads();
-  const int tile = blockIdx.x;
+  const int tile = bx;
   for (int k = threadIdx.x; k < L * L; k += kBlock) {
     const int li = k % L, lj = k / L;
     const int xi = bi + li, yi = bj + lj;
@@ -1020,6 +1056,15 @@ __global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) {
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) { tile_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  tile_body(A, w.y);
+}
+
 
 // ---------------------------------------------------------------------------
 // eik_solve: one directional sweep of the whole grid, boxes in wavefront order
@@ -1115,10 +1160,10 @@ __global__ void k_grid_init(GS2<T> A) {
 // node.  Threads: (P0-1) vertical interface lines x n1 nodes, then (P1-1)
 // horizontal lines x n0 nodes (crossings are done by the vertical pass).
 template <typename T>
-__global__ void k_reconcile(DD2<T> A) {
+__device__ __forceinline__ void reconcile_body(const DD2<T>& A, int bx) {
   const int64_t nv = (int64_t)(A.P0 - 1) * A.n1;
   const int64_t nh = (int64_t)(A.P1 - 1) * A.n0;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
   int xi, yi;
   if (t < nv) {
     xi = (int)(t / A.n1 + 1) * A.S;
@@ -1193,6 +1238,15 @@ __global__ void k_reconcile(DD2<T> A) {
   A.wk[X] = cw[best];
   A.u_out[X] = cu[best];
 }
+template <typename T>
+__global__ void k_reconcile(DD2<T> A) { reconcile_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  reconcile_body(A, w.y);
+}
+
 
 // ---------------------------------------------------------------------------
 // causal sweep (Alg. causalsweep2D), one direction = three kernels
@@ -1212,11 +1266,11 @@ template <typename T>
 __device__ __forceinline__ T vmax(T a, T b) { return a < b ? b : a; }
 
 template <typename T>
-__global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) {
+__device__ __forceinline__ void causal_a_body(const DD2<T>& A, int bx, T* U, const uint8_t* W, int sx, int sy) {
   const int nC = (A.NI + 1) * (A.NJ + 1);
   const int nH = A.NI * (A.NJ + 1);
   const int nV = (A.NI + 1) * A.NJ;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = bx * blockDim.x + threadIdx.x;
   const int M = A.M;
   if (t < nC) {
     const int I = t % (A.NI + 1), J = t / (A.NI + 1);
@@ -1288,6 +1342,16 @@ __global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) {
   if (horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
   else { A.vseg_p[s] = P; A.vseg_l[s] = L ? 1 : 0; }
 }
+template <typename T>
+__global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) { causal_a_body(A, (int)blockIdx.x, U, W, sx, sy); }
+// batched: which = 0 sweeps U/W of each problem, 1 sweeps Un/Wn
+template <typename T>
+__global__ void k_causal_a_b(const DD2<T>* descs, const int2* work, int which, int sx, int sy) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  causal_a_body(A, w.y, which ? A.Un : A.U, which ? A.Wn : A.W, sx, sy);
+}
+
 
 // The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
 // on the coarse grid of corners, swept by one wave like a subdomain: the
@@ -1331,7 +1395,7 @@ struct CausalRule {
 };
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_causal_b(DD2<T> A, T* U, int dir) {
+__device__ __forceinline__ void causal_b_body(const DD2<T>& A, int bx, T* U, int dir) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int CI = A.NI + 1, CJ = A.NJ + 1;
@@ -1371,12 +1435,21 @@ __global__ __launch_bounds__(kBlock) void k_causal_b(DD2<T> A, T* U, int dir) {
     U[(I * A.M) + A.n0 * (J * A.M)] = cu[(J + 1) * SP + (I + 1)];
   }
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_causal_b(DD2<T> A, T* U, int dir) { causal_b_body(A, (int)blockIdx.x, U, dir); }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_causal_b_b(const DD2<T>* descs, const int2* work, int which, int dir) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  causal_b_body(A, w.y, which ? A.Un : A.U, dir);
+}
+
 
 template <typename T>
-__global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
+__device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy) {
   const int nH = A.NI * (A.NJ + 1);
   const int nV = (A.NI + 1) * A.NJ;
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  int s = bx * blockDim.x + threadIdx.x;
   bool horiz;
   int I, J;
   if (s < nH) { horiz = true; I = s % A.NI; J = s / A.NI; }
@@ -1406,13 +1479,22 @@ __global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
     }
   }
 }
+template <typename T>
+__global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) { causal_c_body(A, (int)blockIdx.x, U, sx, sy); }
+template <typename T>
+__global__ void k_causal_c_b(const DD2<T>* descs, const int2* work, int which, int sx, int sy) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  causal_c_body(A, w.y, which ? A.Un : A.U, sx, sy);
+}
+
 
 // max |Un - U| over the skeleton, |inf - inf| = 0, NaN counts as +inf.
 template <typename T>
-__global__ void k_residual(DD2<T> A) {
+__device__ __forceinline__ void residual_body(const DD2<T>& A, int bx) {
   const int64_t nh = (int64_t)(A.NJ + 1) * A.n0;
   const int64_t nv = (int64_t)(A.NI + 1) * A.n1;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
   double dv = 0.0;
   if (t < nh) {
     const int X = (int)(t % A.n0) + A.n0 * ((int)(t / A.n0) * A.M);
@@ -1434,16 +1516,28 @@ __global__ void k_residual(DD2<T> A) {
   if ((threadIdx.x & 63) == 0 && dv > 0.0)
     atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(dv));
 }
+template <typename T>
+__global__ void k_residual(DD2<T> A) { residual_body(A, (int)blockIdx.x); }
+template <typename T>
+__global__ void k_residual_b(const DD2<T>* descs, const int2* work) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  residual_body(A, w.y);
+}
+
 
 // U_out: U on the skeleton, NaN elsewhere
 template <typename T>
-__global__ void k_export_U(DD2<T> A, const T* U, T* out) {
+__device__ __forceinline__ void export_U_body(const DD2<T>& A, int bx, const T* U, T* out) {
   const int64_t N = (int64_t)A.n0 * A.n1;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
   if (t >= N) return;
   const int xi = (int)(t % A.n0), yi = (int)(t / A.n0);
   out[t] = (xi % A.M == 0 || yi % A.M == 0) ? U[t] : T(__builtin_nan(""));
 }
+template <typename T>
+__global__ void k_export_U(DD2<T> A, const T* U, T* out) { export_U_body(A, (int)blockIdx.x, U, out); }
+
 
 template <typename T>
 __global__ void k_import_U(DD2<T> A, const T* Uin, T* U) {

@@ -262,6 +262,43 @@ def model_strip(N: int, M: int) -> Problem:
     return Problem(f"strip_N{N}_M{M}", n, h, r, gi, gv, S=M, M=M)
 
 
+def config4(n_prob: int = 64, seed: int = 4, sizes=(257, 513, 1025, 2049)) -> list:
+    """Batching workload: n_prob independent 2D problems, side lengths drawn
+    uniformly from `sizes`, subdomains of 64^2 cells (S = 64).  Each problem
+    has its own medium, the config-2 recipe with r0 = 1 and the wavenumber
+    band [1/eps, 4/eps], eps drawn from {1/32, 1/64} (32 modes, phase and
+    direction uniform, amplitude N(0, 0.02), floored at 0.2), and one random
+    interior source node with g = 0.  H is not stated: M = 16 where the
+    coarse lattices then have <= 65 nodes per axis (n <= 1025), else
+    M = (n-1)/64 (M = 32 at n = 2049).  Per-problem generators come from
+    SeedSequence(seed).spawn."""
+    children = np.random.SeedSequence(seed).spawn(n_prob)
+    out = []
+    for i, ss in enumerate(children):
+        rng = np.random.default_rng(ss)
+        n_side = int(rng.choice(sizes))
+        eps = float(rng.choice([1.0 / 32, 1.0 / 64]))
+        n = (n_side, n_side)
+        h = 1.0 / (n_side - 1)
+        kmag = rng.uniform(1.0 / eps, 4.0 / eps, 32)
+        ang = rng.uniform(0.0, 2 * np.pi, 32)
+        phi = rng.uniform(0.0, 2 * np.pi, 32)
+        amp = rng.normal(0.0, 0.02, 32)
+        # sum_k amp_k cos(2 pi k (x cos a + y sin a) + phi), each mode split
+        # into x and y factors: cos(X + Y) = cos X cos Y - sin X sin Y
+        t = np.arange(n_side, dtype=np.float64) * h
+        X = 2 * np.pi * np.outer(t, kmag * np.cos(ang))             # (nx, 32)
+        Y = 2 * np.pi * np.outer(t, kmag * np.sin(ang)) + phi        # (ny, 32)
+        a = (np.cos(Y) * amp) @ np.cos(X).T - (np.sin(Y) * amp) @ np.sin(X).T   # (ny, nx)
+        r = np.maximum(1.0 + a, 0.2)
+        src = (int(rng.integers(1, n_side - 1)), int(rng.integers(1, n_side - 1)))
+        gi, gv = _gamma(n, [src], [0.0])
+        M = 16 if (n_side - 1) // 16 + 1 <= 65 else (n_side - 1) // 64
+        out.append(Problem(f"c4_{i}_{n_side}sq_eps{int(round(1 / eps))}", n, h, r, gi, gv, S=64, M=M,
+                           theta=0.25, tol=1e-6))
+    return out
+
+
 @dataclasses.dataclass
 class GradProblem:
     """The travel-time gradient workload: one slowness, many point sources,

@@ -1,0 +1,101 @@
+"""GPU batching (eik_dd_solve_batch): every problem of a batch gives exactly
+the results of its own eik_dd_solve (which the other GPU tests hold to the
+oracle bit for bit), whatever else is in the batch and whenever the others
+converge; and a batch checked directly against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_04198_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1805_04198_amd as E  # noqa: E402
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def inputs(p, dtype):
+    return (dev(p.r, dtype), (torch.from_numpy(p.gamma_idx).cuda(), dev(p.gamma_val, dtype)))
+
+
+def same_t(a, b):
+    return torch.equal(torch.nan_to_num(a, nan=-7.0), torch.nan_to_num(b, nan=-7.0))
+
+
+MIX = [
+    dict(seed=80, n=(65, 65), S=16, M=8, kind="fourier", theta=0.3, mode="constant"),
+    dict(seed=81, n=(129, 97), S=32, M=8, kind="blocks", theta=0.25, mode="constant"),
+    dict(seed=82, n=(97, 161), S=32, M=16, kind="fourier", theta=0.5, mode="estimate"),
+    dict(seed=83, n=(33, 33), S=16, M=4, kind="const", theta=0.2, mode="field"),
+    dict(seed=84, n=(257, 129), S=64, M=16, kind="fourier", theta=0.25, mode="constant"),
+    dict(seed=85, n=(65, 129), S=32, M=8, kind="fourier", theta=0.7, mode="constant"),  # may not converge
+]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batch_equals_single_solves(dtype):
+    probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=2, kind=c["kind"]) for c in MIX]
+    tol = 1e-6 if dtype == np.float32 else 1e-12
+    rs, gams, refs = [], [], []
+    for c, p in zip(MIX, probs):
+        r, g = inputs(p, dtype)
+        rs.append(r)
+        gams.append(g)
+        refs.append(dev(np.full(p.r.shape, 0.35), dtype) if c["mode"] == "field" else None)
+    print(f"batch of {len(probs)} dtype={np.dtype(dtype).name}", flush=True)
+    B = E.dd_solve_batch(rs, gams, [p.h for p in probs], [c["S"] for c in MIX], [c["M"] for c in MIX],
+                         theta=[c["theta"] for c in MIX], tol=tol, max_iter=60,
+                         theta_mode=[c["mode"] for c in MIX], theta_refs=refs)
+    for i, (c, p) in enumerate(zip(MIX, probs)):
+        S_ = E.dd_solve(rs[i], gams[i][0], gams[i][1], p.h, c["S"], c["M"], theta=c["theta"], tol=tol, max_iter=60,
+                        theta_mode=c["mode"], theta_ref=refs[i])
+        b = B[i]
+        assert b["iterations"] == S_["iterations"], (i, b["iterations"], S_["iterations"])
+        assert b["converged"] == S_["converged"]
+        assert b["fine_updates"] == S_["fine_updates"] and b["coarse_updates"] == S_["coarse_updates"]
+        assert b["residuals"] == S_["residuals"]
+        assert same_t(b["u"], S_["u"]) and same_t(b["U"], S_["U"]) and torch.equal(b["W"], S_["W"]), i
+
+
+def test_batch_against_oracle():
+    cases = [dict(seed=90, n=(65, 65), S=16, M=8), dict(seed=91, n=(97, 65), S=32, M=16),
+             dict(seed=92, n=(129, 129), S=32, M=8)]
+    probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=1) for c in cases]
+    rs, gams = zip(*[inputs(p, np.float64) for p in probs])
+    print("batch vs oracle fp64", flush=True)
+    B = E.dd_solve_batch(list(rs), list(gams), [p.h for p in probs], [c["S"] for c in cases],
+                         [c["M"] for c in cases], theta=0.25, tol=0.0, max_iter=5)
+    for b, p in zip(B, probs):
+        O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=0.25, tol=0.0, max_iter=5)
+        assert np.array_equal(b["U"].cpu().numpy().reshape(-1), O["U"], equal_nan=True)
+        assert np.array_equal(b["u"].cpu().numpy().reshape(-1), O["u"])
+        assert b["fine_updates"] == O["fine_updates"] and b["coarse_updates"] == O["coarse_updates"]
+
+
+def test_config4_sample_batch_equals_single():
+    """A sample of the batching workload (the 257 and 513 problems among the
+    first 16): batch vs single solves, fp32 to convergence."""
+    probs = [p for p in W.config4(n_prob=16) if p.n[0] <= 513][:6]
+    rs, gams = zip(*[inputs(p, np.float32) for p in probs])
+    print(f"config4 sample {[p.n[0] for p in probs]}", flush=True)
+    B = E.dd_solve_batch(list(rs), list(gams), [p.h for p in probs], [p.S for p in probs], [p.M for p in probs],
+                         theta=0.25, tol=1e-6, max_iter=400)
+    for i, p in enumerate(probs):
+        S_ = E.dd_solve(rs[i], gams[i][0], gams[i][1], p.h, p.S, p.M, theta=0.25, tol=1e-6, max_iter=400)
+        assert B[i]["iterations"] == S_["iterations"] and same_t(B[i]["u"], S_["u"]), i
+
+
+def test_batch_argument_errors():
+    p = W.random_problem(93, (65, 65), 16, 8)
+    r, g = inputs(p, np.float32)
+    r64, g64 = inputs(p, np.float64)
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve_batch([r, r64], [g, g64], [p.h, p.h], 16, 8, max_iter=2)
+    assert ei.value.status == E.EIK_ERR_ARG
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve_batch([r, r], [g, g], [p.h, p.h], [16, 12], 8, max_iter=2)
+    assert ei.value.status == E.EIK_ERR_SHAPE
