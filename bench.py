@@ -39,6 +39,10 @@ OPS_PER_CORRECTION = 18
 # = 39.3 T lane-ops/s (the published 157.3 TFLOP/s fp32 counts an FMA as two
 # flops and packed fp32 as two lanes; 78.6 TFLOP/s fp64 counts the FMA).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# 3D local solve: 3 neighbour minima (6 compares), a 3-element sort (3
+# compares), the one-, two- and three-sided roots (~12 ops and 2 sqrt, one
+# division), the FSM minimum compare: about 25 algorithmic ops per update
+OPS3_PER_UPDATE = 25
 
 
 def parse():
@@ -51,6 +55,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"], default="config2",
+                    help="config2 (default): the headline 2D DD solve; config3: 3D 257^3; config4: 64 "
+                         "problems in one batched solve; config5: batched travel-time gradient")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
@@ -105,6 +112,191 @@ def cpu_baseline(p, theta, iters):
                       f"{R['fine_updates']} fine updates in {dt:.2f} s"}
 
 
+def common(a, metric, value, unit, ms, dtype, workload, extra):
+    line = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": {"workload": workload, "global_batch": 1, "seq_len": None,
+                                            "parallelism": "none"}}
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def bench_config3(a):
+    """3D 257^3, S = 32, M = 8, fp32, theta = 0.1, tol 1e-6 (the weight is
+    not stated for this workload; 0.25 stalls in an fp32 limit cycle)."""
+    import numpy as np
+    import torch
+
+    import paper_1805_04198_amd as E
+    from paper_1805_04198_amd import workloads as W
+    p = W.config3()
+    r = torch.from_numpy(p.r.astype(np.float32)).cuda()
+    gi = torch.from_numpy(p.gamma_idx).cuda()
+    gv = torch.from_numpy(p.gamma_val.astype(np.float32)).cuda()
+    kw = dict(theta=0.1, tol=1e-6, max_iter=400)
+    for _ in range(a.warmup):
+        E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    last = outs[-1]
+    fine = sum(o["fine_updates"] for o in outs)
+    uf, _, _ = E.solve(r, gi, gv, p.h)
+    err = float((last["u"] - uf).abs().max() / uf.max())
+    it = last["iterations"]
+    upl = last["fine_updates"] / it
+    msl = last["ms_fine"] / it
+    ach = upl * OPS3_PER_UPDATE / (msl * 1e-3) / 1e12
+    extra = {"iterations": it, "converged": last["converged"], "fine_updates_per_solve": last["fine_updates"],
+             "rel_err_vs_gpu_fine_fsm": err, "gate": 2e-5,
+             "ms_fine_per_solve": last["ms_fine"], "ms_correct_per_solve": last["ms_correct"],
+             "ms_causal_per_solve": last["ms_causal"],
+             "roofline": {"bound": "alu", "kernel": "k_tile3 (Step 3 subdomain FSM, 33^3 boxes)", "achieved": ach,
+                          "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None,
+                          "per_launch": {"updates": upl, "ms": msl, "ops_per_update": OPS3_PER_UPDATE}}}
+    if not a.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=0.1, tol=0.0, max_iter=1,
+                      dtype=np.float32)
+        dt = time.perf_counter() - t0
+        extra["cpu_baseline"] = {"value": R["fine_updates"] / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"config 3: Step 1 + 1 DD iteration, fp32 serial oracle, "
+                                           f"{R['fine_updates']} fine updates in {dt:.1f} s"}
+    common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle", fine / wall,
+           "updates/s", wall * 1e3 / a.steps, "f32",
+           "config 3: 3D 257^3, h=1/256, 8^3 subdomains (S=32), H=1/32 (M=8), sin-product x lognormal "
+           "block slowness (seed 3), two sources, theta=0.1, tol=1e-6", extra)
+
+
+def bench_config4(a):
+    """64 independent 2D problems (257^2..2049^2), autotuned S, M, theta per
+    size, one batched solve; compared with the same problems solved one by
+    one with the same parameters (identical results)."""
+    import numpy as np
+    import torch
+
+    import paper_1805_04198_amd as E
+    from paper_1805_04198_amd import autotune
+    from paper_1805_04198_amd import workloads as W
+    P = W.config4()
+    rs = [torch.from_numpy(p.r.astype(np.float32)).cuda() for p in P]
+    gams = [(torch.from_numpy(p.gamma_idx).cuda(), torch.from_numpy(p.gamma_val.astype(np.float32)).cuda())
+            for p in P]
+    hs = [p.h for p in P]
+    t0 = time.perf_counter()
+    best, table = autotune.tune(rs, gams, hs, tol=1e-6, max_iter=300)
+    t_tune = time.perf_counter() - t0
+    S, M, th = autotune.apply(rs, best)
+    kw = dict(tol=1e-6, max_iter=600)
+    for _ in range(a.warmup):
+        E.dd_solve_batch(rs, gams, hs, S, M, theta=th, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        B = E.dd_solve_batch(rs, gams, hs, S, M, theta=th, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fine = sum(b["fine_updates"] for b in B)
+    t0 = time.perf_counter()
+    same = 0
+    for i in range(len(P)):
+        R = E.dd_solve(rs[i], gams[i][0], gams[i][1], hs[i], S[i], M[i], theta=th[i], **kw)
+        same += int(R["iterations"] == B[i]["iterations"] and torch.equal(R["u"], B[i]["u"]))
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    extra = {"problems": len(P), "converged": sum(b["converged"] for b in B), "identical_to_single": same,
+             "fine_updates_per_batch": fine, "ms_single_solves_total": t_single * 1e3,
+             "speedup_vs_single_solves": t_single / (wall / a.steps), "autotune_s": t_tune,
+             "tuned": {f"{k[1]}x{k[0]}": {"S": v[0], "M": v[1], "theta": v[2]} for k, v in best.items()},
+             "max_iterations": max(b["iterations"] for b in B)}
+    common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle", fine / wall,
+           "updates/s", wall * 1e3 / a.steps, "f32",
+           "config 4: 64 independent 2D problems, sides {257,513,1025,2049} (seed 4), 64^2-cell subdomains "
+           "(autotuned), random-Fourier media, random point sources, tol=1e-6, one batched solve", extra)
+
+
+def bench_config5(a):
+    """Travel-time gradient: 1025^2, 32 top-edge sources, 256 receivers,
+    targets solved through the perturbed slowness; one step = forward solves
+    of all sources + the batched adjoint (fp32).  Central differences of the
+    loss (fp64 forward solves) on 20 random cells check the gradient."""
+    import numpy as np
+    import torch
+
+    import paper_1805_04198_amd as E
+    from paper_1805_04198_amd import workloads as W
+    p = W.config5_problem()
+    r = torch.from_numpy(p.r.astype(np.float32)).cuda()
+    rcv = torch.from_numpy(p.receivers).cuda()
+    with torch.no_grad():
+        rp = torch.from_numpy(p.r_perturbed.astype(np.float32)).cuda()
+        target = E.travel_times(rp, p.h, p.sources).reshape(len(p.sources), -1)[:, rcv]
+
+    def step(rr):
+        rr = rr.detach().requires_grad_(True)
+        U = E.travel_times(rr, p.h, p.sources)
+        loss = ((U.reshape(len(p.sources), -1)[:, rcv] - target) ** 2).sum()
+        loss.backward()
+        return float(loss), rr.grad
+
+    for _ in range(a.warmup):
+        step(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        loss, g = step(r)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # central differences in fp64 on 20 random cells
+    r64 = torch.from_numpy(p.r).cuda()
+    t64 = target.double()
+    cells = np.random.default_rng(5).choice(p.r.size, 20, replace=False)
+    worst = 0.0
+
+    def loss64(rr):
+        with torch.no_grad():
+            U = E.travel_times(rr, p.h, p.sources)
+            return float(((U.reshape(len(p.sources), -1)[:, rcv] - t64) ** 2).sum())
+
+    rr64 = r64.clone().requires_grad_(True)
+    U = E.travel_times(rr64, p.h, p.sources)
+    L = ((U.reshape(len(p.sources), -1)[:, rcv] - t64) ** 2).sum()
+    L.backward()
+    gd = rr64.grad.reshape(-1).cpu().numpy()
+    g32 = g.reshape(-1).double().cpu().numpy()
+    fd_rows = []
+    for c in cells:
+        eps = 1e-6 * float(p.r.reshape(-1)[c])
+        rr = r64.clone().reshape(-1)
+        rr[c] += eps
+        lp = loss64(rr.reshape(p.r.shape))
+        rr[c] -= 2 * eps
+        lm = loss64(rr.reshape(p.r.shape))
+        fd = (lp - lm) / (2 * eps)
+        print(f"bench.py: fd cell {len(fd_rows) + 1}/20", file=sys.stderr, flush=True)
+        scale = max(abs(fd), abs(gd[c]), 1e-12)
+        rel = abs(fd - gd[c]) / scale if scale > 1e-9 else 0.0
+        worst = max(worst, rel)
+        fd_rows.append((int(c), fd, float(gd[c]), float(g32[c]), rel))
+    rels = np.array([x[4] for x in fd_rows])
+    extra = {"sources": len(p.sources), "receivers": len(p.receivers), "loss": loss,
+             "fd_check_fp64": {"cells": len(fd_rows), "within_1e-4": int(np.sum(rels <= 1e-4)),
+                               # central differences resolve about 1e-9 absolute here
+                               # (loss rounding / step); smaller gradients are below it
+                               "pass_rel1e-4_abs1e-9": int(sum(abs(x[1] - x[2]) <= 1e-4 * abs(x[2]) + 1e-9
+                                                               for x in fd_rows)),
+                               "median_rel_err": float(np.median(rels)), "max_rel_err": worst},
+             "fd_cells": fd_rows,
+             "fp32_vs_fp64_grad_max_rel": float(np.max(np.abs(g32 - gd)) / max(np.max(np.abs(gd)), 1e-30))}
+    common(a, "gradient evaluations/s (32 forward FSM solves + batched adjoint)", a.steps / wall, "gradients/s",
+           wall * 1e3 / a.steps, "f32",
+           "config 5: 2D 1025^2, config-1 slowness, 32 top-edge sources, 256 bottom-edge receivers, targets "
+           "through r + 8 Gaussian bumps (seed 5)", extra)
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -115,6 +307,9 @@ def main():
               "path would shard subdomains across GPUs with one skeleton exchange per "
               "iteration, which is not built.", file=sys.stderr)
         sys.exit(2)
+    if a.workload != "config2":
+        {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[a.workload](a)
+        return
     import numpy as np
     import torch
 

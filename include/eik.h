@@ -181,6 +181,22 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);
 
+/* eik_solve_batch -- eik_solve for nb problems on one grid and slowness,
+ * each with its own Gamma (e.g. one point source each): every launch of a
+ * sweep covers one box diagonal of all problems that have not yet had a
+ * sweep without change.  Problem b's u and winds are exactly those of its
+ * own eik_solve (a problem whose sweep changed nothing is stationary and is
+ * not swept again).
+ *   gammas    host array of nb boundary sets
+ *   u_out     device, nb x N (problem b at offset b*N)
+ *   wind_out  device, nb x N codes, or NULL
+ *   stats     host array of nb entries or NULL (sweeps per problem; device
+ *             time of the whole call)
+ * This build: d = 2. */
+eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
+                           int32_t max_sweeps, void* u_out, int8_t* wind_out, eik_stats* stats,
+                           void* hip_stream);
+
 /* eik_dd_solve_batch -- eik_dd_solve on nprob independent problems at once
  * (d = 2, one dtype; the subdomains of Sec. 3.2 and the problems are all
  * independent work): every DD step is one launch over the subdomains,

@@ -24,8 +24,8 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "
                 -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE"}
 
 # exported symbols of include/eik.h
-SYMBOLS = ("eik_solve", "eik_dd_solve", "eik_dd_solve_batch", "eik_adjoint", "eik_adjoint_batch",
-           "eik_last_error", "eik_release", "eik_version")
+SYMBOLS = ("eik_solve", "eik_solve_batch", "eik_dd_solve", "eik_dd_solve_batch", "eik_adjoint",
+           "eik_adjoint_batch", "eik_last_error", "eik_release", "eik_version")
 
 
 class EikError(RuntimeError):
@@ -96,6 +96,9 @@ def load_library(path: Optional[str] = None):
     L.eik_dd_solve.restype = ctypes.c_int32
     L.eik_dd_solve.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
                                ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
+    L.eik_solve_batch.restype = ctypes.c_int32
+    L.eik_solve_batch.argtypes = [ctypes.POINTER(Grid), vp, ctypes.c_int32, ctypes.POINTER(Gamma), ctypes.c_int32,
+                                  vp, vp, ctypes.POINTER(Stats), vp]
     L.eik_dd_solve_batch.restype = ctypes.c_int32
     L.eik_dd_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
                                      ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
@@ -231,6 +234,32 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     return out
 
 
+def solve_batch(r, gammas, h, max_sweeps: int = 100000, with_wind: bool = False):
+    """eik_solve_batch: the whole-grid FSM for several boundary sets (e.g.
+    one source each) on one slowness.  gammas: list of (idx, val).  Returns
+    (u (nb, *r.shape), wind codes or None, list of stats dicts)."""
+    torch = _torch()
+    L = load_library()
+    r = r.contiguous()
+    g = _grid(r, h)
+    nb = len(gammas)
+    gms = (Gamma * nb)()
+    keep = []
+    for b, (gi, gv) in enumerate(gammas):
+        gm, k = _gamma(gi, gv, r)
+        gms[b] = gm
+        keep.append(k)
+    u = torch.empty((nb,) + tuple(r.shape), dtype=r.dtype, device=r.device)
+    w = torch.empty(u.shape, dtype=torch.int8, device=r.device) if with_wind else None
+    st = (Stats * nb)()
+    status = L.eik_solve_batch(ctypes.byref(g), r.data_ptr(), nb, gms, int(max_sweeps), u.data_ptr(),
+                               w.data_ptr() if w is not None else None, st, _stream())
+    _check(L, status)
+    info = [{"status": status, "converged": bool(x.converged), "sweeps": int(x.sweeps),
+             "updates": int(x.fine_updates), "ms": float(x.ms_total)} for x in st]
+    return u, w, info
+
+
 def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
                    max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
                    theta_refs=None, history_cap: int = 4096):
@@ -340,21 +369,16 @@ def _travel_times_function():
     torch = _torch()
 
     class TravelTimes(torch.autograd.Function):
-        """u_b = the converged fine travel times (eik_solve) from point source
-        b (g = 0 there), stacked; the backward pass is the batched adjoint."""
+        """u_b = the converged fine travel times (eik_solve_batch) from point
+        source b (g = 0 there), stacked; the backward pass is the batched
+        adjoint."""
 
         @staticmethod
         def forward(ctx, r, h, sources):
-            us, ws, gams = [], [], []
-            for s_ in sources:
-                gi = torch.tensor([int(s_)], dtype=torch.int64, device=r.device)
-                gv = torch.zeros(1, dtype=r.dtype, device=r.device)
-                u, w, _ = solve(r, gi, gv, h, with_wind=True)
-                us.append(u)
-                ws.append(w)
-                gams.append((gi, gv))
-            U = torch.stack(us)
-            ctx.save_for_backward(r, U, torch.stack(ws))
+            gams = [(torch.tensor([int(s_)], dtype=torch.int64, device=r.device),
+                     torch.zeros(1, dtype=r.dtype, device=r.device)) for s_ in sources]
+            U, Wd, _ = solve_batch(r, gams, h, with_wind=True)
+            ctx.save_for_backward(r, U, Wd)
             ctx.h = h
             ctx.gams = gams
             return U

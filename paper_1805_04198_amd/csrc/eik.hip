@@ -1123,13 +1123,18 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
 // eik_solve, d = 2
 // ---------------------------------------------------------------------------
 
+// eik_solve on nb problems that share the grid and the slowness (one
+// Gamma each, e.g. one source each): every launch of a sweep covers the
+// boxes of one box diagonal of all problems that have not yet had a sweep
+// without change; a problem that had one is stationary and is left alone.
 template <typename T>
-eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int32_t max_sweeps,
+eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* gam, int32_t max_sweeps,
                    void* u_outv, int8_t* wind_out, eik_stats* st, hipStream_t s) {
   const int n0 = (int)G->n[0], n1 = (int)G->n[1];
   const int64_t N = (int64_t)n0 * n1;
+  const int64_t NB = (int64_t)nb * N;
   if (max_sweeps < 1) return fail(EIK_ERR_ARG, "max_sweeps must be >= 1");
-  auto side = [](int n) { int nb = (n + eik::kMaxL - 1) / eik::kMaxL; return (n + nb - 1) / nb; };
+  auto side = [](int n) { int k = (n + eik::kMaxL - 1) / eik::kMaxL; return (n + k - 1) / k; };
   const int B = std::max(side(n0), side(n1));
   const int BX = (n0 + B - 1) / B, BY = (n1 + B - 1) / B;
   int dev = 0;
@@ -1137,7 +1142,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
   if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
   std::lock_guard<std::mutex> lock(g_ws[dev].mu);
   const size_t szT = sizeof(T);
-  size_t need = N * szT + 256 + (wind_out ? 0 : N + 256) + 4096;
+  size_t need = NB * szT + 256 + (wind_out ? 0 : NB + 256) + 4096 + 8 * (size_t)nb + 512;
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -1147,63 +1152,78 @@ eik_status solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int3
   A.n0 = n0; A.n1 = n1; A.B = B; A.BX = BX; A.BY = BY;
   A.hT = (T)G->h;
   A.r = as<T>(rv);
-  T* gfull = cv.take<T>(N);
+  T* gfull = cv.take<T>(NB);
   A.gfull = gfull;
   A.u = as<T>(u_outv);
-  A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(N);
+  A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(NB);
   unsigned int* dflag = cv.take<unsigned int>(4);
-  A.changed = dflag + 1;
-  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  unsigned int* dchg = cv.take<unsigned int>(nb);
+  int* dmem = cv.take<int>(nb);
+  A.changed = dchg;
+  A.members = dmem;
+  for (int b = 0; b < nb; ++b)
+    if ((e = validate<T>(A.r, N, &gam[b], dflag, host, s)) != EIK_OK) return e;
   const size_t lds = eik::box_bytes(eik::halo_count(B, B), 2, 1, szT);
   if ((e = allow_lds(eik::k_grid_sweep<T>, lds)) != EIK_OK) return e;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } evg{e0, e1};
   HIPCHK(hipEventRecord(e0, s));
   const int bs = 256;
-  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, (T)NAN, N);
-  if (gam->count > 0)
-    hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
-                       gam->idx, as<T>(gam->g), gam->count);
-  hipLaunchKernelGGL(eik::k_grid_init<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(NB, bs)), dim3(bs), 0, s, gfull, (T)NAN, NB);
+  for (int b = 0; b < nb; ++b)
+    if (gam[b].count > 0)
+      hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam[b].count, bs)), dim3(bs), 0, s,
+                         gfull + (int64_t)b * N, gam[b].idx, as<T>(gam[b].g), gam[b].count);
+  hipLaunchKernelGGL(eik::k_grid_init<T>, dim3(nblocks(N, bs), nb), dim3(bs), 0, s, A);
   HIPCHK(hipGetLastError());
-  int sw = 0, conv = 0;
-  while (sw < max_sweeps) {
+  std::vector<int> active(nb), sweeps(nb, 0);
+  std::vector<unsigned int> hchg(nb);
+  for (int b = 0; b < nb; ++b) active[b] = b;
+  int sw = 0;
+  while (sw < max_sweeps && !active.empty()) {
     const int dir = sw & 3;
-    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
+    const int na = (int)active.size();
+    HIPCHK(hipMemcpyAsync(dmem, active.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(dchg, 0, nb * sizeof(unsigned int), s));
     for (int d = 0; d <= BX + BY - 2; ++d) {
       const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
-      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1), dim3(eik::kBlock), lds, s, A, dir, d);
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1, na), dim3(eik::kBlock), lds, s, A, dir, d);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hchg.data(), dchg, nb * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     ++sw;
-    if (*(unsigned int*)host == 0) {
-      conv = 1;
-      break;
+    std::vector<int> next;
+    for (int b : active) {
+      sweeps[b] = sw;
+      if (hchg[b]) next.push_back(b);
     }
+    active.swap(next);
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (st) {
-    st->iterations = 0;
-    st->converged = conv;
-    st->sweeps = sw;
-    st->fine_updates = (int64_t)sw * (N - gam->count);
-    st->coarse_updates = 0;
-    st->final_residual = 0.0;
-    st->ms_total = ms;
-    st->ms_fine = ms;
-    st->ms_coarse = 0.f;
-    st->ms_correct = 0.f;
-    st->ms_causal = 0.f;
+    for (int b = 0; b < nb; ++b) {
+      const bool done = std::find(active.begin(), active.end(), b) == active.end();
+      st[b].iterations = 0;
+      st[b].converged = done ? 1 : 0;
+      st[b].sweeps = sweeps[b];
+      st[b].fine_updates = (int64_t)sweeps[b] * (N - gam[b].count);
+      st[b].coarse_updates = 0;
+      st[b].final_residual = 0.0;
+      st[b].ms_total = ms;
+      st[b].ms_fine = ms;
+      st[b].ms_coarse = st[b].ms_correct = st[b].ms_causal = 0.f;
+    }
   }
-  if (!conv) return fail(EIK_ERR_NOCONV, "FSM not stationary after %d sweeps", sw);
+  if (!active.empty()) return fail(EIK_ERR_NOCONV, "FSM not stationary after %d sweeps", sw);
   return EIK_OK;
 }
 
@@ -1343,8 +1363,8 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
     if (grid->dtype == EIK_F32) return solve3_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
     return solve3_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
   }
-  if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
-  return solve_t<double>(grid, r, gamma, max_sweeps, u_out, wind_out, stats, s);
+  if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, 1, gamma, max_sweeps, u_out, wind_out, stats, s);
+  return solve_t<double>(grid, r, 1, gamma, max_sweeps, u_out, wind_out, stats, s);
 }
 
 eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma, const eik_dd_opts* opts,
@@ -1360,6 +1380,19 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
   if (grid->dtype == EIK_F32)
     return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
   return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+}
+
+eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
+                           int32_t max_sweeps, void* u_out, int8_t* wind_out, eik_stats* stats, void* hip_stream) {
+  if (!gammas || nb < 1) return fail(EIK_ERR_ARG, "need nb >= 1 boundary sets");
+  for (int b = 0; b < nb; ++b) {
+    eik_status e = check_common(grid, r, &gammas[b], u_out);
+    if (e != EIK_OK) return e;
+  }
+  if (grid->dim != 2) return fail(EIK_ERR_UNSUPPORTED, "eik_solve_batch: d = 3 is not implemented in this build");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, nb, gammas, max_sweeps, u_out, wind_out, stats, s);
+  return solve_t<double>(grid, r, nb, gammas, max_sweeps, u_out, wind_out, stats, s);
 }
 
 eik_status eik_dd_solve_batch(int32_t nprob, const eik_grid* grids, const void* const* r, const eik_gamma* gammas,

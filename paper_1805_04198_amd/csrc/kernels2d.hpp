@@ -1077,10 +1077,11 @@ struct GS2 {
   int BX, BY;       // boxes per axis
   T hT;
   const T* r;
-  const T* gfull;
-  T* u;
-  uint8_t* w;
-  unsigned int* changed;
+  const T* gfull;   // [member][N]
+  T* u;             // [member][N]
+  uint8_t* w;       // [member][N]
+  unsigned int* changed;  // [member]
+  const int* members;     // batch: blockIdx.y -> member (NULL: member = blockIdx.y)
 };
 
 // Boxes with (I' + J') == diag in sweep order.  Box (I, J) reads its halo
@@ -1091,6 +1092,13 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int diag) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
+  // problem of the batch (same grid and slowness, its own Gamma)
+  const int mem = A.members ? A.members[blockIdx.y] : (int)blockIdx.y;
+  const int64_t mo = (int64_t)mem * A.n0 * A.n1;
+  A.gfull += mo;
+  A.u += mo;
+  A.w += mo;
+  A.changed += mem;
   const int q0 = max(0, diag - (A.BY - 1));
   const int Iq = q0 + (int)blockIdx.x;
   const int Jq = diag - Iq;
@@ -1151,9 +1159,10 @@ __global__ void k_grid_init(GS2<T> A) {
   const int64_t N = (int64_t)A.n0 * A.n1;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= N) return;
-  const T g = A.gfull[t];
-  A.u[t] = disnan(g) ? pinf<T>() : g;
-  A.w[t] = 0;
+  const int64_t x = (int64_t)blockIdx.y * N + t;
+  const T g = A.gfull[x];
+  A.u[x] = disnan(g) ? pinf<T>() : g;
+  A.w[x] = 0;
 }
 
 // Reconciliation (Alg. fineupdate, per interface axis) at every interface

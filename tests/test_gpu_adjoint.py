@@ -150,6 +150,21 @@ def test_config5_full_size_two_sources_fp32():
     assert same(g, go), show_diff("grad", g, go)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_solve_batch_equals_single_solves(dtype):
+    n = (131, 70)
+    p = W.random_problem(13, n, 1, 1, kind="blocks")
+    r = dev(p.r, dtype)
+    srcs = [W.linear_index(n, i, j) for i, j in ((3, 69), (64, 0), (130, 35), (70, 40), (0, 0))]
+    gams = [(torch.tensor([s]).cuda(), torch.zeros(1, dtype=r.dtype).cuda()) for s in srcs]
+    print(f"solve_batch dtype={np.dtype(dtype).name}", flush=True)
+    U, Wd, info = E.solve_batch(r, gams, p.h, with_wind=True)
+    for b, (gi, gv) in enumerate(gams):
+        u, w, i1 = E.solve(r, gi, gv, p.h, with_wind=True)
+        assert torch.equal(U[b], u) and torch.equal(Wd[b], w), b
+        assert info[b]["sweeps"] == i1["sweeps"]
+
+
 def test_adjoint_errors():
     p = W.random_problem(12, (9, 9, 9), 1, 1)
     r = dev(p.r, np.float64)
