@@ -1049,6 +1049,10 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
   if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
   std::lock_guard<std::mutex> lock(g_ws[dev].mu);
   size_t need = N * szT + 256 + (wind_out ? 0 : N + 256) + 4096;
+  int nbx[3];
+  for (int a = 0; a < 3; ++a) nbx[a] = (n[a] + B - 1) / B;
+  const size_t nbox = (size_t)nbx[0] * nbx[1] * nbx[2];
+  need += 2 * (nbox * sizeof(int) + 256);
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -1065,6 +1069,8 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
   A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(N);
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.changed = dflag + 1;
+  A.eval_at = cv.take<int>(nbox);
+  A.chg_at = cv.take<int>(nbox);
   if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
   const size_t lds = (size_t)B * B * B * szT;
   if ((e = allow_lds(eik::k_grid_sweep3<T>, lds)) != EIK_OK) return e;
@@ -1078,6 +1084,8 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
     hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
                        gam->idx, as<T>(gam->g), gam->count);
   hipLaunchKernelGGL(eik::k_grid_init3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  HIPCHK(hipMemsetAsync(A.eval_at, 0xff, nbox * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(A.chg_at, 0xff, nbox * sizeof(int), s));
   HIPCHK(hipGetLastError());
   const int ndiag = A.nb[0] + A.nb[1] + A.nb[2] - 2;
   int sw = 0, conv = 0;
@@ -1086,7 +1094,7 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
     HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
     for (int d = 0; d < ndiag; ++d)
       hipLaunchKernelGGL(eik::k_grid_sweep3<T>, dim3(cells_on_diag(A.nb, d)), dim3(eik::kBlock3), lds, s, A,
-                         dir, d);
+                         dir, d, sw * ndiag + d);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1143,6 +1151,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   std::lock_guard<std::mutex> lock(g_ws[dev].mu);
   const size_t szT = sizeof(T);
   size_t need = NB * szT + 256 + (wind_out ? 0 : NB + 256) + 4096 + 8 * (size_t)nb + 512;
+  need += 2 * ((size_t)nb * BX * BY * sizeof(int) + 256);
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -1161,6 +1170,8 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   int* dmem = cv.take<int>(nb);
   A.changed = dchg;
   A.members = dmem;
+  A.eval_at = cv.take<int>((size_t)nb * BX * BY);
+  A.chg_at = cv.take<int>((size_t)nb * BX * BY);
   for (int b = 0; b < nb; ++b)
     if ((e = validate<T>(A.r, N, &gam[b], dflag, host, s)) != EIK_OK) return e;
   const size_t lds = eik::box_bytes(eik::halo_count(B, B), 2, 1, szT);
@@ -1180,6 +1191,8 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
       hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam[b].count, bs)), dim3(bs), 0, s,
                          gfull + (int64_t)b * N, gam[b].idx, as<T>(gam[b].g), gam[b].count);
   hipLaunchKernelGGL(eik::k_grid_init<T>, dim3(nblocks(N, bs), nb), dim3(bs), 0, s, A);
+  HIPCHK(hipMemsetAsync(A.eval_at, 0xff, (size_t)nb * BX * BY * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(A.chg_at, 0xff, (size_t)nb * BX * BY * sizeof(int), s));
   HIPCHK(hipGetLastError());
   std::vector<int> active(nb), sweeps(nb, 0);
   std::vector<unsigned int> hchg(nb);
@@ -1192,7 +1205,8 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
     HIPCHK(hipMemsetAsync(dchg, 0, nb * sizeof(unsigned int), s));
     for (int d = 0; d <= BX + BY - 2; ++d) {
       const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
-      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1, na), dim3(eik::kBlock), lds, s, A, dir, d);
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1, na), dim3(eik::kBlock), lds, s, A, dir, d,
+                         sw * (BX + BY - 1) + d);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hchg.data(), dchg, nb * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
@@ -1251,6 +1265,8 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   size_t need = (size_t)NB * (1 + 1) + 2 * 256;           // fixed, wd
   need += (size_t)NB * szT * (2 + 1 + 4) + 3 * 256;       // c, q, pc
   if (!lamv) need += (size_t)NB * szT + 256;
+  const int BXa = (n0 + B - 1) / B, BYa = (n1 + B - 1) / B;
+  need += 2 * ((size_t)nb * BXa * BYa * sizeof(int) + 256);  // box stamps
   need += 4096;
   void* wsv;
   unsigned long long* host;
@@ -1274,6 +1290,8 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   A.grad = as<T>(gradv);
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.changed = dflag + 1;
+  A.eval_at = cv.take<int>((size_t)nb * BXa * BYa);
+  A.chg_at = cv.take<int>((size_t)nb * BXa * BYa);
   // the slowness and every boundary set are checked like the forward solve's
   for (int b = 0; b < nb; ++b)
     if ((e = validate<T>(A.r, N, &gams[b], dflag, host, s)) != EIK_OK) return e;
@@ -1296,13 +1314,16 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   hipLaunchKernelGGL(eik::k_adj_coef<T>, gridN, dim3(bs), 0, s, A);
   hipLaunchKernelGGL(eik::k_adj_pull<T>, gridN, dim3(bs), 0, s, A);
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(NB, bs)), dim3(bs), 0, s, A.lam, T(0), NB);
+  HIPCHK(hipMemsetAsync(A.eval_at, 0xff, (size_t)nb * BXa * BYa * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(A.chg_at, 0xff, (size_t)nb * BXa * BYa * sizeof(int), s));
   HIPCHK(hipGetLastError());
   int sw = 0, conv = 0;
   while (sw < max_sweeps) {
     HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
     for (int d = 0; d <= A.BX + A.BY - 2; ++d) {
       const int q0 = std::max(0, d - (A.BY - 1)), q1 = std::min(d, A.BX - 1);
-      hipLaunchKernelGGL(eik::k_adj_sweep<T>, dim3(q1 - q0 + 1, nb), dim3(eik::kBlock), lds, s, A, sw & 3, d);
+      hipLaunchKernelGGL(eik::k_adj_sweep<T>, dim3(q1 - q0 + 1, nb), dim3(eik::kBlock), lds, s, A, sw & 3, d,
+                         sw * (A.BX + A.BY - 1) + d);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));

@@ -1082,14 +1082,33 @@ struct GS2 {
   uint8_t* w;       // [member][N]
   unsigned int* changed;  // [member]
   const int* members;     // batch: blockIdx.y -> member (NULL: member = blockIdx.y)
+  int* eval_at;           // [member][box] launch at which the box was last swept (-1: never)
+  int* chg_at;            // [member][box] launch at which it last changed (-1: never)
 };
+
+// A box must be swept unless it changed nothing when it was last swept and
+// none of its face neighbours has changed since: then every node's
+// neighbours kept their values since the node was last computed, so the
+// sweep would reproduce every value (the box is stationary).  t: this
+// launch's number (sweep * diagonals + diagonal); boxes on one diagonal
+// share no face.
+__device__ __forceinline__ bool box_needed(const int* eval_at, const int* chg_at, int I, int J, int BX, int BY) {
+  const int b = I + BX * J;
+  const int ev = eval_at[b];
+  if (chg_at[b] == ev) return true;  // changed at its last sweep, or never swept
+  if (I > 0 && chg_at[b - 1] > ev) return true;
+  if (I < BX - 1 && chg_at[b + 1] > ev) return true;
+  if (J > 0 && chg_at[b - BX] > ev) return true;
+  if (J < BY - 1 && chg_at[b + BX] > ev) return true;
+  return false;
+}
 
 // Boxes with (I' + J') == diag in sweep order.  Box (I, J) reads its halo
 // from global memory: the upwind neighbours were finished by the previous
 // diagonals, the downwind ones are untouched, so the sweep of the whole grid
 // is the paper's serial Gauss-Seidel sweep exactly.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int diag) {
+__global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int diag, int t) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   // problem of the batch (same grid and slowness, its own Gamma)
@@ -1099,12 +1118,15 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int di
   A.u += mo;
   A.w += mo;
   A.changed += mem;
+  A.eval_at += mem * A.BX * A.BY;
+  A.chg_at += mem * A.BX * A.BY;
   const int q0 = max(0, diag - (A.BY - 1));
   const int Iq = q0 + (int)blockIdx.x;
   const int Jq = diag - Iq;
   if (Iq >= A.BX || Jq < 0) return;
   const int I = sx > 0 ? Iq : A.BX - 1 - Iq;
   const int J = sy > 0 ? Jq : A.BY - 1 - Jq;
+  if (!box_needed(A.eval_at, A.chg_at, I, J, A.BX, A.BY)) return;
   const int bi = I * A.B, bj = J * A.B;
   const int L0 = min(A.B, A.n0 - bi), L1 = min(A.B, A.n1 - bj);
   const int SP = halo_stride(L0);
@@ -1151,7 +1173,13 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int di
     A.u[X] = u[x];
     A.w[X] = w[x];
   }
-  if (threadIdx.x == 0 && sh_ch) atomicOr(A.changed, 1u);
+  if (threadIdx.x == 0) {
+    A.eval_at[I + A.BX * J] = t;
+    if (sh_ch) {
+      A.chg_at[I + A.BX * J] = t;
+      atomicOr(A.changed, 1u);
+    }
+  }
 }
 
 template <typename T>

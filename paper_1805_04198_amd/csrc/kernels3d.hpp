@@ -910,7 +910,24 @@ struct GS3 {
   T* u;
   uint8_t* w;
   unsigned int* changed;
+  int* eval_at;    // [box] launch at which the box was last swept (-1: never)
+  int* chg_at;     // [box] launch at which it last changed (-1: never)
 };
+
+// the stationary-box test of the 2D whole-grid sweep (box_needed), with six
+// face neighbours
+__device__ __forceinline__ bool box_needed3(const int* eval_at, const int* chg_at, const int (&T)[3],
+                                           const int (&nb)[3]) {
+  const int b = T[0] + nb[0] * (T[1] + nb[1] * T[2]);
+  const int ev = eval_at[b];
+  if (chg_at[b] == ev) return true;
+  const int st[3] = {1, nb[0], nb[0] * nb[1]};
+  for (int a = 0; a < 3; ++a) {
+    if (T[a] > 0 && chg_at[b - st[a]] > ev) return true;
+    if (T[a] < nb[a] - 1 && chg_at[b + st[a]] > ev) return true;
+  }
+  return false;
+}
 
 template <typename T>
 __global__ void k_grid_init3(GS3<T> A) {
@@ -923,7 +940,7 @@ __global__ void k_grid_init3(GS3<T> A) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int diag) {
+__global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int diag, int t) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
   int rem = blockIdx.x;
@@ -939,6 +956,7 @@ __global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int 
   if (Iq < 0) return;
   const int Tb[3] = {s[0] > 0 ? Iq : A.nb[0] - 1 - Iq, s[1] > 0 ? Jq : A.nb[1] - 1 - Jq,
                      s[2] > 0 ? Kq : A.nb[2] - 1 - Kq};
+  if (!box_needed3(A.eval_at, A.chg_at, Tb, A.nb)) return;
   int o[3], L[3];
   for (int a = 0; a < 3; ++a) {
     o[a] = Tb[a] * A.B;
@@ -1008,7 +1026,14 @@ __global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int 
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
     A.u[base + p0 + p1 * gs1 + p2 * gs2] = u[x];
   }
-  if (ch && threadIdx.x == 0) atomicOr(A.changed, 1u);
+  if (threadIdx.x == 0) {
+    const int bidx = Tb[0] + A.nb[0] * (Tb[1] + A.nb[1] * Tb[2]);
+    A.eval_at[bidx] = t;
+    if (ch) {
+      A.chg_at[bidx] = t;
+      atomicOr(A.changed, 1u);
+    }
+  }
 }
 
 }  // namespace eik

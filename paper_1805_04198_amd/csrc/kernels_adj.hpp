@@ -42,6 +42,8 @@ struct ADJ2 {
   T* lam;             // [nb][N]
   T* grad;            // [N]
   unsigned int* changed;
+  int* eval_at;       // [nb][box] as in GS2 (box_needed)
+  int* chg_at;
 };
 
 template <typename T>
@@ -181,7 +183,7 @@ struct AdjRule {
 // problem blockIdx.y.  Halo values come from global memory (upwind boxes
 // finished, downwind boxes untouched); outside the grid they are 0.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, int dir, int diag) {
+__global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, int dir, int diag, int t) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int q0 = max(0, diag - (A.BY - 1));
@@ -190,6 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, int dir, int di
   if (Iq >= A.BX || Jq < 0) return;
   const int I = sx > 0 ? Iq : A.BX - 1 - Iq;
   const int J = sy > 0 ? Jq : A.BY - 1 - Jq;
+  // lambda(y) is a function of its neighbours only, so the stationary-box
+  // test of the forward sweeps applies unchanged
+  int* eval_at = A.eval_at + blockIdx.y * A.BX * A.BY;
+  int* chg_at = A.chg_at + blockIdx.y * A.BX * A.BY;
+  if (!box_needed(eval_at, chg_at, I, J, A.BX, A.BY)) return;
   const int bi = I * A.B, bj = J * A.B;
   const int L0 = min(A.B, A.n0 - bi), L1 = min(A.B, A.n1 - bj);
   const int SP = halo_stride(L0);
@@ -243,7 +250,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, int dir, int di
     const int li = k % L0, lj = k / L0;
     lamg[(bi + li) + (int64_t)A.n0 * (bj + lj)] = lam[(lj + 1) * SP + (li + 1)];
   }
-  if (threadIdx.x == 0 && sh_ch) atomicOr(A.changed, 1u);
+  if (threadIdx.x == 0) {
+    eval_at[I + A.BX * J] = t;
+    if (sh_ch) {
+      chg_at[I + A.BX * J] = t;
+      atomicOr(A.changed, 1u);
+    }
+  }
 }
 
 // dL/dr = sum over the batch, in order, of lambda_b q_b
