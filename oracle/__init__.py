@@ -70,7 +70,7 @@ def lib():
                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
                           vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
-                          ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]
+                          ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, ctypes.c_int]
             f = getattr(L, "eikref_adjoint" + sfx)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int, i64p, vp, vp, vp, vp,
@@ -151,7 +151,7 @@ THETA_PARAMS = (0.75, 0.01, 0.9, 1.0, 1.0, 1.0, 0.001)
 
 def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.float64,
        max_fine_sweeps=256, max_coarse_sweeps=32, U_init=None, W_init=None, hist_cap=4096,
-       theta_mode="constant", theta_params=THETA_PARAMS, theta_ref=None):
+       theta_mode="constant", theta_params=THETA_PARAMS, theta_ref=None, coarse_solver="godunov"):
     """The DD iteration of Sec. 3.2.  Returns a dict with the patched fine
     solution u, coarse values U (NaN off the skeleton), coarse winds W (d, N),
     the last iteration's reconciled fine values uk / winds wk, the last
@@ -159,7 +159,8 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
     theta_mode selects the Step 4 weight (see theta_node in eikref.c):
     "constant", "estimate" (eqs. secthetaest, thetaest), "reference"
     (M-bar minus a margin, theta_ref = u^f) or "field" (theta_ref = theta
-    per node)."""
+    per node).  coarse_solver: "godunov" (C_H of Sec. 3.2) or "l1" (the
+    homogenised coarse solver of the squares medium, Sec. 5.3)."""
     d = len(n)
     n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
     N = int(np.prod(n))
@@ -184,7 +185,8 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
         float(theta), float(tol), int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps),
         _p(Ui), _p(Wi), _p(u), _p(U), _p(W), _p(uk), _p(wk), _p(Upre), _i64(info),
         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(hist_cap), int(mode),
-        tpar.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(tref))
+        tpar.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(tref),
+        {"godunov": 0, "l1": 1}[coarse_solver])
     if st not in (0, -3):
         raise ValueError(f"eikref_dd: {STATUS.get(st, st)}")
     it = int(info[0])

@@ -23,6 +23,11 @@
  *                       closed form of the coarse solver C_H (Sec. 3.2), with
  *                       the wind rules of Alg. fineupdate2D (fine) and
  *                       Alg. update2D (coarse); 3D by the sorted cascade.
+ *                       Rule 2 is the homogenised coarse solver of the
+ *                       squares medium (Sec. 5.3, eq. homog): smallest
+ *                       neighbour plus r*H, i.e. r times the lattice L1
+ *                       distance, used in place of C_H in Steps 1 and 4
+ *                       when eikref_dd is given coarse_solver = 1.
  *   fsm_run          -- fast sweeping method (Sec. 1.1: initialisation, the
  *                       2^d orderings, eq. FSMupdate).
  *   eikref_fsm       -- FSM on the whole fine grid: the "overall fine
@@ -109,10 +114,35 @@ static int dir_sign(int d, int dir, int a) { return ((dir >> (d - 1 - a)) & 1) ?
  * ws[a] : wind sign of that choice (+1: minus-side neighbour, -1: plus side;
  *         ties take the plus side, as the strict '<' in the algorithms)
  * rd    : r * Delta (Delta = h on the fine grid, H on a coarse lattice)
- * rule  : 0 = fine wind rule (Alg. fineupdate2D), 1 = coarse (Alg. update2D)
+ * rule  : 0 = fine wind rule (Alg. fineupdate2D), 1 = coarse (Alg. update2D),
+ *         2 = the homogenised coarse solver of the squares medium (coarse winds)
  * wt    : output wind of the candidate value */
 static real local_solve(int d, const real* m, const signed char* ws, real rd, int rule,
                         signed char* wt) {
+    if (rule == 2) {
+        /* the homogenised coarse solver of the squares medium (Sec. 5.3):
+         * optimal paths run along grid lines, so the effective metric is the
+         * L1 distance and its upwind scheme, max(|u_x|, |u_y|) = r, gives
+         * the smallest neighbour plus r Delta; winds by the coarse rule */
+        real mn = m[0];
+        for (int a = 1; a < d; a++)
+            if (m[a] < mn) mn = m[a];
+        real ut = mn + rd;
+        for (int a = 0; a < 3; a++) wt[a] = 0;
+        if (d == 2) {
+            if (ut < m[1]) {
+                wt[0] = ws[0];
+            } else if (ut < m[0]) {
+                wt[1] = ws[1];
+            } else {
+                wt[0] = ws[0];
+                wt[1] = ws[1];
+            }
+        } else {
+            for (int a = 0; a < 3; a++) wt[a] = (ut < m[a]) ? 0 : ws[a];
+        }
+        return ut;
+    }
     if (d == 2) {
         real a = m[0], b = m[1];
         real dd = a - b;
@@ -507,6 +537,7 @@ typedef struct {
     unsigned char* isg;   /* Gamma flag per node */
     real* gv;             /* Gamma data per node */
     /* weight of the Step 4 correction (theta_node) */
+    int crule;            /* coarse solver: 1 = C_H (Sec. 3.2), 2 = homogenised (Sec. 5.3) */
     int theta_mode;       /* 0 constant, 1 estimate, 2 reference, 3 field */
     double tpar[7];       /* gamma, delta, x0, omega0, omega1, omega2, margin */
     const real* tref;     /* mode 2: u^f per node; mode 3: theta per node */
@@ -643,7 +674,7 @@ static int64_t step1_init(const ddp* D, real* U, signed char* W, int max_sweeps,
                 nfree++;
             }
         }
-        fsm_ctx C = {u, w, fixed, rd, 1};
+        fsm_ctx C = {u, w, fixed, rd, D->crule};
         int64_t ns = 0;
         run_sweeps(&l->B, max_sweeps, fsm_node, &C, &ns);
         upd += nfree * ns;
@@ -929,7 +960,7 @@ static int corr_node(const box* B, int64_t li, void* vctx) {
     real m[3];
     signed char ws[3], wt[3];
     gather(B, C->u, li, m, ws);
-    real Ut = local_solve(d, m, ws, C->rd[li], 1, wt);
+    real Ut = local_solve(d, m, ws, C->rd[li], C->D->crule, wt);
     int cond = 1;
     for (int e = 0; e < d; e++) {
         if (!((C->normal[li] >> e) & 1)) continue;
@@ -1000,7 +1031,7 @@ static int64_t step4_correct(const ddp* D, const real* Uk, const signed char* Wk
             real m[3];
             signed char ws[3], wt[3];
             gather(&l->B, lUk, li, m, ws);
-            lCk[li] = local_solve(d, m, ws, rd[li], 1, wt);
+            lCk[li] = local_solve(d, m, ws, rd[li], D->crule, wt);
             if (Ck_out) Ck_out[lattice_global(D, l, li)] = lCk[li];
         }
         corr_ctx C = {D, l, u, lUk, luk, lCk, lwk, lWk, rd, fixed, normal};
@@ -1028,7 +1059,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
                     const real* U_init, const signed char* W_init, real* u_out, real* U_out,
                     signed char* W_out, real* uk_out, signed char* wk_out, real* Upre_out,
                     int64_t* info, double* hist, int hist_cap, int theta_mode, const double* tpar,
-                    const real* tref) {
+                    const real* tref, int coarse_solver) {
     int64_t N;
     int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
     if (st != OK) return st;
@@ -1038,6 +1069,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     if (theta_mode < 0 || theta_mode > 3) return ERR_ARG;
     if (theta_mode != 0 && !tpar) return ERR_ARG;
     if ((theta_mode == 2 || theta_mode == 3) && !tref) return ERR_ARG;
+    if (coarse_solver != 0 && coarse_solver != 1) return ERR_ARG;
     ddp D;
     memset(&D, 0, sizeof(D));
     D.d = d;
@@ -1056,6 +1088,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     D.HT = (real)((double)M * h);
     D.thetaT = (real)theta;
     D.theta_mode = theta_mode;
+    D.crule = coarse_solver ? 2 : 1;
     for (int q = 0; q < 7; q++) D.tpar[q] = tpar ? tpar[q] : 0.0;
     D.tref = tref;
     D.r = r;

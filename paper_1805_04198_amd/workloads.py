@@ -262,6 +262,23 @@ def model_strip(N: int, M: int) -> Problem:
     return Problem(f"strip_N{N}_M{M}", n, h, r, gi, gv, S=M, M=M)
 
 
+def squares(n_side: int = 449, period: int = 8, S: int = 32, M: int = 32) -> Problem:
+    """The squares medium of Sec. 5.3: r = 1 on the lines x = 0 or y = 0
+    modulo the period eps, 2 elsewhere; source (0.5, 0.5), g = 0.  The paper
+    uses h = 1/1400, eps = 7h, H = 1/14 and says r is 1 at every coarse node;
+    here h = 1/(n-1), eps = period * h with H = M h a multiple of eps, so
+    that the coarse nodes lie on the lines as stated (defaults: h = 1/448,
+    eps = 8h = 1/56, H = 32h = 1/14)."""
+    n = (n_side, n_side)
+    h = 1.0 / (n_side - 1)
+    i = np.arange(n_side)
+    on = (i % period) == 0
+    r = np.where(on[None, :] | on[:, None], 1.0, 2.0)
+    c = (n_side - 1) // 2
+    gi, gv = _gamma(n, [(c, c)], [0.0])
+    return Problem(f"squares_{n_side}_eps{period}h", n, h, r, gi, gv, S=S, M=M, theta=0.25, tol=1e-12)
+
+
 def config4(n_prob: int = 64, seed: int = 4, sizes=(257, 513, 1025, 2049)) -> list:
     """Batching workload: n_prob independent 2D problems, side lengths drawn
     uniformly from `sizes`, subdomains of 64^2 cells (S = 64).  Each problem
