@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=40)
-    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5"], default="config2",
+    ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5", "squares"], default="config2",
                     help="config2 (default): the headline 2D DD solve; config3: 3D 257^3; config4: 64 "
                          "problems in one batched solve; config5: batched travel-time gradient")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -297,6 +297,62 @@ def bench_config5(a):
            "through r + 8 Gaussian bumps (seed 5)", extra)
 
 
+def bench_squares(a):
+    """The squares medium of Sec. 5.3 (r = 1 on the lines of period eps = 8h,
+    2 elsewhere; source at the centre) on 897^2 (h = 1/896, H = 64h = 1/14,
+    S = 64): time to solution with the homogenised coarse solver (timed) and
+    with C_H, fp32, tol 1e-6, for theta = 0.1 and 0.25, and the relative L1
+    error of U^k against the fine solution u^f over the first iterations
+    (Fig. b5's comparison)."""
+    import numpy as np
+    import torch
+
+    import paper_1805_04198_amd as E
+    from paper_1805_04198_amd import workloads as W
+    p = W.squares(n_side=897, period=8, S=64, M=64)
+    r = torch.from_numpy(p.r.astype(np.float32)).cuda()
+    gi = torch.from_numpy(p.gamma_idx).cuda()
+    gv = torch.from_numpy(p.gamma_val.astype(np.float32)).cuda()
+    theta = 0.25
+
+    def solve(cs, th, **kw):
+        kw.setdefault("tol", 1e-6)
+        kw.setdefault("max_iter", 400)
+        return E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=th, coarse_solver=cs, **kw)
+
+    for _ in range(a.warmup):
+        solve("l1", theta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [solve("l1", theta) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fine = sum(o["fine_updates"] for o in outs)
+    # the fine solution u^f in fp64 (eik_solve) for the error curves
+    uf, _, _ = E.solve(r.double(), gi, gv.double(), p.h)
+    ufn = uf.cpu().numpy().reshape(-1)
+    runs = {}
+    for cs in ("l1", "godunov"):
+        for th in (0.1, 0.25):
+            R = solve(cs, th)
+            u = R["u"].double().cpu().numpy().reshape(-1)
+            curve = []
+            for k in (0, 1, 2, 4, 8, 16):
+                U = solve(cs, th, tol=0.0, max_iter=k)["U"].double().cpu().numpy().reshape(-1)
+                m = np.isfinite(U)
+                curve.append(float(np.sum(np.abs(U[m] - ufn[m])) / np.sum(np.abs(ufn[m]))))
+            runs[f"{cs}_theta{th}"] = {"iterations": R["iterations"], "converged": R["converged"],
+                                       "ms_to_solution": R["ms_total"],
+                                       "max_rel_err_u_vs_uf": float(np.max(np.abs(u - ufn)) / np.max(ufn)),
+                                       "rel_L1_err_U_k_0_1_2_4_8_16": curve}
+    extra = {"coarse_solver": "l1 (homogenised, timed)", "theta": theta, "iterations": outs[-1]["iterations"],
+             "converged": outs[-1]["converged"], "runs": runs}
+    common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle", fine / wall,
+           "updates/s", wall * 1e3 / a.steps, "f32",
+           "squares medium (Sec. 5.3): 2D 897x897, h=1/896, eps=8h, H=64h=1/14, S=64, centre source, "
+           "homogenised coarse solver, theta=0.25, tol=1e-6", extra)
+
+
 def main():
     a = parse()
     if a.copy_calibration:
@@ -308,7 +364,8 @@ def main():
               "iteration, which is not built.", file=sys.stderr)
         sys.exit(2)
     if a.workload != "config2":
-        {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[a.workload](a)
+        {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5,
+         "squares": bench_squares}[a.workload](a)
         return
     import numpy as np
     import torch

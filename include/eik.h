@@ -91,7 +91,7 @@ typedef struct {
  *                        call, also after a resume) and where a term is not
  *                        finite or the denominator is 0.
  *   EIK_THETA_REFERENCE  M-bar of Sec. 4.2 minus a margin: (u_ref - u^k) /
- *                        (U~ - C^k) - margin, clamped at 0 (Sec. 5.4 uses
+ *                        (U~ - C^k) - margin, clamped at 0 (Sec. 5.3 uses
  *                        u_ref = u^f and margin 0.001); opts->theta where not
  *                        defined.
  *   EIK_THETA_FIELD      theta_ref holds theta per node.
@@ -103,6 +103,21 @@ typedef struct {
 #define EIK_THETA_ESTIMATE 1
 #define EIK_THETA_REFERENCE 2
 #define EIK_THETA_FIELD 3
+
+/* Coarse solver of Steps 1 and 4 (Sec. 3.2 uses C_H; Sec. 5.3 replaces it,
+ * on the squares medium, by a solver of the homogenised equation eq. homog):
+ *   EIK_COARSE_GODUNOV  C_H: the Godunov scheme of |grad U| = r on the lattice.
+ *   EIK_COARSE_L1       the homogenised solver of a medium whose optimal paths
+ *                       run along the axes (travel cost r (|a1| + |a2| (+ |a3|))
+ *                       per unit length in direction a): the upwind scheme of
+ *                       max_a |dU/dx_a| = r, i.e. the smallest neighbour plus
+ *                       r*H, which makes U r times the lattice L1 distance.
+ *                       r is the slowness at the coarse node (1 on every node of
+ *                       the squares medium).  The fine solver is unchanged.
+ * The choice changes the iterates, not the fixed point: a converged run gives
+ * the fine solution u^f either way. */
+#define EIK_COARSE_GODUNOV 0
+#define EIK_COARSE_L1 1
 
 /* Options of the domain-decomposition iteration (Sec. 3.2). */
 typedef struct {
@@ -121,6 +136,7 @@ typedef struct {
     double theta_params[7];    /* gamma, delta, x0, omega0, omega1, omega2, margin (ESTIMATE and
                                 * REFERENCE; the paper's values are 0.75, 0.01, 0.9, -, -, -, 0.001;
                                 * the omegas are not stated there) */
+    int32_t coarse_solver;     /* EIK_COARSE_*; 0 = C_H */
 } eik_dd_opts;
 
 /* Host-side statistics.  residual_history (host, may be NULL) receives

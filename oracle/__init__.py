@@ -145,7 +145,7 @@ def fmm(n, h, r, gidx, gval, dtype=np.float64):
 THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
 # gamma, delta, x0 of eq. thetaest (Sec. 4.2 figure) and the omega weights
 # of eq. secthetaest (unstated in the paper: equal weights), margin of the
-# reference weight M-bar - 0.001 (Sec. 5.4)
+# reference weight M-bar - 0.001 (Sec. 5.3)
 THETA_PARAMS = (0.75, 0.01, 0.9, 1.0, 1.0, 1.0, 0.001)
 
 

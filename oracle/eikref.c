@@ -44,7 +44,7 @@
  *   theta_node       -- the weight of the Step 4 correction at one node:
  *                       constant, the estimate of eqs. secthetaest and
  *                       thetaest (Sec. 4.2), the reference weight M-bar
- *                       minus a margin (Sec. 5.4), or a caller field.
+ *                       minus a margin (Sec. 5.3), or a caller field.
  */
 #include <math.h>
 #include <stdint.h>

@@ -53,10 +53,13 @@ class DDOpts(ctypes.Structure):
                 ("max_fine_sweeps", ctypes.c_int32), ("max_coarse_sweeps", ctypes.c_int32),
                 ("theta_mode", ctypes.c_int32), ("U_init", ctypes.c_void_p),
                 ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug)),
-                ("theta_ref", ctypes.c_void_p), ("theta_params", ctypes.c_double * 7)]
+                ("theta_ref", ctypes.c_void_p), ("theta_params", ctypes.c_double * 7),
+                ("coarse_solver", ctypes.c_int32)]
 
 
 THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
+# coarse solver of Steps 1 and 4: C_H, or the homogenised solver of Sec. 5.3
+COARSE_SOLVERS = {"godunov": 0, "l1": 1}
 # gamma, delta, x0 of eq. thetaest (the paper's values), equal omegas for
 # eq. secthetaest (not stated in the paper), margin 0.001 of the reference
 # weight
@@ -181,11 +184,12 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
              max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
              max_coarse_sweeps: int = 32, U_init=None, W_init=None, debug: bool = False,
              history_cap: int = 4096, theta_mode: str = "constant", theta_params=THETA_PARAMS,
-             theta_ref=None):
+             theta_ref=None, coarse_solver: str = "godunov"):
     """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
     with the patched fine solution u, coarse values U (NaN off the skeleton),
     coarse wind codes W, counters and timings; with debug=True also the last
-    iteration's u^k, w^k and pre-causal-sweep U."""
+    iteration's u^k, w^k and pre-causal-sweep U.  coarse_solver: "godunov"
+    (C_H) or "l1" (the homogenised solver of the squares medium, Sec. 5.3)."""
     torch = _torch()
     L = load_library()
     r = r.contiguous()
@@ -200,6 +204,7 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     o.S, o.M, o.theta, o.tol = int(S), int(M), float(theta), float(tol)
     o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps)
     o.theta_mode = THETA_MODES[theta_mode]
+    o.coarse_solver = COARSE_SOLVERS[coarse_solver]
     for q, v in enumerate(theta_params):
         o.theta_params[q] = float(v)
     if theta_ref is not None:
@@ -262,19 +267,19 @@ def solve_batch(r, gammas, h, max_sweeps: int = 100000, with_wind: bool = False)
 
 def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
                    max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
-                   theta_refs=None, history_cap: int = 4096):
+                   theta_refs=None, history_cap: int = 4096, coarse_solver="godunov"):
     """eik_dd_solve_batch: the DD iteration on independent 2D problems at
     once (every DD step is one launch over all problems that have not
     converged).  rs: list of device slowness tensors (one dtype); gammas:
     list of (idx, val); hs: list of spacings; S, M, theta, tol, max_iter,
-    theta_mode: one value for all or a list.  Returns a list of result dicts
+    theta_mode, coarse_solver: one value for all or a list.  Returns a list of result dicts
     as dd_solve, plus the batch's device time in each."""
     torch = _torch()
     L = load_library()
     P = len(rs)
     per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * P
     hs, Ss, Ms, thetas, tols = per(hs), per(S), per(M), per(theta), per(tol)
-    iters, modes = per(max_iter), per(theta_mode)
+    iters, modes, solvers = per(max_iter), per(theta_mode), per(coarse_solver)
     refs = per(theta_refs) if theta_refs is not None else [None] * P
     grids = (Grid * P)()
     gms = (Gamma * P)()
@@ -297,6 +302,7 @@ def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, ma
         o.S, o.M, o.theta, o.tol = int(Ss[p]), int(Ms[p]), float(thetas[p]), float(tols[p])
         o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(mi), int(max_fine_sweeps), int(max_coarse_sweeps)
         o.theta_mode = THETA_MODES[modes[p]]
+        o.coarse_solver = COARSE_SOLVERS[solvers[p]]
         for q_, v in enumerate(theta_params):
             o.theta_params[q_] = float(v)
         if refs[p] is not None:

@@ -126,7 +126,10 @@ void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t 
   }
 }
 
-eik_status check_theta(const eik_dd_opts* o) {
+// the Step 4 weight options and the coarse solver choice
+eik_status check_weight_solver(const eik_dd_opts* o) {
+  if (o->coarse_solver != EIK_COARSE_GODUNOV && o->coarse_solver != EIK_COARSE_L1)
+    return fail(EIK_ERR_ARG, "coarse_solver must be one of EIK_COARSE_*");
   if (o->theta_mode < EIK_THETA_CONSTANT || o->theta_mode > EIK_THETA_FIELD)
     return fail(EIK_ERR_ARG, "theta_mode must be one of EIK_THETA_*");
   if ((o->theta_mode == EIK_THETA_REFERENCE || o->theta_mode == EIK_THETA_FIELD) && !o->theta_ref)
@@ -172,7 +175,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const size_t szT = sizeof(T);
   const int L = S + 1;
   const size_t lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
-  eik_status e = check_theta(o);
+  eik_status e = check_weight_solver(o);
   if (e != EIK_OK) return e;
   const int tmode = o->theta_mode;
   // Step 4 holds two doubles more per node when the weight varies
@@ -244,6 +247,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.u_out = as<T>(u_outv);
   A.theta_mode = tmode;
+  A.coarse_homog = o->coarse_solver;
   set_theta<T>(A.tq, o);
   A.tref = as<T>(o->theta_ref);
   A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
@@ -442,7 +446,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     if ((op->U_init == nullptr) != (op->W_init == nullptr))
       return fail(EIK_ERR_ARG, "problem %d: U_init and W_init go together", p);
     if (op->debug) return fail(EIK_ERR_ARG, "problem %d: debug snapshots are not available in a batch", p);
-    eik_status e = check_theta(op);
+    eik_status e = check_weight_solver(op);
     if (e != EIK_OK) return e;
     if (!rv[p] || !u_out[p] || rv[p] == u_out[p]) return fail(EIK_ERR_ARG, "problem %d: bad r / u_out", p);
     q.tmode = op->theta_mode;
@@ -550,6 +554,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.counters = d_cnt + 4 * (size_t)p;
     A.u_out = as<T>(u_out[p]);
     A.theta_mode = q.tmode;
+    A.coarse_homog = op->coarse_solver;
     set_theta<T>(A.tq, op);
     A.tref = as<T>(op->theta_ref);
     A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
@@ -826,7 +831,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     return fail(EIK_ERR_ARG, "max_iter >= 0, max_fine_sweeps >= 1, max_coarse_sweeps >= 1");
   if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
   {
-    const eik_status et = check_theta(o);
+    const eik_status et = check_weight_solver(o);
     if (et != EIK_OK) return et;
   }
   const int tmode = o->theta_mode;
@@ -883,6 +888,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   A.counters = cv.take<unsigned long long>(4);
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.u_out = as<T>(u_outv);
+  A.coarse_homog = o->coarse_solver;
   set_theta<T>(A.tq, o);
   A.tref = as<T>(o->theta_ref);
   A.ukm1 = A.ckm1 = A.ckm2 = nullptr;

@@ -100,7 +100,7 @@ __device__ __forceinline__ double exp_cw(double x) {
 }
 
 // Step 4 weight rule (eqs. secthetaest and thetaest, Sec. 4.2; the reference
-// weight M-bar - margin of Sec. 5.4): parameters and per-node terms
+// weight M-bar - margin of Sec. 5.3): parameters and per-node terms
 struct ThetaPar {
   double gamma, delta, x0, w0, w1, w2, margin;
 };
@@ -202,6 +202,14 @@ __device__ __forceinline__ T godunov2_sel(T a, T b, T rd, bool& two) {
   const T u2 = ((a + b) + dsqrt(t)) * T(0.5);
   const T u1 = ((a < b) ? a : b) + rd;
   return two ? u2 : u1;
+}
+
+// The homogenised coarse solver of the squares medium (Sec. 5.3, eq. homog),
+// read as the upwind scheme of max(|u_x|, |u_y|) = r: the smaller neighbour
+// plus r*H, which is the one-sided value of the Godunov solve.
+template <typename T>
+__device__ __forceinline__ T homog2(T a, T b, T rd) {
+  return ((a < b) ? a : b) + rd;
 }
 
 // Sweep-order columns of the nodes a lane changed during a sweep (min and
@@ -356,7 +364,6 @@ __device__ __forceinline__ bool sweep_box(Rule& R, int L0, int L1, int SP, NodeB
   StepSpan sp;
   const bool ch = sweep_dir<SX, SY, EXTRA>(R, L0, L1, SP, t0, tmax, sp);
   // changed nodes in sweep-order coordinates
-  const int lane = threadIdx.x;
   // rows: the lanes that changed a value (lane 0 stands for row 0 even if
   // only its row 64 changed, which only widens the box), plus row 64
   const unsigned long long rows = __ballot(ch);
@@ -450,6 +457,7 @@ struct MinRule {
   uint8_t* w;
   const T* rd;
   int SP;
+  bool homog;  // coarse only: the homogenised solver in place of C_H
   __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
@@ -472,7 +480,8 @@ struct MinRule {
     pick(xm, xp, a, wx);
     pick(ym, yp, b, wy);
     bool two;
-    const T ut = godunov2_sel(a, b, p.rd, two);
+    T ut = godunov2_sel(a, b, p.rd, two);
+    if (Coarse && homog) ut = homog2(a, b, p.rd);
     ch = act && (ut < p.self);
     // axes that enter the wind: Alg. update2D (coarse) or Alg. fineupdate2D
     bool useX, useY;
@@ -533,6 +542,7 @@ struct CorrectRule {
   const double* ta;  // per-node weight terms (MODE != 0)
   const double* tb;
   ThetaPar q;
+  bool homog;        // the homogenised coarse solver in place of C_H
   __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
@@ -558,7 +568,8 @@ struct CorrectRule {
     pick(xm, xp, a, wx);
     pick(ym, yp, b, wy);
     bool two;
-    const T ut = godunov2_sel(a, b, p.rd, two);
+    T ut = godunov2_sel(a, b, p.rd, two);
+    if (homog) ut = homog2(a, b, p.rd);
     // W~ of Alg. update2D: U~ < b -> (Wx, 0); else U~ < a -> (0, Wy); else both
     const bool lb = ut < b, la = ut < a;
     const int tx = (!lb && la) ? 0 : wx;
@@ -622,6 +633,9 @@ struct DD2 {
   const T* ckm1;
   const T* ckm2;
   T* ck_out;
+  // coarse solver of Steps 1 and 4: 0 = C_H (Sec. 3.2), 1 = the homogenised
+  // solver of the squares medium (Sec. 5.3)
+  int coarse_homog;
 };
 
 __device__ __forceinline__ bool is_iface(int c, int S, int n) { return (c % S == 0) && c > 0 && c < n - 1; }
@@ -805,7 +819,7 @@ __device__ __forceinline__ void lattice_init_body(const DD2<T>& A, int bx) {
   if (threadIdx.x == 0) sh_free = 0;
   __syncthreads();
   if (threadIdx.x < kWave) {
-    MinRule<T, true, false> R{u, w, rd, SP};
+    MinRule<T, true, false> R{u, w, rd, SP, A.coarse_homog != 0};
     const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
     if (threadIdx.x == 0) sh_ns = ns;
   }
@@ -868,7 +882,8 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     if (!gam) ++nfree;
   }
   __syncthreads();
-  // C^k = C_H(nbrs^H(U^k)) once per node (Jacobi), and the condition masks
+  // C^k = C_H(nbrs^H(U^k)) (or the homogenised solver) once per node
+  // (Jacobi), and the condition masks
   for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
@@ -877,7 +892,7 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     const T a = xm < xp ? xm : xp;
     const T b = ym < yp ? ym : yp;
     bool two;
-    const T c = godunov2(a, b, rd[x], two);
+    const T c = A.coarse_homog ? homog2(a, b, rd[x]) : godunov2(a, b, rd[x], two);
     ck[x] = c;
     mk[x] = corr_mask(A.wk[X], A.W[X], nx, ny, dfinite(c));
     if (A.theta_mode == 1) {
@@ -922,22 +937,22 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     int ns;
     switch (A.theta_mode) {
       case 0: {
-        CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
         ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
         break;
       }
       case 1: {
-        CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
         ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
         break;
       }
       case 2: {
-        CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
         ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
         break;
       }
       default: {
-        CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq};
+        CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
         ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
         break;
       }
@@ -1024,7 +1039,7 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   if (threadIdx.x == 0) sh_free = 0;
   __syncthreads();
   if (threadIdx.x < kWave) {
-    MinRule<T, false, false> R{u, w, rd, SP};
+    MinRule<T, false, false> R{u, w, rd, SP, false};
     const int ns = wave_fsm(R, L, L, SP, A.max_fine_sweeps);
     if (threadIdx.x == 0) sh_ns = ns;
   }
@@ -1161,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int di
   if (threadIdx.x == 0) sh_ch = 0;
   __syncthreads();
   if (threadIdx.x < kWave) {
-    MinRule<T, false, true> R{u, w, rd, SP};
+    MinRule<T, false, true> R{u, w, rd, SP, false};
     const bool ch = sweep_any(R, L0, L1, SP, dir);
     if (__any(ch) && threadIdx.x == 0) sh_ch = 1;
   }

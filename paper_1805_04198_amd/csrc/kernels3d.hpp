@@ -41,9 +41,12 @@ __device__ __forceinline__ uint8_t wenc3(int wx, int wy, int wz) {
 }
 
 // 3D local solve.  m: per-axis neighbour minima; ws: their wind signs.
-// Coarse = false: fine wind, true: coarse wind.  Returns u~ and the wind code.
+// Coarse = false: fine wind, true: coarse wind.  homog (coarse only): the
+// homogenised solver of the squares medium (Sec. 5.3), the smallest
+// neighbour plus r*H, in place of C_H.  Returns u~ and the wind code.
 template <typename T, bool Coarse>
-__device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd, uint8_t& code) {
+__device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd, uint8_t& code,
+                                      bool homog = false) {
   int p0 = 0, p1 = 1, p2 = 2;
   // stable insertion sort of the three axes by value
   if (m[p1] < m[p0]) { const int t = p0; p0 = p1; p1 = t; }
@@ -55,7 +58,7 @@ __device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd,
   T ut;
   int used;
   const T d12 = a1 - a2;
-  if (!(dabs(d12) < rd)) {
+  if ((Coarse && homog) || !(dabs(d12) < rd)) {
     ut = a1 + rd;
     used = 1;
   } else {
@@ -132,6 +135,8 @@ struct DD3 {
   const T* ukm1;
   const T* ckm1;
   const T* ckm2;
+  // coarse solver of Steps 1 and 4: 0 = C_H, 1 = the homogenised solver
+  int coarse_homog;
 };
 
 __device__ __forceinline__ int64_t idx3(const int (&n)[3], int i, int j, int k) {
@@ -377,6 +382,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_init3(DD3<T> A) {
     const long long* near_win;
     const T* rdH;
     uint8_t* W;
+    bool homog;
     int64_t base;
     int gs0, gs1, gs2;
     struct In {
@@ -394,7 +400,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_init3(DD3<T> A) {
       int ws[3];
       gather3(u, L0, L1, L2, i, j, k, m, ws);
       uint8_t code;
-      const T ut = godunov3<T, true>(m, ws, in.rd, code);
+      const T ut = godunov3<T, true>(m, ws, in.rd, code, homog);
       const int x = i + L0 * (j + L1 * k);
       if (ut < u[x]) {
         u[x] = ut;
@@ -403,7 +409,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_init3(DD3<T> A) {
       }
       return false;
     }
-  } R{u, L[0], L[1], L[2], A.gfull, A.near_win, A.rdH, A.W, base, gs[0], gs[1], gs[2]};
+  } R{u, L[0], L[1], L[2], A.gfull, A.near_win, A.rdH, A.W, A.coarse_homog != 0, base, gs[0], gs[1], gs[2]};
   const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
@@ -610,7 +616,7 @@ __global__ void k_ck3(DD3<T> A) {
   }
   uint8_t code;
   const T rd = A.r[t] * A.HT;
-  const T v = godunov3<T, true>(m, ws, rd, code);
+  const T v = godunov3<T, true>(m, ws, rd, code, A.coarse_homog != 0);
   A.ck[t] = v;
   const uint8_t wk = A.wk[t], Wk = A.W[t];
   uint16_t mask = dfinite(v) ? (uint16_t)512 : (uint16_t)0;
@@ -663,6 +669,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
     const T* ckm1;
     const T* ckm2;
     ThetaPar q;
+    bool homog;
     struct In {
       T rd;   // NaN at Gamma nodes
       T ukx, ckx;
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
       int ws[3];
       gather3(u, L0, L1, L2, i, j, k, m, ws);
       uint8_t code;
-      const T ut = godunov3<T, true>(m, ws, in.rd, code);
+      const T ut = godunov3<T, true>(m, ws, in.rd, code, homog);
       const unsigned mask = in.mask;
       bool cond = dfinite(ut) && (mask & 512u);
       for (int a = 0; a < 3; ++a) cond = cond && ((mask >> (3 * a + w_of(code, a) + 1)) & 1u);
@@ -710,7 +717,7 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
       return false;
     }
   } R{u, L[0], L[1], L[2], A.gfull, A.rdH, A.mk, A.uk, A.ck, A.theta, base, gs[0], gs[1], gs[2],
-      A.tref, A.ukm1, A.ckm1, A.ckm2, A.tq};
+      A.tref, A.ukm1, A.ckm1, A.ckm2, A.tq, A.coarse_homog != 0};
   const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);

@@ -1,4 +1,4 @@
-"""Pins for the Step 4 weight rules (Sec. 4.2 and Sec. 5.4).
+"""Pins for the Step 4 weight rules (Sec. 4.2 and Sec. 5.3).
 
 What fixes them:
   * e^x of the damping function is the library exponential to within two
@@ -94,7 +94,7 @@ def test_estimate_converges_faster_on_smooth_media(seed):
 
 
 def test_reference_weight_converges_on_config1():
-    """Sec. 5.4 runs the method with M-bar - 0.001 computed from u^f."""
+    """Sec. 5.3 runs the method with M-bar - 0.001 computed from u^f."""
     p = W.config1()
     uf, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
     R = _run(p, theta=0.5, tol=1e-12, max_iter=200, theta_mode="reference", theta_ref=uf)
