@@ -112,18 +112,17 @@ T* as(const void* p) { return (T*)p; }
 // eik_dd_solve, d = 2
 // ---------------------------------------------------------------------------
 
+// Alg. causalsweep2D: per direction the segment kernel (phase C of the
+// previous direction, phase A of this one) and the corner kernel (phase B),
+// then phase C of the last direction.
 template <typename T>
 void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t ldsB) {
-  const int nC = (A.NI + 1) * (A.NJ + 1);
-  const int nH = A.NI * (A.NJ + 1);
-  const int nV = (A.NI + 1) * A.NJ;
+  const int nb = eik::causal_blocks(A);
   for (int dir = 0; dir < 4; ++dir) {
-    const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
-    hipLaunchKernelGGL(eik::k_causal_a<T>, dim3(nblocks(nC + nH + nV, 256)), dim3(256), 0, s, A, U, W,
-                       sx, sy);
-    hipLaunchKernelGGL(eik::k_causal_b<T>, dim3(1), dim3(eik::kBlock), ldsB, s, A, U, dir);
-    hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nblocks(nH + nV, 256)), dim3(256), 0, s, A, U, sx, sy);
+    hipLaunchKernelGGL(eik::k_causal_seg<T>, dim3(nb), dim3(eik::kBlock), 0, s, A, U, W, dir, dir - 1);
+    hipLaunchKernelGGL(eik::k_causal_corner<T>, dim3(1), dim3(eik::kCornerBlock), ldsB, s, A, U, W, dir);
   }
+  hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nb), dim3(eik::kBlock), 0, s, A, U, 1, 1);
 }
 
 // the Step 4 weight options and the coarse solver choice
@@ -204,7 +203,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   need += 6 * (N + 256);                 // W Wn wk cflag
   need += 2 * (N * 8 + 256);             // near keys
   need += ntile * 4 * L * (szT + 1) + 512;
-  need += nC * (szT + 1) + (nH + nV) * (szT + 1) + 2048;
+  need += 2 * nC * szT + (nH + nV) * (szT + 1) + 2048;
   need += 4096;
   if (tmode == EIK_THETA_ESTIMATE) need += 4 * (N * szT + 256);  // u^{k-1}, C^k, C^{k-1}, C^{k-2}
   void* wsv;
@@ -237,8 +236,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.near_win = cv.take<long long>(N);
   A.edge_u = cv.take<T>((size_t)ntile * 4 * L);
   A.edge_w = cv.take<uint8_t>((size_t)ntile * 4 * L);
-  A.corner_v = cv.take<T>(nC);
-  A.corner_f = cv.take<uint8_t>(nC);
+  A.ncx = cv.take<T>(nC);
+  A.ncy = cv.take<T>(nC);
   A.hseg_p = cv.take<T>(std::max(nH, 1));
   A.hseg_l = cv.take<uint8_t>(std::max(nH, 1));
   A.vseg_p = cv.take<T>(std::max(nV, 1));
@@ -263,7 +262,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if ((e = allow_lds(eik::k_tile<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_correct<T>, lds_lat)) != EIK_OK) return e;
-  if ((e = allow_lds(eik::k_causal_b<T>, lds_cb)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal_corner<T>, lds_cb)) != EIK_OK) return e;
 
   hipEvent_t ev[6];
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
@@ -425,7 +424,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   const int bs = 256;
   std::vector<BatchProb<T>> pr(P);
   size_t need = 4096 + (size_t)P * (sizeof(eik::DD2<T>) + 4 * 8) + 512;
-  int64_t tot_tile = 0, tot_lat = 0, tot_rec = 0, tot_res = 0, tot_ca = 0, tot_cc = 0;
+  int64_t tot_tile = 0, tot_lat = 0, tot_rec = 0, tot_res = 0, tot_cc = 0;
   size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
   for (int p = 0; p < P; ++p) {
     const eik_dd_opts* op = &o[p];
@@ -477,19 +476,18 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     nd += 6 * (q.N + 256);
     nd += 2 * (q.N * 8 + 256);
     nd += (size_t)q.ntile * 4 * L * (szT + 1) + 512;
-    nd += q.nC * (szT + 1) + (q.nH + q.nV) * (szT + 1) + 2048;
+    nd += 2 * q.nC * szT + (q.nH + q.nV) * (szT + 1) + 2048;
     if (q.tmode == EIK_THETA_ESTIMATE) nd += 4 * (q.N * szT + 256);
     need += nd;
     tot_tile += q.ntile;
     tot_lat += q.nlat;
     tot_rec += nblocks(q.nrec, bs);
     tot_res += nblocks(q.nres, bs);
-    tot_ca += nblocks(q.nC + q.nH + q.nV, bs);
     tot_cc += nblocks(q.nH + q.nV, bs);
   }
   int64_t tot_near = 0;
   for (int p = 0; p < P; ++p) tot_near += nblocks(pr[p].npair, bs);
-  const int64_t tot_work = tot_tile + tot_lat + tot_rec + tot_res + tot_ca + tot_cc + P + tot_near;
+  const int64_t tot_work = tot_tile + tot_lat + tot_rec + tot_res + tot_cc + P + tot_near;
   need += (size_t)tot_work * sizeof(int2) + 8 * 256;
 
   int dev = 0;
@@ -509,7 +507,6 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   int2* w_lat = cv.take<int2>(std::max<int64_t>(tot_lat, 1));
   int2* w_rec = cv.take<int2>(std::max<int64_t>(tot_rec, 1));
   int2* w_res = cv.take<int2>(std::max<int64_t>(tot_res, 1));
-  int2* w_ca = cv.take<int2>(std::max<int64_t>(tot_ca, 1));
   int2* w_cc = cv.take<int2>(std::max<int64_t>(tot_cc, 1));
   int2* w_cb = cv.take<int2>(P);
   int2* w_near = cv.take<int2>(std::max<int64_t>(tot_near, 1));
@@ -545,8 +542,8 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.near_win = cv.take<long long>(N);
     A.edge_u = cv.take<T>((size_t)q.ntile * 4 * L);
     A.edge_w = cv.take<uint8_t>((size_t)q.ntile * 4 * L);
-    A.corner_v = cv.take<T>(q.nC);
-    A.corner_f = cv.take<uint8_t>(q.nC);
+    A.ncx = cv.take<T>(q.nC);
+    A.ncy = cv.take<T>(q.nC);
     A.hseg_p = cv.take<T>(std::max(q.nH, 1));
     A.hseg_l = cv.take<uint8_t>(std::max(q.nH, 1));
     A.vseg_p = cv.take<T>(std::max(q.nV, 1));
@@ -568,7 +565,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   if ((e = allow_lds(eik::k_tile_b<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init_b<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_correct_b<T>, lds_lat)) != EIK_OK) return e;
-  if ((e = allow_lds(eik::k_causal_b_b<T>, lds_cb)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal_corner_b<T>, lds_cb)) != EIK_OK) return e;
 
   hipEvent_t ev[5];
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
@@ -625,16 +622,17 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     hipLaunchKernelGGL(eik::k_near_a_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
     hipLaunchKernelGGL(eik::k_near_b_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
   }
-  int64_t tot_cb_ = 0;
+  int64_t tot_cb = 0;
   auto causal_batch = [&](int which) -> eik_status {
-    // tables for the selected problems are in w_ca, w_cb, w_cc (counts below)
+    // tables of the selected problems: w_cc, causal_blocks() segment blocks
+    // per problem (kBlock == bs); w_cb, one corner block per problem
     for (int dir = 0; dir < 4; ++dir) {
-      const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
-      hipLaunchKernelGGL(eik::k_causal_a_b<T>, dim3((unsigned)tot_ca), dim3(bs), 0, s, d_desc, w_ca, which, sx, sy);
-      hipLaunchKernelGGL(eik::k_causal_b_b<T>, dim3((unsigned)tot_cb_), dim3(eik::kBlock), lds_cb, s, d_desc, w_cb,
-                         which, dir);
-      hipLaunchKernelGGL(eik::k_causal_c_b<T>, dim3((unsigned)tot_cc), dim3(bs), 0, s, d_desc, w_cc, which, sx, sy);
+      hipLaunchKernelGGL(eik::k_causal_seg_b<T>, dim3((unsigned)tot_cc), dim3(eik::kBlock), 0, s, d_desc, w_cc,
+                         which, dir, dir - 1);
+      hipLaunchKernelGGL(eik::k_causal_corner_b<T>, dim3((unsigned)tot_cb), dim3(eik::kCornerBlock), lds_cb, s,
+                         d_desc, w_cb, which, dir);
     }
+    hipLaunchKernelGGL(eik::k_causal_c_b<T>, dim3((unsigned)tot_cc), dim3(eik::kBlock), 0, s, d_desc, w_cc, which, 1, 1);
     HIPCHK(hipGetLastError());
     return EIK_OK;
   };
@@ -652,15 +650,12 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nres, bs) : 0; });
     tot_res = (int64_t)tab.size();
     if ((ee = upload(w_res, tab)) != EIK_OK) return ee;
-    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nC + pr[p].nH + pr[p].nV, bs) : 0; });
-    tot_ca = (int64_t)tab.size();
-    if ((ee = upload(w_ca, tab)) != EIK_OK) return ee;
-    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)1 : 0; });
-    tot_cb_ = (int64_t)tab.size();
-    if ((ee = upload(w_cb, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nH + pr[p].nV, bs) : 0; });
     tot_cc = (int64_t)tab.size();
     if ((ee = upload(w_cc, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)1 : 0; });
+    tot_cb = (int64_t)tab.size();
+    if ((ee = upload(w_cb, tab)) != EIK_OK) return ee;
     return EIK_OK;
   };
   if ((e = set_tables(fresh)) != EIK_OK) return e;

@@ -614,8 +614,8 @@ struct DD2 {
   uint8_t* edge_w;
   T* cwork;           // causal sweep scratch (full grid)
   uint8_t* cflag;     // causal sweep scratch (full grid)
-  T* corner_v;        // (NI+1)(NJ+1)
-  uint8_t* corner_f;
+  T* ncx;             // causal sweep: per corner, its x / y successor's value
+  T* ncy;
   T* hseg_p;          // NI*(NJ+1) segment end values
   uint8_t* hseg_l;
   T* vseg_p;          // (NI+1)*NJ
@@ -1301,7 +1301,7 @@ __global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
 
 
 // ---------------------------------------------------------------------------
-// causal sweep (Alg. causalsweep2D), one direction = three kernels
+// causal sweep (Alg. causalsweep2D)
 //
 // In sweep direction (sx, sy) a coarse node X with wind component W_e = s_e
 // (flow along the sweep) is raised to the NEW value of its upwind fine
@@ -1309,50 +1309,48 @@ __global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
 // Both are maxima, so the result is: V(X) = max(U(X), old successors), then
 // U_new(X) = max(V(X), U_new of every linked predecessor).  Between corners
 // the links form chains (segments of M-1 nodes); corners join the
-// horizontal and vertical chains.  Phase A: V and the chain prefix maxima
-// per segment; phase B: the corner recurrence on the coarse grid in
-// anti-diagonal order; phase C: fill the segments from their start corner.
+// horizontal and vertical chains.  Per direction: phase A, V and the chain
+// prefix maxima of every segment; phase B, the corner recurrence on the
+// coarse grid in anti-diagonal order; phase C, fill the segments from their
+// start corner.
+//
+// Two launches per direction: k_causal_seg, one thread per segment, runs
+// phase C of the previous direction on it, then phase A of this one (phase A
+// of a segment reads only the segment and its end corner, both final after
+// the previous phase B), and stores the value of its node next to the
+// corner it leaves in sweep order, which that corner's V needs (ncx / ncy);
+// k_causal_corner, one block, evaluates V and the links of every corner from
+// independent loads and runs phase B.  A last k_causal_c fills the segments
+// of the fourth direction.
 // ---------------------------------------------------------------------------
 
 template <typename T>
 __device__ __forceinline__ T vmax(T a, T b) { return a < b ? b : a; }
 
-template <typename T>
-__device__ __forceinline__ void causal_a_body(const DD2<T>& A, int bx, T* U, const uint8_t* W, int sx, int sy) {
-  const int nC = (A.NI + 1) * (A.NJ + 1);
-  const int nH = A.NI * (A.NJ + 1);
-  const int nV = (A.NI + 1) * A.NJ;
-  const int t = bx * blockDim.x + threadIdx.x;
-  const int M = A.M;
-  if (t < nC) {
-    const int I = t % (A.NI + 1), J = t / (A.NI + 1);
-    const int xi = I * M, yi = J * M;
-    const int X = xi + A.n0 * yi;
-    T v = U[X];
-    uint8_t f = 0;
-    if (disnan(A.gfull[X])) {
-      const uint8_t c = W[X];
-      const int ex = wx_of(c), ey = wy_of(c);
-      const int nxi = xi + sx, nyi = yi + sy;
-      if (ex == -sx && nxi >= 0 && nxi < A.n0) v = vmax(v, U[X + sx]);
-      if (ey == -sy && nyi >= 0 && nyi < A.n1) v = vmax(v, U[X + sy * A.n0]);
-      const int pxi = xi - sx, pyi = yi - sy;
-      if (ex == sx && pxi >= 0 && pxi < A.n0) f |= 1;
-      if (ey == sy && pyi >= 0 && pyi < A.n1) f |= 2;
-    }
-    A.corner_v[t] = v;
-    A.corner_f[t] = f;
-    return;
-  }
-  int s = t - nC;
+// segment s of the skeleton: horizontal segments first (I < NI, J <= NJ),
+// then vertical ones (I <= NI, J < NJ); corner (I, J) at its minus end
+struct Seg {
   bool horiz;
   int I, J;
-  if (s < nH) { horiz = true; I = s % A.NI; J = s / A.NI; }
-  else if (s < nH + nV) { s -= nH; horiz = false; I = s % (A.NI + 1); J = s / (A.NI + 1); }
-  else return;
-  const int sg = horiz ? sx : sy;
-  const int stride = horiz ? 1 : A.n0;
-  const int base = (I * M) + A.n0 * (J * M);  // corner (I, J)
+};
+template <typename T>
+__device__ __forceinline__ Seg seg_of(const DD2<T>& A, int s) {
+  const int nH = A.NI * (A.NJ + 1);
+  if (s < nH) return Seg{true, s % A.NI, s / A.NI};
+  s -= nH;
+  return Seg{false, s % (A.NI + 1), s / (A.NI + 1)};
+}
+
+// phase A on one segment: V, the running maximum over the linked chain from
+// the segment's start (cwork) and whether the chain is linked to the start
+// corner (cflag); the segment's end value and link go to hseg / vseg
+template <typename T>
+__device__ __forceinline__ void causal_seg_a(const DD2<T>& A, int s, T* U, const uint8_t* W, int sx, int sy) {
+  const Seg g = seg_of(A, s);
+  const int M = A.M;
+  const int sg = g.horiz ? sx : sy;
+  const int stride = g.horiz ? 1 : A.n0;
+  const int base = (g.I * M) + A.n0 * (g.J * M);  // corner (I, J)
   T P = T(0);
   bool L = true;
   // the segment's M-1 nodes in sweep order, in chunks whose loads are
@@ -1381,7 +1379,7 @@ __device__ __forceinline__ void causal_a_body(const DD2<T>& A, int bx, T* U, con
       T vv = v[k];
       bool link = false;
       if (!gm[k]) {
-        const int e = horiz ? wx_of(wc[k]) : wy_of(wc[k]);
+        const int e = g.horiz ? wx_of(wc[k]) : wy_of(wc[k]);
         if (e == -sg) vv = vmax(vv, nx[k]);
         link = (e == sg);
       }
@@ -1391,19 +1389,39 @@ __device__ __forceinline__ void causal_a_body(const DD2<T>& A, int bx, T* U, con
       A.cflag[X] = L ? 1 : 0;
     }
   }
-  if (horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
-  else { A.vseg_p[s] = P; A.vseg_l[s] = L ? 1 : 0; }
-}
-template <typename T>
-__global__ void k_causal_a(DD2<T> A, T* U, const uint8_t* W, int sx, int sy) { causal_a_body(A, (int)blockIdx.x, U, W, sx, sy); }
-// batched: which = 0 sweeps U/W of each problem, 1 sweeps Un/Wn
-template <typename T>
-__global__ void k_causal_a_b(const DD2<T>* descs, const int2* work, int which, int sx, int sy) {
-  const int2 w = work[blockIdx.x];
-  const DD2<T> A = descs[w.x];
-  causal_a_body(A, w.y, which ? A.Un : A.U, which ? A.Wn : A.W, sx, sy);
+  if (g.horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
+  else { A.vseg_p[s - A.NI * (A.NJ + 1)] = P; A.vseg_l[s - A.NI * (A.NJ + 1)] = L ? 1 : 0; }
 }
 
+// phase C on one segment: a node linked to the start corner takes the
+// maximum of its chain value and the corner's final value
+template <typename T>
+__device__ __forceinline__ void causal_seg_c(const DD2<T>& A, int s, T* U, int sx, int sy) {
+  const Seg g = seg_of(A, s);
+  const int M = A.M;
+  const int sg = g.horiz ? sx : sy;
+  const int stride = g.horiz ? 1 : A.n0;
+  const int base = (g.I * M) + A.n0 * (g.J * M);
+  const int start = sg > 0 ? base : base + M * stride;
+  const T cs = U[start];
+  constexpr int C = 8;
+  for (int q0 = 1; q0 < M; q0 += C) {
+    T P[C];
+    uint8_t F[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int X = base + min(q0 + k, M - 1) * stride;
+      P[k] = A.cwork[X];
+      F[k] = A.cflag[X];
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      if (q0 + k >= M) break;
+      const int X = base + (q0 + k) * stride;
+      U[X] = F[k] ? vmax(P[k], cs) : P[k];
+    }
+  }
+}
 
 // The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
 // on the coarse grid of corners, swept by one wave like a subdomain: the
@@ -1446,31 +1464,51 @@ struct CausalRule {
   }
 };
 
+// phase B for one direction, by one block: the corners' V and links (from
+// U, W, the segments' phase-A results and ncx / ncy) into LDS, the
+// recurrence by one wave, the corner values back to U
 template <typename T>
-__device__ __forceinline__ void causal_b_body(const DD2<T>& A, int bx, T* U, int dir) {
+__device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const uint8_t* W, int dir) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int CI = A.NI + 1, CJ = A.NJ + 1;
   const int SP = halo_stride(CI);
   const int cnt = halo_count(CI, CJ);
+  const int M = A.M;
+  const int nH = A.NI * CJ, nV = CI * A.NJ;
   unsigned char* lc = smem;
   T* cu = carve<T>(lc, cnt);
   T* cb = carve<T>(lc, cnt);
   uint8_t* ca = carve<uint8_t>(lc, cnt);
-  for (int t = threadIdx.x; t < CI * CJ; t += kBlock) {
+  for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
     const int I = t % CI, J = t / CI;
-    T b = A.corner_v[t];
-    const uint8_t f = A.corner_f[t];
+    const int xi = I * M, yi = J * M;
+    const int X = xi + A.n0 * yi;
+    // incoming segments in sweep order (clamped; used only when linked)
+    const int hs = min(max((sx > 0 ? I - 1 : I) + A.NI * J, 0), nH - 1);
+    const int vs = min(max(I + CI * (sy > 0 ? J - 1 : J), 0), nV - 1);
+    const T u = U[X];
+    const T g = A.gfull[X];
+    const uint8_t c = W[X];
+    const T nx = A.ncx[t], ny = A.ncy[t];
+    const T hp = A.hseg_p[hs], vp = A.vseg_p[vs];
+    const uint8_t hl = A.hseg_l[hs], vl = A.vseg_l[vs];
+    T b = u;
     uint8_t al = 0;
-    if (f & 1) {
-      const int hs = (sx > 0 ? I - 1 : I) + A.NI * J;  // incoming horizontal segment
-      b = vmax(b, A.hseg_p[hs]);
-      if (A.hseg_l[hs]) al |= 1;
-    }
-    if (f & 2) {
-      const int vs = I + CI * (sy > 0 ? J - 1 : J);
-      b = vmax(b, A.vseg_p[vs]);
-      if (A.vseg_l[vs]) al |= 2;
+    if (disnan(g)) {
+      const int ex = wx_of(c), ey = wy_of(c);
+      const int nxi = xi + sx, nyi = yi + sy;
+      if (ex == -sx && nxi >= 0 && nxi < A.n0) b = vmax(b, nx);
+      if (ey == -sy && nyi >= 0 && nyi < A.n1) b = vmax(b, ny);
+      const int pxi = xi - sx, pyi = yi - sy;
+      if (ex == sx && pxi >= 0 && pxi < A.n0) {
+        b = vmax(b, hp);
+        if (hl) al |= 1;
+      }
+      if (ey == sy && pyi >= 0 && pyi < A.n1) {
+        b = vmax(b, vp);
+        if (vl) al |= 2;
+      }
     }
     const int x = (J + 1) * SP + (I + 1);
     cb[x] = b;
@@ -1482,59 +1520,75 @@ __device__ __forceinline__ void causal_b_body(const DD2<T>& A, int bx, T* U, int
     sweep_any(R, CI, CJ, SP, dir);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < CI * CJ; t += kBlock) {
+  for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
     const int I = t % CI, J = t / CI;
-    U[(I * A.M) + A.n0 * (J * A.M)] = cu[(J + 1) * SP + (I + 1)];
+    U[(I * M) + A.n0 * (J * M)] = cu[(J + 1) * SP + (I + 1)];
   }
 }
+constexpr int kCornerBlock = 1024;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_causal_b(DD2<T> A, T* U, int dir) { causal_b_body(A, (int)blockIdx.x, U, dir); }
+__global__ __launch_bounds__(kCornerBlock) void k_causal_corner(DD2<T> A, T* U, const uint8_t* W, int dir) {
+  causal_corner_body(A, U, W, dir);
+}
+// batched: one block per problem (work = (problem, 0)); which = 0 sweeps
+// U/W of each problem, 1 sweeps Un/Wn
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_causal_b_b(const DD2<T>* descs, const int2* work, int which, int dir) {
+__global__ __launch_bounds__(kCornerBlock) void k_causal_corner_b(const DD2<T>* descs, const int2* work, int which,
+                                                                 int dir) {
   const int2 w = work[blockIdx.x];
   const DD2<T> A = descs[w.x];
-  causal_b_body(A, w.y, which ? A.Un : A.U, dir);
+  causal_corner_body(A, which ? A.Un : A.U, which ? A.Wn : A.W, dir);
 }
 
+// phase C of direction prev (prev < 0: none) and phase A of direction dir
+// on segment s, then the successor value of the corner the segment leaves
+template <typename T>
+__device__ __forceinline__ void causal_seg_body(const DD2<T>& A, int bx, T* U, const uint8_t* W, int dir, int prev) {
+  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
+  const int s = bx * kBlock + (int)threadIdx.x;
+  if (s >= nseg) return;
+  const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
+  if (prev >= 0) causal_seg_c(A, s, U, (prev & 2) ? 1 : -1, (prev & 1) ? 1 : -1);
+  causal_seg_a(A, s, U, W, sx, sy);
+  const Seg g = seg_of(A, s);
+  const int M = A.M, CI = A.NI + 1;
+  const int sg = g.horiz ? sx : sy;
+  const int stride = g.horiz ? 1 : A.n0;
+  const int base = (g.I * M) + A.n0 * (g.J * M);
+  const int X = sg > 0 ? base + stride : base + (M - 1) * stride;
+  if (g.horiz) A.ncx[(sg > 0 ? g.I : g.I + 1) + CI * g.J] = U[X];
+  else A.ncy[g.I + CI * (sg > 0 ? g.J : g.J + 1)] = U[X];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_causal_seg(DD2<T> A, T* U, const uint8_t* W, int dir, int prev) {
+  causal_seg_body(A, (int)blockIdx.x, U, W, dir, prev);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_causal_seg_b(const DD2<T>* descs, const int2* work, int which, int dir,
+                                                        int prev) {
+  const int2 w = work[blockIdx.x];
+  const DD2<T> A = descs[w.x];
+  causal_seg_body(A, w.y, which ? A.Un : A.U, which ? A.Wn : A.W, dir, prev);
+}
+// blocks of k_causal_seg / k_causal_c per problem
+template <typename T>
+__host__ __device__ __forceinline__ int causal_blocks(const DD2<T>& A) {
+  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
+  return (nseg + kBlock - 1) / kBlock;
+}
 
 template <typename T>
 __device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy) {
-  const int nH = A.NI * (A.NJ + 1);
-  const int nV = (A.NI + 1) * A.NJ;
-  int s = bx * blockDim.x + threadIdx.x;
-  bool horiz;
-  int I, J;
-  if (s < nH) { horiz = true; I = s % A.NI; J = s / A.NI; }
-  else if (s < nH + nV) { s -= nH; horiz = false; I = s % (A.NI + 1); J = s / (A.NI + 1); }
-  else return;
-  const int M = A.M;
-  const int sg = horiz ? sx : sy;
-  const int stride = horiz ? 1 : A.n0;
-  const int base = (I * M) + A.n0 * (J * M);
-  const int start = sg > 0 ? base : base + M * stride;
-  const T cs = U[start];
-  constexpr int C = 8;
-  for (int q0 = 1; q0 < M; q0 += C) {
-    T P[C];
-    uint8_t F[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const int X = base + min(q0 + k, M - 1) * stride;
-      P[k] = A.cwork[X];
-      F[k] = A.cflag[X];
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      if (q0 + k >= M) break;
-      const int X = base + (q0 + k) * stride;
-      U[X] = F[k] ? vmax(P[k], cs) : P[k];
-    }
-  }
+  const int s = bx * kBlock + (int)threadIdx.x;
+  if (s < A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ) causal_seg_c(A, s, U, sx, sy);
 }
 template <typename T>
-__global__ void k_causal_c(DD2<T> A, T* U, int sx, int sy) { causal_c_body(A, (int)blockIdx.x, U, sx, sy); }
+__global__ __launch_bounds__(kBlock) void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
+  causal_c_body(A, (int)blockIdx.x, U, sx, sy);
+}
 template <typename T>
-__global__ void k_causal_c_b(const DD2<T>* descs, const int2* work, int which, int sx, int sy) {
+__global__ __launch_bounds__(kBlock) void k_causal_c_b(const DD2<T>* descs, const int2* work, int which, int sx,
+                                                      int sy) {
   const int2 w = work[blockIdx.x];
   const DD2<T> A = descs[w.x];
   causal_c_body(A, w.y, which ? A.Un : A.U, sx, sy);
