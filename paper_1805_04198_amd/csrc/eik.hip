@@ -483,7 +483,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     tot_lat += q.nlat;
     tot_rec += nblocks(q.nrec, bs);
     tot_res += nblocks(q.nres, bs);
-    tot_cc += nblocks(q.nH + q.nV, bs);
+    tot_cc += nblocks(q.nH + q.nV, bs / (M - 1));  // = causal_blocks(q.A)
   }
   int64_t tot_near = 0;
   for (int p = 0; p < P; ++p) tot_near += nblocks(pr[p].npair, bs);
@@ -503,13 +503,17 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   unsigned long long* d_cnt = cv.take<unsigned long long>(4 * (size_t)P);
   unsigned int* dflag = cv.take<unsigned int>(4);
   // one device table per kind of launch, sized for all problems
-  int2* w_tile = cv.take<int2>(std::max<int64_t>(tot_tile, 1));
-  int2* w_lat = cv.take<int2>(std::max<int64_t>(tot_lat, 1));
-  int2* w_rec = cv.take<int2>(std::max<int64_t>(tot_rec, 1));
-  int2* w_res = cv.take<int2>(std::max<int64_t>(tot_res, 1));
-  int2* w_cc = cv.take<int2>(std::max<int64_t>(tot_cc, 1));
+  // capacities: the tables of all problems (later tables hold a subset)
+  const int64_t cap_tile = std::max<int64_t>(tot_tile, 1), cap_lat = std::max<int64_t>(tot_lat, 1),
+                cap_rec = std::max<int64_t>(tot_rec, 1), cap_res = std::max<int64_t>(tot_res, 1),
+                cap_cc = std::max<int64_t>(tot_cc, 1), cap_near = std::max<int64_t>(tot_near, 1);
+  int2* w_tile = cv.take<int2>(cap_tile);
+  int2* w_lat = cv.take<int2>(cap_lat);
+  int2* w_rec = cv.take<int2>(cap_rec);
+  int2* w_res = cv.take<int2>(cap_res);
+  int2* w_cc = cv.take<int2>(cap_cc);
   int2* w_cb = cv.take<int2>(P);
-  int2* w_near = cv.take<int2>(std::max<int64_t>(tot_near, 1));
+  int2* w_near = cv.take<int2>(cap_near);
   for (int p = 0; p < P; ++p) {
     BatchProb<T>& q = pr[p];
     const eik_dd_opts* op = &o[p];
@@ -583,7 +587,8 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     return EIK_OK;
   };
   std::vector<int2> tab;
-  auto upload = [&](int2* dst, std::vector<int2>& v) -> eik_status {
+  auto upload = [&](int2* dst, int64_t cap, std::vector<int2>& v) -> eik_status {
+    if ((int64_t)v.size() > cap) return fail(EIK_ERR_HIP, "batch: work table larger than its buffer (internal)");
     if (!v.empty()) HIPCHK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));  // the host vector is reused
     return EIK_OK;
@@ -618,7 +623,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   auto fresh = [&](int p) { return !pr[p].resumed; };
   build_work(tab, P, [&](int p) { return fresh(p) ? (int64_t)nblocks(pr[p].npair, bs) : 0; });
   if (!tab.empty()) {
-    if ((e = upload(w_near, tab)) != EIK_OK) return e;
+    if ((e = upload(w_near, cap_near, tab)) != EIK_OK) return e;
     hipLaunchKernelGGL(eik::k_near_a_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
     hipLaunchKernelGGL(eik::k_near_b_b<T>, dim3(tab.size()), dim3(bs), 0, s, d_desc, w_near);
   }
@@ -640,22 +645,22 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     eik_status ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)pr[p].ntile : 0; });
     tot_tile = (int64_t)tab.size();
-    if ((ee = upload(w_tile, tab)) != EIK_OK) return ee;
+    if ((ee = upload(w_tile, cap_tile, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)pr[p].nlat : 0; });
     tot_lat = (int64_t)tab.size();
-    if ((ee = upload(w_lat, tab)) != EIK_OK) return ee;
+    if ((ee = upload(w_lat, cap_lat, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nrec, bs) : 0; });
     tot_rec = (int64_t)tab.size();
-    if ((ee = upload(w_rec, tab)) != EIK_OK) return ee;
+    if ((ee = upload(w_rec, cap_rec, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nres, bs) : 0; });
     tot_res = (int64_t)tab.size();
-    if ((ee = upload(w_res, tab)) != EIK_OK) return ee;
-    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nH + pr[p].nV, bs) : 0; });
+    if ((ee = upload(w_res, cap_res, tab)) != EIK_OK) return ee;
+    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)eik::causal_blocks(pr[p].A) : 0; });
     tot_cc = (int64_t)tab.size();
-    if ((ee = upload(w_cc, tab)) != EIK_OK) return ee;
+    if ((ee = upload(w_cc, cap_cc, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)1 : 0; });
     tot_cb = (int64_t)tab.size();
-    if ((ee = upload(w_cb, tab)) != EIK_OK) return ee;
+    if ((ee = upload(w_cb, (int64_t)P, tab)) != EIK_OK) return ee;
     return EIK_OK;
   };
   if ((e = set_tables(fresh)) != EIK_OK) return e;

@@ -1314,10 +1314,10 @@ __global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
 // coarse grid in anti-diagonal order; phase C, fill the segments from their
 // start corner.
 //
-// Two launches per direction: k_causal_seg, one thread per segment, runs
-// phase C of the previous direction on it, then phase A of this one (phase A
+// Two launches per direction: k_causal_seg, one thread per segment node,
+// runs phase C of the previous direction, then phase A of this one (phase A
 // of a segment reads only the segment and its end corner, both final after
-// the previous phase B), and stores the value of its node next to the
+// the previous phase B), and stores the value of the segment's node next to the
 // corner it leaves in sweep order, which that corner's V needs (ncx / ncy);
 // k_causal_corner, one block, evaluates V and the links of every corner from
 // independent loads and runs phase B.  A last k_causal_c fills the segments
@@ -1339,88 +1339,6 @@ __device__ __forceinline__ Seg seg_of(const DD2<T>& A, int s) {
   if (s < nH) return Seg{true, s % A.NI, s / A.NI};
   s -= nH;
   return Seg{false, s % (A.NI + 1), s / (A.NI + 1)};
-}
-
-// phase A on one segment: V, the running maximum over the linked chain from
-// the segment's start (cwork) and whether the chain is linked to the start
-// corner (cflag); the segment's end value and link go to hseg / vseg
-template <typename T>
-__device__ __forceinline__ void causal_seg_a(const DD2<T>& A, int s, T* U, const uint8_t* W, int sx, int sy) {
-  const Seg g = seg_of(A, s);
-  const int M = A.M;
-  const int sg = g.horiz ? sx : sy;
-  const int stride = g.horiz ? 1 : A.n0;
-  const int base = (g.I * M) + A.n0 * (g.J * M);  // corner (I, J)
-  T P = T(0);
-  bool L = true;
-  // the segment's M-1 nodes in sweep order, in chunks whose loads are
-  // independent of the running maximum
-  constexpr int C = 8;
-  for (int q0 = 1; q0 < M; q0 += C) {
-    T v[C], nx[C];
-    uint8_t wc[C];
-    bool gm[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const int q = min(q0 + k, M - 1);
-      const int off = sg > 0 ? q : M - q;
-      const int X = base + off * stride;
-      v[k] = U[X];
-      nx[k] = U[X + sg * stride];
-      wc[k] = W[X];
-      gm[k] = !disnan(A.gfull[X]);
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const int q = q0 + k;
-      if (q >= M) break;
-      const int off = sg > 0 ? q : M - q;
-      const int X = base + off * stride;
-      T vv = v[k];
-      bool link = false;
-      if (!gm[k]) {
-        const int e = g.horiz ? wx_of(wc[k]) : wy_of(wc[k]);
-        if (e == -sg) vv = vmax(vv, nx[k]);
-        link = (e == sg);
-      }
-      P = (link && q > 1) ? vmax(vv, P) : vv;
-      L = L && link;
-      A.cwork[X] = P;
-      A.cflag[X] = L ? 1 : 0;
-    }
-  }
-  if (g.horiz) { A.hseg_p[s] = P; A.hseg_l[s] = L ? 1 : 0; }
-  else { A.vseg_p[s - A.NI * (A.NJ + 1)] = P; A.vseg_l[s - A.NI * (A.NJ + 1)] = L ? 1 : 0; }
-}
-
-// phase C on one segment: a node linked to the start corner takes the
-// maximum of its chain value and the corner's final value
-template <typename T>
-__device__ __forceinline__ void causal_seg_c(const DD2<T>& A, int s, T* U, int sx, int sy) {
-  const Seg g = seg_of(A, s);
-  const int M = A.M;
-  const int sg = g.horiz ? sx : sy;
-  const int stride = g.horiz ? 1 : A.n0;
-  const int base = (g.I * M) + A.n0 * (g.J * M);
-  const int start = sg > 0 ? base : base + M * stride;
-  const T cs = U[start];
-  constexpr int C = 8;
-  for (int q0 = 1; q0 < M; q0 += C) {
-    T P[C];
-    uint8_t F[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const int X = base + min(q0 + k, M - 1) * stride;
-      P[k] = A.cwork[X];
-      F[k] = A.cflag[X];
-    }
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      if (q0 + k >= M) break;
-      const int X = base + (q0 + k) * stride;
-      U[X] = F[k] ? vmax(P[k], cs) : P[k];
-    }
-  }
 }
 
 // The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
@@ -1540,24 +1458,118 @@ __global__ __launch_bounds__(kCornerBlock) void k_causal_corner_b(const DD2<T>* 
   causal_corner_body(A, which ? A.Un : A.U, which ? A.Wn : A.W, dir);
 }
 
+// The segment kernels run one thread per segment node: a block holds
+// kBlock / (M-1) whole segments, node q = 1 .. M-1 of a segment (counted
+// from its minus-end corner) at thread (segment slot) * (M-1) + q - 1.
+template <typename T>
+__host__ __device__ __forceinline__ int causal_blocks(const DD2<T>& A) {
+  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
+  const int per = kBlock / (A.M - 1);
+  return (nseg + per - 1) / per;
+}
+struct SegNode {
+  bool on;    // a node of an existing segment
+  Seg g;
+  int s, q;   // segment, node position from the minus-end corner
+  int slot;   // the segment's slot in the block
+  int stride, base, X;
+};
+template <typename T>
+__device__ __forceinline__ SegNode seg_node(const DD2<T>& A, int bx) {
+  SegNode n;
+  const int m1 = A.M - 1;
+  const int per = kBlock / m1;
+  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
+  n.slot = (int)threadIdx.x / m1;
+  n.q = (int)threadIdx.x % m1 + 1;
+  n.s = bx * per + n.slot;
+  n.on = n.slot < per && n.s < nseg;
+  n.g = seg_of(A, n.on ? n.s : 0);
+  n.stride = n.g.horiz ? 1 : A.n0;
+  n.base = (n.g.I * A.M) + A.n0 * (n.g.J * A.M);
+  n.X = n.base + n.q * n.stride;
+  return n;
+}
+// phase C of direction (sx, sy) at one node; returns the node's value
+template <typename T>
+__device__ __forceinline__ T seg_fill(const DD2<T>& A, const SegNode& n, T* U, int sx, int sy) {
+  const int sg = n.g.horiz ? sx : sy;
+  const T cs = U[sg > 0 ? n.base : n.base + A.M * n.stride];
+  const T P = A.cwork[n.X];
+  const uint8_t F = A.cflag[n.X];
+  const T v = F ? vmax(P, cs) : P;
+  U[n.X] = v;
+  return v;
+}
+
 // phase C of direction prev (prev < 0: none) and phase A of direction dir
-// on segment s, then the successor value of the corner the segment leaves
+// on every segment node, then the value the corner each segment leaves needs
 template <typename T>
 __device__ __forceinline__ void causal_seg_body(const DD2<T>& A, int bx, T* U, const uint8_t* W, int dir, int prev) {
-  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
-  const int s = bx * kBlock + (int)threadIdx.x;
-  if (s >= nseg) return;
+  __shared__ T sv[kBlock];
+  __shared__ uint8_t sl[kBlock];
+  const SegNode n = seg_node(A, bx);
+  const int t = threadIdx.x;
+  const int M = A.M, m1 = M - 1;
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
-  if (prev >= 0) causal_seg_c(A, s, U, (prev & 2) ? 1 : -1, (prev & 1) ? 1 : -1);
-  causal_seg_a(A, s, U, W, sx, sy);
-  const Seg g = seg_of(A, s);
-  const int M = A.M, CI = A.NI + 1;
-  const int sg = g.horiz ? sx : sy;
-  const int stride = g.horiz ? 1 : A.n0;
-  const int base = (g.I * M) + A.n0 * (g.J * M);
-  const int X = sg > 0 ? base + stride : base + (M - 1) * stride;
-  if (g.horiz) A.ncx[(sg > 0 ? g.I : g.I + 1) + CI * g.J] = U[X];
-  else A.ncy[g.I + CI * (sg > 0 ? g.J : g.J + 1)] = U[X];
+  const int sg = n.g.horiz ? sx : sy;
+  T u = T(0), vv = T(0);
+  bool link = false;
+  if (n.on) {
+    u = prev >= 0 ? seg_fill(A, n, U, (prev & 2) ? 1 : -1, (prev & 1) ? 1 : -1) : U[n.X];
+    sv[t] = u;
+  }
+  __syncthreads();
+  if (n.on) {
+    // the node's successor in sweep order: a node of the same segment (its
+    // value after phase C is in LDS) or the end corner (final)
+    const int qn = n.q + sg;
+    const T nx = (qn >= 1 && qn <= m1) ? sv[t + sg] : U[n.base + qn * n.stride];
+    vv = u;
+    if (disnan(A.gfull[n.X])) {
+      const uint8_t wc = W[n.X];
+      const int e = n.g.horiz ? wx_of(wc) : wy_of(wc);
+      if (e == -sg) vv = vmax(vv, nx);
+      link = (e == sg);
+    }
+  }
+  __syncthreads();
+  if (n.on) {
+    sv[t] = vv;
+    sl[t] = link ? 1 : 0;
+  }
+  __syncthreads();
+  // the chain prefix maximum and the link to the start corner, in sweep
+  // order, by one thread per segment
+  if (n.on && n.q == 1) {
+    const int b0 = n.slot * m1;
+    T P = T(0);
+    bool L = true;
+    for (int k = 1; k <= m1; ++k) {
+      const int i = b0 + (sg > 0 ? k : M - k) - 1;
+      const T v = sv[i];
+      const bool lk = sl[i] != 0;
+      P = (lk && k > 1) ? vmax(v, P) : v;
+      L = L && lk;
+      sv[i] = P;
+      sl[i] = L ? 1 : 0;
+    }
+    const int nH = A.NI * (A.NJ + 1);
+    if (n.g.horiz) { A.hseg_p[n.s] = P; A.hseg_l[n.s] = L ? 1 : 0; }
+    else { A.vseg_p[n.s - nH] = P; A.vseg_l[n.s - nH] = L ? 1 : 0; }
+  }
+  __syncthreads();
+  if (n.on) {
+    A.cwork[n.X] = sv[t];
+    A.cflag[n.X] = sl[t];
+    // the corner the segment leaves in sweep order takes this node's value
+    // as its successor value
+    const int CI = A.NI + 1;
+    if (n.q == (sg > 0 ? 1 : m1)) {
+      if (n.g.horiz) A.ncx[(sg > 0 ? n.g.I : n.g.I + 1) + CI * n.g.J] = u;
+      else A.ncy[n.g.I + CI * (sg > 0 ? n.g.J : n.g.J + 1)] = u;
+    }
+  }
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_causal_seg(DD2<T> A, T* U, const uint8_t* W, int dir, int prev) {
@@ -1570,17 +1582,12 @@ __global__ __launch_bounds__(kBlock) void k_causal_seg_b(const DD2<T>* descs, co
   const DD2<T> A = descs[w.x];
   causal_seg_body(A, w.y, which ? A.Un : A.U, which ? A.Wn : A.W, dir, prev);
 }
-// blocks of k_causal_seg / k_causal_c per problem
-template <typename T>
-__host__ __device__ __forceinline__ int causal_blocks(const DD2<T>& A) {
-  const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
-  return (nseg + kBlock - 1) / kBlock;
-}
 
+// phase C of the last direction
 template <typename T>
 __device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy) {
-  const int s = bx * kBlock + (int)threadIdx.x;
-  if (s < A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ) causal_seg_c(A, s, U, sx, sy);
+  const SegNode n = seg_node(A, bx);
+  if (n.on) seg_fill(A, n, U, sx, sy);
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
