@@ -115,14 +115,16 @@ T* as(const void* p) { return (T*)p; }
 // Alg. causalsweep2D: per direction the segment kernel (phase C of the
 // previous direction, phase A of this one) and the corner kernel (phase B),
 // then phase C of the last direction.
+// res: also take the residual max |U - A.U| into A.counters[2] (U = A.Un)
 template <typename T>
-void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t ldsB) {
+void causal_sweep(eik::DD2<T>& A, T* U, const uint8_t* W, hipStream_t s, size_t ldsB, int res) {
   const int nb = eik::causal_blocks(A);
   for (int dir = 0; dir < 4; ++dir) {
     hipLaunchKernelGGL(eik::k_causal_seg<T>, dim3(nb), dim3(eik::kBlock), 0, s, A, U, W, dir, dir - 1);
-    hipLaunchKernelGGL(eik::k_causal_corner<T>, dim3(1), dim3(eik::kCornerBlock), ldsB, s, A, U, W, dir);
+    hipLaunchKernelGGL(eik::k_causal_corner<T>, dim3(1), dim3(eik::kCornerBlock), ldsB, s, A, U, W, dir,
+                       res && dir == 3 ? 1 : 0);
   }
-  hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nb), dim3(eik::kBlock), 0, s, A, U, 1, 1);
+  hipLaunchKernelGGL(eik::k_causal_c<T>, dim3(nb), dim3(eik::kBlock), 0, s, A, U, 1, 1, res);
 }
 
 // the Step 4 weight options and the coarse solver choice
@@ -302,7 +304,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
       hipLaunchKernelGGL(eik::k_near_b<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
     }
     hipLaunchKernelGGL(eik::k_lattice_init<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
-    causal_sweep(A, A.U, A.W, s, lds_cb);
+    causal_sweep(A, A.U, A.W, s, lds_cb, 0);
     HIPCHK(hipGetLastError());
   }
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.Un, nanT, N);
@@ -311,7 +313,6 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const eik_dd_debug* dbg = o->debug;
   int it = 0, conv = 0;
   double last = 0.0;
-  const int64_t nres = (int64_t)(NJ + 1) * n0 + (int64_t)(NI + 1) * n1;
   for (int k = 0; k < o->max_iter; ++k) {
     HIPCHK(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
@@ -330,9 +331,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     HIPCHK(hipEventRecord(ev[4], s));
     if (dbg && dbg->U_pre_causal)
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
-    causal_sweep(A, A.Un, A.Wn, s, lds_cb);
-    HIPCHK(hipMemsetAsync(&A.counters[2], 0, sizeof(unsigned long long), s));
-    hipLaunchKernelGGL(eik::k_residual<T>, dim3(nblocks(nres, bs)), dim3(bs), 0, s, A);
+    causal_sweep(A, A.Un, A.Wn, s, lds_cb, 1);  // also the residual (counters[2], zeroed by k_tile)
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -394,7 +393,7 @@ template <typename T>
 struct BatchProb {
   eik::DD2<T> A;
   int ntile = 0, nlat = 0, nC = 0, nH = 0, nV = 0;
-  int64_t N = 0, nrec = 0, nres = 0, npair = 0;
+  int64_t N = 0, nrec = 0, npair = 0;
   size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
   int tmode = 0;
   T* hist_u = nullptr;
@@ -424,7 +423,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   const int bs = 256;
   std::vector<BatchProb<T>> pr(P);
   size_t need = 4096 + (size_t)P * (sizeof(eik::DD2<T>) + 4 * 8) + 512;
-  int64_t tot_tile = 0, tot_lat = 0, tot_rec = 0, tot_res = 0, tot_cc = 0;
+  int64_t tot_tile = 0, tot_lat = 0, tot_rec = 0, tot_cc = 0;
   size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
   for (int p = 0; p < P; ++p) {
     const eik_dd_opts* op = &o[p];
@@ -468,7 +467,6 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     q.nH = NI * (NJ + 1);
     q.nV = (NI + 1) * NJ;
     q.nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
-    q.nres = (int64_t)(NJ + 1) * n0 + (int64_t)(NI + 1) * n1;
     q.npair = gam[p].count * (int64_t)(2 * M - 1) * (2 * M - 1);
     q.resumed = op->U_init != nullptr;
     size_t nd = 0;
@@ -482,12 +480,11 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     tot_tile += q.ntile;
     tot_lat += q.nlat;
     tot_rec += nblocks(q.nrec, bs);
-    tot_res += nblocks(q.nres, bs);
     tot_cc += nblocks(q.nH + q.nV, bs / (M - 1));  // = causal_blocks(q.A)
   }
   int64_t tot_near = 0;
   for (int p = 0; p < P; ++p) tot_near += nblocks(pr[p].npair, bs);
-  const int64_t tot_work = tot_tile + tot_lat + tot_rec + tot_res + tot_cc + P + tot_near;
+  const int64_t tot_work = tot_tile + tot_lat + tot_rec + tot_cc + P + tot_near;
   need += (size_t)tot_work * sizeof(int2) + 8 * 256;
 
   int dev = 0;
@@ -505,12 +502,11 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   // one device table per kind of launch, sized for all problems
   // capacities: the tables of all problems (later tables hold a subset)
   const int64_t cap_tile = std::max<int64_t>(tot_tile, 1), cap_lat = std::max<int64_t>(tot_lat, 1),
-                cap_rec = std::max<int64_t>(tot_rec, 1), cap_res = std::max<int64_t>(tot_res, 1),
+                cap_rec = std::max<int64_t>(tot_rec, 1),
                 cap_cc = std::max<int64_t>(tot_cc, 1), cap_near = std::max<int64_t>(tot_near, 1);
   int2* w_tile = cv.take<int2>(cap_tile);
   int2* w_lat = cv.take<int2>(cap_lat);
   int2* w_rec = cv.take<int2>(cap_rec);
-  int2* w_res = cv.take<int2>(cap_res);
   int2* w_cc = cv.take<int2>(cap_cc);
   int2* w_cb = cv.take<int2>(P);
   int2* w_near = cv.take<int2>(cap_near);
@@ -652,9 +648,6 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nrec, bs) : 0; });
     tot_rec = (int64_t)tab.size();
     if ((ee = upload(w_rec, cap_rec, tab)) != EIK_OK) return ee;
-    build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)nblocks(pr[p].nres, bs) : 0; });
-    tot_res = (int64_t)tab.size();
-    if ((ee = upload(w_res, cap_res, tab)) != EIK_OK) return ee;
     build_work(tab, P, [&](int p) { return sel(p) ? (int64_t)eik::causal_blocks(pr[p].A) : 0; });
     tot_cc = (int64_t)tab.size();
     if ((ee = upload(w_cc, cap_cc, tab)) != EIK_OK) return ee;
@@ -700,10 +693,9 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
       if (pr[p].active && pr[p].tmode == EIK_THETA_ESTIMATE)
         HIPCHK(hipMemcpyAsync(pr[p].hist_u, pr[p].A.uk, pr[p].N * szT, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipEventRecord(ev[3], s));
+    // the sweep of U^{k+1} also takes each problem's residual (counters[2],
+    // zeroed by the problem's k_tile)
     if ((e = causal_batch(1)) != EIK_OK) return e;
-    // clear the residual word of every problem, then the residuals
-    HIPCHK(hipMemset2DAsync(d_cnt + 2, 4 * sizeof(unsigned long long), 0, sizeof(unsigned long long), P, s));
-    hipLaunchKernelGGL(eik::k_residual_b<T>, dim3((unsigned)tot_res), dim3(bs), 0, s, d_desc, w_res);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[4], s));
     HIPCHK(hipMemcpyAsync(hc.data(), d_cnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));

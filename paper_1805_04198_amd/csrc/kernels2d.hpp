@@ -989,6 +989,8 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* desc
 template <typename T>
 __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // this iteration's residual (taken by the causal sweep) starts at 0
+  if (bx == 0 && threadIdx.x == 0) A.counters[2] = 0ull;
   const int I = bx % A.P0, J = bx / A.P0;
   const int L = A.S + 1;
   const int SP = halo_stride(L);
@@ -1300,6 +1302,33 @@ __global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
 }
 
 
+constexpr int kCornerBlockMax = 1024;  // largest block that calls res_reduce
+// |a - b| in double for the residual max |U^{k+1} - U^k| over the skeleton:
+// equal values (also inf and inf) give 0, NaN counts as +inf
+template <typename T>
+__device__ __forceinline__ double res_term(T a, T b) {
+  double dv = 0.0;
+  if (!(a == b)) dv = dabs((double)a - (double)b);
+  return disnan(dv) ? __builtin_huge_val() : dv;
+}
+// block maximum of dv (every thread of the block calls this), then one
+// atomic maximum per block on the bits (the order of non-negative doubles is
+// that of their bit patterns)
+__device__ __forceinline__ void res_reduce(double dv, unsigned long long* out) {
+  __shared__ double wmax[kCornerBlockMax / kWave];
+  for (int o = 32; o > 0; o >>= 1) {
+    const double v = __shfl_xor(dv, o);
+    dv = dv < v ? v : dv;
+  }
+  const int nw = (int)blockDim.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = dv;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < nw; ++i) dv = dv < wmax[i] ? wmax[i] : dv;
+    if (dv > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(dv));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // causal sweep (Alg. causalsweep2D)
 //
@@ -1321,7 +1350,9 @@ __global__ void k_reconcile_b(const DD2<T>* descs, const int2* work) {
 // corner it leaves in sweep order, which that corner's V needs (ncx / ncy);
 // k_causal_corner, one block, evaluates V and the links of every corner from
 // independent loads and runs phase B.  A last k_causal_c fills the segments
-// of the fourth direction.
+// of the fourth direction.  When the sweep finishes U^{k+1} (Step 4) the
+// last corner kernel and k_causal_c also take the residual against U^k, as
+// they write the skeleton's final values (corners, segment nodes).
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -1386,7 +1417,7 @@ struct CausalRule {
 // U, W, the segments' phase-A results and ncx / ncy) into LDS, the
 // recurrence by one wave, the corner values back to U
 template <typename T>
-__device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const uint8_t* W, int dir) {
+__device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const uint8_t* W, int dir, bool res) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int CI = A.NI + 1, CJ = A.NJ + 1;
@@ -1438,24 +1469,33 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
     sweep_any(R, CI, CJ, SP, dir);
   }
   __syncthreads();
+  double dv = 0.0;
   for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
     const int I = t % CI, J = t / CI;
-    U[(I * M) + A.n0 * (J * M)] = cu[(J + 1) * SP + (I + 1)];
+    const int X = (I * M) + A.n0 * (J * M);
+    const T v = cu[(J + 1) * SP + (I + 1)];
+    U[X] = v;
+    if (res) {
+      const double d = res_term(v, A.U[X]);
+      dv = dv < d ? d : dv;
+    }
   }
+  if (res) res_reduce(dv, &A.counters[2]);
 }
-constexpr int kCornerBlock = 1024;
+constexpr int kCornerBlock = kCornerBlockMax;
 template <typename T>
-__global__ __launch_bounds__(kCornerBlock) void k_causal_corner(DD2<T> A, T* U, const uint8_t* W, int dir) {
-  causal_corner_body(A, U, W, dir);
+__global__ __launch_bounds__(kCornerBlock) void k_causal_corner(DD2<T> A, T* U, const uint8_t* W, int dir, int res) {
+  causal_corner_body(A, U, W, dir, res != 0);
 }
 // batched: one block per problem (work = (problem, 0)); which = 0 sweeps
-// U/W of each problem, 1 sweeps Un/Wn
+// U/W of each problem, 1 sweeps Un/Wn (and takes the residual in the last
+// direction)
 template <typename T>
 __global__ __launch_bounds__(kCornerBlock) void k_causal_corner_b(const DD2<T>* descs, const int2* work, int which,
                                                                  int dir) {
   const int2 w = work[blockIdx.x];
   const DD2<T> A = descs[w.x];
-  causal_corner_body(A, which ? A.Un : A.U, which ? A.Wn : A.W, dir);
+  causal_corner_body(A, which ? A.Un : A.U, which ? A.Wn : A.W, dir, which != 0 && dir == 3);
 }
 
 // The segment kernels run one thread per segment node: a block holds
@@ -1583,59 +1623,27 @@ __global__ __launch_bounds__(kBlock) void k_causal_seg_b(const DD2<T>* descs, co
   causal_seg_body(A, w.y, which ? A.Un : A.U, which ? A.Wn : A.W, dir, prev);
 }
 
-// phase C of the last direction
+// phase C of the last direction (and the residual of the segment nodes)
 template <typename T>
-__device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy) {
+__device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy, bool res) {
   const SegNode n = seg_node(A, bx);
-  if (n.on) seg_fill(A, n, U, sx, sy);
+  double dv = 0.0;
+  if (n.on) {
+    const T v = seg_fill(A, n, U, sx, sy);
+    if (res) dv = res_term(v, A.U[n.X]);
+  }
+  if (res) res_reduce(dv, &A.counters[2]);
 }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_causal_c(DD2<T> A, T* U, int sx, int sy) {
-  causal_c_body(A, (int)blockIdx.x, U, sx, sy);
+__global__ __launch_bounds__(kBlock) void k_causal_c(DD2<T> A, T* U, int sx, int sy, int res) {
+  causal_c_body(A, (int)blockIdx.x, U, sx, sy, res != 0);
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_causal_c_b(const DD2<T>* descs, const int2* work, int which, int sx,
                                                       int sy) {
   const int2 w = work[blockIdx.x];
   const DD2<T> A = descs[w.x];
-  causal_c_body(A, w.y, which ? A.Un : A.U, sx, sy);
-}
-
-
-// max |Un - U| over the skeleton, |inf - inf| = 0, NaN counts as +inf.
-template <typename T>
-__device__ __forceinline__ void residual_body(const DD2<T>& A, int bx) {
-  const int64_t nh = (int64_t)(A.NJ + 1) * A.n0;
-  const int64_t nv = (int64_t)(A.NI + 1) * A.n1;
-  const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
-  double dv = 0.0;
-  if (t < nh) {
-    const int X = (int)(t % A.n0) + A.n0 * ((int)(t / A.n0) * A.M);
-    const T a = A.Un[X], b = A.U[X];
-    if (!(a == b)) dv = dabs((double)a - (double)b);
-    if (disnan(dv)) dv = __builtin_huge_val();
-  } else if (t < nh + nv) {
-    const int64_t s = t - nh;
-    const int X = (int)(s / A.n1) * A.M + A.n0 * (int)(s % A.n1);
-    const T a = A.Un[X], b = A.U[X];
-    if (!(a == b)) dv = dabs((double)a - (double)b);
-    if (disnan(dv)) dv = __builtin_huge_val();
-  }
-  // wave max, then one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) {
-    double v = __shfl_xor(dv, o);
-    dv = dv < v ? v : dv;
-  }
-  if ((threadIdx.x & 63) == 0 && dv > 0.0)
-    atomicMax(&A.counters[2], (unsigned long long)__double_as_longlong(dv));
-}
-template <typename T>
-__global__ void k_residual(DD2<T> A) { residual_body(A, (int)blockIdx.x); }
-template <typename T>
-__global__ void k_residual_b(const DD2<T>* descs, const int2* work) {
-  const int2 w = work[blockIdx.x];
-  const DD2<T> A = descs[w.x];
-  residual_body(A, w.y);
+  causal_c_body(A, w.y, which ? A.Un : A.U, sx, sy, which != 0);
 }
 
 
