@@ -249,6 +249,9 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.u_out = as<T>(u_outv);
   A.theta_mode = tmode;
   A.coarse_homog = o->coarse_solver;
+  A.res_out = nullptr;   // set per DD iteration
+  A.res_prev = nullptr;  // Step 1 always runs
+  A.tol = o->tol;
   set_theta<T>(A.tq, o);
   A.tref = as<T>(o->theta_ref);
   A.ukm1 = A.ckm1 = A.ckm2 = nullptr;
@@ -313,49 +316,88 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const eik_dd_debug* dbg = o->debug;
   int it = 0, conv = 0;
   double last = 0.0;
-  for (int k = 0; k < o->max_iter; ++k) {
-    HIPCHK(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
-    HIPCHK(hipEventRecord(ev[2], s));
-    const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
-    if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
-    if (tmode == EIK_THETA_ESTIMATE) {
-      // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
-      A.ck_out = hist_c[k % 3];
-      A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
-      A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
-      A.ukm1 = k >= 1 ? hist_u : nullptr;
+  // Iterations are launched up to `lag` ahead of the host's check of the
+  // stopping rule; iteration k's residual goes to slot k % kSlots, and every
+  // kernel of iteration k returns at once when iteration k-1 stopped (the
+  // same rule, dd_stopped), so the launched-ahead iterations change nothing.
+  // The debug snapshots are taken by plain copies: one iteration at a time.
+  constexpr int kLag = 4, kSlots = 2 * kLag;
+  static_assert(kSlots <= 8, "the pinned host buffer holds 8 words");
+  const int lag = dbg ? 1 : kLag;
+  unsigned long long* resid = cv.take<unsigned long long>(kSlots);
+  HIPCHK(hipMemsetAsync(resid, 0, kSlots * sizeof(unsigned long long), s));
+  A.tol = o->tol;
+  hipEvent_t evi[kLag][4];
+  for (auto& row : evi)
+    for (auto& x : row) HIPCHK(hipEventCreate(&x));
+  struct EviGuard {
+    hipEvent_t (*e)[4];
+    ~EviGuard() {
+      for (int i = 0; i < kLag; ++i)
+        for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[i][j]);
     }
-    hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
-    if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipEventRecord(ev[4], s));
-    if (dbg && dbg->U_pre_causal)
-      HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
-    causal_sweep(A, A.Un, A.Wn, s, lds_cb, 1);  // also the residual (counters[2], zeroed by k_tile)
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(ev[3], s));
-    HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  } evig{evi};
+  int launched = 0;
+  bool done = false;
+  while (!done && launched < o->max_iter) {
+    const int k0 = launched, k1 = std::min(o->max_iter, k0 + lag);
+    for (int k = k0; k < k1; ++k) {
+      hipEvent_t* E = evi[k - k0];
+      A.res_out = resid + k % kSlots;
+      A.res_prev = k > 0 ? resid + (k - 1) % kSlots : nullptr;
+      HIPCHK(hipEventRecord(E[0], s));
+      hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
+      HIPCHK(hipEventRecord(E[1], s));
+      const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
+      if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
+      if (tmode == EIK_THETA_ESTIMATE) {
+        // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
+        A.ck_out = hist_c[k % 3];
+        A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
+        A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
+        A.ukm1 = k >= 1 ? hist_u : nullptr;
+      }
+      hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
+      if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipEventRecord(E[2], s));
+      if (dbg && dbg->U_pre_causal)
+        HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
+      causal_sweep(A, A.Un, A.Wn, s, lds_cb, 1);  // also the residual (resid slot, zeroed by k_tile)
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(E[3], s));
+      std::swap(A.U, A.Un);
+      std::swap(A.W, A.Wn);
+    }
+    launched = k1;
+    HIPCHK(hipMemcpyAsync(host, resid, kSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    float a = 0.f, b = 0.f, c = 0.f;
-    HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
-    HIPCHK(hipEventElapsedTime(&b, ev[2], ev[4]));
-    HIPCHK(hipEventElapsedTime(&c, ev[4], ev[3]));
-    ms_fine += a;
-    ms_correct += b;
-    ms_causal += c;
-    unsigned long long bits = host[0];
-    double delta;
-    std::memcpy(&delta, &bits, sizeof delta);
+    // the host's stopping rule on the iterations of this block, in order
+    for (int k = k0; k < k1; ++k) {
+      float a = 0.f, b = 0.f, c = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, evi[k - k0][0], evi[k - k0][1]));
+      HIPCHK(hipEventElapsedTime(&b, evi[k - k0][1], evi[k - k0][2]));
+      HIPCHK(hipEventElapsedTime(&c, evi[k - k0][2], evi[k - k0][3]));
+      ms_fine += a;
+      ms_correct += b;
+      ms_causal += c;
+      double delta;
+      std::memcpy(&delta, &host[k % kSlots], sizeof delta);
+      it = k + 1;
+      last = delta;
+      if (st && st->residual_history && k < st->history_cap) st->residual_history[k] = delta;
+      if (std::isnan(delta)) return fail(EIK_ERR_NONFINITE, "residual is NaN");
+      if (delta < o->tol || delta == 0.0) {
+        conv = 1;
+        done = true;
+        break;
+      }
+    }
+  }
+  // U^it and W^it are where the it-th iteration put them: undo the swap of
+  // an odd number of launched-ahead iterations
+  if ((launched - it) % 2) {
     std::swap(A.U, A.Un);
     std::swap(A.W, A.Wn);
-    it = k + 1;
-    last = delta;
-    if (st && st->residual_history && k < st->history_cap) st->residual_history[k] = delta;
-    if (std::isnan(delta)) return fail(EIK_ERR_NONFINITE, "residual is NaN");
-    if (delta < o->tol || delta == 0.0) {
-      conv = 1;
-      break;
-    }
   }
   if (U_outv) hipLaunchKernelGGL(eik::k_export_U<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A, A.U, as<T>(U_outv));
   if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
@@ -552,6 +594,9 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.u_out = as<T>(u_out[p]);
     A.theta_mode = q.tmode;
     A.coarse_homog = op->coarse_solver;
+    A.res_out = A.counters + 2;  // read back after every iteration
+    A.res_prev = nullptr;        // the batch checks on the host
+    A.tol = op->tol;
     set_theta<T>(A.tq, op);
     A.tref = as<T>(op->theta_ref);
     A.ukm1 = A.ckm1 = A.ckm2 = nullptr;

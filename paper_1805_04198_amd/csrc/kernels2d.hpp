@@ -636,7 +636,22 @@ struct DD2 {
   // coarse solver of Steps 1 and 4: 0 = C_H (Sec. 3.2), 1 = the homogenised
   // solver of the squares medium (Sec. 5.3)
   int coarse_homog;
+  // this DD iteration's residual max |U^{k+1} - U^k| (double bits; k_tile
+  // zeroes it, the causal sweep of U^{k+1} raises it) ...
+  unsigned long long* res_out;
+  // ... and the previous iteration's, or NULL: when that one met the
+  // stopping rule (< tol or 0) every kernel of this iteration returns at
+  // once, so iterations can be launched ahead of the host's check
+  const unsigned long long* res_prev;
+  double tol;
 };
+
+template <typename T>
+__device__ __forceinline__ bool dd_stopped(const DD2<T>& A) {
+  if (!A.res_prev) return false;
+  const double r = __longlong_as_double((long long)*A.res_prev);
+  return r < A.tol || r == 0.0;
+}
 
 __device__ __forceinline__ bool is_iface(int c, int S, int n) { return (c % S == 0) && c > 0 && c < n - 1; }
 
@@ -849,6 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_lattice_init_b(const DD2<T>* descs, 
 template <typename T>
 __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (dd_stopped(A)) return;
   int o0, o1;
   lattice_offset(bx, A.M, o0, o1);
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
@@ -989,8 +1005,10 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* desc
 template <typename T>
 __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // this iteration's residual (taken by the causal sweep) starts at 0
-  if (bx == 0 && threadIdx.x == 0) A.counters[2] = 0ull;
+  // this iteration's residual (taken by the causal sweep) starts at 0, also
+  // when the iteration does not run
+  if (bx == 0 && threadIdx.x == 0) *A.res_out = 0ull;
+  if (dd_stopped(A)) return;
   const int I = bx % A.P0, J = bx / A.P0;
   const int L = A.S + 1;
   const int SP = halo_stride(L);
@@ -1215,6 +1233,7 @@ __global__ void k_grid_init(GS2<T> A) {
 // horizontal lines x n0 nodes (crossings are done by the vertical pass).
 template <typename T>
 __device__ __forceinline__ void reconcile_body(const DD2<T>& A, int bx) {
+  if (dd_stopped(A)) return;
   const int64_t nv = (int64_t)(A.P0 - 1) * A.n1;
   const int64_t nh = (int64_t)(A.P1 - 1) * A.n0;
   const int64_t t = bx * (int64_t)blockDim.x + threadIdx.x;
@@ -1419,6 +1438,7 @@ struct CausalRule {
 template <typename T>
 __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const uint8_t* W, int dir, bool res) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (dd_stopped(A)) return;
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int CI = A.NI + 1, CJ = A.NJ + 1;
   const int SP = halo_stride(CI);
@@ -1480,7 +1500,7 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
       dv = dv < d ? d : dv;
     }
   }
-  if (res) res_reduce(dv, &A.counters[2]);
+  if (res) res_reduce(dv, A.res_out);
 }
 constexpr int kCornerBlock = kCornerBlockMax;
 template <typename T>
@@ -1548,6 +1568,7 @@ template <typename T>
 __device__ __forceinline__ void causal_seg_body(const DD2<T>& A, int bx, T* U, const uint8_t* W, int dir, int prev) {
   __shared__ T sv[kBlock];
   __shared__ uint8_t sl[kBlock];
+  if (dd_stopped(A)) return;
   const SegNode n = seg_node(A, bx);
   const int t = threadIdx.x;
   const int M = A.M, m1 = M - 1;
@@ -1626,13 +1647,14 @@ __global__ __launch_bounds__(kBlock) void k_causal_seg_b(const DD2<T>* descs, co
 // phase C of the last direction (and the residual of the segment nodes)
 template <typename T>
 __device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int sx, int sy, bool res) {
+  if (dd_stopped(A)) return;
   const SegNode n = seg_node(A, bx);
   double dv = 0.0;
   if (n.on) {
     const T v = seg_fill(A, n, U, sx, sy);
     if (res) dv = res_term(v, A.U[n.X]);
   }
-  if (res) res_reduce(dv, &A.counters[2]);
+  if (res) res_reduce(dv, A.res_out);
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_causal_c(DD2<T> A, T* U, int sx, int sy, int res) {
