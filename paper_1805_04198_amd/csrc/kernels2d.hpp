@@ -884,17 +884,27 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   const bool nx = o0 == 0, ny = o1 == 0;  // normal axes shared by the whole lattice
   for (int k = threadIdx.x; k < cnt; k += kBlock) { u[k] = inf; rd[k] = nan; uk[k] = inf; ck[k] = inf; mk[k] = 0; }
   __syncthreads();
+  // every global input of a node in one pass: U^k, u^k (g at Gamma nodes),
+  // r*H, w^k | W^k << 4 in the mask byte and the Gamma flag in the C^k
+  // array until the C^k pass replaces them (then the flag is bit 7 of the
+  // mask, which the condition bits 0-6 leave free)
   int nfree = 0;
   for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
     const int X = xi + A.n0 * yi;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    u[x] = A.U[X];  // U^k, used for C^k first
+    const T Uk = A.U[X];
     const T g = A.gfull[X];
+    const T ukX = A.uk[X];
+    const T r = A.r[X];
+    const uint8_t wkX = A.wk[X], WkX = A.W[X];
     const bool gam = !disnan(g);
-    uk[x] = gam ? g : A.uk[X];
-    rd[x] = A.r[X] * A.HT;
+    u[x] = Uk;  // U^k, used for C^k first
+    uk[x] = gam ? g : ukX;
+    rd[x] = r * A.HT;
+    mk[x] = (uint8_t)((wkX & 15) | ((WkX & 15) << 4));
+    ck[x] = gam ? T(1) : T(0);
     if (!gam) ++nfree;
   }
   __syncthreads();
@@ -909,8 +919,10 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     const T b = ym < yp ? ym : yp;
     bool two;
     const T c = A.coarse_homog ? homog2(a, b, rd[x]) : godunov2(a, b, rd[x], two);
+    const unsigned st = mk[x];
+    const bool gam = ck[x] != T(0);
     ck[x] = c;
-    mk[x] = corr_mask(A.wk[X], A.W[X], nx, ny, dfinite(c));
+    mk[x] = (uint8_t)(corr_mask((uint8_t)(st & 15), (uint8_t)(st >> 4), nx, ny, dfinite(c)) | (gam ? 128 : 0));
     if (A.theta_mode == 1) {
       // u^k - u^{k-1} (NaN when it cannot be used) and w1 d1 + w2 d2 with
       // d1 = C^k - C^{k-1}, d2 = C^{k-1} - C^{k-2}
@@ -936,10 +948,8 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
     const int p0 = k % L0, p1 = k / L0;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
-    const T g = A.gfull[X];
-    if (!disnan(g)) {
-      u[x] = g;
+    if (mk[x] & 128) {
+      u[x] = uk[x];  // g
       rd[x] = nan;
     } else {
       u[x] = inf;
@@ -981,7 +991,7 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const int x = (p1 + 1) * SP + (p0 + 1);
     A.Un[X] = u[x];
-    A.Wn[X] = disnan(A.gfull[X]) ? A.wk[X] : (uint8_t)0;
+    A.Wn[X] = (mk[x] & 128) ? (uint8_t)0 : A.wk[X];
   }
   for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);

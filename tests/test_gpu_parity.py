@@ -175,6 +175,29 @@ def test_dd_resume_matches_uninterrupted():
     assert torch.equal(full["u"], rest["u"])
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("case", [dict(seed=21, n=(129, 97), S=32, M=8, theta=0.25, tol=None, max_iter=200),
+                                  dict(seed=22, n=(97, 65), S=32, M=16, theta=0.2, tol=0.0, max_iter=7),
+                                  dict(seed=23, n=(65, 65), S=16, M=8, theta=0.7, tol=None, max_iter=9)])
+def test_iterations_launched_ahead_change_nothing(case, dtype):
+    """The solver launches iterations ahead of its convergence check; with
+    debug snapshots it checks after every iteration.  Both must give the same
+    results, counters and residual history (converged at any point of a
+    block, capped by max_iter at any point, or not converging)."""
+    p = W.random_problem(case["seed"], case["n"], case["S"], case["M"], n_src=2, kind="fourier")
+    r, gi, gv = gpu_inputs(p, dtype)
+    tol = case["tol"] if case["tol"] is not None else (1e-12 if dtype == np.float64 else 1e-6)
+    print(f"launch-ahead case={case} dtype={np.dtype(dtype).name}", flush=True)
+    kw = dict(theta=case["theta"], tol=tol, max_iter=case["max_iter"])
+    a = E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw)
+    b = E.dd_solve(r, gi, gv, p.h, p.S, p.M, debug=True, **kw)
+    for k in ("iterations", "converged", "fine_updates", "coarse_updates", "residuals"):
+        assert a[k] == b[k], k
+    assert torch.equal(a["u"], b["u"])
+    assert torch.equal(torch.nan_to_num(a["U"], nan=-1.0), torch.nan_to_num(b["U"], nan=-1.0))
+    assert torch.equal(a["W"], b["W"])
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(S=12, M=8), E.EIK_ERR_SHAPE),
     (dict(S=16, M=1), E.EIK_ERR_SHAPE),
