@@ -1037,27 +1037,31 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
     const int xi = bi + li, yi = bj + lj;
     const int X = xi + A.n0 * yi;
     const int x = (lj + 1) * SP + (li + 1);
+    // all loads of the node first (independent), then the decisions
+    const bool bx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
+    const bool by = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
     const T g = A.gfull[X];
+    const T r = A.r[X];
+    uint8_t Wc = 0;
+    T Uc = pinf<T>();
+    if (bx || by) {
+      Wc = A.W[X];
+      Uc = A.U[X];
+    }
     if (!disnan(g)) {
       u[x] = g; w[x] = 0; rd[x] = nan;
       continue;
     }
     ++nfree;
-    rd[x] = A.r[X] * A.hT;
+    rd[x] = r * A.hT;
     // Step 2: a subdomain-boundary node on an interface is inflow if the
     // coarse wind points into the subdomain; it starts at U with wind W and,
     // like every non-Gamma node, still takes the FSM minimum.
     bool inflow = false;
-    uint8_t Wc = 0;
-    const bool bx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
-    const bool by = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
-    if (bx || by) {
-      Wc = A.W[X];
-      if (bx && ((li == 0 && wx_of(Wc) > 0) || (li == A.S && wx_of(Wc) < 0))) inflow = true;
-      if (by && ((lj == 0 && wy_of(Wc) > 0) || (lj == A.S && wy_of(Wc) < 0))) inflow = true;
-    }
+    if (bx && ((li == 0 && wx_of(Wc) > 0) || (li == A.S && wx_of(Wc) < 0))) inflow = true;
+    if (by && ((lj == 0 && wy_of(Wc) > 0) || (lj == A.S && wy_of(Wc) < 0))) inflow = true;
     if (inflow) {
-      u[x] = A.U[X];
+      u[x] = Uc;
       w[x] = Wc;
     } else {
       u[x] = pinf<T>();
