@@ -205,7 +205,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   need += 6 * (N + 256);                 // W Wn wk cflag
   need += 2 * (N * 8 + 256);             // near keys
   need += ntile * 4 * L * (szT + 1) + 512;
-  need += 2 * nC * szT + (nH + nV) * (szT + 1) + 2048;
+  need += 3 * nC * szT + 2 * nC + (nH + nV) * (szT + 1) + 4096;
   need += 4096;
   if (tmode == EIK_THETA_ESTIMATE) need += 4 * (N * szT + 256);  // u^{k-1}, C^k, C^{k-1}, C^{k-2}
   void* wsv;
@@ -240,6 +240,9 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.edge_w = cv.take<uint8_t>((size_t)ntile * 4 * L);
   A.ncx = cv.take<T>(nC);
   A.ncy = cv.take<T>(nC);
+  A.cU = cv.take<T>(nC);
+  A.cW = cv.take<uint8_t>(nC);
+  A.cG = cv.take<uint8_t>(nC);
   A.hseg_p = cv.take<T>(std::max(nH, 1));
   A.hseg_l = cv.take<uint8_t>(std::max(nH, 1));
   A.vseg_p = cv.take<T>(std::max(nV, 1));
@@ -516,13 +519,13 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     nd += 6 * (q.N + 256);
     nd += 2 * (q.N * 8 + 256);
     nd += (size_t)q.ntile * 4 * L * (szT + 1) + 512;
-    nd += 2 * q.nC * szT + (q.nH + q.nV) * (szT + 1) + 2048;
+    nd += 3 * q.nC * szT + 2 * q.nC + (q.nH + q.nV) * (szT + 1) + 4096;
     if (q.tmode == EIK_THETA_ESTIMATE) nd += 4 * (q.N * szT + 256);
     need += nd;
     tot_tile += q.ntile;
     tot_lat += q.nlat;
     tot_rec += nblocks(q.nrec, bs);
-    tot_cc += nblocks(q.nH + q.nV, bs / (M - 1));  // = causal_blocks(q.A)
+    tot_cc += nblocks(q.nH + q.nV, bs / (M - 1)) + nblocks(q.nC, bs);  // = causal_blocks(q.A)
   }
   int64_t tot_near = 0;
   for (int p = 0; p < P; ++p) tot_near += nblocks(pr[p].npair, bs);
@@ -586,6 +589,9 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.edge_w = cv.take<uint8_t>((size_t)q.ntile * 4 * L);
     A.ncx = cv.take<T>(q.nC);
     A.ncy = cv.take<T>(q.nC);
+    A.cU = cv.take<T>(q.nC);
+    A.cW = cv.take<uint8_t>(q.nC);
+    A.cG = cv.take<uint8_t>(q.nC);
     A.hseg_p = cv.take<T>(std::max(q.nH, 1));
     A.hseg_l = cv.take<uint8_t>(std::max(q.nH, 1));
     A.vseg_p = cv.take<T>(std::max(q.nV, 1));

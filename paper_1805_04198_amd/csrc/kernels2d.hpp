@@ -616,6 +616,9 @@ struct DD2 {
   uint8_t* cflag;     // causal sweep scratch (full grid)
   T* ncx;             // causal sweep: per corner, its x / y successor's value
   T* ncy;
+  T* cU;              // causal sweep: per corner, U, W and the Gamma flag,
+  uint8_t* cW;        // gathered by the segment kernel so that the corner
+  uint8_t* cG;        // kernel's loads are contiguous
   T* hseg_p;          // NI*(NJ+1) segment end values
   uint8_t* hseg_l;
   T* vseg_p;          // (NI+1)*NJ
@@ -1466,19 +1469,18 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
   for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
     const int I = t % CI, J = t / CI;
     const int xi = I * M, yi = J * M;
-    const int X = xi + A.n0 * yi;
     // incoming segments in sweep order (clamped; used only when linked)
     const int hs = min(max((sx > 0 ? I - 1 : I) + A.NI * J, 0), nH - 1);
     const int vs = min(max(I + CI * (sy > 0 ? J - 1 : J), 0), nV - 1);
-    const T u = U[X];
-    const T g = A.gfull[X];
-    const uint8_t c = W[X];
+    const T u = A.cU[t];
+    const bool gam = A.cG[t] != 0;
+    const uint8_t c = A.cW[t];
     const T nx = A.ncx[t], ny = A.ncy[t];
     const T hp = A.hseg_p[hs], vp = A.vseg_p[vs];
     const uint8_t hl = A.hseg_l[hs], vl = A.vseg_l[vs];
     T b = u;
     uint8_t al = 0;
-    if (disnan(g)) {
+    if (!gam) {
       const int ex = wx_of(c), ey = wy_of(c);
       const int nxi = xi + sx, nyi = yi + sy;
       if (ex == -sx && nxi >= 0 && nxi < A.n0) b = vmax(b, nx);
@@ -1536,10 +1538,17 @@ __global__ __launch_bounds__(kCornerBlock) void k_causal_corner_b(const DD2<T>* 
 // kBlock / (M-1) whole segments, node q = 1 .. M-1 of a segment (counted
 // from its minus-end corner) at thread (segment slot) * (M-1) + q - 1.
 template <typename T>
-__host__ __device__ __forceinline__ int causal_blocks(const DD2<T>& A) {
+__host__ __device__ __forceinline__ int causal_seg_blocks(const DD2<T>& A) {
   const int nseg = A.NI * (A.NJ + 1) + (A.NI + 1) * A.NJ;
   const int per = kBlock / (A.M - 1);
   return (nseg + per - 1) / per;
+}
+// launch size of k_causal_seg and k_causal_c: the segment blocks, then the
+// blocks that gather the corners (idle in k_causal_c)
+template <typename T>
+__host__ __device__ __forceinline__ int causal_blocks(const DD2<T>& A) {
+  const int nc = (A.NI + 1) * (A.NJ + 1);
+  return causal_seg_blocks(A) + (nc + kBlock - 1) / kBlock;
 }
 struct SegNode {
   bool on;    // a node of an existing segment
@@ -1583,6 +1592,19 @@ __device__ __forceinline__ void causal_seg_body(const DD2<T>& A, int bx, T* U, c
   __shared__ T sv[kBlock];
   __shared__ uint8_t sl[kBlock];
   if (dd_stopped(A)) return;
+  const int nsb = causal_seg_blocks(A);
+  if (bx >= nsb) {
+    // the corners' U (final since the last corner kernel), W and Gamma flag
+    const int CI = A.NI + 1;
+    const int t = (bx - nsb) * kBlock + (int)threadIdx.x;
+    if (t < CI * (A.NJ + 1)) {
+      const int X = (t % CI) * A.M + A.n0 * ((t / CI) * A.M);
+      A.cU[t] = U[X];
+      A.cW[t] = W[X];
+      A.cG[t] = disnan(A.gfull[X]) ? 0 : 1;
+    }
+    return;
+  }
   const SegNode n = seg_node(A, bx);
   const int t = threadIdx.x;
   const int M = A.M, m1 = M - 1;
