@@ -11,7 +11,11 @@ What the paper fixes and these tests check:
   * a planar front aligned with the grid is solved exactly by the coarse
     initialisation, so the iteration stops at once;
   * the iteration state is (U^k, W^k): restarting from it continues the run
-    bitwise (Steps 2-4 read nothing else).
+    bitwise (Steps 2-4 read nothing else);
+  * Sec. 4's model problem at H = 1/20, h = 1/1000 (Figs. theta1,
+    vartheta): theta = 1 makes the coarse error grow from the first
+    iteration and stay large until exactness at k >= N; small weights make
+    it fall at every iteration.
 The detailed readings of Steps 2-4 (which the paper leaves open) are pinned
 only through these properties; see the oracle's header."""
 import numpy as np
@@ -164,3 +168,37 @@ def test_argument_errors(kw):
     with pytest.raises(ValueError):
         oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, args["S"], args["M"],
                   theta=args["theta"], max_iter=2)
+
+
+def _strip_errors(theta, ks, N=20, M=50):
+    p = W.model_strip(N, M)
+    uf = fine(p)
+    out = []
+    for k in ks:
+        R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=0.0, max_iter=k,
+                      max_coarse_sweeps=1000)
+        m = ~np.isnan(R["U"])
+        out.append(np.max(np.abs(R["U"][m] - uf[m])))
+    return np.array(out)
+
+
+def test_model_problem_theta_one_is_unstable():
+    """Sec. 4, Fig. theta1 (H = 1/20, h = 1/1000): with theta = 1 (standard
+    parareal) the coarse error grows from the first iteration and stays
+    large over many iterations; Theorem exactness still makes it vanish once
+    k >= N."""
+    ks = [0, 1, 3, 5, 9, 13, 20, 21]
+    e = _strip_errors(1.0, ks)
+    assert e[1] > e[0]
+    assert np.all(e[2:6] >= 2 * e[0]), e
+    assert e[6] <= 16 * EPS and e[7] <= 16 * EPS
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.1, 0.25])
+def test_model_problem_small_theta_converges_monotonically(theta):
+    """Sec. 4, Fig. vartheta: small weights converge, the error falling at
+    every iteration shown (and exact from k = N on)."""
+    ks = [0, 2, 4, 8, 12, 16, 20]
+    e = _strip_errors(theta, ks)
+    assert np.all(np.diff(e) < 0), e
+    assert e[-1] <= 16 * EPS
