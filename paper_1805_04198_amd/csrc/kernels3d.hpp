@@ -174,38 +174,64 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir) {
   const int sx = (dir & 4) ? 1 : -1, sy = (dir & 2) ? 1 : -1, sz = (dir & 1) ? 1 : -1;
   const int nsteps = L0 + L1 + L2 - 2;
   const int np = L1 * L2;
+  // Pencils (j, k) in sweep coordinates are numbered by anti-diagonal
+  // s = j + k (then by j): the pencils that hold a node of hyperplane t are
+  // those with t - L0 < s <= t, a contiguous run of threads, so the waves
+  // outside it skip the step as a whole.
   int jq[2], kq[2], jj[2], kk[2];
   bool has[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int p = threadIdx.x + q * blockDim.x;
     has[q] = p < np;
-    jq[q] = has[q] ? p % L1 : 0;
-    kq[q] = has[q] ? p / L1 : 0;
+    int d = 0, sd = 0, len = 1;
+    for (;;) {  // the anti-diagonal sd that holds pencil number p
+      len = min(sd, L1 - 1) - max(0, sd - (L2 - 1)) + 1;
+      if (!has[q] || p < d + len) break;
+      d += len;
+      ++sd;
+    }
+    jq[q] = has[q] ? max(0, sd - (L2 - 1)) + (p - d) : 0;
+    kq[q] = has[q] ? sd - jq[q] : 0;
     jj[q] = sy > 0 ? jq[q] : L1 - 1 - jq[q];
     kk[q] = sz > 0 ? kq[q] : L2 - 1 - kq[q];
   }
-  In cur[2], nxt[2];
+  // The read-only operands (global memory) of hyperplane t + kAhead are
+  // requested while hyperplane t is updated: a ring of kAhead register sets,
+  // the loop unrolled kAhead times so that every slot is a fixed register
+  // (two sets where the operands are large, to stay clear of spills).
+  constexpr int kAhead = sizeof(In) <= 32 ? 3 : 2;
+  In buf[2][kAhead];
+  auto fetch = [&](int t, int q, In& dst) {
+    const int iq = t - jq[q] - kq[q];
+    if (has[q] && iq >= 0 && iq < L0) dst = R.load(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q]);
+  };
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int iq = -jq[q] - kq[q];
-    if (has[q] && iq >= 0 && iq < L0) cur[q] = R.load(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q]);
+  for (int r = 0; r < kAhead; ++r) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) fetch(r, q, buf[q][r]);
   }
   int changed = 0;
-  for (int t = 0; t < nsteps; ++t) {
+  for (int t0 = 0; t0 < nsteps; t0 += kAhead) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int iq = t + 1 - jq[q] - kq[q];
-      if (has[q] && iq >= 0 && iq < L0) nxt[q] = R.load(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q]);
+    for (int r = 0; r < kAhead; ++r) {
+      const int t = t0 + r;
+      if (t < nsteps) {  // the same in every thread
+        In cur[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          cur[q] = buf[q][r];
+          fetch(t + kAhead, q, buf[q][r]);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int iq = t - jq[q] - kq[q];
+          if (has[q] && iq >= 0 && iq < L0)
+            changed |= R.update(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q], cur[q]) ? 1 : 0;
+        }
+        __syncthreads();
+      }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int iq = t - jq[q] - kq[q];
-      if (has[q] && iq >= 0 && iq < L0) changed |= R.update(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q], cur[q]) ? 1 : 0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) cur[q] = nxt[q];
   }
   return __syncthreads_or(changed) != 0;
 }
