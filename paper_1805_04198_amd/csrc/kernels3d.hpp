@@ -825,11 +825,20 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
     owned_coords(q, E, l);
     const int c[3] = {C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2]};
     const int64_t X = idx3(A.n, c[0], c[1], c[2]);
+    // every value the node may need, requested at once: its own, Gamma,
+    // wind, and both fine neighbours along each axis (where they exist)
     T v = U[X];
+    const T g = A.gfull[X];
+    const uint8_t wc = W[X];
+    T nb[3][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      nb[a][0] = c[a] > 0 ? U[X - st[a]] : T(0);
+      nb[a][1] = c[a] < A.n[a] - 1 ? U[X + st[a]] : T(0);
+    }
     uint8_t lv = 255;
     short pr[3] = {-1, -1, -1};
-    if (disnan(A.gfull[X])) {
-      const uint8_t wc = W[X];
+    if (disnan(g)) {
       for (int a = 0; a < 3; ++a) {
         const int wa = w_of(wc, a);
         if (wa == 0) continue;
@@ -843,7 +852,7 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
           ll[a] = la;
           pr[a] = (short)owned_index(ll, E);
         } else {
-          v = vmax(v, U[X - wa * st[a]]);
+          v = vmax(v, nb[a][wa > 0 ? 0 : 1]);  // U[X - wa * st[a]]
         }
       }
       int lq = 0;
