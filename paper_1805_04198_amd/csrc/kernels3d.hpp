@@ -820,6 +820,10 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
   short* pred = (short*)(val + cap);                   // in-cell link per axis, -1 = none
   uint8_t* lvl = (uint8_t*)(pred + 3 * cap);           // level, 255 = not updated (Gamma)
   const int64_t st[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
+  // the thread's first node, kept in registers for the level loop
+  T myv = T(0);
+  uint8_t mylv = 255;
+  short mypr[3] = {-1, -1, -1};
   for (int q = threadIdx.x; q < nown; q += blockDim.x) {
     int l[3];
     owned_coords(q, E, l);
@@ -862,21 +866,39 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
     val[q] = v;
     lvl[q] = lv;
     for (int a = 0; a < 3; ++a) pred[3 * q + a] = pr[a];
+    if (q == (int)threadIdx.x) {
+      myv = v;
+      mylv = lv;
+      for (int a = 0; a < 3; ++a) mypr[a] = pr[a];
+    }
   }
   __syncthreads();
   const int nlev = (E[0] - 1) + (E[1] - 1) + (E[2] - 1);
   // level 0 has no in-cell link
-  for (int lev = 1; lev <= nlev; ++lev) {
-    for (int q = threadIdx.x; q < nown; q += blockDim.x) {
-      if (lvl[q] != lev) continue;
-      T v = val[q];
-      for (int a = 0; a < 3; ++a) {
-        const int pq = pred[3 * q + a];
-        if (pq >= 0) v = vmax(v, val[pq]);
+  if (nown <= (int)blockDim.x) {
+    // one node per thread: only the predecessors' values come from LDS
+    T v = myv;
+    for (int lev = 1; lev <= nlev; ++lev) {
+      if (mylv == lev) {
+        for (int a = 0; a < 3; ++a)
+          if (mypr[a] >= 0) v = vmax(v, val[mypr[a]]);
+        val[threadIdx.x] = v;
       }
-      val[q] = v;
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    for (int lev = 1; lev <= nlev; ++lev) {
+      for (int q = threadIdx.x; q < nown; q += blockDim.x) {
+        if (lvl[q] != lev) continue;
+        T v = val[q];
+        for (int a = 0; a < 3; ++a) {
+          const int pq = pred[3 * q + a];
+          if (pq >= 0) v = vmax(v, val[pq]);
+        }
+        val[q] = v;
+      }
+      __syncthreads();
+    }
   }
   for (int q = threadIdx.x; q < nown; q += blockDim.x) {
     int l[3];
