@@ -47,14 +47,13 @@ __device__ __forceinline__ uint8_t wenc3(int wx, int wy, int wz) {
 template <typename T, bool Coarse>
 __device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd, uint8_t& code,
                                       bool homog = false) {
-  int p0 = 0, p1 = 1, p2 = 2;
-  // stable insertion sort of the three axes by value
-  if (m[p1] < m[p0]) { const int t = p0; p0 = p1; p1 = t; }
-  if (m[p2] < m[p1]) {
-    int t = p1; p1 = p2; p2 = t;
-    if (m[p1] < m[p0]) { t = p0; p0 = p1; p1 = t; }
-  }
-  const T a1 = m[p0], a2 = m[p1], a3 = m[p2];
+  // a1 <= a2 <= a3: the neighbour minima in increasing order (min, median,
+  // max; exact)
+  const bool l01 = m[0] < m[1];
+  const T lo01 = l01 ? m[0] : m[1], hi01 = l01 ? m[1] : m[0];
+  const T a1 = lo01 < m[2] ? lo01 : m[2];
+  const T a3 = hi01 < m[2] ? m[2] : hi01;
+  const T a2 = hi01 < m[2] ? hi01 : (lo01 < m[2] ? m[2] : lo01);
   T ut;
   int used;
   const T d12 = a1 - a2;
@@ -79,16 +78,22 @@ __device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd,
       used = 3;
     }
   }
-  int w[3] = {0, 0, 0};
+  int w0, w1, w2;
   if (!Coarse) {
-    w[p0] = ws[p0];
-    if (used >= 2) w[p1] = ws[p1];
-    if (used >= 3) w[p2] = ws[p2];
+    // the axes of the used terms: those whose rank in the stable ascending
+    // order of the minima (ties: lower axis first) is below `used`
+    const int r0 = (m[1] < m[0] ? 1 : 0) + (m[2] < m[0] ? 1 : 0);
+    const int r1 = (m[0] <= m[1] ? 1 : 0) + (m[2] < m[1] ? 1 : 0);
+    const int r2 = (m[0] <= m[2] ? 1 : 0) + (m[1] <= m[2] ? 1 : 0);
+    w0 = r0 < used ? ws[0] : 0;
+    w1 = r1 < used ? ws[1] : 0;
+    w2 = r2 < used ? ws[2] : 0;
   } else {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) w[a] = (ut < m[a]) ? 0 : ws[a];
+    w0 = (ut < m[0]) ? 0 : ws[0];
+    w1 = (ut < m[1]) ? 0 : ws[1];
+    w2 = (ut < m[2]) ? 0 : ws[2];
   }
-  code = wenc3(w[0], w[1], w[2]);
+  code = wenc3(w0, w1, w2);
   return ut;
 }
 
