@@ -1,4 +1,5 @@
-"""Build libeik.so (HIP, gfx950) in-tree.
+"""Build libeik.so (HIP, gfx950) in-tree, and libeik_ceilings.so, the
+measured-ceiling probes the benchmark reports beside the published peaks.
 
     python -m paper_1805_04198_amd.build
 
@@ -15,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc", "eik.hip")
 OUT_DIR = os.path.join(HERE, "_lib")
 OUT = os.path.join(OUT_DIR, "libeik.so")
+CEIL_SRC = os.path.join(HERE, "csrc", "ceilings.hip")
+CEIL_OUT = os.path.join(OUT_DIR, "libeik_ceilings.so")
 ARCH = os.environ.get("EIK_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -40,6 +43,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, OUT)
+    tmp = CEIL_OUT + ".tmp"
+    cmd = [hipcc, *FLAGS, CEIL_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, CEIL_OUT)
     return OUT
 
 
