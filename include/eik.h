@@ -45,6 +45,8 @@ typedef int32_t eik_status;
 #define EIK_ERR_HIP (-4)          /* a HIP runtime call failed */
 #define EIK_ERR_UNSUPPORTED (-5)  /* valid problem outside what this build implements (see eik_last_error) */
 #define EIK_ERR_NONFINITE (-6)    /* the residual became NaN */
+#define EIK_ERR_INTERNAL (-7)     /* an internal bound was exceeded (a wait between the two waves of a 2D box sweep
+                                     gave up); outputs unspecified */
 
 typedef enum { EIK_F32 = 0, EIK_F64 = 1 } eik_dtype;
 

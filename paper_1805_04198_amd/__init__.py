@@ -19,9 +19,11 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libeik.so")
 
 EIK_OK, EIK_ERR_ARG, EIK_ERR_SHAPE, EIK_ERR_NOCONV = 0, -1, -2, -3
 EIK_ERR_HIP, EIK_ERR_UNSUPPORTED, EIK_ERR_NONFINITE = -4, -5, -6
+EIK_ERR_INTERNAL = -7
 EIK_F32, EIK_F64 = 0, 1
 STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "ERR_HIP",
-                -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE"}
+                -5: "ERR_UNSUPPORTED", -6: "ERR_NONFINITE",
+                -7: "ERR_INTERNAL"}
 
 # exported symbols of include/eik.h
 SYMBOLS = ("eik_solve", "eik_solve_batch", "eik_dd_solve", "eik_dd_solve_batch", "eik_adjoint",

@@ -62,14 +62,14 @@ float timed(hipStream_t s, void (*launch)(hipStream_t, void*), void* arg) {
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0f;
   launch(s, arg);  // warm-up
-  hipEventRecord(a, s);
+  (void)hipEventRecord(a, s);
   launch(s, arg);
-  hipEventRecord(b, s);
-  hipEventSynchronize(b);
+  (void)hipEventRecord(b, s);
+  (void)hipEventSynchronize(b);
   float ms = -1.0f;
-  hipEventElapsedTime(&ms, a, b);
-  hipEventDestroy(a);
-  hipEventDestroy(b);
+  (void)hipEventElapsedTime(&ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
   return ms;
 }
 

@@ -406,7 +406,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(host, A.counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(host, A.counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(ev[3], s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
@@ -425,6 +425,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     st->ms_correct = ms_correct;
     st->ms_causal = ms_causal;
   }
+  if (host[3]) return fail(EIK_ERR_INTERNAL, "a wait between the two waves of a box sweep gave up");
   if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
   return EIK_OK;
 }
@@ -817,6 +818,8 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     st[p].ms_causal = ms_causal;
   }
   if (bad != EIK_OK) return bad;
+  for (int p = 0; p < P; ++p)
+    if (hc[4 * (size_t)p + 3]) return fail(EIK_ERR_INTERNAL, "a wait between the two waves of a box sweep gave up");
   if (!all_conv) return fail(EIK_ERR_NOCONV, "some problems did not converge within max_iter");
   return EIK_OK;
 }

@@ -41,7 +41,7 @@ constexpr int kMaxL = 65;  // nodes per axis of a tile / lattice held in LDS
 // addresses, so the discarded stores do not serialise on one bank).
 constexpr int kGuard = 72;
 constexpr int kDummy = -kGuard;
-__device__ __forceinline__ int dummy_slot() { return kDummy + (int)threadIdx.x; }
+__device__ __forceinline__ int dummy_slot() { return kDummy + (int)(threadIdx.x & (kWave - 1)); }
 
 template <typename T> __device__ __forceinline__ T pinf();
 template <> __device__ __forceinline__ float pinf<float>() { return __builtin_huge_valf(); }
@@ -212,6 +212,84 @@ __device__ __forceinline__ T homog2(T a, T b, T rd) {
   return ((a < b) ? a : b) + rd;
 }
 
+// Axis-aligned box of nodes [i0, i1] x [j0, j1] in box coordinates (i0 > i1:
+// empty).
+struct NodeBox {
+  int i0, i1, j0, j1;
+};
+
+// Two waves on one box.  In the loop nest's order of the sweep directions,
+// sweeps 4m and 4m+1 (likewise 4m+2 and 4m+3) differ in the y direction only.
+// The node in column c, row r of the first sweep's order lies on its
+// anti-diagonal c + r and on the second's c + (L1 - 1 - r), so the second
+// sweep can run on another wave (another SIMD) L1 + 4 steps behind the first:
+// it then reads every node after the first sweep has written it for the last
+// time and writes none before the first sweep has read it for the last time,
+// and computes the values of the two sweeps run one after the other.  Wave 0
+// (the leader) runs the even sweeps and publishes its progress; wave 1 (the
+// follower) runs the odd ones behind it.  The other transitions (4m+1 to
+// 4m+2, 4m+3 to 4m+4) reverse both directions; there the next sweep waits
+// for the whole previous one.  All fields live in LDS; each is written by one
+// wave only.
+constexpr int kPipeDone = 1 << 28;
+constexpr int kPipeSpin = 1 << 22;  // polls after which a wait gives up and sets err
+struct PipeSync {
+  int prog;        // leader: steps of its current sweep completed (kPipeDone after its end)
+  int key[kWave];  // leader, per lane: min of (column - row), sweep order, over the nodes it changed
+  int lsweep;      // leader: index of its current sweep
+  int fin;         // follower: 1 + the index of its last completed sweep
+  int err;         // a wait gave up
+  int ch[2];       // whether the last sweep of the leader [0] / follower [1] changed a node
+  NodeBox box[2];  // the nodes next to that sweep's changes
+};
+
+__device__ __forceinline__ void pipe_init(PipeSync& ps) {
+  ps.prog = 0;
+  ps.lsweep = -1;
+  ps.fin = 0;
+  ps.err = 0;
+  ps.ch[0] = ps.ch[1] = 0;
+}
+__device__ __forceinline__ int lds_load_acq(int* p) {
+  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+// one lane publishes; the release orders every earlier LDS access of the wave
+// before it
+__device__ __forceinline__ void lds_store_rel(int* p, int v) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// The first step of the follower's sweep that reaches a node next to a change
+// of the leader's sweep (key as in PipeSync), and the step count the leader
+// must have completed before the follower runs step pair (t, t+1).
+__device__ __forceinline__ int follow_t0(int key, int L1) { return max(key + L1 - 2, 0); }
+__device__ __forceinline__ int follow_lag(int L1, bool extra) { return L1 + 4 + (extra ? 1 : 0); }
+// last step of a sweep (signs sx, sy) that reaches box P
+__device__ __forceinline__ int box_tmax(const NodeBox& P, int sx, int sy, int L0, int L1, bool extra) {
+  const int qi1 = sx > 0 ? P.i1 : L0 - 1 - P.i0;
+  const int qj1 = sy > 0 ? P.j1 : L1 - 1 - P.j0;
+  return qi1 + qj1 + (extra ? 1 : 0);
+}
+// Follower: wait until the leader has completed `need` steps or ended its
+// sweep (then tmax becomes the last step that reaches the nodes next to the
+// leader's changes).  Returns the steps known to be complete.
+__device__ __forceinline__ int pipe_wait(PipeSync* ps, int need, int sx, int sy, int L0, int L1, bool extra, int& tmax) {
+  for (int n = 0;; ++n) {
+    const int p = lds_load_acq(&ps->prog);
+    if (p >= kPipeDone) {
+      const NodeBox b = ps->box[0];
+      tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, sx, sy, L0, L1, extra));
+      return 0x7fffffff;
+    }
+    if (p >= need) return p;
+    if (n >= kPipeSpin) {
+      if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
+      return 0x7fffffff;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // Sweep-order columns of the nodes a lane changed during a sweep (min and
 // max over both rows of lane 0 in a 65-row box), and whether lane 0 changed
 // a node of row 64.
@@ -244,12 +322,20 @@ struct StepSpan {
 // step pair at or beyond tmax in which no lane changed a value.  span
 // receives the steps at which each lane changed values.  Returns true in
 // lanes that changed a value.
-template <int SX, int SY, bool EXTRA, typename Rule>
-__device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t0, int tmax, StepSpan& span) {
+//
+// PIPE selects the two-wave mode (PipeSync): 0 alone, 1 leader (publishes its
+// progress and the key of its changes after every step pair), 2 follower
+// (waits before every step pair until the leader is far enough ahead, and
+// takes tmax from the leader once the leader's sweep has ended; `allowed` is
+// the leader progress already known).
+template <int SX, int SY, bool EXTRA, int PIPE = 0, typename Rule>
+__device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t0, int tmax, StepSpan& span,
+                                          PipeSync* ps = nullptr, int allowed = 0) {
   using T = typename Rule::real;
   using Pre = typename Rule::Pre;
+  static_assert(PIPE == 0 || !Rule::kHalo, "two-wave sweeps read no halo values");
   const T inf = pinf<T>();
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
   const int nsteps = L0 + L1 - 1 + (EXTRA ? 1 : 0);
   const int jA = min(max(SY > 0 ? lane : L1 - 1 - lane, 0), L1 - 1);
   const int jB = SY > 0 ? kWave : L1 - 1 - kWave;
@@ -318,24 +404,46 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   // steps run unconditionally; after that the sweep ends with the first step
   // pair that changes nothing.
   int t = t0;
+  if (PIPE == 2) {
+    // tmax may arrive during the sweep; until then every pair runs
+    const int lag = follow_lag(L1, EXTRA);
+    while (t < nsteps) {
+      if (t + lag > allowed) allowed = pipe_wait(ps, t + lag, SX, SY, L0, L1, EXTRA, tmax);
+      const bool tail = t + 1 >= tmax;
+      if (tail) recent = 0;
+      step(t, pa, pb);
+      step(t + 1, pb, pa);
+      t += 2;
+      if (tail && recent == 0) break;
+    }
+    return changed;
+  }
+  int kpub = 0x7fffffff;
+  // leader: the key of this lane's changes (lane 0 also holds row 64: a
+  // smaller key than its own only widens the follower's sweep), then the
+  // completed step count
+  auto publish = [&](int done) {
+    const int k = span.cmax >= 0 ? span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane) : 0x7fffffff;
+    if (k < kpub) {
+      ps->key[lane] = k;
+      kpub = k;
+    }
+    lds_store_rel(&ps->prog, done);
+  };
   for (; t + 1 < tmax && t < nsteps; t += 2) {
     step(t, pa, pb);
     step(t + 1, pb, pa);
+    if (PIPE == 1) publish(t + 2);
   }
   for (; t < nsteps; t += 2) {
     recent = 0;
     step(t, pa, pb);
     step(t + 1, pb, pa);
+    if (PIPE == 1) publish(t + 2);
     if (recent == 0) break;
   }
   return changed;
 }
-
-// Axis-aligned box of nodes [i0, i1] x [j0, j1] in box coordinates (i0 > i1:
-// empty).
-struct NodeBox {
-  int i0, i1, j0, j1;
-};
 
 __device__ __forceinline__ int wave_min(int v) {
   for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
@@ -346,24 +454,11 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// A sweep restricted to what can change.  P holds every node that may change
-// in this sweep without an upwind change inside the sweep (a node whose
-// neighbours kept their values since its last evaluation computes the same
-// candidate again and cannot change).  The sweep starts at the first step
-// that reaches P and runs at least to the last; changes propagate within
-// the sweep until a step pair changes nothing.  On return P holds the nodes
-// next to a change (a superset of those evaluated before a neighbour
-// changed), empty if nothing changed.
-template <int SX, int SY, bool EXTRA, typename Rule>
-__device__ __forceinline__ bool sweep_box(Rule& R, int L0, int L1, int SP, NodeBox& P) {
-  // sweep-order coordinates of the box corners
-  const int qi0 = SX > 0 ? P.i0 : L0 - 1 - P.i1, qi1 = SX > 0 ? P.i1 : L0 - 1 - P.i0;
-  const int qj0 = SY > 0 ? P.j0 : L1 - 1 - P.j1, qj1 = SY > 0 ? P.j1 : L1 - 1 - P.j0;
-  const int t0 = qi0 + qj0;
-  const int tmax = qi1 + qj1 + (EXTRA ? 1 : 0);  // row 64 runs one step late
-  StepSpan sp;
-  const bool ch = sweep_dir<SX, SY, EXTRA>(R, L0, L1, SP, t0, tmax, sp);
-  // changed nodes in sweep-order coordinates
+// The nodes next to a sweep's changes (the box of the changed nodes grown by
+// one node and clipped), from the lanes' change flags and spans; empty if
+// nothing changed.
+template <int SX, int SY, bool EXTRA>
+__device__ __forceinline__ void change_box(bool ch, const StepSpan& sp, int L0, int L1, NodeBox& P) {
   // rows: the lanes that changed a value (lane 0 stands for row 0 even if
   // only its row 64 changed, which only widens the box), plus row 64
   const unsigned long long rows = __ballot(ch);
@@ -371,7 +466,7 @@ __device__ __forceinline__ bool sweep_box(Rule& R, int L0, int L1, int SP, NodeB
   const int ci0 = wave_min(sp.cmin), ci1 = wave_max(sp.cmax);
   if (rows == 0) {
     P.i0 = 1; P.i1 = 0; P.j0 = 1; P.j1 = 0;
-    return ch;
+    return;
   }
   const int cj0 = __builtin_ctzll(rows);
   const int cj1 = rowB ? kWave : 63 - __builtin_clzll(rows);
@@ -380,14 +475,68 @@ __device__ __forceinline__ bool sweep_box(Rule& R, int L0, int L1, int SP, NodeB
   const int j0 = SY > 0 ? cj0 : L1 - 1 - cj1, j1 = SY > 0 ? cj1 : L1 - 1 - cj0;
   P.i0 = __builtin_amdgcn_readfirstlane(max(i0 - 1, 0));
   P.i1 = __builtin_amdgcn_readfirstlane(min(i1 + 1, L0 - 1));
-  P.j0 = max(j0 - 1, 0);
-  P.j1 = min(j1 + 1, L1 - 1);
+  P.j0 = __builtin_amdgcn_readfirstlane(max(j0 - 1, 0));
+  P.j1 = __builtin_amdgcn_readfirstlane(min(j1 + 1, L1 - 1));
+}
+
+// first step of a sweep (signs SX, SY) that reaches box P
+template <int SX, int SY>
+__device__ __forceinline__ int box_t0(const NodeBox& P, int L0, int L1) {
+  const int qi0 = SX > 0 ? P.i0 : L0 - 1 - P.i1;
+  const int qj0 = SY > 0 ? P.j0 : L1 - 1 - P.j1;
+  return qi0 + qj0;
+}
+
+// Sweeps restricted to what can change.  P holds every node that may change
+// in a sweep without an upwind change inside the sweep (a node whose
+// neighbours kept their values since its last evaluation computes the same
+// candidate again and cannot change).  A sweep starts at its first step that
+// reaches P and runs at least to its last; changes propagate within the
+// sweep until a step pair changes nothing.  Afterwards P holds the nodes
+// next to a change (a superset of those evaluated before a neighbour
+// changed), empty if nothing changed.  The follower, which starts before the
+// leader's P is complete, starts at the first step next to a change the
+// leader has published (later changes of the leader lie ahead of it) and
+// takes its last step from the leader's P once the leader has ended.
+//
+// The leader's sweep s over box P, with its progress published
+// for the follower; at its end the box of the nodes next to its changes and
+// whether it changed anything.  Returns that flag (the same in every lane).
+template <int SX, int SY, bool EXTRA, typename Rule>
+__device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, NodeBox& P, PipeSync* ps, int s) {
+  const int t0 = box_t0<SX, SY>(P, L0, L1);
+  const int tmax = box_tmax(P, SX, SY, L0, L1, EXTRA);
+  ps->key[threadIdx.x & (kWave - 1)] = 0x7fffffff;
+  if ((threadIdx.x & (kWave - 1)) == 0) ps->prog = t0;  // steps before t0 change nothing
+  lds_store_rel(&ps->lsweep, s);
+  StepSpan sp;
+  const bool lane_ch = sweep_dir<SX, SY, EXTRA, 1>(R, L0, L1, SP, t0, tmax, sp, ps);
+  change_box<SX, SY, EXTRA>(lane_ch, sp, L0, L1, P);
+  const bool ch = __any(lane_ch);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    ps->box[0] = P;
+    ps->ch[0] = ch ? 1 : 0;
+  }
+  lds_store_rel(&ps->prog, kPipeDone);
   return ch;
 }
 
-template <int SX, int SY, typename Rule>
-__device__ __forceinline__ bool sweep_box2(Rule& R, int L0, int L1, int SP, NodeBox& P) {
-  return (L1 > kWave) ? sweep_box<SX, SY, true>(R, L0, L1, SP, P) : sweep_box<SX, SY, false>(R, L0, L1, SP, P);
+// The follower's sweep s from step t0 (tmax: its last step that reaches the
+// leader's change box, or "none yet" while the leader runs); publishes its
+// own change box and flag, then fin = s + 1.
+template <int SX, int SY, bool EXTRA, typename Rule>
+__device__ __forceinline__ bool sweep_follow(Rule& R, int L0, int L1, int SP, NodeBox& P, PipeSync* ps, int s, int t0,
+                                             int tmax, int allowed) {
+  StepSpan sp;
+  const bool lane_ch = sweep_dir<SX, SY, EXTRA, 2>(R, L0, L1, SP, t0, tmax, sp, ps, allowed);
+  change_box<SX, SY, EXTRA>(lane_ch, sp, L0, L1, P);
+  const bool ch = __any(lane_ch);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    ps->box[1] = P;
+    ps->ch[1] = ch ? 1 : 0;
+  }
+  lds_store_rel(&ps->fin, s + 1);
+  return ch;
 }
 
 // One full directional sweep (used by the whole-grid FSM, one sweep per
@@ -413,25 +562,99 @@ __device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int d
 // Sweep in the 2^d orders of the paper's loop nest ((-,-), (-,+), (+,-),
 // (+,+), x outermost) until a whole sweep changes nothing, at most
 // max_sweeps.  Every node starts out as possibly changing; afterwards each
-// sweep covers only the steps that can change a value (sweep_box), which
-// gives the full sweeps' values, winds and sweep count.
-template <typename Rule>
-__device__ int wave_fsm(Rule& R, int L0, int L1, int SP, int max_sweeps) {
+// sweep covers only the steps that can change a value, which gives the full
+// sweeps' values, winds and sweep count.  Runs on waves 0 and 1 of the block
+// (PipeSync, initialised by pipe_init and a block barrier); returns the
+// number of sweeps in wave 0.
+template <bool EXTRA, typename Rule>
+__device__ __forceinline__ int fsm_leader(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
   NodeBox P{0, L0 - 1, 0, L1 - 1};
-  int s = 0;
-  while (s < max_sweeps) {
-    bool ch;
-    switch (s & 3) {
-      case 0: ch = sweep_box2<-1, -1>(R, L0, L1, SP, P); break;
-      case 1: ch = sweep_box2<-1, 1>(R, L0, L1, SP, P); break;
-      case 2: ch = sweep_box2<1, -1>(R, L0, L1, SP, P); break;
-      default: ch = sweep_box2<1, 1>(R, L0, L1, SP, P); break;
+  for (int s = 0;; s += 2) {
+    if (s > 0) {
+      // the follower's sweep s-1 has ended: its change box is this sweep's
+      for (int n = 0; lds_load_acq(&ps->fin) < s; ++n) {
+        if (n >= kPipeSpin) {
+          if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
+          return s;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (!__builtin_amdgcn_readfirstlane(ps->ch[1])) return s;
+      P = ps->box[1];
+      P.i0 = __builtin_amdgcn_readfirstlane(P.i0);
+      P.i1 = __builtin_amdgcn_readfirstlane(P.i1);
+      P.j0 = __builtin_amdgcn_readfirstlane(P.j0);
+      P.j1 = __builtin_amdgcn_readfirstlane(P.j1);
     }
-    step_fence();
-    ++s;
-    if (!__any(ch)) break;
+    if (s >= max_sweeps) return max_sweeps;
+    const bool ch = (s & 2) ? sweep_lead<1, -1, EXTRA>(R, L0, L1, SP, P, ps, s)
+                            : sweep_lead<-1, -1, EXTRA>(R, L0, L1, SP, P, ps, s);
+    if (!ch || s + 1 >= max_sweeps) return s + 1;
   }
-  return s;
+}
+
+template <bool EXTRA, typename Rule>
+__device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
+  const int lag = follow_lag(L1, EXTRA);
+  for (int s = 1; s < max_sweeps; s += 2) {
+    // the leader has begun sweep s-1 ...
+    for (int n = 0; lds_load_acq(&ps->lsweep) < s - 1; ++n) {
+      if (n >= kPipeSpin) {
+        if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
+        return;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    // ... and has changed a node and run far enough past this sweep's first
+    // step, or has ended
+    int t0 = 0, tmax = 0x7fffffff, allowed = 0;
+    for (int n = 0;; ++n) {
+      const int p = lds_load_acq(&ps->prog);
+      const int key = __builtin_amdgcn_readfirstlane(wave_min(ps->key[threadIdx.x & (kWave - 1)]));  // after prog
+      if (p >= kPipeDone) {
+        if (!__builtin_amdgcn_readfirstlane(ps->ch[0])) return;
+        const NodeBox b = ps->box[0];
+        t0 = follow_t0(key, L1);
+        tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, (s & 2) ? 1 : -1, 1, L0, L1, EXTRA));
+        allowed = 0x7fffffff;
+        break;
+      }
+      if (key != 0x7fffffff && p >= follow_t0(key, L1) + lag) {
+        t0 = follow_t0(key, L1);
+        allowed = p;
+        break;
+      }
+      if (n >= kPipeSpin) {
+        if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
+        return;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    NodeBox P;
+    const bool ch = (s & 2) ? sweep_follow<1, 1, EXTRA>(R, L0, L1, SP, P, ps, s, t0, tmax, allowed)
+                            : sweep_follow<-1, 1, EXTRA>(R, L0, L1, SP, P, ps, s, t0, tmax, allowed);
+    if (!ch) return;
+  }
+}
+
+// The waves of a block that run wave_fsm2: the leader (wave 0) and the
+// follower (wave kFollower).
+constexpr int kFollower = 1;
+__device__ __forceinline__ bool fsm_wave() {
+  const int wv = (int)(threadIdx.x / kWave);
+  return wv == 0 || wv == kFollower;
+}
+
+template <typename Rule>
+__device__ __forceinline__ int wave_fsm2(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
+  const bool extra = L1 > kWave;
+  if (threadIdx.x < kWave)
+    return extra ? fsm_leader<true>(R, L0, L1, SP, max_sweeps, ps) : fsm_leader<false>(R, L0, L1, SP, max_sweeps, ps);
+  if (extra)
+    fsm_follower<true>(R, L0, L1, SP, max_sweeps, ps);
+  else
+    fsm_follower<false>(R, L0, L1, SP, max_sweeps, ps);
+  return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -625,7 +848,7 @@ struct DD2 {
   uint8_t* vseg_l;
   unsigned long long* near_key;  // Step 1 nearest-Gamma keys (full grid)
   long long* near_win;
-  unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits
+  unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits, [3] nonzero if a two-wave sweep wait gave up
   // Step 4 weight (ThetaPar, theta_at): mode, parameters, u_ref or theta per
   // node, and the history u^{k-1}, C^{k-1}, C^{k-2} (NULL until it exists);
   // this iteration's C^k goes to ck_out
@@ -834,11 +1057,15 @@ __device__ __forceinline__ void lattice_init_body(const DD2<T>& A, int bx) {
   }
   __syncthreads();
   __shared__ int sh_ns, sh_free;
-  if (threadIdx.x == 0) sh_free = 0;
+  __shared__ PipeSync ps;
+  if (threadIdx.x == 0) {
+    sh_free = 0;
+    pipe_init(ps);
+  }
   __syncthreads();
-  if (threadIdx.x < kWave) {
+  if (fsm_wave()) {
     MinRule<T, true, false> R{u, w, rd, SP, A.coarse_homog != 0};
-    const int ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+    const int ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
     if (threadIdx.x == 0) sh_ns = ns;
   }
   __syncthreads();
@@ -853,6 +1080,7 @@ __device__ __forceinline__ void lattice_init_body(const DD2<T>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lattice_init(DD2<T> A) { lattice_init_body(A, (int)blockIdx.x); }
@@ -960,29 +1188,33 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   }
   __syncthreads();
   __shared__ int sh_ns, sh_free;
-  if (threadIdx.x == 0) sh_free = 0;
+  __shared__ PipeSync ps;
+  if (threadIdx.x == 0) {
+    sh_free = 0;
+    pipe_init(ps);
+  }
   __syncthreads();
-  if (threadIdx.x < kWave) {
+  if (fsm_wave()) {
     int ns;
     switch (A.theta_mode) {
       case 0: {
         CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
-        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       case 1: {
         CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
-        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       case 2: {
         CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
-        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       default: {
         CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
-        ns = wave_fsm(R, L0, L1, SP, A.max_coarse_sweeps);
+        ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
     }
@@ -1000,6 +1232,7 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) { lattice_correct_body(A, (int)blockIdx.x); }
@@ -1073,11 +1306,15 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   }
   __syncthreads();
   __shared__ int sh_ns, sh_free;
-  if (threadIdx.x == 0) sh_free = 0;
+  __shared__ PipeSync ps;
+  if (threadIdx.x == 0) {
+    sh_free = 0;
+    pipe_init(ps);
+  }
   __syncthreads();
-  if (threadIdx.x < kWave) {
+  if (fsm_wave()) {
     MinRule<T, false, false> R{u, w, rd, SP, false};
-    const int ns = wave_fsm(R, L, L, SP, A.max_fine_sweeps);
+    const int ns = wave_fsm2(R, L, L, SP, A.max_fine_sweeps, &ps);
     if (threadIdx.x == 0) sh_ns = ns;
   }
   __syncthreads();
@@ -1107,6 +1344,7 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) { tile_body(A, (int)blockIdx.x); }
