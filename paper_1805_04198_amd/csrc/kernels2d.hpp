@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace eik {
 
@@ -232,10 +233,15 @@ struct NodeBox {
 // for the whole previous one.  All fields live in LDS; each is written by one
 // wave only.
 constexpr int kPipeDone = 1 << 28;
+constexpr int kPipeNoKey = 1 << 29;
 constexpr int kPipeSpin = 1 << 22;  // polls after which a wait gives up and sets err
 struct PipeSync {
-  int prog;        // leader: steps of its current sweep completed (kPipeDone after its end)
-  int key[kWave];  // leader, per lane: min of (column - row), sweep order, over the nodes it changed
+  // leader, per lane: the minimum of (column - row), sweep order, over the
+  // nodes the lane changed in the current sweep (from kPipeNoKey on: none),
+  // and the steps of the sweep completed (every lane writes the same count;
+  // it is read from lane 0's slot; kPipeDone after the sweep's end).  One
+  // 8-byte store per lane and step pair publishes both.
+  int2 kp[kWave];
   int lsweep;      // leader: index of its current sweep
   int fin;         // follower: 1 + the index of its last completed sweep
   int err;         // a wait gave up
@@ -244,7 +250,6 @@ struct PipeSync {
 };
 
 __device__ __forceinline__ void pipe_init(PipeSync& ps) {
-  ps.prog = 0;
   ps.lsweep = -1;
   ps.fin = 0;
   ps.err = 0;
@@ -258,6 +263,20 @@ __device__ __forceinline__ int lds_load_acq(int* p) {
 __device__ __forceinline__ void lds_store_rel(int* p, int v) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   if ((threadIdx.x & (kWave - 1)) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// The per-step-pair progress signals (the leader's publish in sweep_dir, the
+// follower's peek).  The LDS operations of one wave are performed in the
+// order they are issued (the LDS counter of s_waitcnt counts them down in
+// order, which the compiler's own partial waits rely on), so a store issued
+// after the wave's earlier LDS accesses is performed after them, and a load
+// issued after a load is performed after it.  Only the compiler must be kept
+// from moving memory accesses across these, which saves the full LDS wait of
+// a release or acquire on every step pair.
+__device__ __forceinline__ int lds_peek(int* p) {
+  __asm__ __volatile__("" ::: "memory");
+  const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __asm__ __volatile__("" ::: "memory");
+  return v;
 }
 // The first step of the follower's sweep that reaches a node next to a change
 // of the leader's sweep (key as in PipeSync), and the step count the leader
@@ -275,7 +294,7 @@ __device__ __forceinline__ int box_tmax(const NodeBox& P, int sx, int sy, int L0
 // leader's changes).  Returns the steps known to be complete.
 __device__ __forceinline__ int pipe_wait(PipeSync* ps, int need, int sx, int sy, int L0, int L1, bool extra, int& tmax) {
   for (int n = 0;; ++n) {
-    const int p = lds_load_acq(&ps->prog);
+    const int p = lds_load_acq(&ps->kp[0].y);
     if (p >= kPipeDone) {
       const NodeBox b = ps->box[0];
       tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, sx, sy, L0, L1, extra));
@@ -365,39 +384,79 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   unsigned long long recent = 0;
   int x = x_at(t0);
   Pre pa = R.template load<SX, SY>(x), pb;
-  // one step; p holds this step's operands, pn receives the next step's
-  auto step = [&](int t, const Pre& p, Pre& pn) {
-    const bool useB = laneB && t > kWave;
-    const int iq = t - (useB ? kWave + 1 : lane);
-    const bool act = (useB || rowA) && (unsigned)iq < (unsigned)L0;
-    const int x1 = ((laneB && t >= kWave) ? xB0 : xA0) + SX * (t + 1);
+  // Lane state that changes only when lane 0 moves from row 0 to row 64
+  // (EXTRA): the column offset (column = t - ioff), whether the lane's row is
+  // the first one (no upwind-y neighbour: halo), whether it is row 64.
+  const bool startB = laneB && t0 > kWave;
+  int ioff = startB ? kWave + 1 : lane;
+  bool ytop = lane == 0 && !startB;
+  bool inB = startB;
+  const int xB1 = xB0 + SX * (kWave + 1);
+  const int ioffB = laneB ? kWave + 1 : lane;
+  // One step; p holds this step's operands, pn receives the next step's.
+  // PH: 0 any step; with EXTRA, 1 a step before step kWave (lane 0 on row 0,
+  // cur_prev not needed) and 2 a step after step kWave + 1 (lane 0 on row
+  // 64), which drop the checks for the switch.
+  auto step = [&](auto ph, int t, const Pre& p, Pre& pn) {
+    constexpr int PH = decltype(ph)::value;
+    bool restart = false;
+    if (PH == 0 && EXTRA && t == kWave + 1) {
+      // lane 0 starts row 64 at its column 0
+      ioff = laneB ? kWave + 1 : ioff;
+      ytop = false;
+      inB = laneB;
+      restart = laneB;
+    }
+    const int iq = t - (PH == 2 ? ioffB : PH == 1 ? lane : ioff);
+    const bool act = (EXTRA || rowA) && (unsigned)iq < (unsigned)L0;
+    int x1 = x + SX;
+    if (PH == 0 && EXTRA && t == kWave) x1 = laneB ? xB1 : x1;
     pn = R.template load<SX, SY>(x1);
     // keep the loads at the top of the step, a whole step ahead of their use
     __builtin_amdgcn_sched_barrier(0);
-    const T ex = (EXTRA && lane == kWave - 1) ? cur_prev : cur;
+    const T ex = (EXTRA && PH != 1 && lane == kWave - 1) ? cur_prev : cur;
     const T from_prev_row = dpp_ror1(ex);
+    const bool top = PH == 2 ? false : PH == 1 ? lane == 0 : ytop;
     T yprev, xprev;
     if (Rule::kHalo) {
-      yprev = (lane == 0 && !useB) ? p.hy : from_prev_row;
+      yprev = top ? p.hy : from_prev_row;
       xprev = (iq == 0) ? p.hx : cur;
     } else {
       // the halo is +inf: the first row has no upwind-y neighbour, and a
       // lane's cur is +inf until its row starts (the delayed row restarts)
-      yprev = (lane == 0 && !useB) ? inf : from_prev_row;
-      xprev = (EXTRA && laneB && t == kWave + 1) ? inf : cur;
+      yprev = top ? inf : from_prev_row;
+      xprev = (EXTRA && restart) ? inf : cur;
     }
     const T xm = SX > 0 ? xprev : p.xn, xp = SX > 0 ? p.xn : xprev;
     const T ym = SY > 0 ? yprev : p.yn, yp = SY > 0 ? p.yn : yprev;
     bool ch;
     const T v = R.template compute<SX, SY>(xm, xp, ym, yp, p, x, act, ch);
-    if (EXTRA) cur_prev = cur;
+    if (EXTRA && PH != 1) cur_prev = cur;
     cur = act ? v : cur;
     changed = changed || ch;
     recent |= __ballot(ch);
     span.cmin = min(span.cmin, ch ? iq : 0x7fffffff);
     span.cmax = max(span.cmax, ch ? iq : -1);
-    if (EXTRA) span.rowB = span.rowB || (ch && useB);
+    if (EXTRA && PH != 1) span.rowB = span.rowB || (ch && (PH == 2 ? laneB : inB));
     x = x1;
+  };
+  using Any = std::integral_constant<int, 0>;
+  using RowA = std::integral_constant<int, 1>;
+  using RowB = std::integral_constant<int, 2>;
+  // the step pair (t, t+1): with EXTRA, pairs wholly before step kWave or
+  // wholly after step kWave + 1 take the lean steps (t only grows, so the
+  // state the full steps keep is not needed after the first lean row-64 pair)
+  auto pair = [&](int t) {
+    if (EXTRA && t + 1 < kWave) {
+      step(RowA{}, t, pa, pb);
+      step(RowA{}, t + 1, pb, pa);
+    } else if (EXTRA && t > kWave + 1) {
+      step(RowB{}, t, pa, pb);
+      step(RowB{}, t + 1, pb, pa);
+    } else {
+      step(Any{}, t, pa, pb);
+      step(Any{}, t + 1, pb, pa);
+    }
   };
   // unrolled by two so that the prefetch buffers alternate without copies;
   // a trailing step past the end is idle in every lane.  Up to tmax the
@@ -405,54 +464,74 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   // pair that changes nothing.
   int t = t0;
   if (PIPE == 2) {
-    // tmax may arrive during the sweep; until then every pair runs
+    // while the leader runs: every pair waits until the leader is far enough
+    // ahead (the progress for the next pair is read during this one, its wait
+    // merges with the steps' own); tmax arrives when the leader ends
     const int lag = follow_lag(L1, EXTRA);
-    while (t < nsteps) {
-      if (t + lag > allowed) allowed = pipe_wait(ps, t + lag, SX, SY, L0, L1, EXTRA, tmax);
-      const bool tail = t + 1 >= tmax;
-      if (tail) recent = 0;
-      step(t, pa, pb);
-      step(t + 1, pb, pa);
+    while (allowed < kPipeDone && t < nsteps) {
+      if (t + lag > allowed) {
+        allowed = pipe_wait(ps, t + lag, SX, SY, L0, L1, EXTRA, tmax);
+        if (allowed >= kPipeDone) break;
+      }
+      const int seen = lds_peek(&ps->kp[0].y);
+      pair(t);
       t += 2;
-      if (tail && recent == 0) break;
+      const int seen_u = __builtin_amdgcn_readfirstlane(seen);
+      if (seen_u >= kPipeDone) {
+        const NodeBox b = ps->box[0];
+        tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, SX, SY, L0, L1, EXTRA));
+        allowed = 0x7fffffff;
+      } else if (seen_u > allowed) {
+        allowed = seen_u;
+      }
     }
-    return changed;
+    // then as a lone sweep (below).  Pairs this phase ran past tmax without
+    // checking for a change are harmless: after a pair past tmax that changes
+    // nothing, no later step can change anything either.
   }
-  int kpub = 0x7fffffff;
   // leader: the key of this lane's changes (lane 0 also holds row 64: a
-  // smaller key than its own only widens the follower's sweep), then the
-  // completed step count
+  // smaller key than its own only widens the follower's sweep; no change
+  // leaves cmin at INT_MAX, a key above kPipeNoKey) and the completed step
+  // count, in one store per lane
+  int2* const kp_lane = PIPE == 1 ? &ps->kp[lane] : nullptr;
   auto publish = [&](int done) {
-    const int k = span.cmax >= 0 ? span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane) : 0x7fffffff;
-    if (k < kpub) {
-      ps->key[lane] = k;
-      kpub = k;
-    }
-    lds_store_rel(&ps->prog, done);
+    const int k = span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane);
+    __asm__ __volatile__("" ::: "memory");
+    *kp_lane = make_int2(k, done);
+    __asm__ __volatile__("" ::: "memory");
   };
   for (; t + 1 < tmax && t < nsteps; t += 2) {
-    step(t, pa, pb);
-    step(t + 1, pb, pa);
+    pair(t);
     if (PIPE == 1) publish(t + 2);
   }
   for (; t < nsteps; t += 2) {
     recent = 0;
-    step(t, pa, pb);
-    step(t + 1, pb, pa);
+    pair(t);
     if (PIPE == 1) publish(t + 2);
     if (recent == 0) break;
   }
   return changed;
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-  return v;
+// Minimum / maximum over the 64 lanes (all active), returned in every lane:
+// a prefix scan within each row of 16 lanes (DPP row_shr 1, 2, 4, 8), then
+// row 0's result into row 1 and row 2's into row 3 (row_bcast:15), then the
+// first half's into the second (row_bcast:31); lane 63 ends with the result.
+// Lanes without a source keep the identity.
+template <bool MIN>
+__device__ __forceinline__ int wave_reduce(int v) {
+  constexpr int id = MIN ? 0x7fffffff : (int)0x80000000;
+  auto op = [](int a, int b) { return MIN ? min(a, b) : max(a, b); };
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(v, kWave - 1);
 }
-__device__ __forceinline__ int wave_max(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-  return v;
-}
+__device__ __forceinline__ int wave_min(int v) { return wave_reduce<true>(v); }
+__device__ __forceinline__ int wave_max(int v) { return wave_reduce<false>(v); }
 
 // The nodes next to a sweep's changes (the box of the changed nodes grown by
 // one node and clipped), from the lanes' change flags and spans; empty if
@@ -506,8 +585,7 @@ template <int SX, int SY, bool EXTRA, typename Rule>
 __device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, NodeBox& P, PipeSync* ps, int s) {
   const int t0 = box_t0<SX, SY>(P, L0, L1);
   const int tmax = box_tmax(P, SX, SY, L0, L1, EXTRA);
-  ps->key[threadIdx.x & (kWave - 1)] = 0x7fffffff;
-  if ((threadIdx.x & (kWave - 1)) == 0) ps->prog = t0;  // steps before t0 change nothing
+  ps->kp[threadIdx.x & (kWave - 1)] = make_int2(0x7fffffff, t0);  // steps before t0 change nothing
   lds_store_rel(&ps->lsweep, s);
   StepSpan sp;
   const bool lane_ch = sweep_dir<SX, SY, EXTRA, 1>(R, L0, L1, SP, t0, tmax, sp, ps);
@@ -517,7 +595,7 @@ __device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, Node
     ps->box[0] = P;
     ps->ch[0] = ch ? 1 : 0;
   }
-  lds_store_rel(&ps->prog, kPipeDone);
+  lds_store_rel(&ps->kp[0].y, kPipeDone);
   return ch;
 }
 
@@ -609,8 +687,8 @@ __device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, in
     // step, or has ended
     int t0 = 0, tmax = 0x7fffffff, allowed = 0;
     for (int n = 0;; ++n) {
-      const int p = lds_load_acq(&ps->prog);
-      const int key = __builtin_amdgcn_readfirstlane(wave_min(ps->key[threadIdx.x & (kWave - 1)]));  // after prog
+      const int p = lds_load_acq(&ps->kp[0].y);
+      const int key = __builtin_amdgcn_readfirstlane(wave_min(ps->kp[threadIdx.x & (kWave - 1)].x));  // after p
       if (p >= kPipeDone) {
         if (!__builtin_amdgcn_readfirstlane(ps->ch[0])) return;
         const NodeBox b = ps->box[0];
@@ -619,7 +697,7 @@ __device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, in
         allowed = 0x7fffffff;
         break;
       }
-      if (key != 0x7fffffff && p >= follow_t0(key, L1) + lag) {
+      if (key < kPipeNoKey && p >= follow_t0(key, L1) + lag) {
         t0 = follow_t0(key, L1);
         allowed = p;
         break;
