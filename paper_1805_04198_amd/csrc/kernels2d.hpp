@@ -1782,38 +1782,60 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
   T* cu = carve<T>(lc, cnt);
   T* cb = carve<T>(lc, cnt);
   uint8_t* ca = carve<uint8_t>(lc, cnt);
-  for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
-    const int I = t % CI, J = t / CI;
-    const int xi = I * M, yi = J * M;
-    // incoming segments in sweep order (clamped; used only when linked)
-    const int hs = min(max((sx > 0 ? I - 1 : I) + A.NI * J, 0), nH - 1);
-    const int vs = min(max(I + CI * (sy > 0 ? J - 1 : J), 0), nV - 1);
-    const T u = A.cU[t];
-    const bool gam = A.cG[t] != 0;
-    const uint8_t c = A.cW[t];
-    const T nx = A.ncx[t], ny = A.ncy[t];
-    const T hp = A.hseg_p[hs], vp = A.vseg_p[vs];
-    const uint8_t hl = A.hseg_l[hs], vl = A.vseg_l[vs];
-    T b = u;
-    uint8_t al = 0;
-    if (!gam) {
-      const int ex = wx_of(c), ey = wy_of(c);
-      const int nxi = xi + sx, nyi = yi + sy;
-      if (ex == -sx && nxi >= 0 && nxi < A.n0) b = vmax(b, nx);
-      if (ey == -sy && nyi >= 0 && nyi < A.n1) b = vmax(b, ny);
-      const int pxi = xi - sx, pyi = yi - sy;
-      if (ex == sx && pxi >= 0 && pxi < A.n0) {
-        b = vmax(b, hp);
-        if (hl) al |= 1;
-      }
-      if (ey == sy && pyi >= 0 && pyi < A.n1) {
-        b = vmax(b, vp);
-        if (vl) al |= 2;
+  // a thread's corners are blockDim.x apart; all loads of up to kPer corners
+  // are issued before any is used (the loads are independent; in a loop
+  // they would wait one corner at a time)
+  constexpr int kPer = 5;
+  const int nc = CI * CJ;
+  for (int base = threadIdx.x; base < nc; base += kPer * (int)blockDim.x) {
+    T u[kPer], nx[kPer], ny[kPer], hp[kPer], vp[kPer];
+    uint8_t gm[kPer], cw[kPer], hl[kPer], vl[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = base + k * (int)blockDim.x;
+      if (t < nc) {
+        const int I = t % CI, J = t / CI;
+        // incoming segments in sweep order (clamped; used only when linked)
+        const int hs = min(max((sx > 0 ? I - 1 : I) + A.NI * J, 0), nH - 1);
+        const int vs = min(max(I + CI * (sy > 0 ? J - 1 : J), 0), nV - 1);
+        u[k] = A.cU[t];
+        gm[k] = A.cG[t];
+        cw[k] = A.cW[t];
+        nx[k] = A.ncx[t];
+        ny[k] = A.ncy[t];
+        hp[k] = A.hseg_p[hs];
+        vp[k] = A.vseg_p[vs];
+        hl[k] = A.hseg_l[hs];
+        vl[k] = A.vseg_l[vs];
       }
     }
-    const int x = (J + 1) * SP + (I + 1);
-    cb[x] = b;
-    ca[x] = al;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = base + k * (int)blockDim.x;
+      if (t >= nc) break;
+      const int I = t % CI, J = t / CI;
+      const int xi = I * M, yi = J * M;
+      T b = u[k];
+      uint8_t al = 0;
+      if (gm[k] == 0) {
+        const int ex = wx_of(cw[k]), ey = wy_of(cw[k]);
+        const int nxi = xi + sx, nyi = yi + sy;
+        if (ex == -sx && nxi >= 0 && nxi < A.n0) b = vmax(b, nx[k]);
+        if (ey == -sy && nyi >= 0 && nyi < A.n1) b = vmax(b, ny[k]);
+        const int pxi = xi - sx, pyi = yi - sy;
+        if (ex == sx && pxi >= 0 && pxi < A.n0) {
+          b = vmax(b, hp[k]);
+          if (hl[k]) al |= 1;
+        }
+        if (ey == sy && pyi >= 0 && pyi < A.n1) {
+          b = vmax(b, vp[k]);
+          if (vl[k]) al |= 2;
+        }
+      }
+      const int x = (J + 1) * SP + (I + 1);
+      cb[x] = b;
+      ca[x] = al;
+    }
   }
   __syncthreads();
   if (threadIdx.x < kWave) {
@@ -1822,14 +1844,27 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
   }
   __syncthreads();
   double dv = 0.0;
-  for (int t = threadIdx.x; t < CI * CJ; t += blockDim.x) {
-    const int I = t % CI, J = t / CI;
-    const int X = (I * M) + A.n0 * (J * M);
-    const T v = cu[(J + 1) * SP + (I + 1)];
-    U[X] = v;
+  for (int base = threadIdx.x; base < nc; base += kPer * (int)blockDim.x) {
+    T prev[kPer];
     if (res) {
-      const double d = res_term(v, A.U[X]);
-      dv = dv < d ? d : dv;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int t = base + k * (int)blockDim.x;
+        if (t < nc) prev[k] = A.U[(t % CI) * M + A.n0 * ((t / CI) * M)];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = base + k * (int)blockDim.x;
+      if (t >= nc) break;
+      const int I = t % CI, J = t / CI;
+      const int X = (I * M) + A.n0 * (J * M);
+      const T v = cu[(J + 1) * SP + (I + 1)];
+      U[X] = v;
+      if (res) {
+        const double d = res_term(v, prev[k]);
+        dv = dv < d ? d : dv;
+      }
     }
   }
   if (res) res_reduce(dv, A.res_out);
@@ -1928,19 +1963,26 @@ __device__ __forceinline__ void causal_seg_body(const DD2<T>& A, int bx, T* U, c
   const int sg = n.g.horiz ? sx : sy;
   T u = T(0), vv = T(0);
   bool link = false;
+  // the node's successor in sweep order: a node of the same segment (its
+  // value after phase C is in LDS) or the end corner (final; corners are not
+  // written here).  Every global load of the node is issued in this first
+  // phase, so the kernel waits for global memory once.
+  const int qn = n.q + sg;
+  const bool inner = qn >= 1 && qn <= m1;
+  T g = T(0), endc = T(0);
+  uint8_t wc = 0;
   if (n.on) {
+    g = A.gfull[n.X];
+    wc = W[n.X];
+    if (!inner) endc = U[n.base + qn * n.stride];
     u = prev >= 0 ? seg_fill(A, n, U, (prev & 2) ? 1 : -1, (prev & 1) ? 1 : -1) : U[n.X];
     sv[t] = u;
   }
   __syncthreads();
   if (n.on) {
-    // the node's successor in sweep order: a node of the same segment (its
-    // value after phase C is in LDS) or the end corner (final)
-    const int qn = n.q + sg;
-    const T nx = (qn >= 1 && qn <= m1) ? sv[t + sg] : U[n.base + qn * n.stride];
+    const T nx = inner ? sv[t + sg] : endc;
     vv = u;
-    if (disnan(A.gfull[n.X])) {
-      const uint8_t wc = W[n.X];
+    if (disnan(g)) {
       const int e = n.g.horiz ? wx_of(wc) : wy_of(wc);
       if (e == -sg) vv = vmax(vv, nx);
       link = (e == sg);
@@ -2003,8 +2045,10 @@ __device__ __forceinline__ void causal_c_body(const DD2<T>& A, int bx, T* U, int
   const SegNode n = seg_node(A, bx);
   double dv = 0.0;
   if (n.on) {
+    // with res, U is the other array (U^{k+1}), so A.U can be read first
+    const T old = res ? A.U[n.X] : T(0);
     const T v = seg_fill(A, n, U, sx, sy);
-    if (res) dv = res_term(v, A.U[n.X]);
+    if (res) dv = res_term(v, old);
   }
   if (res) res_reduce(dv, A.res_out);
 }
