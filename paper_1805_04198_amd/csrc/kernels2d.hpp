@@ -223,7 +223,8 @@ struct NodeBox {
 // sweeps 4m and 4m+1 (likewise 4m+2 and 4m+3) differ in the y direction only.
 // The node in column c, row r of the first sweep's order lies on its
 // anti-diagonal c + r and on the second's c + (L1 - 1 - r), so the second
-// sweep can run on another wave (another SIMD) L1 + 4 steps behind the first:
+// sweep can run on another wave (another SIMD) L1 + 4 steps behind the first
+// (L1 + 5 when row 64 runs late on lane 0):
 // it then reads every node after the first sweep has written it for the last
 // time and writes none before the first sweep has read it for the last time,
 // and computes the values of the two sweeps run one after the other.  Wave 0
