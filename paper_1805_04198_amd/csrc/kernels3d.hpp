@@ -168,16 +168,45 @@ __device__ __forceinline__ void lattice_offset3(int q, int M, int& o0, int& o1, 
 // the 3D box sweep engine
 // ---------------------------------------------------------------------------
 
+// Axis-aligned box of box nodes [lo, hi] per axis (lo > hi on axis 0: empty).
+struct Box3 {
+  int lo[3], hi[3];
+};
+
 // One directional sweep over an L0 x L1 x L2 box in LDS (index i + L0*(j +
 // L1*k)); returns true (block-wide) if any value changed.  A thread owns at
 // most two pencils (L1*L2 <= 2*blockDim); the read-only inputs of the node a
 // pencil reaches at step t+1 (Rule::load) are fetched before the update of
 // step t, so their global-memory latency overlaps a step.
+//
+// Restricted to what can change: P holds every node that may change in this
+// sweep without an upwind change inside it (a node whose neighbours kept
+// their values since its last evaluation computes the same value again).
+// The sweep starts at the first hyperplane that reaches P and, from the last
+// one that does, stops after the first hyperplane without a change (a node
+// beyond P changes only if an upwind neighbour, one hyperplane earlier,
+// changed).  On return P holds the nodes next to a change (the box of the
+// changed nodes grown by one node and clipped), empty if nothing changed.
 template <typename Rule>
-__device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir) {
+__device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
   using In = typename Rule::In;
+  __shared__ int sh_box[6];
   const int sx = (dir & 4) ? 1 : -1, sy = (dir & 2) ? 1 : -1, sz = (dir & 1) ? 1 : -1;
   const int nsteps = L0 + L1 + L2 - 2;
+  const int Ls[3] = {L0, L1, L2}, sg[3] = {sx, sy, sz};
+  int t0 = 0, tmax = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    t0 += sg[a] > 0 ? P.lo[a] : Ls[a] - 1 - P.hi[a];
+    tmax += sg[a] > 0 ? P.hi[a] : Ls[a] - 1 - P.lo[a];
+  }
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) {
+      sh_box[a] = 0x7fffffff;
+      sh_box[3 + a] = -1;
+    }
+  }
+  __syncthreads();
   const int np = L1 * L2;
   // Pencils (j, k) in sweep coordinates are numbered by anti-diagonal
   // s = j + k (then by j): the pencils that hold a node of hyperplane t are
@@ -214,40 +243,75 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir) {
 #pragma unroll
   for (int r = 0; r < kAhead; ++r) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) fetch(r, q, buf[q][r]);
+    for (int q = 0; q < 2; ++q) fetch(t0 + r, q, buf[q][r]);
   }
-  int changed = 0;
-  for (int t0 = 0; t0 < nsteps; t0 += kAhead) {
+  // box of the nodes this thread changed (box coordinates)
+  int cmin[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, cmax[3] = {-1, -1, -1};
+  bool done = false;
+  for (int tb = t0; tb < nsteps && !done; tb += kAhead) {
 #pragma unroll
     for (int r = 0; r < kAhead; ++r) {
-      const int t = t0 + r;
-      if (t < nsteps) {  // the same in every thread
+      const int t = tb + r;
+      if (t < nsteps && !done) {  // the same in every thread
         In cur[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           cur[q] = buf[q][r];
           fetch(t + kAhead, q, buf[q][r]);
         }
+        int stepch = 0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int iq = t - jq[q] - kq[q];
-          if (has[q] && iq >= 0 && iq < L0)
-            changed |= R.update(sx > 0 ? iq : L0 - 1 - iq, jj[q], kk[q], cur[q]) ? 1 : 0;
+          if (has[q] && iq >= 0 && iq < L0) {
+            const int i = sx > 0 ? iq : L0 - 1 - iq;
+            if (R.update(i, jj[q], kk[q], cur[q])) {
+              stepch = 1;
+              const int c[3] = {i, jj[q], kk[q]};
+#pragma unroll
+              for (int a = 0; a < 3; ++a) {
+                cmin[a] = min(cmin[a], c[a]);
+                cmax[a] = max(cmax[a], c[a]);
+              }
+            }
+          }
         }
-        __syncthreads();
+        if (t >= tmax) {
+          if (!__syncthreads_or(stepch)) done = true;
+        } else {
+          __syncthreads();
+        }
       }
     }
   }
-  return __syncthreads_or(changed) != 0;
+  if (cmax[0] >= 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&sh_box[a], cmin[a]);
+      atomicMax(&sh_box[3 + a], cmax[a]);
+    }
+  }
+  __syncthreads();
+  const bool any = sh_box[3] >= 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.lo[a] = any ? max(sh_box[a] - 1, 0) : 1;
+    P.hi[a] = any ? min(sh_box[3 + a] + 1, Ls[a] - 1) : 0;
+  }
+  __syncthreads();  // every thread has read sh_box before the next sweep resets it
+  return any;
 }
 
 // 2^d orders of the loop nest (x outermost, z innermost) until a sweep
-// changes nothing, at most max_sweeps.
+// changes nothing, at most max_sweeps; every node starts out as possibly
+// changing, then each sweep covers what can change (sweep3), which gives the
+// full sweeps' values, winds and sweep count.
 template <typename Rule>
 __device__ int fsm3(Rule& R, int L0, int L1, int L2, int max_sweeps) {
   int s = 0;
+  Box3 P{{0, 0, 0}, {L0 - 1, L1 - 1, L2 - 1}};
   while (s < max_sweeps) {
-    const bool ch = sweep3(R, L0, L1, L2, s & 7);
+    const bool ch = sweep3(R, L0, L1, L2, s & 7, P);
     ++s;
     if (!ch) break;
   }
@@ -1090,7 +1154,8 @@ __global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int 
   } R{u, L[0], L[1], L[2], A.u, A.gfull, A.r, A.w, A.hT, base, gs1, gs2,
       o[0] > 0, o[1] > 0, o[2] > 0,
       o[0] + L[0] < A.n[0], o[1] + L[1] < A.n[1], o[2] + L[2] < A.n[2]};
-  const bool ch = sweep3(R, L[0], L[1], L[2], dir);
+  Box3 P{{0, 0, 0}, {L[0] - 1, L[1] - 1, L[2] - 1}};
+  const bool ch = sweep3(R, L[0], L[1], L[2], dir, P);
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
     A.u[base + p0 + p1 * gs1 + p2 * gs2] = u[x];
