@@ -168,9 +168,10 @@ __device__ __forceinline__ void lattice_offset3(int q, int M, int& o0, int& o1, 
 // the 3D box sweep engine
 // ---------------------------------------------------------------------------
 
-// Axis-aligned box of box nodes [lo, hi] per axis (lo > hi on axis 0: empty).
-struct Box3 {
-  int lo[3], hi[3];
+// The hyperplanes [t0, tmax] of a sweep that hold every node that may
+// change in it without an upwind change inside it (t0 > tmax: none).
+struct Range3 {
+  int t0, tmax;
 };
 
 // One directional sweep over an L0 x L1 x L2 box in LDS (index i + L0*(j +
@@ -179,32 +180,30 @@ struct Box3 {
 // pencil reaches at step t+1 (Rule::load) are fetched before the update of
 // step t, so their global-memory latency overlaps a step.
 //
-// Restricted to what can change: P holds every node that may change in this
-// sweep without an upwind change inside it (a node whose neighbours kept
-// their values since its last evaluation computes the same value again).
-// The sweep starts at the first hyperplane that reaches P and, from the last
-// one that does, stops after the first hyperplane without a change (a node
-// beyond P changes only if an upwind neighbour, one hyperplane earlier,
-// changed).  On return P holds the nodes next to a change (the box of the
-// changed nodes grown by one node and clipped), empty if nothing changed.
+// Restricted to what can change: P holds the hyperplanes with every node
+// that may change in this sweep without an upwind change inside it (a node
+// whose neighbours kept their values since its last evaluation computes the
+// same value again).  The sweep starts at P.t0 and, from P.tmax on, stops
+// after the first hyperplane without a change (a node past P changes only if
+// an upwind neighbour, one hyperplane earlier, changed).  On return P holds
+// the same for the next sweep, in direction ndir: the hyperplanes of that
+// sweep within one of a node this sweep changed (the nodes next to a change
+// lie there); empty if nothing changed.
 template <typename Rule>
-__device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
+__device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, int ndir, Range3& P) {
   using In = typename Rule::In;
-  __shared__ int sh_box[6];
+  __shared__ int sh_rng[2];
   const int sx = (dir & 4) ? 1 : -1, sy = (dir & 2) ? 1 : -1, sz = (dir & 1) ? 1 : -1;
   const int nsteps = L0 + L1 + L2 - 2;
-  const int Ls[3] = {L0, L1, L2}, sg[3] = {sx, sy, sz};
-  int t0 = 0, tmax = 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    t0 += sg[a] > 0 ? P.lo[a] : Ls[a] - 1 - P.hi[a];
-    tmax += sg[a] > 0 ? P.hi[a] : Ls[a] - 1 - P.lo[a];
-  }
+  const int t0 = P.t0, tmax = P.tmax;
+  // hyperplane of box node (i, j, k) in the next sweep
+  const int nsx = (ndir & 4) ? 1 : -1, nsy = (ndir & 2) ? 1 : -1, nsz = (ndir & 1) ? 1 : -1;
+  auto next_plane = [&](int i, int j, int k) {
+    return (nsx > 0 ? i : L0 - 1 - i) + (nsy > 0 ? j : L1 - 1 - j) + (nsz > 0 ? k : L2 - 1 - k);
+  };
   if (threadIdx.x == 0) {
-    for (int a = 0; a < 3; ++a) {
-      sh_box[a] = 0x7fffffff;
-      sh_box[3 + a] = -1;
-    }
+    sh_rng[0] = 0x7fffffff;
+    sh_rng[1] = -1;
   }
   __syncthreads();
   const int np = L1 * L2;
@@ -245,8 +244,8 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) fetch(t0 + r, q, buf[q][r]);
   }
-  // box of the nodes this thread changed (box coordinates)
-  int cmin[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, cmax[3] = {-1, -1, -1};
+  // next-sweep hyperplanes of the nodes this thread changed
+  int hmin = 0x7fffffff, hmax = -1;
   bool done = false;
   for (int tb = t0; tb < nsteps && !done; tb += kAhead) {
 #pragma unroll
@@ -267,12 +266,9 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
             const int i = sx > 0 ? iq : L0 - 1 - iq;
             if (R.update(i, jj[q], kk[q], cur[q])) {
               stepch = 1;
-              const int c[3] = {i, jj[q], kk[q]};
-#pragma unroll
-              for (int a = 0; a < 3; ++a) {
-                cmin[a] = min(cmin[a], c[a]);
-                cmax[a] = max(cmax[a], c[a]);
-              }
+              const int h = next_plane(i, jj[q], kk[q]);
+              hmin = min(hmin, h);
+              hmax = max(hmax, h);
             }
           }
         }
@@ -284,21 +280,15 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
       }
     }
   }
-  if (cmax[0] >= 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&sh_box[a], cmin[a]);
-      atomicMax(&sh_box[3 + a], cmax[a]);
-    }
+  if (hmax >= 0) {
+    atomicMin(&sh_rng[0], hmin);
+    atomicMax(&sh_rng[1], hmax);
   }
   __syncthreads();
-  const bool any = sh_box[3] >= 0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    P.lo[a] = any ? max(sh_box[a] - 1, 0) : 1;
-    P.hi[a] = any ? min(sh_box[3 + a] + 1, Ls[a] - 1) : 0;
-  }
-  __syncthreads();  // every thread has read sh_box before the next sweep resets it
+  const bool any = sh_rng[1] >= 0;
+  P.t0 = any ? max(sh_rng[0] - 1, 0) : 1;
+  P.tmax = any ? min(sh_rng[1] + 1, nsteps - 1) : 0;
+  __syncthreads();  // every thread has read sh_rng before the next sweep resets it
   return any;
 }
 
@@ -309,9 +299,9 @@ __device__ bool sweep3(Rule& R, int L0, int L1, int L2, int dir, Box3& P) {
 template <typename Rule>
 __device__ int fsm3(Rule& R, int L0, int L1, int L2, int max_sweeps) {
   int s = 0;
-  Box3 P{{0, 0, 0}, {L0 - 1, L1 - 1, L2 - 1}};
+  Range3 P{0, L0 + L1 + L2 - 3};
   while (s < max_sweeps) {
-    const bool ch = sweep3(R, L0, L1, L2, s & 7, P);
+    const bool ch = sweep3(R, L0, L1, L2, s & 7, (s + 1) & 7, P);
     ++s;
     if (!ch) break;
   }
@@ -1154,8 +1144,8 @@ __global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int 
   } R{u, L[0], L[1], L[2], A.u, A.gfull, A.r, A.w, A.hT, base, gs1, gs2,
       o[0] > 0, o[1] > 0, o[2] > 0,
       o[0] + L[0] < A.n[0], o[1] + L[1] < A.n[1], o[2] + L[2] < A.n[2]};
-  Box3 P{{0, 0, 0}, {L[0] - 1, L[1] - 1, L[2] - 1}};
-  const bool ch = sweep3(R, L[0], L[1], L[2], dir, P);
+  Range3 P{0, L[0] + L[1] + L[2] - 3};
+  const bool ch = sweep3(R, L[0], L[1], L[2], dir, dir, P);
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
     A.u[base + p0 + p1 * gs1 + p2 * gs2] = u[x];
