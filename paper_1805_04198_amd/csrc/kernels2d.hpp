@@ -213,10 +213,10 @@ __device__ __forceinline__ T homog2(T a, T b, T rd) {
   return ((a < b) ? a : b) + rd;
 }
 
-// Axis-aligned box of nodes [i0, i1] x [j0, j1] in box coordinates (i0 > i1:
-// empty).
-struct NodeBox {
-  int i0, i1, j0, j1;
+// The steps [t0, tmax] of a sweep that reach every node that may change in
+// it without an upwind change inside it.
+struct Range2 {
+  int t0, tmax;
 };
 
 // Two waves on one box.  In the loop nest's order of the sweep directions,
@@ -247,7 +247,8 @@ struct PipeSync {
   int fin;         // follower: 1 + the index of its last completed sweep
   int err;         // a wait gave up
   int ch[2];       // whether the last sweep of the leader [0] / follower [1] changed a node
-  NodeBox box[2];  // the nodes next to that sweep's changes
+  int ftmax;       // leader: the follower's last step that reaches a node next to its changes
+  Range2 lrng;     // follower: the next leader sweep's steps that reach the nodes next to its changes
 };
 
 __device__ __forceinline__ void pipe_init(PipeSync& ps) {
@@ -284,21 +285,14 @@ __device__ __forceinline__ int lds_peek(int* p) {
 // must have completed before the follower runs step pair (t, t+1).
 __device__ __forceinline__ int follow_t0(int key, int L1) { return max(key + L1 - 2, 0); }
 __device__ __forceinline__ int follow_lag(int L1, bool extra) { return L1 + 4 + (extra ? 1 : 0); }
-// last step of a sweep (signs sx, sy) that reaches box P
-__device__ __forceinline__ int box_tmax(const NodeBox& P, int sx, int sy, int L0, int L1, bool extra) {
-  const int qi1 = sx > 0 ? P.i1 : L0 - 1 - P.i0;
-  const int qj1 = sy > 0 ? P.j1 : L1 - 1 - P.j0;
-  return qi1 + qj1 + (extra ? 1 : 0);
-}
 // Follower: wait until the leader has completed `need` steps or ended its
 // sweep (then tmax becomes the last step that reaches the nodes next to the
 // leader's changes).  Returns the steps known to be complete.
-__device__ __forceinline__ int pipe_wait(PipeSync* ps, int need, int sx, int sy, int L0, int L1, bool extra, int& tmax) {
+__device__ __forceinline__ int pipe_wait(PipeSync* ps, int need, int& tmax) {
   for (int n = 0;; ++n) {
     const int p = lds_load_acq(&ps->kp[0].y);
     if (p >= kPipeDone) {
-      const NodeBox b = ps->box[0];
-      tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, sx, sy, L0, L1, extra));
+      tmax = __builtin_amdgcn_readfirstlane(ps->ftmax);
       return 0x7fffffff;
     }
     if (p >= need) return p;
@@ -471,7 +465,7 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
     const int lag = follow_lag(L1, EXTRA);
     while (allowed < kPipeDone && t < nsteps) {
       if (t + lag > allowed) {
-        allowed = pipe_wait(ps, t + lag, SX, SY, L0, L1, EXTRA, tmax);
+        allowed = pipe_wait(ps, t + lag, tmax);
         if (allowed >= kPipeDone) break;
       }
       const int seen = lds_peek(&ps->kp[0].y);
@@ -479,8 +473,7 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
       t += 2;
       const int seen_u = __builtin_amdgcn_readfirstlane(seen);
       if (seen_u >= kPipeDone) {
-        const NodeBox b = ps->box[0];
-        tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, SX, SY, L0, L1, EXTRA));
+        tmax = __builtin_amdgcn_readfirstlane(ps->ftmax);
         allowed = 0x7fffffff;
       } else if (seen_u > allowed) {
         allowed = seen_u;
@@ -534,84 +527,60 @@ __device__ __forceinline__ int wave_reduce(int v) {
 __device__ __forceinline__ int wave_min(int v) { return wave_reduce<true>(v); }
 __device__ __forceinline__ int wave_max(int v) { return wave_reduce<false>(v); }
 
-// The nodes next to a sweep's changes (the box of the changed nodes grown by
-// one node and clipped), from the lanes' change flags and spans; empty if
-// nothing changed.
-template <int SX, int SY, bool EXTRA>
-__device__ __forceinline__ void change_box(bool ch, const StepSpan& sp, int L0, int L1, NodeBox& P) {
-  // rows: the lanes that changed a value (lane 0 stands for row 0 even if
-  // only its row 64 changed, which only widens the box), plus row 64
-  const unsigned long long rows = __ballot(ch);
-  const bool rowB = EXTRA && __any(sp.rowB);
-  const int ci0 = wave_min(sp.cmin), ci1 = wave_max(sp.cmax);
-  if (rows == 0) {
-    P.i0 = 1; P.i1 = 0; P.j0 = 1; P.j1 = 0;
-    return;
-  }
-  const int cj0 = __builtin_ctzll(rows);
-  const int cj1 = rowB ? kWave : 63 - __builtin_clzll(rows);
-  // back to box coordinates, grown by one node and clipped
-  const int i0 = SX > 0 ? ci0 : L0 - 1 - ci1, i1 = SX > 0 ? ci1 : L0 - 1 - ci0;
-  const int j0 = SY > 0 ? cj0 : L1 - 1 - cj1, j1 = SY > 0 ? cj1 : L1 - 1 - cj0;
-  P.i0 = __builtin_amdgcn_readfirstlane(max(i0 - 1, 0));
-  P.i1 = __builtin_amdgcn_readfirstlane(min(i1 + 1, L0 - 1));
-  P.j0 = __builtin_amdgcn_readfirstlane(max(j0 - 1, 0));
-  P.j1 = __builtin_amdgcn_readfirstlane(min(j1 + 1, L1 - 1));
-}
-
-// first step of a sweep (signs SX, SY) that reaches box P
-template <int SX, int SY>
-__device__ __forceinline__ int box_t0(const NodeBox& P, int L0, int L1) {
-  const int qi0 = SX > 0 ? P.i0 : L0 - 1 - P.i1;
-  const int qj0 = SY > 0 ? P.j0 : L1 - 1 - P.j1;
-  return qi0 + qj0;
-}
-
-// Sweeps restricted to what can change.  P holds every node that may change
-// in a sweep without an upwind change inside the sweep (a node whose
-// neighbours kept their values since its last evaluation computes the same
-// candidate again and cannot change).  A sweep starts at its first step that
-// reaches P and runs at least to its last; changes propagate within the
-// sweep until a step pair changes nothing.  Afterwards P holds the nodes
-// next to a change (a superset of those evaluated before a neighbour
-// changed), empty if nothing changed.  The follower, which starts before the
-// leader's P is complete, starts at the first step next to a change the
-// leader has published (later changes of the leader lie ahead of it) and
-// takes its last step from the leader's P once the leader has ended.
+// Sweeps restricted to what can change.  The nodes that may change in a
+// sweep without an upwind change inside it are those next to a change of the
+// previous sweep (a node whose neighbours kept their values since its last
+// evaluation computes the same candidate again and cannot change); they lie
+// on the anti-diagonals of the sweep within one of a changed node.  A sweep
+// starts at the first such step and, from the last one on, stops after the
+// first step pair that changes nothing.  Each lane's span (its smallest and
+// largest changed column; the row is the lane's) gives the extreme
+// anti-diagonals of its changes in the next sweep's order: in the follower's
+// (y reversed) column - row + L1 - 1, in the next leader's (both reversed)
+// L0 + L1 - 2 - (column + row).  Row 64 runs one step late, hence the
+// margin of one step at the end.  The follower starts from the published
+// keys (later changes of the leader lie ahead of it) and takes its last step
+// once the leader has ended.
 //
-// The leader's sweep s over box P, with its progress published
-// for the follower; at its end the box of the nodes next to its changes and
-// whether it changed anything.  Returns that flag (the same in every lane).
+// The leader's sweep s over the steps P, with its progress published for the
+// follower; at its end the follower's last step and whether it changed
+// anything.  Returns that flag (the same in every lane).
 template <int SX, int SY, bool EXTRA, typename Rule>
-__device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, NodeBox& P, PipeSync* ps, int s) {
-  const int t0 = box_t0<SX, SY>(P, L0, L1);
-  const int tmax = box_tmax(P, SX, SY, L0, L1, EXTRA);
-  ps->kp[threadIdx.x & (kWave - 1)] = make_int2(0x7fffffff, t0);  // steps before t0 change nothing
+__device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, const Range2& P, PipeSync* ps, int s) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int t0 = P.t0, tmax = P.tmax;
+  ps->kp[lane] = make_int2(0x7fffffff, t0);  // steps before t0 change nothing
   lds_store_rel(&ps->lsweep, s);
   StepSpan sp;
   const bool lane_ch = sweep_dir<SX, SY, EXTRA, 1>(R, L0, L1, SP, t0, tmax, sp, ps);
-  change_box<SX, SY, EXTRA>(lane_ch, sp, L0, L1, P);
   const bool ch = __any(lane_ch);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    ps->box[0] = P;
+  // lane 0's row 64 (column - 64) never exceeds its row 0 (column - 0)
+  const int kx = wave_max(sp.cmax >= 0 ? sp.cmax - lane : (int)0x80000000);
+  if (lane == 0) {
+    ps->ftmax = ch ? kx + L1 + (EXTRA ? 1 : 0) : 0;
     ps->ch[0] = ch ? 1 : 0;
   }
   lds_store_rel(&ps->kp[0].y, kPipeDone);
   return ch;
 }
 
-// The follower's sweep s from step t0 (tmax: its last step that reaches the
-// leader's change box, or "none yet" while the leader runs); publishes its
-// own change box and flag, then fin = s + 1.
+// The follower's sweep s from step t0 (tmax: its last step that reaches a
+// node next to the leader's changes, or "none yet" while the leader runs);
+// publishes the next leader sweep's steps and its own flag, then fin = s + 1.
 template <int SX, int SY, bool EXTRA, typename Rule>
-__device__ __forceinline__ bool sweep_follow(Rule& R, int L0, int L1, int SP, NodeBox& P, PipeSync* ps, int s, int t0,
-                                             int tmax, int allowed) {
+__device__ __forceinline__ bool sweep_follow(Rule& R, int L0, int L1, int SP, PipeSync* ps, int s, int t0, int tmax,
+                                             int allowed) {
+  const int lane = threadIdx.x & (kWave - 1);
   StepSpan sp;
   const bool lane_ch = sweep_dir<SX, SY, EXTRA, 2>(R, L0, L1, SP, t0, tmax, sp, ps, allowed);
-  change_box<SX, SY, EXTRA>(lane_ch, sp, L0, L1, P);
   const bool ch = __any(lane_ch);
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-    ps->box[1] = P;
+  // anti-diagonals (column + row) of the changes; lane 0 may hold row 64
+  const int dmax = wave_max(sp.cmax >= 0 ? sp.cmax + ((EXTRA && lane == 0 && sp.rowB) ? kWave : lane)
+                                         : (int)0x80000000);
+  const int dmin = wave_min(sp.cmax >= 0 ? sp.cmin + lane : 0x7fffffff);
+  if (lane == 0) {
+    ps->lrng.t0 = ch ? max(L0 + L1 - 2 - dmax - 1, 0) : 0;
+    ps->lrng.tmax = ch ? L0 + L1 - 2 - dmin + 1 + (EXTRA ? 1 : 0) : 0;
     ps->ch[1] = ch ? 1 : 0;
   }
   lds_store_rel(&ps->fin, s + 1);
@@ -647,10 +616,10 @@ __device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int d
 // number of sweeps in wave 0.
 template <bool EXTRA, typename Rule>
 __device__ __forceinline__ int fsm_leader(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
-  NodeBox P{0, L0 - 1, 0, L1 - 1};
+  Range2 P{0, L0 + L1 - 2 + (EXTRA ? 1 : 0)};
   for (int s = 0;; s += 2) {
     if (s > 0) {
-      // the follower's sweep s-1 has ended: its change box is this sweep's
+      // the follower's sweep s-1 has ended: it gives this sweep's steps
       for (int n = 0; lds_load_acq(&ps->fin) < s; ++n) {
         if (n >= kPipeSpin) {
           if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
@@ -659,11 +628,8 @@ __device__ __forceinline__ int fsm_leader(Rule& R, int L0, int L1, int SP, int m
         __builtin_amdgcn_s_sleep(1);
       }
       if (!__builtin_amdgcn_readfirstlane(ps->ch[1])) return s;
-      P = ps->box[1];
-      P.i0 = __builtin_amdgcn_readfirstlane(P.i0);
-      P.i1 = __builtin_amdgcn_readfirstlane(P.i1);
-      P.j0 = __builtin_amdgcn_readfirstlane(P.j0);
-      P.j1 = __builtin_amdgcn_readfirstlane(P.j1);
+      P.t0 = __builtin_amdgcn_readfirstlane(ps->lrng.t0);
+      P.tmax = __builtin_amdgcn_readfirstlane(ps->lrng.tmax);
     }
     if (s >= max_sweeps) return max_sweeps;
     const bool ch = (s & 2) ? sweep_lead<1, -1, EXTRA>(R, L0, L1, SP, P, ps, s)
@@ -692,9 +658,8 @@ __device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, in
       const int key = __builtin_amdgcn_readfirstlane(wave_min(ps->kp[threadIdx.x & (kWave - 1)].x));  // after p
       if (p >= kPipeDone) {
         if (!__builtin_amdgcn_readfirstlane(ps->ch[0])) return;
-        const NodeBox b = ps->box[0];
         t0 = follow_t0(key, L1);
-        tmax = __builtin_amdgcn_readfirstlane(box_tmax(b, (s & 2) ? 1 : -1, 1, L0, L1, EXTRA));
+        tmax = __builtin_amdgcn_readfirstlane(ps->ftmax);
         allowed = 0x7fffffff;
         break;
       }
@@ -709,9 +674,8 @@ __device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, in
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    NodeBox P;
-    const bool ch = (s & 2) ? sweep_follow<1, 1, EXTRA>(R, L0, L1, SP, P, ps, s, t0, tmax, allowed)
-                            : sweep_follow<-1, 1, EXTRA>(R, L0, L1, SP, P, ps, s, t0, tmax, allowed);
+    const bool ch = (s & 2) ? sweep_follow<1, 1, EXTRA>(R, L0, L1, SP, ps, s, t0, tmax, allowed)
+                            : sweep_follow<-1, 1, EXTRA>(R, L0, L1, SP, ps, s, t0, tmax, allowed);
     if (!ch) return;
   }
 }
