@@ -844,17 +844,25 @@ void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
   const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
   const int ndiag = CN[0] + CN[1] + CN[2] - 2;
   const size_t lds = eik::causal3_lds<T>(A.M);
-  // directions 2m and 2m+1 (z reversed) together, the second CN2 + 1
-  // diagonals behind the first
-  const int lag = CN[2] + 1;
-  for (int m = 0; m < 4; ++m)
-    for (int tau = 0; tau < ndiag + lag; ++tau) {
-      const int d1 = tau, d2 = tau - lag;
-      const int n1 = d1 < ndiag ? cells_on_diag(CN, d1) : 0;
-      const int n2 = (d2 >= 0 && d2 < ndiag) ? cells_on_diag(CN, d2) : 0;
-      if (n1 + n2 == 0) continue;
-      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(n1 + n2), dim3(256), lds, s, A, U, W, 2 * m, d1, n1, 2 * m + 1,
-                         d2);
+  // directions 4m .. 4m+3 together, each behind the one before by the lag
+  // its reversed axes need (z: CN2 + 1; y and z: CN1 + CN2)
+  const int off[4] = {0, CN[2] + 1, CN[2] + 1 + CN[1] + CN[2], 2 * (CN[2] + 1) + CN[1] + CN[2]};
+  for (int m = 0; m < 2; ++m)
+    for (int tau = 0; tau < off[3] + ndiag; ++tau) {
+      eik::CausalLaunch3 L{};
+      int nb = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int d = tau - off[k];
+        if (d < 0 || d >= ndiag) continue;
+        L.dir[L.n] = 4 * m + k;
+        L.diag[L.n] = d;
+        L.start[L.n] = nb;
+        nb += cells_on_diag(CN, d);
+        ++L.n;
+      }
+      L.start[L.n] = nb;
+      if (nb == 0) continue;
+      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(nb), dim3(256), lds, s, A, U, W, L);
     }
 }
 

@@ -819,11 +819,20 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
 // ---------------------------------------------------------------------------
 // causal sweep: coarse-cell wavefront
 //
-// Directions 2m and 2m+1 differ in z only: a cell on anti-diagonal t of the
-// first is on t' = t - 2K' + CN2 - 1 of the second (K' its z index in the
-// first's order), so the second can run CN2 + 1 diagonals behind the first in
-// the same launches: every cell it takes, and the cells next to it, the first
-// has finished, and it writes no cell the first will still read.
+// Directions that keep the x direction overlap: when a later direction
+// reverses the axes in a set R, a cell on anti-diagonal t of the earlier one
+// is on t - 2 sum_{a in R} C'_a + sum_{a in R} (CN_a - 1) of the later, so
+// the later can run sum_{a in R} (CN_a - 1) + 2 diagonals behind (z reversed:
+// CN2 + 1; y and z: CN1 + CN2) in the same launches:
+// every cell it takes, and the cells next to it, the earlier one has
+// finished, and it writes no cell the earlier one will still read.  So
+// directions 4m .. 4m+3 share launches; 4m+3 -> 4m+4 reverses x as well.
+//
+// The directions, diagonals and block ranges of one launch of k_causal3.
+struct CausalLaunch3 {
+  int n;
+  int dir[4], diag[4], start[5];
+};
 //
 // Cell (I, J, K) owns the coarse nodes with coordinates in [IM, IM+M) x
 // [JM, JM+M) x [KM, KM+M) (its three low faces).  In sweep direction s a node
@@ -859,18 +868,18 @@ __device__ __forceinline__ int owned_index(const int (&l)[3], const int (&E)[3])
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* W, int dir1, int diag1, int nc1,
-                                                int dir2, int diag2) {
+__global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* W, CausalLaunch3 L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // the first nc1 blocks take cells of diagonal diag1 in direction dir1, the
-  // others cells of diagonal diag2 in direction dir2 (the z-reversed
-  // direction, far enough behind that no two of these cells are adjacent)
-  const bool second = (int)blockIdx.x >= nc1;
-  const int dir = second ? dir2 : dir1, diag = second ? diag2 : diag1;
+  // blocks [start[g], start[g+1]) take cells of diagonal diag[g] in direction
+  // dir[g]; the directions of one launch are far enough apart that no two of
+  // its cells are adjacent
+  int g = 0;
+  while (g + 1 < L.n && (int)blockIdx.x >= L.start[g + 1]) ++g;
+  const int dir = L.dir[g], diag = L.diag[g];
   const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
   const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
   // the block enumerates the cells (in sweep coordinates) with I'+J'+K' = diag
-  int rem = second ? (int)blockIdx.x - nc1 : (int)blockIdx.x;
+  int rem = (int)blockIdx.x - L.start[g];
   int Iq = -1, Jq = -1, Kq = -1;
   for (int i = max(0, diag - (CN[1] - 1) - (CN[2] - 1)); i <= min(diag, CN[0] - 1); ++i) {
     const int r2 = diag - i;
