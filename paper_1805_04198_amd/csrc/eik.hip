@@ -1134,7 +1134,7 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
   A.gfull = gfull;
   A.u = as<T>(u_outv);
   A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(N);
-  unsigned int* dflag = cv.take<unsigned int>(4);
+  unsigned int* dflag = cv.take<unsigned int>(8);
   A.changed = dflag + 1;
   A.eval_at = cv.take<int>(nbox);
   A.chg_at = cv.take<int>(nbox);
@@ -1155,21 +1155,46 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
   HIPCHK(hipMemsetAsync(A.chg_at, 0xff, nbox * sizeof(int), s));
   HIPCHK(hipGetLastError());
   const int ndiag = A.nb[0] + A.nb[1] + A.nb[2] - 2;
+  // sweeps 4m .. 4m+3 share launches, each behind the one before by the lag
+  // its reversed axes need (as the causal sweep's directions); a sweep
+  // without change leaves the grid stationary for every order, so the later
+  // sweeps of its group then change nothing and the count stops there
+  const int off[4] = {0, A.nb[2] + 1, A.nb[2] + 1 + A.nb[1] + A.nb[2], 2 * (A.nb[2] + 1) + A.nb[1] + A.nb[2]};
   int sw = 0, conv = 0;
   while (sw < max_sweeps) {
-    const int dir = sw & 7;
-    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
-    for (int d = 0; d < ndiag; ++d)
-      hipLaunchKernelGGL(eik::k_grid_sweep3<T>, dim3(cells_on_diag(A.nb, d)), dim3(eik::kBlock3), lds, s, A,
-                         dir, d, sw * ndiag + d);
+    const int nsw = std::min(4, max_sweeps - sw);
+    HIPCHK(hipMemsetAsync(A.changed, 0, 4 * sizeof(unsigned int), s));
+    for (int tau = 0; tau < off[nsw - 1] + ndiag; ++tau) {
+      eik::GridLaunch3 L{};
+      int nbk = 0;
+      for (int k = 0; k < nsw; ++k) {
+        const int d = tau - off[k];
+        if (d < 0 || d >= ndiag) continue;
+        L.dir[L.n] = (sw + k) & 7;
+        L.diag[L.n] = d;
+        L.t[L.n] = (sw + k) * ndiag + d;
+        L.chg_off[L.n] = k;
+        L.start[L.n] = nbk;
+        nbk += cells_on_diag(A.nb, d);
+        ++L.n;
+      }
+      L.start[L.n] = nbk;
+      if (nbk == 0) continue;
+      hipLaunchKernelGGL(eik::k_grid_sweep3<T>, dim3(nbk), dim3(eik::kBlock3), lds, s, A, L);
+    }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host, A.changed, 4 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    ++sw;
-    if (*(unsigned int*)host == 0) {
+    const unsigned int* hc = (const unsigned int*)host;
+    int k0 = -1;
+    for (int k = 0; k < nsw && k0 < 0; ++k)
+      if (hc[k] == 0) k0 = k;
+    if (k0 >= 0) {
+      sw += k0 + 1;
       conv = 1;
       break;
     }
+    sw += nsw;
   }
   HIPCHK(hipEventRecord(e1, s));
   HIPCHK(hipEventSynchronize(e1));
@@ -1217,7 +1242,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
   std::lock_guard<std::mutex> lock(g_ws[dev].mu);
   const size_t szT = sizeof(T);
-  size_t need = NB * szT + 256 + (wind_out ? 0 : NB + 256) + 4096 + 8 * (size_t)nb + 512;
+  size_t need = NB * szT + 256 + (wind_out ? 0 : NB + 256) + 4096 + 12 * (size_t)nb + 512;
   need += 2 * ((size_t)nb * BX * BY * sizeof(int) + 256);
   void* wsv;
   unsigned long long* host;
@@ -1233,7 +1258,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   A.u = as<T>(u_outv);
   A.w = wind_out ? (uint8_t*)wind_out : cv.take<uint8_t>(NB);
   unsigned int* dflag = cv.take<unsigned int>(4);
-  unsigned int* dchg = cv.take<unsigned int>(nb);
+  unsigned int* dchg = cv.take<unsigned int>(2 * (size_t)nb);  // per problem, for the two sweeps of a launch pair
   int* dmem = cv.take<int>(nb);
   A.changed = dchg;
   A.members = dmem;
@@ -1262,28 +1287,56 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   HIPCHK(hipMemsetAsync(A.chg_at, 0xff, (size_t)nb * BX * BY * sizeof(int), s));
   HIPCHK(hipGetLastError());
   std::vector<int> active(nb), sweeps(nb, 0);
-  std::vector<unsigned int> hchg(nb);
+  std::vector<unsigned int> hchg(2 * (size_t)nb);
   for (int b = 0; b < nb; ++b) active[b] = b;
+  const int D = BX + BY - 1;  // box diagonals per sweep
+  auto boxes_on = [&](int d) { return (d < 0 || d >= D) ? 0 : std::min(d, BX - 1) - std::max(0, d - (BY - 1)) + 1; };
   int sw = 0;
   while (sw < max_sweeps && !active.empty()) {
-    const int dir = sw & 3;
+    // sweeps sw (even: x fixed, y - or +) and sw + 1 (y reversed) in shared
+    // launches, the second BY + 1 diagonals behind; if sweep sw changes
+    // nothing the grid is stationary for every order, so sweep sw + 1 then
+    // changes nothing either and the problem stops after sweep sw
+    const int nsw = (sw + 1 < max_sweeps) ? 2 : 1;
+    const int lag = nsw == 2 ? BY + 1 : 0;
     const int na = (int)active.size();
     HIPCHK(hipMemcpyAsync(dmem, active.data(), na * sizeof(int), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(dchg, 0, nb * sizeof(unsigned int), s));
-    for (int d = 0; d <= BX + BY - 2; ++d) {
-      const int q0 = std::max(0, d - (BY - 1)), q1 = std::min(d, BX - 1);
-      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(q1 - q0 + 1, na), dim3(eik::kBlock), lds, s, A, dir, d,
-                         sw * (BX + BY - 1) + d);
+    HIPCHK(hipMemsetAsync(dchg, 0, 2 * (size_t)nb * sizeof(unsigned int), s));
+    for (int tau = 0; tau < D + lag; ++tau) {
+      eik::GridLaunch2 L{};
+      int nbk = 0;
+      for (int k = 0; k < nsw; ++k) {
+        const int d = tau - k * lag;
+        const int cnt = boxes_on(d);
+        if (cnt == 0) continue;
+        L.dir[L.n] = (sw + k) & 3;
+        L.diag[L.n] = d;
+        L.t[L.n] = (sw + k) * D + d;
+        L.chg_off[L.n] = k * nb;
+        L.start[L.n] = nbk;
+        nbk += cnt;
+        ++L.n;
+      }
+      L.start[L.n] = nbk;
+      if (nbk == 0) continue;
+      hipLaunchKernelGGL(eik::k_grid_sweep<T>, dim3(nbk, na), dim3(eik::kBlock), lds, s, A, L);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(hchg.data(), dchg, nb * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hchg.data(), dchg, 2 * (size_t)nb * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    ++sw;
     std::vector<int> next;
     for (int b : active) {
-      sweeps[b] = sw;
-      if (hchg[b]) next.push_back(b);
+      if (!hchg[b]) {
+        sweeps[b] = sw + 1;
+      } else if (nsw == 2 && hchg[nb + b]) {
+        sweeps[b] = sw + 2;
+        next.push_back(b);
+      } else {
+        sweeps[b] = sw + nsw;
+        if (nsw == 1) next.push_back(b);
+      }
     }
+    sw += nsw;
     active.swap(next);
   }
   HIPCHK(hipEventRecord(e1, s));
@@ -1385,18 +1438,47 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   HIPCHK(hipMemsetAsync(A.chg_at, 0xff, (size_t)nb * BXa * BYa * sizeof(int), s));
   HIPCHK(hipGetLastError());
   int sw = 0, conv = 0;
+  const int D = A.BX + A.BY - 1;
+  auto boxes_on = [&](int d) {
+    return (d < 0 || d >= D) ? 0 : std::min(d, A.BX - 1) - std::max(0, d - (A.BY - 1)) + 1;
+  };
   while (sw < max_sweeps) {
-    HIPCHK(hipMemsetAsync(A.changed, 0, sizeof(unsigned int), s));
-    for (int d = 0; d <= A.BX + A.BY - 2; ++d) {
-      const int q0 = std::max(0, d - (A.BY - 1)), q1 = std::min(d, A.BX - 1);
-      hipLaunchKernelGGL(eik::k_adj_sweep<T>, dim3(q1 - q0 + 1, nb), dim3(eik::kBlock), lds, s, A, sw & 3, d,
-                         sw * (A.BX + A.BY - 1) + d);
+    // sweeps sw and sw + 1 (y reversed) in shared launches, as in eik_solve:
+    // a sweep without change leaves every problem stationary, so the second
+    // then changes nothing
+    const int nsw = (sw + 1 < max_sweeps) ? 2 : 1;
+    const int lag = nsw == 2 ? A.BY + 1 : 0;
+    HIPCHK(hipMemsetAsync(A.changed, 0, 2 * sizeof(unsigned int), s));
+    for (int tau = 0; tau < D + lag; ++tau) {
+      eik::GridLaunch2 L{};
+      int nbk = 0;
+      for (int k = 0; k < nsw; ++k) {
+        const int d = tau - k * lag;
+        const int cnt = boxes_on(d);
+        if (cnt == 0) continue;
+        L.dir[L.n] = (sw + k) & 3;
+        L.diag[L.n] = d;
+        L.t[L.n] = (sw + k) * D + d;
+        L.chg_off[L.n] = k;
+        L.start[L.n] = nbk;
+        nbk += cnt;
+        ++L.n;
+      }
+      L.start[L.n] = nbk;
+      if (nbk == 0) continue;
+      hipLaunchKernelGGL(eik::k_adj_sweep<T>, dim3(nbk, nb), dim3(eik::kBlock), lds, s, A, L);
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(host, A.changed, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(host, A.changed, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    ++sw;
-    if (*(unsigned int*)host == 0) {
+    const unsigned int* hc = (const unsigned int*)host;
+    if (hc[0] == 0) {
+      sw += 1;
+      conv = 1;
+      break;
+    }
+    sw += nsw;
+    if (nsw == 2 && hc[1] == 0) {
       conv = 1;
       break;
     }

@@ -1440,9 +1440,26 @@ __device__ __forceinline__ bool box_needed(const int* eval_at, const int* chg_at
 // from global memory: the upwind neighbours were finished by the previous
 // diagonals, the downwind ones are untouched, so the sweep of the whole grid
 // is the paper's serial Gauss-Seidel sweep exactly.
+// The sweeps, box diagonals and block ranges of one launch of k_grid_sweep:
+// sweep 2m (dir[0]) and, BY + 1 box diagonals behind it, sweep 2m+1 (dir[1],
+// y reversed).  A box on diagonal d of the first lies on d - 2J' + BY - 1 of
+// the second (J' its y index in the first's order), so no box the second
+// takes, nor a face neighbour of it, is still open in the first, and the
+// second writes no box the first will still read: the two give the values
+// of the sweeps one after the other.  Each sweep has its own change flags
+// (chg_off: offset into A.changed) and launch numbers t.
+struct GridLaunch2 {
+  int n;
+  int dir[2], diag[2], t[2], start[3], chg_off[2];
+};
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int diag, int t) {
+__global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, GridLaunch2 L) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const int g = (L.n > 1 && (int)blockIdx.x >= L.start[1]) ? 1 : 0;
+  const int dir = L.dir[g], diag = L.diag[g], t = L.t[g];
+  const int bxl = (int)blockIdx.x - L.start[g];
+  A.changed += L.chg_off[g];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   // problem of the batch (same grid and slowness, its own Gamma)
   const int mem = A.members ? A.members[blockIdx.y] : (int)blockIdx.y;
@@ -1454,7 +1471,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_sweep(GS2<T> A, int dir, int di
   A.eval_at += mem * A.BX * A.BY;
   A.chg_at += mem * A.BX * A.BY;
   const int q0 = max(0, diag - (A.BY - 1));
-  const int Iq = q0 + (int)blockIdx.x;
+  const int Iq = q0 + bxl;
   const int Jq = diag - Iq;
   if (Iq >= A.BX || Jq < 0) return;
   const int I = sx > 0 ? Iq : A.BX - 1 - Iq;

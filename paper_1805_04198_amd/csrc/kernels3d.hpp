@@ -833,6 +833,13 @@ struct CausalLaunch3 {
   int n;
   int dir[4], diag[4], start[5];
 };
+// The same for k_grid_sweep3 (the whole-grid FSM, boxes for cells: sweeps
+// 4m .. 4m+3 share launches), with each sweep's launch number t and change
+// flag (offset into A.changed).
+struct GridLaunch3 {
+  int n;
+  int dir[4], diag[4], t[4], start[5], chg_off[4];
+};
 //
 // Cell (I, J, K) owns the coarse nodes with coordinates in [IM, IM+M) x
 // [JM, JM+M) x [KM, KM+M) (its three low faces).  In sweep direction s a node
@@ -1084,10 +1091,16 @@ __global__ void k_grid_init3(GS3<T> A) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, int dir, int diag, int t) {
+__global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, GridLaunch3 GL) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // blocks [start[g], start[g+1]) take boxes of diagonal diag[g] of sweep g
+  // of the launch (as the causal sweep's groups of directions)
+  int g = 0;
+  while (g + 1 < GL.n && (int)blockIdx.x >= GL.start[g + 1]) ++g;
+  const int dir = GL.dir[g], diag = GL.diag[g], t = GL.t[g];
+  A.changed += GL.chg_off[g];
   const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
-  int rem = blockIdx.x;
+  int rem = (int)blockIdx.x - GL.start[g];
   int Iq = -1, Jq = -1, Kq = -1;
   for (int i = max(0, diag - (A.nb[1] - 1) - (A.nb[2] - 1)); i <= min(diag, A.nb[0] - 1); ++i) {
     const int r2 = diag - i;

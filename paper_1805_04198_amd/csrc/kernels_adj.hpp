@@ -183,11 +183,15 @@ struct AdjRule {
 // problem blockIdx.y.  Halo values come from global memory (upwind boxes
 // finished, downwind boxes untouched); outside the grid they are 0.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, int dir, int diag, int t) {
+__global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, GridLaunch2 L) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // one or two sweeps per launch, as k_grid_sweep
+  const int g = (L.n > 1 && (int)blockIdx.x >= L.start[1]) ? 1 : 0;
+  const int dir = L.dir[g], diag = L.diag[g], t = L.t[g];
+  A.changed += L.chg_off[g];
   const int sx = (dir & 2) ? 1 : -1, sy = (dir & 1) ? 1 : -1;
   const int q0 = max(0, diag - (A.BY - 1));
-  const int Iq = q0 + (int)blockIdx.x;
+  const int Iq = q0 + (int)blockIdx.x - L.start[g];
   const int Jq = diag - Iq;
   if (Iq >= A.BX || Jq < 0) return;
   const int I = sx > 0 ? Iq : A.BX - 1 - Iq;
