@@ -333,9 +333,9 @@ struct StepSpan {
 // The sweep may start at step t0 > 0 and end early: the caller guarantees
 // that no node before step t0 can change (the registers that carry values
 // from step to step are then loaded from LDS), and the sweep stops after a
-// step pair at or beyond tmax in which no lane changed a value.  span
-// receives the steps at which each lane changed values.  Returns true in
-// lanes that changed a value.
+// step pair at or beyond tmax in which no lane changed a value.  span (as
+// constructed) receives the steps at which each lane changed values.  Returns
+// true in lanes that changed a value.
 //
 // PIPE selects the two-wave mode (PipeSync): 0 alone, 1 leader (publishes its
 // progress and the key of its changes after every step pair), 2 follower
@@ -375,7 +375,6 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
     cur = value_at(t0 - 1);
     if (EXTRA) cur_prev = value_at(t0 - 2);
   }
-  bool changed = false;
   unsigned long long recent = 0;
   int x = x_at(t0);
   Pre pa = R.template load<SX, SY>(x), pb;
@@ -428,7 +427,6 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
     const T v = R.template compute<SX, SY>(xm, xp, ym, yp, p, x, act, ch);
     if (EXTRA && PH != 1) cur_prev = cur;
     cur = act ? v : cur;
-    changed = changed || ch;
     recent |= __ballot(ch);
     span.cmin = min(span.cmin, ch ? iq : 0x7fffffff);
     span.cmax = max(span.cmax, ch ? iq : -1);
@@ -504,7 +502,7 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
     if (PIPE == 1) publish(t + 2);
     if (recent == 0) break;
   }
-  return changed;
+  return span.cmax >= 0;  // a change has a column >= 0
 }
 
 // Minimum / maximum over the 64 lanes (all active), returned in every lane:
