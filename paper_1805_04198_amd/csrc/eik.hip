@@ -844,6 +844,9 @@ void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
   const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
   const int ndiag = CN[0] + CN[1] + CN[2] - 2;
   const size_t lds = eik::causal3_lds<T>(A.M);
+  // whole waves enough for the most nodes a cell owns (3M^2 - 3M + 1), at most 256
+  const int own = 3 * A.M * A.M - 3 * A.M + 1;
+  const int threads = std::min(256, (own + eik::kWave - 1) / eik::kWave * eik::kWave);
   // directions 4m .. 4m+3 together, each behind the one before by the lag
   // its reversed axes need (z: CN2 + 1; y and z: CN1 + CN2)
   const int off[4] = {0, CN[2] + 1, CN[2] + 1 + CN[1] + CN[2], 2 * (CN[2] + 1) + CN[1] + CN[2]};
@@ -862,7 +865,7 @@ void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
       }
       L.start[L.n] = nb;
       if (nb == 0) continue;
-      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(nb), dim3(256), lds, s, A, U, W, L);
+      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(nb), dim3(threads), lds, s, A, U, W, L);
     }
 }
 

@@ -83,6 +83,9 @@ DD3_CASES = [
     dict(seed=34, n=(17, 33, 17), S=16, M=2, nsrc=2, kind="fourier", theta=0.0),  # 7 lattices
     dict(seed=35, n=(17, 17, 17), S=8, M=4, nsrc=0, kind="blocks", theta=0.5, edge=0),
     dict(seed=36, n=(9, 9, 41), S=8, M=8, nsrc=1, kind="fourier", theta=0.7),   # a column of tiles
+    # M = 16: a coarse cell owns more nodes (721) than one wave's three per
+    # lane, so the causal sweep takes the 256-thread cell blocks
+    dict(seed=37, n=(33, 33, 49), S=16, M=16, nsrc=2, kind="fourier", theta=0.4),
 ]
 
 
