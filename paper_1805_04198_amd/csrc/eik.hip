@@ -40,6 +40,20 @@ eik_status fail(eik_status st, const char* fmt, ...) {
 constexpr int kMaxDevices = 64;
 constexpr size_t kLdsBytes = 160 * 1024;
 
+// LDS bytes of the lattice kernels (Steps 1 and 4) for NI x NJ coarse cells;
+// packed: whether Step 4 also holds its operands as CorrPack records (fp32,
+// constant weight, when they fit: always for the lattices of at most 65
+// nodes a side that the sweeps take, 155 KB at 65 x 65)
+inline size_t lattice_lds(int NI, int NJ, int tmode, size_t szT, bool& packed) {
+  const int cnt = eik::halo_count(NI + 1, NJ + 1);
+  // Step 4 holds two doubles more per node when the weight varies
+  const size_t step4 = eik::box_bytes(cnt, 4, 1, szT) + (tmode ? eik::box_bytes(cnt, 2, 0, 8) : 0);
+  const size_t step1 = eik::box_bytes(cnt, 2, 1, szT);
+  const size_t with_pk = step4 + eik::box_bytes(cnt, 0, sizeof(eik::CorrPack), szT);
+  packed = szT == 4 && tmode == 0 && std::max(with_pk, step1) <= kLdsBytes;
+  return std::max(packed ? with_pk : step4, step1);
+}
+
 // Per-device workspace: one device buffer grown on demand, plus pinned host
 // words for the per-iteration readback.  Calls on one device are serialised.
 struct Workspace {
@@ -179,10 +193,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   eik_status e = check_weight_solver(o);
   if (e != EIK_OK) return e;
   const int tmode = o->theta_mode;
-  // Step 4 holds two doubles more per node when the weight varies
-  const size_t lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT) +
-                                      (tmode ? eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 0, 8) : 0),
-                                  eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
+  bool corr_packed = false;
+  const size_t lds_lat = lattice_lds(NI, NJ, tmode, szT, corr_packed);
   const int nC = (NI + 1) * (NJ + 1);
   const size_t lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
   if (lds_tile > kLdsBytes || lds_cb > kLdsBytes)
@@ -252,6 +264,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.u_out = as<T>(u_outv);
   A.theta_mode = tmode;
   A.coarse_homog = o->coarse_solver;
+  A.corr_packed = corr_packed ? 1 : 0;
   A.res_out = nullptr;   // set per DD iteration
   A.res_prev = nullptr;  // Step 1 always runs
   A.tol = o->tol;
@@ -442,6 +455,7 @@ struct BatchProb {
   int64_t N = 0, nrec = 0, npair = 0;
   size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
   int tmode = 0;
+  bool corr_packed = false;  // Step 4's CorrPack records (lattice_lds)
   T* hist_u = nullptr;
   T* hist_c[3] = {nullptr, nullptr, nullptr};
   T* gfull = nullptr;
@@ -496,9 +510,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     q.tmode = op->theta_mode;
     const int L = S + 1;
     q.lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
-    q.lds_lat = std::max(eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 4, 1, szT) +
-                             (q.tmode ? eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 0, 8) : 0),
-                         eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT));
+    q.lds_lat = lattice_lds(NI, NJ, q.tmode, szT, q.corr_packed);
     q.lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
     if (q.lds_tile > kLdsBytes || q.lds_lat > kLdsBytes || q.lds_cb > kLdsBytes)
       return fail(EIK_ERR_UNSUPPORTED, "problem %d: LDS footprint too large", p);
@@ -601,6 +613,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.u_out = as<T>(u_out[p]);
     A.theta_mode = q.tmode;
     A.coarse_homog = op->coarse_solver;
+    A.corr_packed = q.corr_packed ? 1 : 0;
     A.res_out = A.counters + 2;  // read back after every iteration
     A.res_prev = nullptr;        // the batch checks on the host
     A.tol = op->tol;

@@ -764,6 +764,14 @@ struct MinRule {
   }
 };
 
+// Step 4's read-only operands of a node in one 16-byte record (fp32): one
+// LDS read per step in place of four.  Used for a constant weight when the
+// records fit in LDS beside the separate arrays they are filled from.
+struct alignas(16) CorrPack {
+  float rd, uk, ck;
+  unsigned m;
+};
+
 template <typename T>
 struct PreCorr {
   T self, xn, yn, hx, hy, rd, uk, ck;
@@ -791,8 +799,9 @@ __device__ __forceinline__ uint8_t corr_mask(uint8_t wk, uint8_t Wk, bool nx, bo
 // U~, C^k are finite; U = u^k otherwise.  Direct assignment, no minimum.
 // Gamma nodes carry u^k = g and r*H = NaN, so they always keep g.  MODE
 // selects the weight (0 constant, else theta_at).
-template <typename T, int MODE>
+template <typename T, int MODE, bool Packed = false>
 struct CorrectRule {
+  static_assert(!Packed || (sizeof(T) == 4 && MODE == 0), "packed operands: fp32, constant weight");
   using real = T;
   using Pre = PreCorr<T>;
   static constexpr bool kHalo = false;
@@ -807,6 +816,7 @@ struct CorrectRule {
   const double* tb;
   ThetaPar q;
   bool homog;        // the homogenised coarse solver in place of C_H
+  const CorrPack* pk;  // Packed: rd, uk, ck, mk in one record per node
   __device__ __forceinline__ T value(int x) const { return u[x]; }
   template <int SX, int SY>
   __device__ __forceinline__ Pre load(int x) const {
@@ -814,10 +824,18 @@ struct CorrectRule {
     p.self = u[x];
     p.xn = u[x + SX];
     p.yn = u[x + SY * SP];
-    p.rd = rd[x];
-    p.uk = uk[x];
-    p.ck = ck[x];
-    p.m = mk[x];
+    if constexpr (Packed) {
+      const CorrPack c = pk[x];
+      p.rd = c.rd;
+      p.uk = c.uk;
+      p.ck = c.ck;
+      p.m = (uint8_t)c.m;
+    } else {
+      p.rd = rd[x];
+      p.uk = uk[x];
+      p.ck = ck[x];
+      p.m = mk[x];
+    }
     if (MODE != 0) {
       p.ta = ta[x];
       if (MODE == 1) p.tb = tb[x];
@@ -903,6 +921,9 @@ struct DD2 {
   // coarse solver of Steps 1 and 4: 0 = C_H (Sec. 3.2), 1 = the homogenised
   // solver of the squares medium (Sec. 5.3)
   int coarse_homog;
+  // Step 4 reads its operands from CorrPack records (fp32, constant weight,
+  // when they fit in LDS)
+  int corr_packed;
   // this DD iteration's residual max |U^{k+1} - U^k| (double bits; k_tile
   // zeroes it, the causal sweep of U^{k+1} raises it) ...
   unsigned long long* res_out;
@@ -1143,7 +1164,9 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   const int SP = halo_stride(L0);
   const int cnt = halo_count(L0, L1);
   unsigned char* lc = smem;
-  // the weight terms come first so that the doubles are 8-byte aligned
+  // the packed records, then the weight terms, come first (16- and 8-byte
+  // alignment)
+  CorrPack* pk = (sizeof(T) == 4 && A.corr_packed) ? carve<CorrPack>(lc, cnt) : nullptr;
   double* ta = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
   double* tb = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
   T* u = carve<T>(lc, cnt);
@@ -1228,6 +1251,11 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     }
   }
   __syncthreads();
+  if (pk) {
+    for (int k = threadIdx.x; k < cnt; k += kBlock)
+      pk[k] = CorrPack{(float)rd[k], (float)uk[k], (float)ck[k], (unsigned)mk[k]};
+    __syncthreads();
+  }
   __shared__ int sh_ns, sh_free;
   __shared__ PipeSync ps;
   if (threadIdx.x == 0) {
@@ -1239,22 +1267,29 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     int ns;
     switch (A.theta_mode) {
       case 0: {
-        CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
+        if constexpr (sizeof(T) == 4) {
+          if (pk) {
+            CorrectRule<T, 0, true> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0, pk};
+            ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
+            break;
+          }
+        }
+        CorrectRule<T, 0> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0, pk};
         ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       case 1: {
-        CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
+        CorrectRule<T, 1> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0, pk};
         ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       case 2: {
-        CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
+        CorrectRule<T, 2> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0, pk};
         ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
       default: {
-        CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0};
+        CorrectRule<T, 3> R{u, uk, ck, rd, mk, A.theta, SP, ta, tb, A.tq, A.coarse_homog != 0, pk};
         ns = wave_fsm2(R, L0, L1, SP, A.max_coarse_sweeps, &ps);
         break;
       }
