@@ -251,6 +251,19 @@ def local(m, ws, rd, rule=0, dtype=np.float64):
     return out[0], wt[:d].copy()
 
 
+def speedup_bound(N: int, M: int, d: int, iterations: int) -> float:
+    """Sec. 4.3 (complexity and speed up): the number of DD iterations k
+    below which the method, with one processor per coarse grid and per
+    subdomain, takes fewer flops than serial FSM on the fine grid.  FSM with
+    `iterations` iterations of 2^d sweeps on (n+1)^d nodes costs
+    A(n, d) = iterations * 2^d * (n+1)^d (unit cost per node update); one DD
+    iteration costs A(N, d) + A(M, d) + 2^d M (N+1)^2 (the causal-sweep term
+    as the paper writes it); the bound is A(NM, d) over that."""
+    def A(n):
+        return iterations * 2 ** d * (n + 1) ** d
+    return A(N * M) / (A(N) + A(M) + 2 ** d * M * (N + 1) ** 2)
+
+
 def solve_problem(p, dtype=np.float64, **kw):
     """Convenience: run dd() on a workloads.Problem."""
     return dd(p.n, p.h, p.r_as(np.float64), p.gamma_idx, p.gamma_val.astype(np.float64),
