@@ -9,6 +9,10 @@ iteration).  It shares no code with the GPU library.
 Functions take numpy arrays (host memory) and return numpy arrays.  Winds
 are returned per axis: array of shape (d, N), int8, +1 = flow from the minus
 side (the upwind neighbour lies at the smaller index).
+
+Two small Python modules hold the paper's worked examples, used only as
+pins: dd1d.py (the one-dimensional method of Sec. 3.1) and model_problem.py
+(the model problem of Sec. 4 as eq. modelprob writes it).
 """
 from __future__ import annotations
 
@@ -21,46 +25,56 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "eikref.c")
 _LIB = os.path.join(_HERE, "libeikref.so")
+# the same source built with OpenMP over subdomains and lattices (Steps 1, 3
+# and 4 of Sec. 3.2; the causal sweep stays serial): the all-core CPU
+# baseline, bitwise equal to the serial build
+_LIB_OMP = os.path.join(_HERE, "libeikref_omp.so")
 
 STATUS = {0: "OK", -1: "ARG", -2: "SHAPE", -3: "NOCONV", -7: "NOMEM"}
 
 
 def build(force: bool = True) -> str:
-    """Compile eikref.c twice (double and float) into libeikref.so."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+    """Compile eikref.c twice (double and float) into libeikref.so, and the
+    same again with OpenMP into libeikref_omp.so."""
+    if not force and all(os.path.exists(x) and os.path.getmtime(x) >= os.path.getmtime(_SRC)
+                         for x in (_LIB, _LIB_OMP)):
         return _LIB
     flags = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-std=c99", "-Wall",
              "-Wno-unused-function"]
-    objs = []
-    for tag, defs in (("f64", ["-DREAL=double", "-DSFX=_f64"]),
-                      ("f32", ["-DREAL=float", "-DSFX=_f32", "-DORACLE_FLOAT"])):
-        obj = os.path.join(_HERE, f"eikref_{tag}.o")
-        subprocess.check_call(["gcc", *flags, *defs, "-c", _SRC, "-o", obj])
-        objs.append(obj)
-    tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-shared", "-o", tmp, *objs, "-lm"])
-    os.replace(tmp, _LIB)
-    for o in objs:
-        os.remove(o)
+    for out, extra, link in ((_LIB, ["-Wno-unknown-pragmas"], []), (_LIB_OMP, ["-fopenmp"], ["-fopenmp"])):
+        objs = []
+        for tag, defs in (("f64", ["-DREAL=double", "-DSFX=_f64"]),
+                          ("f32", ["-DREAL=float", "-DSFX=_f32", "-DORACLE_FLOAT"])):
+            obj = out[:-3] + f"_{tag}.o"
+            subprocess.check_call(["gcc", *flags, *extra, *defs, "-c", _SRC, "-o", obj])
+            objs.append(obj)
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-shared", *link, "-o", tmp, *objs, "-lm"])
+        os.replace(tmp, out)
+        for o in objs:
+            os.remove(o)
     return _LIB
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def lib(omp: bool = False):
+    """The serial oracle library, or (omp=True) its OpenMP build."""
+    global _lib, _lib_omp
+    if (_lib_omp if omp else _lib) is None:
+        path = _LIB_OMP if omp else _LIB
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         i64p = ctypes.POINTER(ctypes.c_int64)
         vp = ctypes.c_void_p
         for sfx in ("_f64", "_f32"):
             f = getattr(L, "eikref_fsm" + sfx)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp,
-                          ctypes.c_int, vp, vp, i64p]
+                          ctypes.c_int, vp, vp, i64p, vp]
             f = getattr(L, "eikref_fmm" + sfx)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int64, i64p, vp, vp]
@@ -70,7 +84,18 @@ def lib():
                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
                           vp, i64p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
-                          ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, ctypes.c_int]
+                          ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp, ctypes.c_int,
+                          ctypes.c_int]
+            f = getattr(L, "eikref_causal" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_int, vp, vp, vp]
+            f = getattr(L, "eikref_reconcile" + sfx)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp]
+            if omp:
+                f = getattr(L, "eikref_set_threads" + sfx)
+                f.restype = ctypes.c_int
+                f.argtypes = [ctypes.c_int]
             f = getattr(L, "eikref_adjoint" + sfx)
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_double, vp, ctypes.c_int, i64p, vp, vp, vp, vp,
@@ -85,8 +110,11 @@ def lib():
             f.restype = ctypes.c_int
             rt = ctypes.c_float if sfx == "_f32" else ctypes.c_double
             f.argtypes = [ctypes.c_int, vp, vp, rt, ctypes.c_int, vp, vp]
-        _lib = L
-    return _lib
+        if omp:
+            _lib_omp = L
+        else:
+            _lib = L
+    return _lib_omp if omp else _lib
 
 
 def _sfx(dtype) -> str:
@@ -110,17 +138,20 @@ def _prep(n, r, gidx, gval, dtype):
     return n64, r, gidx, gval
 
 
-def fsm(n, h, r, gidx, gval, dtype=np.float64, max_sweeps=10000, with_info=False):
-    """u^f: FSM on the whole grid (Sec. 1.1).  Returns u, winds (d, N)."""
+def fsm(n, h, r, gidx, gval, dtype=np.float64, max_sweeps=10000, with_info=False, u_init=None):
+    """u^f: FSM on the whole grid (Sec. 1.1).  Returns u, winds (d, N).
+    u_init: resume from these values (whole cycles of 2^d sweeps resume
+    exactly; see eikref_fsm)."""
     d = len(n)
     n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
     N = int(np.prod(n))
     u = np.empty(N, dtype=dtype)
     w = np.zeros(d * N, dtype=np.int8)
     info = np.zeros(3, dtype=np.int64)
+    ui = None if u_init is None else np.ascontiguousarray(np.asarray(u_init, dtype=dtype).reshape(-1))
     st = getattr(lib(), "eikref_fsm" + _sfx(dtype))(d, _i64(n64), float(h), _p(r), len(gidx),
                                                     _i64(gidx), _p(gval), int(max_sweeps),
-                                                    _p(u), _p(w), _i64(info))
+                                                    _p(u), _p(w), _i64(info), _p(ui))
     if st not in (0, -3):
         raise ValueError(f"eikref_fsm: {STATUS.get(st, st)}")
     out = (u, w.reshape(d, N))
@@ -151,7 +182,8 @@ THETA_PARAMS = (0.75, 0.01, 0.9, 1.0, 1.0, 1.0, 0.001)
 
 def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.float64,
        max_fine_sweeps=256, max_coarse_sweeps=32, U_init=None, W_init=None, hist_cap=4096,
-       theta_mode="constant", theta_params=THETA_PARAMS, theta_ref=None, coarse_solver="godunov"):
+       theta_mode="constant", theta_params=THETA_PARAMS, theta_ref=None, coarse_solver="godunov",
+       threads=None, inflow_fixed=False):
     """The DD iteration of Sec. 3.2.  Returns a dict with the patched fine
     solution u, coarse values U (NaN off the skeleton), coarse winds W (d, N),
     the last iteration's reconciled fine values uk / winds wk, the last
@@ -160,7 +192,10 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
     "constant", "estimate" (eqs. secthetaest, thetaest), "reference"
     (M-bar minus a margin, theta_ref = u^f) or "field" (theta_ref = theta
     per node).  coarse_solver: "godunov" (C_H of Sec. 3.2) or "l1" (the
-    homogenised coarse solver of the squares medium, Sec. 5.3)."""
+    homogenised coarse solver of the squares medium, Sec. 5.3).
+    threads: run the OpenMP build with that many threads (subdomains and
+    lattices in parallel; bitwise the serial result).  inflow_fixed: the
+    test-only literal reading of Step 2 (inflow nodes held at U)."""
     d = len(n)
     n64, r, gidx, gval = _prep(n, r, gidx, gval, dtype)
     N = int(np.prod(n))
@@ -180,13 +215,16 @@ def dd(n, h, r, gidx, gval, S, M, theta=0.5, tol=1e-12, max_iter=None, dtype=np.
     tpar = np.ascontiguousarray(np.asarray(theta_params, dtype=np.float64))
     assert tpar.shape == (7,)
     tref = None if theta_ref is None else np.ascontiguousarray(np.asarray(theta_ref, dtype=dtype).reshape(-1))
-    st = getattr(lib(), "eikref_dd" + _sfx(dtype))(
+    L = lib(omp=threads is not None)
+    if threads is not None:
+        getattr(L, "eikref_set_threads" + _sfx(dtype))(int(threads))
+    st = getattr(L, "eikref_dd" + _sfx(dtype))(
         d, _i64(n64), float(h), _p(r), len(gidx), _i64(gidx), _p(gval), int(S), int(M),
         float(theta), float(tol), int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps),
         _p(Ui), _p(Wi), _p(u), _p(U), _p(W), _p(uk), _p(wk), _p(Upre), _i64(info),
         hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(hist_cap), int(mode),
         tpar.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p(tref),
-        {"godunov": 0, "l1": 1}[coarse_solver])
+        {"godunov": 0, "l1": 1}[coarse_solver], int(bool(inflow_fixed)))
     if st not in (0, -3):
         raise ValueError(f"eikref_dd: {STATUS.get(st, st)}")
     it = int(info[0])
@@ -222,6 +260,46 @@ def adjoint(n, h, r, gammas, u, seed, winds=None, dtype=np.float64):
     if st != 0:
         raise ValueError(f"eikref_adjoint: {STATUS.get(st, st)}")
     return grad, lam, int(info[0])
+
+
+def causal(n, M, U, W, isg, dtype=np.float64):
+    """The causal sweep alone (Alg. causalsweep2D; see eikref_causal) on a
+    full-grid U (returned, a copy), winds W (d, N) and Gamma flags (N,)."""
+    d = len(n)
+    n64 = np.zeros(3, dtype=np.int64)
+    n64[:d] = n
+    U = np.array(np.asarray(U, dtype=dtype).reshape(-1), copy=True)
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.int8).reshape(-1))
+    isg = np.ascontiguousarray(np.asarray(isg, dtype=np.uint8).reshape(-1))
+    st = getattr(lib(), "eikref_causal" + _sfx(dtype))(d, _i64(n64), int(M), _p(U), _p(W), _p(isg))
+    if st != 0:
+        raise ValueError("eikref_causal")
+    return U
+
+
+def reconcile(values, winds, sides, iface, Wk, dtype=np.float64):
+    """The reconciliation at one node (Alg. fineupdate per axis; see
+    reconcile_node in eikref.c): candidate values (nc,), winds (nc, d),
+    sides (nc, d) with 0 = minus, 1 = plus; interface axes (d,); coarse wind
+    W^k (d,).  Returns (u^k, w^k)."""
+    nc = len(values)
+    d = len(iface)
+    cu = np.ascontiguousarray(np.asarray(values, dtype=dtype))
+    cw = np.zeros((nc, 3), dtype=np.int8)
+    cw[:, :d] = winds
+    cs = np.zeros((nc, 3), dtype=np.int32)
+    cs[:, :d] = sides
+    fa = np.zeros(3, dtype=np.int32)
+    fa[:d] = iface
+    wk3 = np.zeros(3, dtype=np.int8)
+    wk3[:d] = Wk
+    uk = np.zeros(1, dtype=dtype)
+    wk = np.zeros(3, dtype=np.int8)
+    st = getattr(lib(), "eikref_reconcile" + _sfx(dtype))(d, nc, _p(cu), _p(cw), _p(cs), _p(fa), _p(wk3),
+                                                         _p(uk), _p(wk))
+    if st != 0:
+        raise ValueError("eikref_reconcile")
+    return uk[0], wk[:d].copy()
 
 
 def exp_cw(x):

@@ -351,9 +351,15 @@ static int check_problem(int d, const int64_t* n, double h, const real* r, int64
 
 /* info[0] = sweeps run, info[1] = local solves evaluated (free nodes x
  * sweeps), info[2] = 1 if stationary.  w may be NULL. */
+/* u_init (may be NULL): start from these values instead of +inf (Gamma
+ * nodes still take g).  A run cut into pieces of whole cycles of 2^d sweeps,
+ * each resumed from the last one's u, visits the same directions on the same
+ * values as one uninterrupted run (the min update does not read the winds),
+ * so its values and total sweep count are the same; the winds then record
+ * only the updates after the last resume. */
 int NAME(eikref_fsm)(int d, const int64_t* n, double h, const real* r, int64_t ng,
                      const int64_t* gidx, const real* gval, int max_sweeps, real* u,
-                     signed char* w, int64_t* info) {
+                     signed char* w, int64_t* info, const real* u_init) {
     int64_t N;
     int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
     if (st != OK) return st;
@@ -370,7 +376,7 @@ int NAME(eikref_fsm)(int d, const int64_t* n, double h, const real* r, int64_t n
         return ERR_NOMEM;
     }
     for (int64_t x = 0; x < N; x++) {
-        u[x] = RINF;
+        u[x] = u_init ? u_init[x] : RINF;
         rd[x] = r[x] * hT;
     }
     /* initialisation: boundary data fixed, all else a large value (+inf) */
@@ -539,6 +545,7 @@ typedef struct {
     /* weight of the Step 4 correction (theta_node) */
     int crule;            /* coarse solver: 1 = C_H (Sec. 3.2), 2 = homogenised (Sec. 5.3) */
     int theta_mode;       /* 0 constant, 1 estimate, 2 reference, 3 field */
+    int inflow_fixed;     /* test-only reading of Step 2: inflow nodes held at U (see tile_solve) */
     double tpar[7];       /* gamma, delta, x0, omega0, omega1, omega2, margin */
     const real* tref;     /* mode 2: u^f per node; mode 3: theta per node */
     const real* ukm1;     /* u^{k-1} per node, or NULL before there is one */
@@ -616,6 +623,8 @@ static int64_t step1_init(const ddp* D, real* U, signed char* W, int max_sweeps,
     int64_t nl = lattice_list(D, &L);
     int64_t upd = 0;
     int d = D->d;
+    /* the lattices are independent (Step 1 of Sec. 3.2) */
+#pragma omp parallel for schedule(dynamic) reduction(+ : upd)
     for (int64_t q = 0; q < nl; q++) {
         lattice* l = &L[q];
         int64_t cnt = l->B.cnt;
@@ -743,11 +752,16 @@ static void causal_sweep(const ddp* D, real* U, const signed char* W) {
 /* ---- Steps 2 and 3 on one subdomain ----
  * Step 2: nodes of the subdomain that are Gamma nodes are fixed at g (wind 0);
  * a boundary node of the subdomain lying on an interface (a subdomain
- * boundary that is not the domain boundary) is fixed at U with its wind W if
+ * boundary that is not the domain boundary) is an inflow node if
  * W . n_in > 0 for an inward normal n_in of the subdomain there (a corner has
- * one normal per interface axis); every other node is free and starts at
- * +inf (boundary data "infinity").  Step 3: FSM on the subdomain grid with
- * one-sided differences at its boundary. */
+ * one normal per interface axis): it starts at U with its wind W and, like
+ * every other non-Gamma node, takes the FSM minimum (the reading that the
+ * boundary value is an upper bound, as u <= g in the exit-time form of the
+ * value function, Sec. 1.1); every other node starts at +inf (boundary data
+ * "infinity").  With D->inflow_fixed (a test-only flag) inflow nodes are held
+ * at U instead, the literal reading of the subdomain problem's u = g.
+ * Step 3: FSM on the subdomain grid with one-sided differences at its
+ * boundary. */
 static int64_t tile_solve(const ddp* D, const int64_t T[3], const real* U, const signed char* W,
                           real* tu, signed char* tw, int max_sweeps) {
     int d = D->d;
@@ -781,6 +795,11 @@ static int64_t tile_solve(const ddp* D, const int64_t T[3], const real* U, const
         if (inflow) {
             tu[li] = U[X];
             for (int a = 0; a < d; a++) tw[a * cnt + li] = W[a * D->N + X];
+            if (D->inflow_fixed) {
+                /* the literal reading ("u = g on the boundary"): held at U */
+                fixed[li] = 1;
+                continue;
+            }
         }
         nfree++;
     }
@@ -993,6 +1012,8 @@ static int64_t step4_correct(const ddp* D, const real* Uk, const signed char* Wk
     int64_t nl = lattice_list(D, &L);
     int d = D->d;
     int64_t upd = 0;
+    /* the lattices are independent (Step 4 of Sec. 3.2) */
+#pragma omp parallel for schedule(dynamic) reduction(+ : upd)
     for (int64_t q = 0; q < nl; q++) {
         lattice* l = &L[q];
         int64_t cnt = l->B.cnt;
@@ -1059,7 +1080,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
                     const real* U_init, const signed char* W_init, real* u_out, real* U_out,
                     signed char* W_out, real* uk_out, signed char* wk_out, real* Upre_out,
                     int64_t* info, double* hist, int hist_cap, int theta_mode, const double* tpar,
-                    const real* tref, int coarse_solver) {
+                    const real* tref, int coarse_solver, int inflow_fixed) {
     int64_t N;
     int st = check_problem(d, n, h, r, ng, gidx, gval, &N);
     if (st != OK) return st;
@@ -1088,6 +1109,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     D.HT = (real)((double)M * h);
     D.thetaT = (real)theta;
     D.theta_mode = theta_mode;
+    D.inflow_fixed = inflow_fixed;
     D.crule = coarse_solver ? 2 : 1;
     for (int q = 0; q < 7; q++) D.tpar[q] = tpar ? tpar[q] : 0.0;
     D.tref = tref;
@@ -1136,6 +1158,7 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     int it = 0, conv = 0;
     for (int k = 0; k < max_iter; k++) {
         /* Steps 2-3: every subdomain independently */
+#pragma omp parallel for schedule(dynamic) reduction(+ : fine_upd)
         for (int64_t t = 0; t < ntile; t++) {
             int64_t T[3] = {t % D.P[0], (t / D.P[0]) % D.P[1], t / (D.P[0] * D.P[1])};
             fine_upd += tile_solve(&D, T, U, W, tu + t * V, tw + t * V * d, max_fine_sweeps);
@@ -1261,6 +1284,56 @@ int NAME(eikref_dd)(int d, const int64_t* n, double h, const real* r, int64_t ng
     free(tu); free(tw);
     return (max_iter == 0 || conv) ? OK : ERR_NOCONV;
 }
+
+/* Test hook: the causal sweep alone (Alg. causalsweep2D, 3D by the same
+ * rule per axis) on a full-grid U (in place), winds W [a*N + X] and Gamma
+ * flags isg; U is read only at coarse nodes (some index = 0 mod M). */
+int NAME(eikref_causal)(int d, const int64_t* n, int M, real* U, const signed char* W,
+                        const unsigned char* isg) {
+    if ((d != 2 && d != 3) || M < 1) return ERR_ARG;
+    ddp D;
+    memset(&D, 0, sizeof(D));
+    D.d = d;
+    D.M = M;
+    D.N = 1;
+    for (int a = 0; a < 3; a++) {
+        D.n[a] = (a < d) ? n[a] : 1;
+        D.N *= D.n[a];
+    }
+    D.st[0] = 1;
+    D.st[1] = D.n[0];
+    D.st[2] = D.n[0] * D.n[1];
+    D.isg = (unsigned char*)isg;
+    causal_sweep(&D, U, W);
+    return OK;
+}
+
+/* Test hook: the reconciliation at one node (Alg. fineupdate, per axis):
+ * nc candidates with values cu[nc], winds cw[nc][3] and sides cside[nc][3]
+ * (0 minus, 1 plus), interface axes iface[3], coarse wind Wk[3]. */
+int NAME(eikref_reconcile)(int d, int nc, const real* cu, const signed char* cw, const int* cside,
+                           const int* iface, const signed char* Wk, real* uk, signed char* wk) {
+    if ((d != 2 && d != 3) || nc < 1 || nc > 8) return ERR_ARG;
+    cand cs[8];
+    for (int x = 0; x < nc; x++) {
+        cs[x].u = cu[x];
+        for (int a = 0; a < 3; a++) {
+            cs[x].w[a] = cw[3 * x + a];
+            cs[x].side[a] = cside[3 * x + a];
+        }
+    }
+    reconcile_node(d, cs, nc, iface, Wk, uk, wk);
+    return OK;
+}
+
+#ifdef _OPENMP
+#include <omp.h>
+/* OpenMP build only: threads for the subdomain and lattice loops. */
+int NAME(eikref_set_threads)(int n) {
+    omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
+#endif
 
 /* Test hook: the local solve alone.  m, ws, wt have 3 entries (unused axes
  * ignored); returns u~ in *out. */

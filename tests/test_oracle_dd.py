@@ -5,19 +5,19 @@ What the paper fixes and these tests check:
     (Sec. 5 states every example converges to it); u^f itself is pinned in
     test_oracle_fsm.py;
   * Theorem exactness (Sec. 4.1): on the strip model problem, the coarse
-    values on column x = iH equal u^f once k >= i, for any theta;
-  * the one-dimensional example of Sec. 3.1: convergence within a few
-    iterations (the paper prints k = 3; its h is not stated);
+    values on column x = iH equal u^f once k >= i, for any theta, and (the
+    proof's last step) so do the reconciled fine values u^{k-1} there;
+  * Step 2's reading (inflow nodes start at U but may still decrease): the
+    literal reading (held at U) settles off u^f on config 1, as it does on
+    the paper's 1D example (test_oracle_1d.py);
   * a planar front aligned with the grid is solved exactly by the coarse
     initialisation, so the iteration stops at once;
   * the iteration state is (U^k, W^k): restarting from it continues the run
-    bitwise (Steps 2-4 read nothing else);
-  * Sec. 4's model problem at H = 1/20, h = 1/1000 (Figs. theta1,
-    vartheta): theta = 1 makes the coarse error grow from the first
-    iteration and stay large until exactness at k >= N; small weights make
-    it fall at every iteration.
-The detailed readings of Steps 2-4 (which the paper leaves open) are pinned
-only through these properties; see the oracle's header."""
+    bitwise (Steps 2-4 read nothing else).
+The causal sweep and the reconciliation are pinned rule by rule in
+test_oracle_causal_reconcile.py, the 1D method of Sec. 3.1 in
+test_oracle_1d.py, the model problem's recurrence (eq. modelprob, Fig.
+theta1) in test_oracle_model_problem.py."""
 import json
 import os
 
@@ -69,11 +69,11 @@ def test_config1_converges_for_moderate_theta():
     assert np.max(np.abs(R["U"][m] - uf[m])) <= 1e-10 * np.max(uf)
 
 
-def test_config1_theta_half_is_a_limit_cycle():
-    """With the weight of the stated config (0.5) the iteration settles into
-    a two-cycle instead of converging, as the paper reports for large fixed
-    weights (Sec. 4: theta must stay below the bound M-bar; it adapts theta
-    per node to stabilise the method)."""
+def test_config1_theta_half_two_cycle_regression():
+    """A record of this oracle's behaviour, not a value the paper prints:
+    with the weight of the stated config (0.5) the iteration settles into a
+    two-cycle instead of converging (large fixed weights are unstable in
+    Sec. 4, which adapts theta per node to stabilise the method)."""
     p = W.config1()
     R = oracle.solve_problem(p, theta=0.5, max_iter=60)
     assert not R["converged"]
@@ -84,15 +84,21 @@ def test_config1_theta_half_is_a_limit_cycle():
 @pytest.mark.parametrize("N,M", [(10, 10), (20, 10)])
 @pytest.mark.parametrize("theta", [0.3, 0.7, 1.0])
 def test_theorem_exactness_on_model_strip(N, M, theta):
+    """U^k on column i is u^f once k >= i; the run's last reconciled fine
+    values u^{k-1} on column i are u^f once k >= i too (the proof computes
+    u^{k-1}_{i} from U^{k-1}_{i-1} = u^f)."""
     p = W.model_strip(N, M)
     uf = fine(p).reshape(p.n[::-1])
     for k in range(0, N + 1, 3):
         R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta,
                       tol=0.0, max_iter=k)
         U = R["U"].reshape(p.n[::-1])
+        uk = R["uk"].reshape(p.n[::-1])
         for i in range(0, min(k, N) + 1):
             col = U[:, i * M]
             assert np.max(np.abs(col - uf[:, i * M])) <= 16 * EPS, (k, i)
+            if k >= 1:
+                assert np.max(np.abs(uk[:, i * M] - uf[:, i * M])) <= 16 * EPS, (k, i)
 
 
 def _golden(name):
@@ -110,24 +116,20 @@ def test_complexity_example_bound():
     assert oracle.speedup_bound(g["N"], 2 * g["M"], g["d"], g["iterations"]) > b
 
 
-def test_one_dimensional_bump_example():
-    """Sec. 3.1: r = 1 + 10 exp(-(x-.75)^2 / (2 .01^2)), u(0) = u(1) = 0,
-    H = 0.1, on a strip so that the solution depends on x only; the paper
-    prints convergence at k = 3 with an unstated h (here h = 1/1000)."""
-    g = _golden("one_dimensional_example")
-    n0, n1, h = 1001, 101, 1e-3
-    x = np.arange(n0) * h
-    r = np.tile(1 + g["bump_height"] * np.exp(-((x - g["bump_centre"]) ** 2) / (2 * g["bump_width"] ** 2)),
-                (n1, 1))
-    nodes = [(0, j) for j in range(n1)] + [(n0 - 1, j) for j in range(n1)]
-    gi = np.array(sorted(W.linear_index((n0, n1), *c) for c in nodes))
-    gv = np.zeros(len(gi))
-    uf, _ = oracle.fsm((n0, n1), h, r, gi, gv)
-    M = round(g["H"] / h)
-    R = oracle.dd((n0, n1), h, r, gi, gv, M, M, theta=0.0, tol=1e-12, max_iter=20)
-    # the last iteration only confirms the fixed point; h differs from the paper's
-    assert R["converged"] and R["iterations"] <= g["iterations"] + 2
-    assert np.max(np.abs(R["u"] - uf)) <= 1e-12
+@pytest.mark.parametrize("theta", [0.0, 0.25])
+def test_literal_step2_settles_off_the_fine_solution(theta):
+    """Config 1 with inflow nodes held at U (the literal reading of Step 2)
+    stops (residual below tol) on a state off u^f by ~3e-5; the reading
+    used (inflow values as upper bounds the subdomain FSM may lower) reaches
+    u^f.  The paper's 1D example makes the same distinction."""
+    p = W.config1()
+    uf = fine(p)
+    kw = dict(theta=theta, tol=1e-12, max_iter=80)
+    Rl = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, inflow_fixed=True, **kw)
+    Rf = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, **kw)
+    assert Rl["converged"] and Rf["converged"]
+    assert np.max(np.abs(Rl["u"] - uf)) > 1e-5 * np.max(uf)
+    assert np.max(np.abs(Rf["u"] - uf)) <= 1e-10 * np.max(uf)
 
 
 def test_planar_front_is_exact_from_the_start():
@@ -193,35 +195,18 @@ def test_argument_errors(kw):
                   theta=args["theta"], max_iter=2)
 
 
-def _strip_errors(theta, ks, N=_golden("model_problem")["N"], M=_golden("model_problem")["M"]):
-    p = W.model_strip(N, M)
-    uf = fine(p)
-    out = []
-    for k in ks:
-        R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=0.0, max_iter=k,
-                      max_coarse_sweeps=1000)
-        m = ~np.isnan(R["U"])
-        out.append(np.max(np.abs(R["U"][m] - uf[m])))
-    return np.array(out)
-
-
-def test_model_problem_theta_one_is_unstable():
-    """Sec. 4, Fig. theta1 (H = 1/20, h = 1/1000): with theta = 1 (standard
-    parareal) the coarse error grows from the first iteration and stays
-    large over many iterations; Theorem exactness still makes it vanish once
-    k >= N."""
-    ks = [0, 1, 3, 5, 9, 13, 20, 21]
-    e = _strip_errors(1.0, ks)
-    assert e[1] > e[0]
-    assert np.all(e[2:6] >= 2 * e[0]), e
-    assert e[6] <= 16 * EPS and e[7] <= 16 * EPS
-
-
-@pytest.mark.parametrize("theta", [0.05, 0.1, 0.25])
-def test_model_problem_small_theta_converges_monotonically(theta):
-    """Sec. 4, Fig. vartheta: small weights converge, the error falling at
-    every iteration shown (and exact from k = N on)."""
-    ks = [0, 2, 4, 8, 12, 16, 20]
-    e = _strip_errors(theta, ks)
-    assert np.all(np.diff(e) < 0), e
-    assert e[-1] <= 16 * EPS
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_openmp_build_is_bitwise_the_serial_oracle(dtype):
+    """The OpenMP build (subdomains and lattices in parallel; each writes
+    only its own nodes, counts are summed) gives the serial results bit for
+    bit, in 2D and 3D."""
+    for p, kw in ((W.config2(257, 32, 8), dict(theta=0.1, max_iter=6)),
+                  (W.random_problem(51, (17, 17, 17), 8, 4, n_src=2), dict(theta=0.25, max_iter=4))):
+        args = (p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M)
+        a = oracle.dd(*args, tol=0.0, dtype=dtype, **kw)
+        b = oracle.dd(*args, tol=0.0, dtype=dtype, threads=4, **kw)
+        for k in ("u", "U", "uk", "Upre"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), k
+        assert np.array_equal(a["W"], b["W"]) and np.array_equal(a["wk"], b["wk"])
+        assert a["fine_updates"] == b["fine_updates"] and a["coarse_updates"] == b["coarse_updates"]
+        assert np.array_equal(a["residuals"], b["residuals"])

@@ -169,3 +169,21 @@ def test_argument_errors():
     bad[3, 3] = np.nan
     with pytest.raises(ValueError):
         oracle.fsm(n, 0.125, bad, [0], [0.0])
+
+
+@pytest.mark.parametrize("n", [(40, 33), (12, 11, 13)])
+def test_fsm_resumed_in_whole_cycles_is_bitwise_the_uninterrupted_run(n):
+    """eikref_fsm from u_init: pieces of 2^d sweeps, each resumed from the
+    previous values, give the same values and sweep total."""
+    p = W.random_problem(7, n, 1, 1, n_src=2, kind="blocks")
+    d = len(n)
+    u_ref, _, info = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, with_info=True)
+    u, total = None, 0
+    while True:
+        u, _, inf = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, max_sweeps=2 ** d, with_info=True,
+                               u_init=u)
+        total += inf["sweeps"]
+        if inf["converged"]:
+            break
+    assert np.array_equal(u, u_ref)
+    assert total == info["sweeps"]
