@@ -9,8 +9,11 @@ until max|U^{k+1}-U^k| < tol.  Inputs are resident in HBM before timing.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64]
 
 Prints one JSON line.  value = fine-grid Godunov updates per second over the
-whole solve (Step 3 local solves / wall time of the solves); ms_per_step is
-the DD time-to-solution.  The roofline object describes the dominant kernel
+whole solve (Step 3 local solves of the serial FSM / wall time of the
+solves); ms_per_step is the DD time-to-solution.  The line also carries a
+"config3" block: the 3D 257^3 workload's time to solution, its error against
+the fp64 u^f, its kernel roofline and its oracle baseline (--no-config3
+leaves it out).  The roofline object describes the dominant kernel
 (the Step 4 lattice correction or the Step 3 subdomain sweep, whichever takes
 longer per launch), timed with HIP events on the stream it runs on, inside
 the library; its traffic comes from the committed rocprofv3 counter summary
@@ -54,7 +57,8 @@ def parse():
     ap.add_argument("--theta", type=float, default=0.1)
     ap.add_argument("--n", type=int, default=1025)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=40)
+    ap.add_argument("--no-config3", action="store_true",
+                    help="leave out the 3D 257^3 block of the default (config 2) line")
     ap.add_argument("--workload", choices=["config2", "config3", "config4", "config5", "squares"], default="config2",
                     help="config2 (default): the headline 2D DD solve; config3: 3D 257^3; config4: 64 "
                          "problems in one batched solve; config5: batched travel-time gradient")
@@ -97,19 +101,57 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
 
 
-def cpu_baseline(p, theta, iters):
-    """The oracle as it stands (serial C, fp64), on a bounded sample of the
-    same workload: Step 1 plus the first `iters` DD iterations."""
+def host_info():
+    """The host CPU model, the logical CPUs the OS reports and the CPUs this
+    process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def oracle_threads():
+    # the GPU box's CPU share is 16 cores per GPU, whatever the OS reports
+    return max(1, min(16, host_info()["cpus_allowed"] or 1))
+
+
+def cpu_baseline(p, theta, tol, dtype, max_iter=400):
+    """The oracle as it stands, on the same workload and in the same
+    precision as the GPU run (so its iterates and update counts are the
+    GPU's, bit for bit): the whole solve to convergence, serial and with the
+    OpenMP build (subdomains and lattices in parallel, causal sweep serial)
+    on the host's cores."""
     import numpy as np
 
     import oracle
+    args = (p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M)
+    kw = dict(theta=theta, tol=tol, max_iter=max_iter, dtype=dtype)
+    nt = oracle_threads()
     t0 = time.perf_counter()
-    R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=theta, tol=0.0,
-                  max_iter=iters, dtype=np.float64)
-    dt = time.perf_counter() - t0
-    return {"value": R["fine_updates"] / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{p.name}: Step 1 + first {iters} DD iterations, fp64 serial oracle, "
-                      f"{R['fine_updates']} fine updates in {dt:.2f} s"}
+    Rm = oracle.dd(*args, threads=nt, **kw)
+    t_omp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Rs = oracle.dd(*args, **kw)
+    t_ser = time.perf_counter() - t0
+    same = bool(np.array_equal(Rm["u"], Rs["u"]) and Rm["iterations"] == Rs["iterations"])
+    prec = "fp32" if np.dtype(dtype) == np.float32 else "fp64"
+    return {"value": Rm["fine_updates"] / t_omp, "unit": "updates/s", "cores": nt, "kind": "oracle",
+            "sample": f"{p.name}: the whole solve to convergence ({Rm['iterations']} DD iterations, "
+                      f"{Rm['fine_updates']} fine updates), {prec} oracle, OpenMP build on {nt} threads",
+            "time_to_solution_s": t_omp, "iterations": Rm["iterations"],
+            "serial": {"value": Rs["fine_updates"] / t_ser, "unit": "updates/s", "cores": 1,
+                       "time_to_solution_s": t_ser},
+            "omp_equals_serial": same, **host_info()}
 
 
 def common(a, metric, value, unit, ms, dtype, workload, extra):
@@ -121,9 +163,15 @@ def common(a, metric, value, unit, ms, dtype, workload, extra):
     print(json.dumps(line), flush=True)
 
 
-def bench_config3(a):
+def config3_block(a, cpu=True):
     """3D 257^3, S = 32, M = 8, fp32, theta = 0.1, tol 1e-6 (the weight is
-    not stated for this workload; 0.25 stalls in an fp32 limit cycle)."""
+    not stated for this workload; 0.25 stalls in an fp32 limit cycle):
+    time to solution, the error against the fp64 u^f (eik_solve in fp64,
+    checked bit for bit against the fp64 oracle's u^f at the stored sample
+    nodes of tests/golden/config3_uf_samples.json), the subdomain kernel's
+    roofline, and the oracle on a bounded sample of the same solve."""
+    import json
+
     import numpy as np
     import torch
 
@@ -134,41 +182,63 @@ def bench_config3(a):
     gi = torch.from_numpy(p.gamma_idx).cuda()
     gv = torch.from_numpy(p.gamma_val.astype(np.float32)).cuda()
     kw = dict(theta=0.1, tol=1e-6, max_iter=400)
-    for _ in range(a.warmup):
+    steps = max(1, min(a.steps, 3))
+    for _ in range(max(1, min(a.warmup, 1))):
         E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = [E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw) for _ in range(a.steps)]
+    outs = [E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw) for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     last = outs[-1]
     fine = sum(o["fine_updates"] for o in outs)
-    uf, _, _ = E.solve(r, gi, gv, p.h)
-    err = float((last["u"] - uf).abs().max() / uf.max())
+    # the fp64 problem (r and g in fp64, not the fp32 run's fl32(r))
+    uf_t, _, _ = E.solve(torch.from_numpy(p.r).cuda(), gi, torch.from_numpy(p.gamma_val).cuda(), p.h)
+    uf = uf_t.cpu().numpy().reshape(-1)
+    u = last["u"].double().cpu().numpy().reshape(-1)
+    gold_path = os.path.join(ROOT, "tests", "golden", "config3_uf_samples.json")
+    with open(gold_path) as f:
+        gold = json.load(f)
+    idx = np.array(gold["idx"], dtype=np.int64)
+    uo = np.array([float.fromhex(x) for x in gold["u"]])
     it = last["iterations"]
     upl = last["fine_updates"] / it
     msl = last["ms_fine"] / it
     ach = upl * OPS3_PER_UPDATE / (msl * 1e-3) / 1e12
-    extra = {"iterations": it, "converged": last["converged"], "fine_updates_per_solve": last["fine_updates"],
-             "rel_err_vs_gpu_fine_fsm": err, "gate": 2e-5,
-             "ms_fine_per_solve": last["ms_fine"], "ms_correct_per_solve": last["ms_correct"],
-             "ms_causal_per_solve": last["ms_causal"],
-             "roofline": {"bound": "alu", "kernel": "k_tile3 (Step 3 subdomain FSM, 33^3 boxes)", "achieved": ach,
-                          "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None,
-                          "per_launch": {"updates": upl, "ms": msl, "ops_per_update": OPS3_PER_UPDATE}}}
-    if not a.no_cpu_baseline:
+    out = {"workload": "3D 257^3, h=1/256, 8^3 subdomains (S=32), H=1/32 (M=8), sin-product x lognormal block "
+                       "slowness (seed 3), two sources, theta=0.1, tol=1e-6, fp32",
+           "time_to_solution_ms": wall * 1e3 / steps, "steps": steps, "updates_per_s": fine / wall,
+           "iterations": it, "converged": last["converged"], "fine_updates_per_solve": last["fine_updates"],
+           "rel_err_vs_fp64_uf": float(np.max(np.abs(u - uf)) / np.max(uf)),
+           "rel_err_vs_fp64_oracle_uf_samples": float(np.max(np.abs(u[idx] - uo)) / gold["max"]),
+           "fp64_uf_equals_oracle_at_samples": bool(np.array_equal(uf[idx], uo)
+                                                    and float(np.max(uf)) == gold["max"]),
+           "gate": 2e-5,
+           "ms_fine_per_solve": last["ms_fine"], "ms_correct_per_solve": last["ms_correct"],
+           "ms_causal_per_solve": last["ms_causal"],
+           "roofline": {"bound": "alu", "kernel": "k_tile3 (Step 3 subdomain FSM, 33^3 boxes)", "achieved": ach,
+                        "peak": ALU_PEAK_TOPS, "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS, "traffic": None,
+                        "per_launch": {"updates": upl, "ms": msl, "ops_per_update": OPS3_PER_UPDATE}}}
+    if cpu:
         import oracle
+        nt = oracle_threads()
         t0 = time.perf_counter()
         R = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=0.1, tol=0.0, max_iter=1,
-                      dtype=np.float32)
+                      dtype=np.float32, threads=nt)
         dt = time.perf_counter() - t0
-        extra["cpu_baseline"] = {"value": R["fine_updates"] / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-                                 "sample": f"config 3: Step 1 + 1 DD iteration, fp32 serial oracle, "
-                                           f"{R['fine_updates']} fine updates in {dt:.1f} s"}
-    common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle", fine / wall,
-           "updates/s", wall * 1e3 / a.steps, "f32",
-           "config 3: 3D 257^3, h=1/256, 8^3 subdomains (S=32), H=1/32 (M=8), sin-product x lognormal "
-           "block slowness (seed 3), two sources, theta=0.1, tol=1e-6", extra)
+        out["cpu_baseline"] = {"value": R["fine_updates"] / dt, "unit": "updates/s", "cores": nt, "kind": "oracle",
+                               "sample": f"3D 257^3: Step 1 + the first DD iteration, fp32 oracle, OpenMP build "
+                                         f"on {nt} threads, {R['fine_updates']} fine updates in {dt:.1f} s",
+                               **host_info()}
+    return out
+
+
+def bench_config3(a):
+    blk = config3_block(a, cpu=not a.no_cpu_baseline)
+    extra = {k: v for k, v in blk.items() if k not in ("workload", "time_to_solution_ms", "updates_per_s", "steps")}
+    common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle",
+           blk["updates_per_s"], "updates/s", blk["time_to_solution_ms"], "f32",
+           "config 3: " + blk["workload"], extra)
 
 
 def bench_config4(a):
@@ -421,10 +491,11 @@ def main():
     dominant, other = (k_corr, k_fine) if k_corr["per_launch"]["ms"] > k_fine["per_launch"]["ms"] \
         else (k_fine, k_corr)
 
-    # error against the fp64 oracle's overall fine solution u^f (the fixed
-    # point the iteration converges to), from eik_solve in fp64, which the
-    # parity tests hold bit-identical to the oracle's
-    uf_t, _, _ = E.solve(r.double(), gi, gv.double(), p.h)
+    # error against the fp64 oracle's overall fine solution u^f of the fp64
+    # problem (the fixed point the iteration converges to), from eik_solve in
+    # fp64, which the parity tests hold bit-identical to the oracle's
+    uf_t, _, _ = E.solve(torch.from_numpy(p.r.astype(np.float64)).to(dev), gi,
+                         torch.from_numpy(p.gamma_val.astype(np.float64)).to(dev), p.h)
     uf = uf_t.cpu().numpy().reshape(-1)
     u = last["u"].double().cpu().numpy().reshape(-1)
     err = float(np.max(np.abs(u - uf)) / np.max(uf))
@@ -451,6 +522,9 @@ def main():
         "converged": last["converged"],
         "fine_updates_per_solve": last["fine_updates"],
         "coarse_updates_per_solve": last["coarse_updates"],
+        "updates_counted_as": "local solves of the serial FSM on every subdomain (free nodes x sweeps, equal "
+                              "to the oracle's count); the GPU sweeps skip the anti-diagonals that cannot "
+                              "change, so updates/s is serial-equivalent work per second of wall time",
         "rel_err_vs_fp64_uf": err,
         "gate": 2e-5 if a.dtype == "f32" else 1e-10,
         "ms_fine_per_solve": last["ms_fine"],
@@ -462,11 +536,13 @@ def main():
     }
     line["measured_ceilings"] = measured_ceilings()
     if not a.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, a.theta, a.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(p, a.theta, tol, dt)
         # the oracle's own u^f (fp64, serial), the error reference of the metric
         import oracle
         uf_o, _ = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val)
         line["rel_err_vs_fp64_oracle_uf"] = float(np.max(np.abs(u - uf_o)) / np.max(uf_o))
+    if not a.no_config3:
+        line["config3"] = config3_block(a, cpu=not a.no_cpu_baseline)
     print(json.dumps(line), flush=True)
 
 

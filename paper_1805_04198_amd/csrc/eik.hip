@@ -102,13 +102,24 @@ eik_status allow_lds(K kernel, size_t bytes) {
   return EIK_OK;
 }
 
+// fp32 only: the smallest r * h accepted.  The correctly rounded fp32
+// square root of the local solve (eik::dsqrt) needs its argument t >= 2^-96.
+// A two-sided solve has t > (r Delta)^2: in 2D t = 2 (r Delta)^2 - (a - b)^2
+// with |a - b| < r Delta; in 3D the three-term root runs only when the
+// two-term one lies above the third neighbour, and then t/3 exceeds
+// (r Delta)^2 - (2/3) (p^2 + q^2) with p^2 + q^2 < (r Delta)^2 (p, q: the
+// gaps of the two smaller neighbours below the third).  Delta >= h, so
+// r h >= 2^-40 keeps t above 2^-80, a margin of 2^16.
+constexpr double kMinRhF32 = 0x1p-40;
+
 template <typename T>
 eik_status validate(const T* r, int64_t N, const eik_gamma* gam, unsigned int* dflag,
-                    unsigned long long* host, hipStream_t s) {
+                    unsigned long long* host, hipStream_t s, double h) {
   HIPCHK(hipMemsetAsync(dflag, 0, sizeof(unsigned int), s));
   const int64_t n = std::max<int64_t>(N, gam->count);
+  const double rh_min = sizeof(T) == 4 ? kMinRhF32 / h : 0.0;
   hipLaunchKernelGGL(eik::k_validate<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, r, N, gam->idx,
-                     (const T*)gam->g, gam->count, dflag);
+                     (const T*)gam->g, gam->count, rh_min, dflag);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(host, dflag, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -116,6 +127,9 @@ eik_status validate(const T* r, int64_t N, const eik_gamma* gam, unsigned int* d
   if (bad & 1) return fail(EIK_ERR_ARG, "r must be > 0 and finite at every node");
   if (bad & 2) return fail(EIK_ERR_ARG, "Gamma indices must be strictly increasing and in [0, N)");
   if (bad & 4) return fail(EIK_ERR_ARG, "Gamma values must be finite");
+  if (bad & 8)
+    return fail(EIK_ERR_UNSUPPORTED, "fp32: r * h below 2^-40 somewhere; the correctly rounded square root of "
+                "the local solve is not exact that far down (use fp64 or rescale r)");
   return EIK_OK;
 }
 
@@ -279,7 +293,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     for (auto& c : hist_c) c = cv.take<T>(N);
   }
 
-  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s, G->h)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_tile<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_correct<T>, lds_lat)) != EIK_OK) return e;
@@ -625,7 +639,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
       q.hist_u = cv.take<T>(N);
       for (auto& c : q.hist_c) c = cv.take<T>(N);
     }
-    if ((e = validate<T>(A.r, N, &gam[p], dflag, host, s)) != EIK_OK) return e;
+    if ((e = validate<T>(A.r, N, &gam[p], dflag, host, s, G[p].h)) != EIK_OK) return e;
   }
   if ((e = allow_lds(eik::k_tile_b<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init_b<T>, lds_lat)) != EIK_OK) return e;
@@ -984,7 +998,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
       default: return eik::k_lattice_correct3<T, 0>;
     }
   }();
-  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s, G->h)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_tile3<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init3<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(correct_kernel, lds_lat)) != EIK_OK) return e;
@@ -1154,7 +1168,7 @@ eik_status solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, int
   A.changed = dflag + 1;
   A.eval_at = cv.take<int>(nbox);
   A.chg_at = cv.take<int>(nbox);
-  if ((e = validate<T>(A.r, N, gam, dflag, host, s)) != EIK_OK) return e;
+  if ((e = validate<T>(A.r, N, gam, dflag, host, s, G->h)) != EIK_OK) return e;
   const size_t lds = (size_t)B * B * B * szT;
   if ((e = allow_lds(eik::k_grid_sweep3<T>, lds)) != EIK_OK) return e;
   hipEvent_t e0, e1;
@@ -1281,7 +1295,7 @@ eik_status solve_t(const eik_grid* G, const void* rv, int nb, const eik_gamma* g
   A.eval_at = cv.take<int>((size_t)nb * BX * BY);
   A.chg_at = cv.take<int>((size_t)nb * BX * BY);
   for (int b = 0; b < nb; ++b)
-    if ((e = validate<T>(A.r, N, &gam[b], dflag, host, s)) != EIK_OK) return e;
+    if ((e = validate<T>(A.r, N, &gam[b], dflag, host, s, G->h)) != EIK_OK) return e;
   const size_t lds = eik::box_bytes(eik::halo_count(B, B), 2, 1, szT);
   if ((e = allow_lds(eik::k_grid_sweep<T>, lds)) != EIK_OK) return e;
   hipEvent_t e0, e1;
@@ -1430,7 +1444,7 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   A.chg_at = cv.take<int>((size_t)nb * BXa * BYa);
   // the slowness and every boundary set are checked like the forward solve's
   for (int b = 0; b < nb; ++b)
-    if ((e = validate<T>(A.r, N, &gams[b], dflag, host, s)) != EIK_OK) return e;
+    if ((e = validate<T>(A.r, N, &gams[b], dflag, host, s, G->h)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_adj_sweep<T>, lds)) != EIK_OK) return e;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

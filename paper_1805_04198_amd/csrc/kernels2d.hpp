@@ -975,14 +975,17 @@ __global__ void k_scatter_gamma(T* gfull, const int64_t* gidx, const T* gval, in
   if (i < ng) gfull[gidx[i]] = gval[i];
 }
 
-// r > 0 and finite everywhere; Gamma sorted, in range, finite.  bad[0] != 0 on failure.
+// r > 0 and finite everywhere (bit 0), and r >= rmin (bit 3: the input
+// domain of the fp32 square root); Gamma sorted, in range (bit 1), finite
+// (bit 2).  bad[0] != 0 on failure.
 template <typename T>
 __global__ void k_validate(const T* r, int64_t N, const int64_t* gidx, const T* gval, int64_t ng,
-                           unsigned int* bad) {
+                           double rmin, unsigned int* bad) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < N) {
     T v = r[i];
     if (!(v > T(0)) || !dfinite(v)) atomicOr(bad, 1u);
+    else if ((double)v < rmin) atomicOr(bad, 8u);
   }
   if (i < ng) {
     int64_t g = gidx[i];

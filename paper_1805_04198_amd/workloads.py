@@ -210,38 +210,25 @@ def random_problem(seed: int, n, S: int, M: int, n_src: int = 1,
     return Problem(f"rand{seed}", n, h, r, gi, gv, S=S, M=M, theta=theta, tol=1e-12)
 
 
-def paper_r1(n_side: int, S: int, M: int) -> Problem:
-    """r^1 = 1 + .99 sin(2 pi x) sin(2 pi y) with a source at the origin
-    (Section 5.1 medium; source placement is ours)."""
+def barriers(n_side: int = 129, S: int = 64, M: int = 16, contrast: float = 100.0,
+             spacing: int = 4) -> Problem:
+    """A 100:1-contrast medium of thin slow walls: r = 1, except on the rows
+    j = spacing, 2 spacing, ... (one node thick), where r = contrast.  Each
+    wall has a gap of `spacing` nodes in every block of S columns: at the
+    block's left end on even walls, at its right end on odd ones.  Crossing
+    a wall costs contrast * h, going round it at most S * h, so inside every
+    subdomain the first arrival snakes between the walls, and the sweeps
+    must change x direction once per wall.  Source: node (0, 0), g = 0.  No
+    randomness."""
     n = (n_side, n_side)
     h = 1.0 / (n_side - 1)
-    x, y = _coords(n, h)
-    r = 1.0 + 0.99 * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    r = np.ones((n_side, n_side))
+    col = np.arange(n_side) % S
+    for k, j in enumerate(range(spacing, n_side - 1, spacing)):
+        gap = col < spacing if k % 2 == 0 else col >= S - spacing
+        r[j, :] = np.where(gap, 1.0, contrast)
     gi, gv = _gamma(n, [(0, 0)], [0.0])
-    return Problem(f"r1_{n_side}", n, h, r, gi, gv, S=S, M=M)
-
-
-def paper_r2(n_side: int, S: int, M: int) -> Problem:
-    """r^2 = 1 + .5 sin(20 pi x) sin(20 pi y) with a source at the origin."""
-    n = (n_side, n_side)
-    h = 1.0 / (n_side - 1)
-    x, y = _coords(n, h)
-    r = 1.0 + 0.5 * np.sin(20 * np.pi * x) * np.sin(20 * np.pi * y)
-    gi, gv = _gamma(n, [(0, 0)], [0.0])
-    return Problem(f"r2_{n_side}", n, h, r, gi, gv, S=S, M=M)
-
-
-def paper_r4(n_side: int, S: int, M: int) -> Problem:
-    """Fast obstacle r^4: r = 0.01 on [0.26,0.27] x [0,0.6], 1 elsewhere;
-    source (0,0) (Section 5.2)."""
-    n = (n_side, n_side)
-    h = 1.0 / (n_side - 1)
-    x, y = _coords(n, h)
-    r = np.ones_like(x)
-    inside = (x >= 0.26 - 1e-12) & (x <= 0.27 + 1e-12) & (y <= 0.6 + 1e-12)
-    r[inside] = 0.01
-    gi, gv = _gamma(n, [(0, 0)], [0.0])
-    return Problem(f"r4_{n_side}", n, h, r, gi, gv, S=S, M=M)
+    return Problem(f"walls_{n_side}", n, h, r, gi, gv, S=S, M=M)
 
 
 def model_strip(N: int, M: int) -> Problem:
