@@ -31,6 +31,7 @@
 #ifndef EIK_H
 #define EIK_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -198,6 +199,34 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
 eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma,
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);
+
+/* eik_dd_solve_noalloc -- eik_dd_solve for callers that cannot allocate
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, same iteration and kernels, and
+ * bitwise the same outputs and counters as eik_dd_solve; it calls no
+ * hipMalloc, hipFree, hipHostMalloc or event creation.  Its scratch (every
+ * buffer eik_dd_solve takes from its workspace) is carved from one fixed
+ * array of EIK_NOALLOC_SCRATCH_BYTES in device memory, one copy per device,
+ * which the library holds until the process ends; its device address is
+ * looked up on the first call on each device.
+ *   - Limit: the problem's scratch must fit in EIK_NOALLOC_SCRATCH_BYTES,
+ *     else EIK_ERR_UNSUPPORTED (the message gives the size needed).  About
+ *     50 bytes per node in fp32 and 78 in fp64 (a 1025^2 grid needs 52.5 MB
+ *     in fp32, 82 MB in fp64), 4 values of the grid dtype more per node
+ *     with EIK_THETA_ESTIMATE, plus the subdomain edge buffers.
+ *   - d = 2 only (d = 3 gives EIK_ERR_UNSUPPORTED).
+ *   - stats: the ms_* fields are 0 (no events); everything else as
+ *     eik_dd_solve.
+ *   - Every call on a device shares that device's array, which keeps the
+ *     last call's contents; each call clears what must start at zero.  Calls
+ *     that overlapped on one device would race on the array; within a
+ *     process the library prevents that by serialising the calls on a
+ *     device (the same lock as the other entry points), and each call
+ *     synchronises its stream before returning. */
+#define EIK_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+eik_status eik_dd_solve_noalloc(const eik_grid* grid, const void* r, const eik_gamma* gamma,
+                                const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
+                                eik_stats* stats, void* hip_stream);
 
 /* eik_solve_batch -- eik_solve for nb problems on one grid and slowness,
  * each with its own Gamma (e.g. one point source each): every launch of a

@@ -26,8 +26,8 @@ STATUS_NAMES = {0: "OK", -1: "ERR_ARG", -2: "ERR_SHAPE", -3: "ERR_NOCONV", -4: "
                 -7: "ERR_INTERNAL"}
 
 # exported symbols of include/eik.h
-SYMBOLS = ("eik_solve", "eik_solve_batch", "eik_dd_solve", "eik_dd_solve_batch", "eik_adjoint",
-           "eik_adjoint_batch", "eik_last_error", "eik_release", "eik_version")
+SYMBOLS = ("eik_solve", "eik_solve_batch", "eik_dd_solve", "eik_dd_solve_batch", "eik_dd_solve_noalloc",
+           "eik_adjoint", "eik_adjoint_batch", "eik_last_error", "eik_release", "eik_version")
 
 
 class EikError(RuntimeError):
@@ -101,6 +101,8 @@ def load_library(path: Optional[str] = None):
     L.eik_dd_solve.restype = ctypes.c_int32
     L.eik_dd_solve.argtypes = [ctypes.POINTER(Grid), vp, ctypes.POINTER(Gamma),
                                ctypes.POINTER(DDOpts), vp, vp, vp, ctypes.POINTER(Stats), vp]
+    L.eik_dd_solve_noalloc.restype = ctypes.c_int32
+    L.eik_dd_solve_noalloc.argtypes = L.eik_dd_solve.argtypes
     L.eik_solve_batch.restype = ctypes.c_int32
     L.eik_solve_batch.argtypes = [ctypes.POINTER(Grid), vp, ctypes.c_int32, ctypes.POINTER(Gamma), ctypes.c_int32,
                                   vp, vp, ctypes.POINTER(Stats), vp]
@@ -186,12 +188,14 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
              max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
              max_coarse_sweeps: int = 32, U_init=None, W_init=None, debug: bool = False,
              history_cap: int = 4096, theta_mode: str = "constant", theta_params=THETA_PARAMS,
-             theta_ref=None, coarse_solver: str = "godunov"):
+             theta_ref=None, coarse_solver: str = "godunov", noalloc: bool = False):
     """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
     with the patched fine solution u, coarse values U (NaN off the skeleton),
     coarse wind codes W, counters and timings; with debug=True also the last
     iteration's u^k, w^k and pre-causal-sweep U.  coarse_solver: "godunov"
-    (C_H) or "l1" (the homogenised solver of the squares medium, Sec. 5.3)."""
+    (C_H) or "l1" (the homogenised solver of the squares medium, Sec. 5.3).
+    noalloc=True calls eik_dd_solve_noalloc (the library's fixed scratch
+    array instead of its workspace; timings are 0)."""
     torch = _torch()
     L = load_library()
     r = r.contiguous()
@@ -226,8 +230,9 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     st = Stats()
     st.residual_history = hist
     st.history_cap = history_cap
-    status = L.eik_dd_solve(ctypes.byref(g), r.data_ptr(), ctypes.byref(gm), ctypes.byref(o),
-                            u.data_ptr(), U.data_ptr(), W.data_ptr(), ctypes.byref(st), _stream())
+    fn = L.eik_dd_solve_noalloc if noalloc else L.eik_dd_solve
+    status = fn(ctypes.byref(g), r.data_ptr(), ctypes.byref(gm), ctypes.byref(o),
+                u.data_ptr(), U.data_ptr(), W.data_ptr(), ctypes.byref(st), _stream())
     _check(L, status)
     it = int(st.iterations)
     out = {"u": u, "U": U, "W": W, "status": status, "iterations": it,

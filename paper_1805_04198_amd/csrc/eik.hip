@@ -79,6 +79,64 @@ eik_status ws_get(int dev, size_t need, void** out, unsigned long long** host) {
   return EIK_OK;
 }
 
+// Scratch of the allocation-free entry point (eik_dd_solve_noalloc): a
+// fixed array in device memory, one copy per device, held until the
+// process ends.  Host code uses the address hipGetSymbolAddress returns on
+// each device, never the array's name.
+constexpr size_t kScratchBytes = EIK_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_dev[kMaxDevices];
+unsigned long long g_scratch_host[kMaxDevices][8];  // readback words (pageable)
+
+// The scratch array of device `dev` (current) as a workspace: its device
+// address, looked up on the first call on the device (under the device's
+// lock), and plain host words.  Allocates nothing.
+eik_status scratch_get(int dev, size_t need, void** out, unsigned long long** host) {
+  if (need > kScratchBytes)
+    return fail(EIK_ERR_UNSUPPORTED, "the allocation-free solve needs %zu bytes of scratch, more than its %zu",
+                need, kScratchBytes);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  *host = g_scratch_host[dev];
+  return EIK_OK;
+}
+
+// K device-time events of a call, or none (the allocation-free entry point:
+// its timing fields stay 0).
+template <int K>
+struct Events {
+  hipEvent_t e[K];
+  bool on = false;
+  int made = 0;
+  eik_status init(bool want) {
+    if (!want) return EIK_OK;
+    for (; made < K; ++made) HIPCHK(hipEventCreate(&e[made]));
+    on = true;
+    return EIK_OK;
+  }
+  eik_status rec(int i, hipStream_t s) {
+    if (on) HIPCHK(hipEventRecord(e[i], s));
+    return EIK_OK;
+  }
+  eik_status ms(int a, int b, float* out) {
+    *out = 0.f;
+    if (on) HIPCHK(hipEventElapsedTime(out, e[a], e[b]));
+    return EIK_OK;
+  }
+  ~Events() {
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(e[i]);
+  }
+};
+#define EVCHK(expr)                  \
+  do {                               \
+    const eik_status es_ = (expr);   \
+    if (es_ != EIK_OK) return es_;   \
+  } while (0)
+
 // carve aligned sub-buffers out of the workspace
 struct Carver {
   char* base;
@@ -185,9 +243,12 @@ void set_theta(eik::ThetaPar& q, const eik_dd_opts* o) {
   q.margin = o->theta_params[6];
 }
 
+// noalloc: take the workspace from the fixed scratch array and time nothing
+// (eik_dd_solve_noalloc); the iteration and its kernels are the same.
 template <typename T>
 eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, const eik_dd_opts* o,
-                      void* u_outv, void* U_outv, int8_t* W_out, eik_stats* st, hipStream_t s) {
+                      void* u_outv, void* U_outv, int8_t* W_out, eik_stats* st, hipStream_t s,
+                      bool noalloc = false) {
   const int n0 = (int)G->n[0], n1 = (int)G->n[1];
   const int S = o->S, M = o->M;
   if (M < 2 || S < M || S % M != 0) return fail(EIK_ERR_SHAPE, "need M >= 2 and S a multiple of M (S=%d M=%d)", S, M);
@@ -236,7 +297,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if (tmode == EIK_THETA_ESTIMATE) need += 4 * (N * szT + 256);  // u^{k-1}, C^k, C^{k-1}, C^{k-2}
   void* wsv;
   unsigned long long* host;
-  e = ws_get(dev, need, &wsv, &host);
+  e = noalloc ? scratch_get(dev, need, &wsv, &host) : ws_get(dev, need, &wsv, &host);
   if (e != EIK_OK) return e;
   Carver cv{(char*)wsv};
   eik::DD2<T> A;
@@ -299,13 +360,9 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if ((e = allow_lds(eik::k_lattice_correct<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_causal_corner<T>, lds_cb)) != EIK_OK) return e;
 
-  hipEvent_t ev[6];
-  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() { for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]); }
-  } evg{ev};
-  HIPCHK(hipEventRecord(ev[0], s));
+  Events<2> ev;
+  EVCHK(ev.init(!noalloc));
+  EVCHK(ev.rec(0, s));
 
   const T nanT = (T)NAN;
   const int bs = 256;
@@ -357,27 +414,19 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   unsigned long long* resid = cv.take<unsigned long long>(kSlots);
   HIPCHK(hipMemsetAsync(resid, 0, kSlots * sizeof(unsigned long long), s));
   A.tol = o->tol;
-  hipEvent_t evi[kLag][4];
-  for (auto& row : evi)
-    for (auto& x : row) HIPCHK(hipEventCreate(&x));
-  struct EviGuard {
-    hipEvent_t (*e)[4];
-    ~EviGuard() {
-      for (int i = 0; i < kLag; ++i)
-        for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[i][j]);
-    }
-  } evig{evi};
+  Events<kLag * 4> evi;  // [iteration of the block][4]
+  EVCHK(evi.init(!noalloc));
   int launched = 0;
   bool done = false;
   while (!done && launched < o->max_iter) {
     const int k0 = launched, k1 = std::min(o->max_iter, k0 + lag);
     for (int k = k0; k < k1; ++k) {
-      hipEvent_t* E = evi[k - k0];
+      const int E = (k - k0) * 4;
       A.res_out = resid + k % kSlots;
       A.res_prev = k > 0 ? resid + (k - 1) % kSlots : nullptr;
-      HIPCHK(hipEventRecord(E[0], s));
+      EVCHK(evi.rec(E + 0, s));
       hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
-      HIPCHK(hipEventRecord(E[1], s));
+      EVCHK(evi.rec(E + 1, s));
       const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
       if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
       if (tmode == EIK_THETA_ESTIMATE) {
@@ -389,12 +438,12 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
       }
       hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
       if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipEventRecord(E[2], s));
+      EVCHK(evi.rec(E + 2, s));
       if (dbg && dbg->U_pre_causal)
         HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
       causal_sweep(A, A.Un, A.Wn, s, lds_cb, 1);  // also the residual (resid slot, zeroed by k_tile)
       HIPCHK(hipGetLastError());
-      HIPCHK(hipEventRecord(E[3], s));
+      EVCHK(evi.rec(E + 3, s));
       std::swap(A.U, A.Un);
       std::swap(A.W, A.Wn);
     }
@@ -404,9 +453,10 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     // the host's stopping rule on the iterations of this block, in order
     for (int k = k0; k < k1; ++k) {
       float a = 0.f, b = 0.f, c = 0.f;
-      HIPCHK(hipEventElapsedTime(&a, evi[k - k0][0], evi[k - k0][1]));
-      HIPCHK(hipEventElapsedTime(&b, evi[k - k0][1], evi[k - k0][2]));
-      HIPCHK(hipEventElapsedTime(&c, evi[k - k0][2], evi[k - k0][3]));
+      const int E = (k - k0) * 4;
+      EVCHK(evi.ms(E + 0, E + 1, &a));
+      EVCHK(evi.ms(E + 1, E + 2, &b));
+      EVCHK(evi.ms(E + 2, E + 3, &c));
       ms_fine += a;
       ms_correct += b;
       ms_causal += c;
@@ -434,12 +484,12 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(host, A.counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(ev[3], s));
+  EVCHK(ev.rec(1, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
   if (st) {
     float tot = 0.f;
-    HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[3]));
+    EVCHK(ev.ms(0, 1, &tot));
     st->iterations = it;
     st->converged = conv;
     st->fine_updates = (int64_t)host[0];
@@ -1580,6 +1630,19 @@ eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* ga
   if (grid->dtype == EIK_F32)
     return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
   return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s);
+}
+
+eik_status eik_dd_solve_noalloc(const eik_grid* grid, const void* r, const eik_gamma* gamma,
+                                const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
+                                eik_stats* stats, void* hip_stream) {
+  eik_status e = check_common(grid, r, gamma, u_out);
+  if (e != EIK_OK) return e;
+  if (!opts) return fail(EIK_ERR_ARG, "NULL opts");
+  if (grid->dim != 2) return fail(EIK_ERR_UNSUPPORTED, "the allocation-free solve is built for d = 2");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dtype == EIK_F32)
+    return dd_solve_t<float>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s, true);
+  return dd_solve_t<double>(grid, r, gamma, opts, u_out, U_out, W_out, stats, s, true);
 }
 
 eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
