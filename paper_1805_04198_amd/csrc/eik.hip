@@ -41,17 +41,15 @@ constexpr int kMaxDevices = 64;
 constexpr size_t kLdsBytes = 160 * 1024;
 
 // LDS bytes of the lattice kernels (Steps 1 and 4) for NI x NJ coarse cells;
-// packed: whether Step 4 also holds its operands as CorrPack records (fp32,
-// constant weight, when they fit: always for the lattices of at most 65
-// nodes a side that the sweeps take, 155 KB at 65 x 65)
+// packed: whether Step 4 runs on its fp32 records (CorrRecF32: fp32 with a
+// constant weight, 150 KB at the fixed 65-node geometry)
 inline size_t lattice_lds(int NI, int NJ, int tmode, size_t szT, bool& packed) {
   const int cnt = eik::halo_count(NI + 1, NJ + 1);
   // Step 4 holds two doubles more per node when the weight varies
   const size_t step4 = eik::box_bytes(cnt, 4, 1, szT) + (tmode ? eik::box_bytes(cnt, 2, 0, 8) : 0);
   const size_t step1 = eik::box_bytes(cnt, 2, 1, szT);
-  const size_t with_pk = step4 + eik::box_bytes(cnt, 0, sizeof(eik::CorrPack), szT);
-  packed = szT == 4 && tmode == 0 && std::max(with_pk, step1) <= kLdsBytes;
-  return std::max(packed ? with_pk : step4, step1);
+  packed = szT == 4 && tmode == 0 && eik::corr_f32_lds_bytes() <= kLdsBytes;
+  return std::max(packed ? eik::corr_f32_lds_bytes() : step4, step1);
 }
 
 // Per-device workspace: one device buffer grown on demand, plus pinned host
@@ -264,14 +262,14 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if ((o->U_init == nullptr) != (o->W_init == nullptr)) return fail(EIK_ERR_ARG, "U_init and W_init go together");
   const size_t szT = sizeof(T);
   const int L = S + 1;
-  const size_t lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
+  const size_t lds_tile = eik::tile_lds_bytes(L, szT);
   eik_status e = check_weight_solver(o);
   if (e != EIK_OK) return e;
   const int tmode = o->theta_mode;
   bool corr_packed = false;
   const size_t lds_lat = lattice_lds(NI, NJ, tmode, szT, corr_packed);
   const int nC = (NI + 1) * (NJ + 1);
-  const size_t lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
+  const size_t lds_cb = eik::corner_lds_bytes(NI + 1, NJ + 1, szT);
   if (lds_tile > kLdsBytes || lds_cb > kLdsBytes)
     return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this build");
   if (lds_lat > kLdsBytes)
@@ -573,9 +571,9 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     if (!rv[p] || !u_out[p] || rv[p] == u_out[p]) return fail(EIK_ERR_ARG, "problem %d: bad r / u_out", p);
     q.tmode = op->theta_mode;
     const int L = S + 1;
-    q.lds_tile = eik::box_bytes(eik::halo_count(L, L), 2, 1, szT);
+    q.lds_tile = eik::tile_lds_bytes(L, szT);
     q.lds_lat = lattice_lds(NI, NJ, q.tmode, szT, q.corr_packed);
-    q.lds_cb = eik::box_bytes(eik::halo_count(NI + 1, NJ + 1), 2, 1, szT);
+    q.lds_cb = eik::corner_lds_bytes(NI + 1, NJ + 1, szT);
     if (q.lds_tile > kLdsBytes || q.lds_lat > kLdsBytes || q.lds_cb > kLdsBytes)
       return fail(EIK_ERR_UNSUPPORTED, "problem %d: LDS footprint too large", p);
     lds_tile = std::max(lds_tile, q.lds_tile);

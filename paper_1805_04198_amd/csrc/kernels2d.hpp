@@ -764,6 +764,70 @@ struct MinRule {
   }
 };
 
+// fp32 subdomain boxes in packed records, at one fixed geometry (row stride
+// kSPf, kCntf nodes with the halo ring) for every box of up to kMaxL nodes a
+// side: a node's value and wind code in one 8-byte record (one LDS store per
+// update), its r*Delta and 2 (r*Delta)^2 in another (the local solve's
+// t = (rd*rd) + (rd*rd), the same bits as evaluating it there).  With the
+// stride and the arrays' offsets known at compile time, every LDS access of
+// a step is an immediate offset from the lane's one record address.
+constexpr int kSPf = (kMaxL + 3) & ~1;
+constexpr int kCntf = kSPf * (kMaxL + 2);
+struct alignas(8) UWf {
+  float u;
+  unsigned w;
+};
+struct alignas(8) RTf {
+  float rd, t2;
+};
+
+// Fine update of Alg. fineupdate2D (flow-direction winds; eq. FSMupdate) on
+// UWf / RTf records.  The wind code is the same as MinRule's: both axes on
+// the two-sided branch, otherwise the axis of the smaller neighbour (x when
+// a < b), written as selects.
+struct MinRuleF32 {
+  using real = float;
+  using Pre = PreFine<float>;
+  static constexpr bool kHalo = false;
+  UWf* uw;
+  const RTf* rt;
+  __device__ __forceinline__ float value(int x) const { return uw[x].u; }
+  template <int SX, int SY>
+  __device__ __forceinline__ Pre load(int x) const {
+    Pre p;
+    p.self = uw[x].u;
+    p.xn = uw[x + SX].u;
+    p.yn = uw[x + SY * kSPf].u;
+    const RTf q = rt[x];
+    p.rd = q.rd;
+    p.hx = q.t2;  // no halo values in this rule: hx carries 2 (r Delta)^2
+    return p;
+  }
+  template <int SX, int SY>
+  __device__ __forceinline__ float compute(float xm, float xp, float ym, float yp, const Pre& p, int x, bool act,
+                                          bool& ch) const {
+    const bool ltx = xm < xp, lty = ym < yp;
+    const float a = ltx ? xm : xp, b = lty ? ym : yp;
+    const float d = a - b;
+    const bool two = dabs(d) < p.rd;
+    float t = p.hx;
+    t = t - d * d;
+    const float u2 = ((a + b) + dsqrt(t)) * 0.5f;
+    const bool ab = a < b;
+    const float u1 = (ab ? a : b) + p.rd;
+    const float ut = two ? u2 : u1;
+    ch = act && (ut < p.self);
+    const unsigned cx = ltx ? 1u : 3u, cy = lty ? 4u : 12u;
+    const unsigned c = two ? (cx | cy) : (ab ? cx : cy);
+    // the store goes to the node's own record or, when nothing changes, to
+    // the lane's dummy record: a select of two addresses, the node's being
+    // the one the loads use
+    UWf* dst = ch ? uw + x : uw + dummy_slot();
+    *dst = UWf{ut, c};
+    return ch ? ut : p.self;
+  }
+};
+
 // Step 4's read-only operands of a node in one 16-byte record (fp32): one
 // LDS read per step in place of four.  Used for a constant weight when the
 // records fit in LDS beside the separate arrays they are filled from.
@@ -864,6 +928,70 @@ struct CorrectRule {
     const T v = cond ? corr : p.uk;
     ch = act && (v != p.self);
     u[ch ? x : dummy_slot()] = v;
+    return v;
+  }
+};
+
+// Step 4 in fp32 with a constant weight: one 32-byte record per node at the
+// fixed box geometry of the subdomain records (kSPf, kCntf): the value U and
+// the condition mask, then r*H, 2 (r*H)^2, u^k and C^k.  Every LDS access of
+// a step is an immediate offset from the lane's record address.
+struct alignas(32) CorrRecF32 {
+  float u;
+  unsigned m;
+  float pad0, pad1;
+  float rd, t2, uk, ck;
+};
+__host__ __device__ __forceinline__ size_t corr_f32_lds_bytes() {
+  return (size_t)(kCntf + 2 * kGuard) * sizeof(CorrRecF32);
+}
+
+struct CorrectRuleF32 {
+  using real = float;
+  using Pre = PreCorr<float>;
+  static constexpr bool kHalo = false;
+  CorrRecF32* rec;
+  float theta;
+  bool homog;
+  __device__ __forceinline__ float value(int x) const { return rec[x].u; }
+  template <int SX, int SY>
+  __device__ __forceinline__ Pre load(int x) const {
+    Pre p;
+    p.self = rec[x].u;
+    p.m = (uint8_t)rec[x].m;
+    p.xn = rec[x + SX].u;
+    p.yn = rec[x + SY * kSPf].u;
+    const float4 q = *reinterpret_cast<const float4*>(&rec[x].rd);
+    p.rd = q.x;
+    p.hx = q.y;  // 2 (r H)^2
+    p.uk = q.z;
+    p.ck = q.w;
+    return p;
+  }
+  template <int SX, int SY>
+  __device__ __forceinline__ float compute(float xm, float xp, float ym, float yp, const Pre& p, int x, bool act,
+                                          bool& ch) const {
+    const bool ltx = xm < xp, lty = ym < yp;
+    const float a = ltx ? xm : xp, b = lty ? ym : yp;
+    const int wx = ltx ? 1 : -1, wy = lty ? 1 : -1;
+    const float d = a - b;
+    const bool two = dabs(d) < p.rd && !homog;
+    float t = p.hx;
+    t = t - d * d;
+    const float u2 = ((a + b) + dsqrt(t)) * 0.5f;
+    const float u1 = ((a < b) ? a : b) + p.rd;
+    const float ut = two ? u2 : u1;
+    // W~ of Alg. update2D and the condition of CorrectRule
+    const bool lb = ut < b, la = ut < a;
+    const int tx = (!lb && la) ? 0 : wx;
+    const int ty = lb ? 0 : wy;
+    const unsigned m = p.m;
+    const bool cond = ((m >> (tx + 1)) & 1u) && ((m >> (ty + 4)) & 1u) && (m & 64u) && dfinite(ut);
+    const float corr = p.uk + theta * (ut - p.ck);
+    const float v = cond ? corr : p.uk;
+    ch = act && (v != p.self);
+    float* dst = ch ? &rec[x].u : &rec[dummy_slot()].u;
+    *dst = v;
     return v;
   }
 };
@@ -1157,10 +1285,108 @@ __global__ __launch_bounds__(kBlock) void k_lattice_init_b(const DD2<T>* descs, 
 }
 
 
+// Step 4 on one lattice, fp32 with a constant weight (CorrRecF32 records);
+// the same steps as lattice_correct_body
+__device__ __forceinline__ void lattice_correct_f32(const DD2<float>& A, int bx) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  int o0, o1;
+  lattice_offset(bx, A.M, o0, o1);
+  const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
+  unsigned char* lc = smem;
+  CorrRecF32* rec = carve<CorrRecF32>(lc, kCntf);
+  const float inf = pinf<float>();
+  const float nan = __builtin_nanf("");
+  const bool nx = o0 == 0, ny = o1 == 0;  // normal axes shared by the whole lattice
+  for (int k = threadIdx.x; k < kCntf; k += kBlock) rec[k] = CorrRecF32{inf, 0u, 0.f, 0.f, nan, nan, inf, inf};
+  __syncthreads();
+  // every global input of a node in one pass: U^k (into u, for C^k first),
+  // u^k (g at Gamma nodes), r*H and 2 (r*H)^2, w^k | W^k << 4 in the mask
+  // and the Gamma flag in C^k's slot until the C^k pass replaces them
+  int nfree = 0;
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+    const int x = (p1 + 1) * kSPf + (p0 + 1);
+    const float Uk = A.U[X];
+    const float g = A.gfull[X];
+    const float ukX = A.uk[X];
+    const float r = A.r[X];
+    const uint8_t wkX = A.wk[X], WkX = A.W[X];
+    const bool gam = !disnan(g);
+    const float rd = r * A.HT;
+    float t2 = rd * rd;
+    t2 = t2 + t2;
+    rec[x] = CorrRecF32{Uk, (unsigned)((wkX & 15) | ((WkX & 15) << 4)), 0.f, 0.f, rd, t2, gam ? g : ukX,
+                        gam ? 1.f : 0.f};
+    if (!gam) ++nfree;
+  }
+  __syncthreads();
+  // C^k = C_H(nbrs^H(U^k)) (or the homogenised solver) once per node
+  // (Jacobi), and the condition masks; U^k stays in u until all are done
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int x = (p1 + 1) * kSPf + (p0 + 1);
+    const float xm = rec[x - 1].u, xp = rec[x + 1].u, ym = rec[x - kSPf].u, yp = rec[x + kSPf].u;
+    const float a = xm < xp ? xm : xp;
+    const float b = ym < yp ? ym : yp;
+    bool two;
+    const float c = A.coarse_homog ? homog2(a, b, rec[x].rd) : godunov2(a, b, rec[x].rd, two);
+    const unsigned st = rec[x].m;
+    const bool gam = rec[x].ck != 0.f;
+    rec[x].ck = c;
+    rec[x].m = corr_mask((uint8_t)(st & 15), (uint8_t)(st >> 4), nx, ny, dfinite(c)) | (gam ? 128u : 0u);
+  }
+  __syncthreads();
+  // start of Step 4: U = +inf, Gamma nodes at g (they keep it: r*H = NaN)
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int x = (p1 + 1) * kSPf + (p0 + 1);
+    if (rec[x].m & 128u) {
+      rec[x].u = rec[x].uk;  // g
+      rec[x].rd = nan;
+      rec[x].t2 = nan;
+    } else {
+      rec[x].u = inf;
+    }
+  }
+  __syncthreads();
+  __shared__ int sh_ns, sh_free;
+  __shared__ PipeSync ps;
+  if (threadIdx.x == 0) {
+    sh_free = 0;
+    pipe_init(ps);
+  }
+  __syncthreads();
+  if (fsm_wave()) {
+    CorrectRuleF32 R{rec, A.theta, A.coarse_homog != 0};
+    const int ns = wave_fsm2(R, L0, L1, kSPf, A.max_coarse_sweeps, &ps);
+    if (threadIdx.x == 0) sh_ns = ns;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < L0 * L1; k += kBlock) {
+    const int p0 = k % L0, p1 = k / L0;
+    const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
+    const int x = (p1 + 1) * kSPf + (p0 + 1);
+    A.Un[X] = rec[x].u;
+    A.Wn[X] = (rec[x].m & 128u) ? (uint8_t)0 : A.wk[X];
+  }
+  for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
+}
+
 template <typename T>
 __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (dd_stopped(A)) return;
+  if constexpr (sizeof(T) == 4) {
+    if (A.corr_packed) {
+      lattice_correct_f32(A, bx);
+      return;
+    }
+  }
   int o0, o1;
   lattice_offset(bx, A.M, o0, o1);
   const int L0 = (A.n0 - 1 - o0) / A.M + 1, L1 = (A.n1 - 1 - o1) / A.M + 1;
@@ -1327,6 +1553,102 @@ __global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* desc
 // Steps 2 and 3: one wave per subdomain
 // ---------------------------------------------------------------------------
 
+// LDS bytes of the subdomain kernel for boxes of L nodes a side
+__host__ __device__ __forceinline__ size_t tile_lds_bytes(int L, size_t szT) {
+  return szT == 4 ? 2 * (size_t)(kCntf + 2 * kGuard) * 8 : box_bytes(halo_count(L, L), 2, 1, szT);
+}
+
+// Steps 2 and 3 on one subdomain, fp32: the packed records (MinRuleF32)
+__device__ __forceinline__ void tile_body_f32(const DD2<float>& A, int bx) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int I = bx % A.P0, J = bx / A.P0;
+  const int L = A.S + 1;
+  unsigned char* lc = smem;
+  UWf* uw = carve<UWf>(lc, kCntf);
+  RTf* rt = carve<RTf>(lc, kCntf);
+  const float nan = __builtin_nanf("");
+  const float inf = pinf<float>();
+  for (int k = threadIdx.x; k < kCntf; k += kBlock) {
+    uw[k] = UWf{inf, 0u};
+    rt[k] = RTf{nan, nan};
+  }
+  __syncthreads();
+  const int bi = I * A.S, bj = J * A.S;
+  int nfree = 0;
+  for (int k = threadIdx.x; k < L * L; k += kBlock) {
+    const int li = k % L, lj = k / L;
+    const int xi = bi + li, yi = bj + lj;
+    const int X = xi + A.n0 * yi;
+    const int x = (lj + 1) * kSPf + (li + 1);
+    const bool bxi = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
+    const bool byi = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
+    const float g = A.gfull[X];
+    const float r = A.r[X];
+    uint8_t Wc = 0;
+    float Uc = inf;
+    if (bxi || byi) {
+      Wc = A.W[X];
+      Uc = A.U[X];
+    }
+    if (!disnan(g)) {
+      uw[x] = UWf{g, 0u};
+      continue;
+    }
+    ++nfree;
+    const float rd = r * A.hT;
+    float t2 = rd * rd;
+    t2 = t2 + t2;
+    rt[x] = RTf{rd, t2};
+    // Step 2 (see tile_body)
+    bool inflow = false;
+    if (bxi && ((li == 0 && wx_of(Wc) > 0) || (li == A.S && wx_of(Wc) < 0))) inflow = true;
+    if (byi && ((lj == 0 && wy_of(Wc) > 0) || (lj == A.S && wy_of(Wc) < 0))) inflow = true;
+    uw[x] = inflow ? UWf{Uc, (unsigned)Wc} : UWf{inf, 0u};
+  }
+  __syncthreads();
+  __shared__ int sh_ns, sh_free;
+  __shared__ PipeSync ps;
+  if (threadIdx.x == 0) {
+    sh_free = 0;
+    pipe_init(ps);
+  }
+  __syncthreads();
+  if (fsm_wave()) {
+    MinRuleF32 R{uw, rt};
+    const int ns = wave_fsm2(R, L, L, kSPf, A.max_fine_sweeps, &ps);
+    if (threadIdx.x == 0) sh_ns = ns;
+  }
+  __syncthreads();
+  const int tile = bx;
+  for (int k = threadIdx.x; k < L * L; k += kBlock) {
+    const int li = k % L, lj = k / L;
+    const int xi = bi + li, yi = bj + lj;
+    const int X = xi + A.n0 * yi;
+    const int x = (lj + 1) * kSPf + (li + 1);
+    const UWf q = uw[x];
+    const float v = q.u;
+    const uint8_t c = (uint8_t)q.w;
+    const bool ifx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
+    const bool ify = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
+    if (!ifx && !ify) {
+      A.u_out[X] = v;
+      if (xi % A.M == 0 || yi % A.M == 0) {
+        A.uk[X] = v;
+        A.wk[X] = c;
+      }
+    }
+    if (li == 0) { A.edge_u[(tile * 4 + 0) * L + lj] = v; A.edge_w[(tile * 4 + 0) * L + lj] = c; }
+    if (li == A.S) { A.edge_u[(tile * 4 + 1) * L + lj] = v; A.edge_w[(tile * 4 + 1) * L + lj] = c; }
+    if (lj == 0) { A.edge_u[(tile * 4 + 2) * L + li] = v; A.edge_w[(tile * 4 + 2) * L + li] = c; }
+    if (lj == A.S) { A.edge_u[(tile * 4 + 3) * L + li] = v; A.edge_w[(tile * 4 + 3) * L + li] = c; }
+  }
+  for (int o = 32; o > 0; o >>= 1) nfree += __shfl_xor(nfree, o);
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
+}
+
 template <typename T>
 __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1334,6 +1656,10 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   // when the iteration does not run
   if (bx == 0 && threadIdx.x == 0) *A.res_out = 0ull;
   if (dd_stopped(A)) return;
+  if constexpr (sizeof(T) == 4) {
+    tile_body_f32(A, bx);
+    return;
+  }
   const int I = bx % A.P0, J = bx / A.P0;
   const int L = A.S + 1;
   const int SP = halo_stride(L);
@@ -1743,45 +2069,75 @@ __device__ __forceinline__ Seg seg_of(const DD2<T>& A, int s) {
 }
 
 // The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
-// on the coarse grid of corners, swept by one wave like a subdomain: the
-// predecessors in sweep order arrive as the engine's upwind-x (register) and
-// upwind-y (DPP) values.
+// on the coarse grid of corners.
+// The corner recurrence of one direction by one wave, without the sweep
+// engine's bookkeeping (nothing here can stop a sweep early): lane j holds
+// row j in sweep order and at step t takes column t - j, its x predecessor
+// being its own previous value and its y predecessor lane j-1's (DPP); a
+// 65th row runs on lane 0 one step late (steps 65 .. 65 + CI - 1), taking
+// lane 63's value of two steps back.  Each node's {V, links} record is read
+// one step ahead.  Links exist only where the predecessor does, so the
+// values a lane holds outside its row are never used.
 template <typename T>
-struct PreCausal {
-  T self, xn, yn, hx, hy, b;
-  uint8_t a;
+struct alignas(2 * sizeof(T)) CornerOp {
+  T b;
+  unsigned a;
 };
-
-template <typename T>
-struct CausalRule {
-  using real = T;
-  using Pre = PreCausal<T>;
-  static constexpr bool kHalo = false;
-  T* cu;
-  const T* cb;
-  const uint8_t* ca;
-  __device__ __forceinline__ T value(int x) const { return cu[x]; }
-  template <int SX, int SY>
-  __device__ __forceinline__ Pre load(int x) const {
-    Pre p;
-    p.b = cb[x];
-    p.a = ca[x];
-    p.xn = p.yn = p.self = p.hx = p.hy = T(0);
-    return p;
-  }
-  template <int SX, int SY>
-  __device__ __forceinline__ T compute(T xm, T xp, T ym, T yp, const Pre& p, int x, bool act,
-                                      bool& ch) const {
-    const T px = SX > 0 ? xm : xp;  // predecessor along x in sweep order
-    const T py = SY > 0 ? ym : yp;
-    T v = p.b;
-    v = (p.a & 1) ? vmax(v, px) : v;
-    v = (p.a & 2) ? vmax(v, py) : v;
-    cu[act ? x : dummy_slot()] = v;
-    ch = false;
-    return v;
-  }
-};
+// LDS bytes of the corner kernel: the records and the values
+__host__ __device__ __forceinline__ size_t corner_lds_bytes(int CI, int CJ, size_t szT) {
+  return (size_t)(halo_count(CI, CJ) + 2 * kGuard) * (3 * szT);
+}
+template <int SX, int SY, typename T>
+__device__ __forceinline__ void corner_wave(T* cu, const CornerOp<T>* op, int CI, int CJ, int SP) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool extra = CJ > kWave;
+  const bool rowA = lane < CJ;
+  // record index at step t: x0 + SX t (row 64 on lane 0: x0B + SX t)
+  const int JA = min(SY > 0 ? lane : CJ - 1 - lane, CJ - 1);
+  const int JB = SY > 0 ? kWave : CJ - 1 - kWave;
+  const int x0A = (JA + 1) * SP + 1 + (SX > 0 ? -lane : CI - 1 + lane);
+  const int x0B = (JB + 1) * SP + 1 + (SX > 0 ? -(kWave + 1) : CI - 1 + kWave + 1);
+  const int last = extra ? kWave + CI : min(CJ, kWave) - 1 + CI - 1;
+  T cur = T(0), prev = T(0);
+  auto run = [&](auto phase, int t0, int t1) {
+    constexpr bool P2 = decltype(phase)::value;
+    // B: lane 0 on row 64 (the steps after kWave)
+    const bool B = P2 && extra && lane == 0;
+    const int x0 = B ? x0B : x0A;
+    const int off = B ? kWave + 1 : lane;
+    const bool rowok = B || rowA;
+    const int dmy = dummy_slot();
+    auto index = [=](int t, bool& act) {
+      act = rowok && (unsigned)(t - off) < (unsigned)CI;
+      return act ? x0 + SX * t : dmy;
+    };
+    bool act;
+    int x = index(t0, act);
+    CornerOp<T> o = op[x];
+    for (int t = t0; t <= t1; ++t) {
+      bool nact;
+      const int nx = index(t + 1, nact);
+      const CornerOp<T> no = op[nx];
+      T py = dpp_ror1(cur);
+      if (P2) {
+        const T py2 = dpp_ror1(prev);
+        py = B ? py2 : py;
+      }
+      T v = o.b;
+      v = (o.a & 1u) ? vmax(v, cur) : v;
+      v = (o.a & 2u) ? vmax(v, py) : v;
+      prev = cur;
+      cur = act ? v : cur;
+      cu[act ? x : dmy] = v;
+      x = nx;
+      o = no;
+      act = nact;
+    }
+  };
+  // steps 0 .. kWave: rows 0 .. 63; then lane 0 switches to row 64
+  run(std::integral_constant<bool, false>{}, 0, min(last, kWave));
+  if (last > kWave) run(std::integral_constant<bool, true>{}, kWave + 1, last);
+}
 
 // phase B for one direction, by one block: the corners' V and links (from
 // U, W, the segments' phase-A results and ncx / ncy) into LDS, the
@@ -1797,9 +2153,8 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
   const int M = A.M;
   const int nH = A.NI * CJ, nV = CI * A.NJ;
   unsigned char* lc = smem;
+  CornerOp<T>* op = carve<CornerOp<T>>(lc, cnt);
   T* cu = carve<T>(lc, cnt);
-  T* cb = carve<T>(lc, cnt);
-  uint8_t* ca = carve<uint8_t>(lc, cnt);
   // a thread's corners are blockDim.x apart; all loads of up to kPer corners
   // are issued before any is used (the loads are independent; in a loop
   // they would wait one corner at a time)
@@ -1851,14 +2206,17 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
         }
       }
       const int x = (J + 1) * SP + (I + 1);
-      cb[x] = b;
-      ca[x] = al;
+      op[x] = CornerOp<T>{b, (unsigned)al};
     }
   }
   __syncthreads();
   if (threadIdx.x < kWave) {
-    CausalRule<T> R{cu, cb, ca};
-    sweep_any(R, CI, CJ, SP, dir);
+    switch (dir) {
+      case 0: corner_wave<-1, -1>(cu, op, CI, CJ, SP); break;
+      case 1: corner_wave<-1, 1>(cu, op, CI, CJ, SP); break;
+      case 2: corner_wave<1, -1>(cu, op, CI, CJ, SP); break;
+      default: corner_wave<1, 1>(cu, op, CI, CJ, SP); break;
+    }
   }
   __syncthreads();
   double dv = 0.0;
