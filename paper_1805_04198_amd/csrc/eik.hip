@@ -914,34 +914,51 @@ static int cells_on_diag(const int CN[3], int d) {
   return c;
 }
 
+// The 3D causal sweep (k_causal3p): the (direction, cell) items in the order
+// of a coarse-cell wavefront schedule, listed once per solve; directions
+// 4m .. 4m+3 interleaved, each behind the one before by the diagonals its
+// reversed axes need (z: CN2 + 1; y and z: CN1 + CN2); the kernel waits per
+// item for the cells it depends on.
+struct Causal3Plan {
+  int* items = nullptr;  // device: dir | C0 << 3 | C1 << 9 | C2 << 15, in schedule order
+  int nitems = 0;
+  int* done = nullptr;   // device: [8][cells] epoch of the sweep that finished the cell
+  int* abort_flag = nullptr;
+  int blocks = 0, threads = 0, per_cu = 0;
+  size_t lds = 0;
+  int epoch = 0;
+};
+
 template <typename T>
-void causal_sweep3(eik::DD3<T>& A, T* U, const uint8_t* W, hipStream_t s) {
+std::vector<int> causal3_items(const eik::DD3<T>& A) {
   const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
   const int ndiag = CN[0] + CN[1] + CN[2] - 2;
-  const size_t lds = eik::causal3_lds<T>(A.M);
-  // whole waves enough for the most nodes a cell owns (3M^2 - 3M + 1), at most 256
-  const int own = 3 * A.M * A.M - 3 * A.M + 1;
-  const int threads = std::min(256, (own + eik::kWave - 1) / eik::kWave * eik::kWave);
-  // directions 4m .. 4m+3 together, each behind the one before by the lag
-  // its reversed axes need (z: CN2 + 1; y and z: CN1 + CN2)
   const int off[4] = {0, CN[2] + 1, CN[2] + 1 + CN[1] + CN[2], 2 * (CN[2] + 1) + CN[1] + CN[2]};
+  std::vector<int> items;
   for (int m = 0; m < 2; ++m)
-    for (int tau = 0; tau < off[3] + ndiag; ++tau) {
-      eik::CausalLaunch3 L{};
-      int nb = 0;
+    for (int tau = 0; tau < off[3] + ndiag; ++tau)
       for (int k = 0; k < 4; ++k) {
         const int d = tau - off[k];
         if (d < 0 || d >= ndiag) continue;
-        L.dir[L.n] = 4 * m + k;
-        L.diag[L.n] = d;
-        L.start[L.n] = nb;
-        nb += cells_on_diag(CN, d);
-        ++L.n;
+        const int dir = 4 * m + k;
+        for (int i = std::max(0, d - (CN[1] - 1) - (CN[2] - 1)); i <= std::min(d, CN[0] - 1); ++i) {
+          const int r2 = d - i;
+          for (int j = std::max(0, r2 - (CN[2] - 1)); j <= std::min(r2, CN[1] - 1); ++j) {
+            const int kk = r2 - j;
+            const int C0 = (dir & 4) ? i : CN[0] - 1 - i, C1 = (dir & 2) ? j : CN[1] - 1 - j,
+                      C2 = (dir & 1) ? kk : CN[2] - 1 - kk;
+            items.push_back(dir | (C0 << 3) | (C1 << 9) | (C2 << 15));
+          }
+        }
       }
-      L.start[L.n] = nb;
-      if (nb == 0) continue;
-      hipLaunchKernelGGL(eik::k_causal3<T>, dim3(nb), dim3(threads), lds, s, A, U, W, L);
-    }
+  return items;
+}
+
+template <typename T>
+void causal_sweep3p(eik::DD3<T>& A, T* U, const uint8_t* W, Causal3Plan& P, hipStream_t s) {
+  ++P.epoch;
+  hipLaunchKernelGGL(eik::k_causal3p<T>, dim3(P.blocks), dim3(P.threads), P.lds, s, A, U, W, P.items, P.nitems,
+                     P.done, P.epoch, P.abort_flag);
 }
 
 template <typename T>
@@ -989,6 +1006,8 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   need += (size_t)ntile * L * L * L + 256;
   need += 4096;
   if (tmode == EIK_THETA_ESTIMATE) need += 3 * (N * szT + 256);  // u^{k-1} and two more C arrays
+  const int ncell = (NC[0] + 1) * (NC[1] + 1) * (NC[2] + 1);
+  need += (size_t)8 * ncell * sizeof(int) * 2 + 1024;  // causal items (8 per cell) and flags
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -1026,6 +1045,31 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   A.cvals = nullptr;
   A.counters = cv.take<unsigned long long>(4);
   unsigned int* dflag = cv.take<unsigned int>(4);
+  Causal3Plan cp;
+  {
+    const std::vector<int> items = causal3_items(A);
+    cp.nitems = (int)items.size();
+    cp.items = cv.take<int>(items.size());
+    cp.done = cv.take<int>((size_t)8 * ncell);
+    cp.abort_flag = cv.take<int>(8);
+    HIPCHK(hipMemcpyAsync(cp.items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(cp.done, 0, (size_t)8 * ncell * sizeof(int), s));
+    HIPCHK(hipMemsetAsync(cp.abort_flag, 0, 8 * sizeof(int), s));
+    // the copy reads `items` (pageable host memory) asynchronously: it must
+    // be complete before the vector goes out of scope
+    HIPCHK(hipStreamSynchronize(s));
+    const int own = 3 * M * M - 3 * M + 1;
+    cp.threads = std::min(256, (own + eik::kWave - 1) / eik::kWave * eik::kWave);
+    cp.lds = eik::causal3_lds<T>(M);
+    int per_cu = 0, ncu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, eik::k_causal3p<T>, cp.threads, cp.lds));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    // every block resident at once (the waits rely on it): half of what the
+    // occupancy calculation allows, so that the count does not depend on
+    // that estimate being exact
+    cp.per_cu = per_cu;
+    cp.blocks = std::max(1, std::min(std::max(1, per_cu / 2) * ncu, cp.nitems));
+  }
   A.u_out = as<T>(u_outv);
   A.coarse_homog = o->coarse_solver;
   set_theta<T>(A.tq, o);
@@ -1050,7 +1094,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   if ((e = allow_lds(eik::k_tile3<T>, lds_tile)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_init3<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(correct_kernel, lds_lat)) != EIK_OK) return e;
-  if ((e = allow_lds(eik::k_causal3<T>, lds_cell)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_causal3p<T>, lds_cell)) != EIK_OK) return e;
 
   hipEvent_t ev[6];
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
@@ -1088,7 +1132,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
       hipLaunchKernelGGL(eik::k_near3_b<T>, dim3(nblocks(npair, bs)), dim3(bs), 0, s, A);
     }
     hipLaunchKernelGGL(eik::k_lattice_init3<T>, dim3(nlat), dim3(eik::kBlock3), lds_lat, s, A);
-    causal_sweep3(A, A.U, A.W, s);
+    causal_sweep3p(A, A.U, A.W, cp, s);
     HIPCHK(hipGetLastError());
   }
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.Un, nanT, N);
@@ -1114,7 +1158,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     HIPCHK(hipEventRecord(ev[4], s));
     if (dbg && dbg->U_pre_causal)
       HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
-    causal_sweep3(A, A.Un, A.Wn, s);
+    causal_sweep3p(A, A.Un, A.Wn, cp, s);
     HIPCHK(hipMemsetAsync(&A.counters[2], 0, sizeof(unsigned long long), s));
     hipLaunchKernelGGL(eik::k_residual3<T>, dim3(std::min(nblocks(N, bs), 2048u)), dim3(bs), 0, s, A);
     HIPCHK(hipGetLastError());
@@ -1146,10 +1190,18 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(host, A.counters, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(host, A.counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(ev[3], s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
+  if (host[3]) {
+    int ab[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    HIPCHK(hipMemcpy(ab, cp.abort_flag, sizeof ab, hipMemcpyDeviceToHost));
+    return fail(EIK_ERR_INTERNAL,
+                "a wait of the persistent causal sweep gave up (item %d of %d in block %d, flag %d read %d, "
+                "epoch %d of %d; %d blocks of %d threads, %d per CU by occupancy)", ab[1], cp.nitems, ab[5], ab[2],
+                ab[3], ab[4], cp.epoch, cp.blocks, cp.threads, cp.per_cu);
+  }
   if (st) {
     float tot = 0.f;
     HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[3]));

@@ -826,14 +826,12 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
 // CN2 + 1; y and z: CN1 + CN2) in the same launches:
 // every cell it takes, and the cells next to it, the earlier one has
 // finished, and it writes no cell the earlier one will still read.  So
-// directions 4m .. 4m+3 share launches; 4m+3 -> 4m+4 reverses x as well.
+// directions 4m .. 4m+3 can run interleaved in that order; 4m+3 -> 4m+4
+// reverses x as well.  The causal sweep takes its cells in this order in
+// one persistent launch (k_causal3p, below); the whole-grid FSM's boxes
+// use the same staggering in launches.
 //
-// The directions, diagonals and block ranges of one launch of k_causal3.
-struct CausalLaunch3 {
-  int n;
-  int dir[4], diag[4], start[5];
-};
-// The same for k_grid_sweep3 (the whole-grid FSM, boxes for cells: sweeps
+// The launches of k_grid_sweep3 (the whole-grid FSM, boxes for cells: sweeps
 // 4m .. 4m+3 share launches), with each sweep's launch number t and change
 // flag (offset into A.changed).
 struct GridLaunch3 {
@@ -874,30 +872,44 @@ __device__ __forceinline__ int owned_index(const int (&l)[3], const int (&E)[3])
   return fa + fb + (l[0] - 1) + (E[0] - 1) * (l[1] - 1);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* W, CausalLaunch3 L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  // blocks [start[g], start[g+1]) take cells of diagonal diag[g] in direction
-  // dir[g]; the directions of one launch are far enough apart that no two of
-  // its cells are adjacent
-  int g = 0;
-  while (g + 1 < L.n && (int)blockIdx.x >= L.start[g + 1]) ++g;
-  const int dir = L.dir[g], diag = L.diag[g];
-  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
-  const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
-  // the block enumerates the cells (in sweep coordinates) with I'+J'+K' = diag
-  int rem = (int)blockIdx.x - L.start[g];
-  int Iq = -1, Jq = -1, Kq = -1;
+// cell (Iq, Jq, Kq) of diagonal diag in sweep order: the rem-th of the
+// diagonal (false past its end)
+__device__ __forceinline__ bool diag_cell(const int (&CN)[3], int diag, int rem, int& Iq, int& Jq, int& Kq) {
   for (int i = max(0, diag - (CN[1] - 1) - (CN[2] - 1)); i <= min(diag, CN[0] - 1); ++i) {
     const int r2 = diag - i;
     const int jlo = max(0, r2 - (CN[2] - 1)), jhi = min(r2, CN[1] - 1);
     const int cntj = jhi - jlo + 1;
     if (cntj <= 0) continue;
-    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; break; }
+    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; return true; }
     rem -= cntj;
   }
-  if (Iq < 0) return;
-  const int C[3] = {s[0] > 0 ? Iq : CN[0] - 1 - Iq, s[1] > 0 ? Jq : CN[1] - 1 - Jq, s[2] > 0 ? Kq : CN[2] - 1 - Kq};
+  return false;
+}
+
+// U as the causal sweep reads and writes it: plain accesses, or (COH) accesses
+// coherent across the whole device (no copy in a cache that another
+// compute die cannot see), for the persistent sweep, whose blocks hand
+// values to each other without kernel boundaries.
+template <bool COH, typename T>
+__device__ __forceinline__ T uld(const T* p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+template <bool COH, typename T>
+__device__ __forceinline__ void ust(T* p, T v) {
+  if constexpr (COH) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
+
+// The causal-sweep update of one cell (C: its actual coordinates) in
+// direction dir, by the whole block (every thread calls it).
+template <bool COH = false, typename T>
+__device__ __forceinline__ void causal3_cell(const DD3<T>& A, T* U, const uint8_t* W, int dir, const int (&C)[3]) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
   const int M = A.M;
   int E[3];  // cell extent along each axis (the last cell holds the far boundary plane only)
   for (int a = 0; a < 3; ++a) E[a] = min(M, A.n[a] - C[a] * M);
@@ -918,14 +930,14 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
     const int64_t X = idx3(A.n, c[0], c[1], c[2]);
     // every value the node may need, requested at once: its own, Gamma,
     // wind, and both fine neighbours along each axis (where they exist)
-    T v = U[X];
+    T v = uld<COH>(&U[X]);
     const T g = A.gfull[X];
     const uint8_t wc = W[X];
     T nb[3][2];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      nb[a][0] = c[a] > 0 ? U[X - st[a]] : T(0);
-      nb[a][1] = c[a] < A.n[a] - 1 ? U[X + st[a]] : T(0);
+      nb[a][0] = c[a] > 0 ? uld<COH>(&U[X - st[a]]) : T(0);
+      nb[a][1] = c[a] < A.n[a] - 1 ? uld<COH>(&U[X + st[a]]) : T(0);
     }
     uint8_t lv = 255;
     short pr[3] = {-1, -1, -1};
@@ -990,7 +1002,94 @@ __global__ __launch_bounds__(256) void k_causal3(DD3<T> A, T* U, const uint8_t* 
   for (int q = threadIdx.x; q < nown; q += blockDim.x) {
     int l[3];
     owned_coords(q, E, l);
-    U[idx3(A.n, C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2])] = val[q];
+    ust<COH>(&U[idx3(A.n, C[0] * M + l[0], C[1] * M + l[1], C[2] * M + l[2])], val[q]);
+  }
+}
+
+// The causal sweep in one persistent launch: the blocks take the (direction,
+// cell) items of the launch schedule above in its order (block b: items b,
+// b + gridDim.x, ...) and start an item once the cells it depends on are
+// done, instead of waiting for whole launches:
+//   - in its own direction, the upwind face neighbour along each axis (its
+//     links and old values come from there or from cells before them);
+//   - in the previous direction, the cell itself and its six face
+//     neighbours (whose nodes it reads and writes; transitively every
+//     earlier direction is then done with them too).
+// done[dir * ncell + cell] holds the epoch of the sweep that finished the
+// cell.  Every item waits only for items earlier in the order, and every
+// block is resident (the host launches no more blocks than fit at once), so
+// every wait ends; a wait that exceeds its bound sets abort (all later waits
+// return at once) and counters[3], which the host reports as an internal
+// error.
+// abort_flag[0]: set by the first wait that gives up, which also records
+// its item, the flag it waited for, the value it last read there, the epoch
+// and its block in abort_flag[1..5] (reported by the host).
+constexpr int kCausalSpin = 1 << 20;
+__device__ __forceinline__ bool causal3_wait(const int* done, int fi, int epoch, int* abort_flag, int item) {
+  int v = 0;
+  for (int n = 0;; ++n) {
+    // device-coherent polls
+    v = __hip_atomic_load(&done[fi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v == epoch) return true;
+    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (n >= kCausalSpin) break;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  if (atomicCAS(abort_flag, 0, 1) == 0) {
+    abort_flag[1] = item;
+    abort_flag[2] = fi;
+    abort_flag[3] = v;
+    abort_flag[4] = epoch;
+    abort_flag[5] = (int)blockIdx.x;
+  }
+  return false;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_causal3p(DD3<T> A, T* U, const uint8_t* W, const int* items, int nitems,
+                                                 int* done, int epoch, int* abort_flag) {
+  const int CN[3] = {A.NC[0] + 1, A.NC[1] + 1, A.NC[2] + 1};
+  const int ncell = CN[0] * CN[1] * CN[2];
+  __shared__ int sh_ok;
+  for (int it = (int)blockIdx.x; it < nitems; it += (int)gridDim.x) {
+    const int code = items[it];
+    const int dir = code & 7;
+    const int C[3] = {(code >> 3) & 63, (code >> 9) & 63, (code >> 15) & 63};
+    const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
+    auto cell = [&](int i, int j, int k) { return i + CN[0] * (j + CN[1] * k); };
+    if (threadIdx.x == 0) {
+      bool ok = true;
+      for (int a = 0; a < 3 && ok; ++a) {
+        int c[3] = {C[0], C[1], C[2]};
+        c[a] -= s[a];
+        if (c[a] >= 0 && c[a] < CN[a])
+          ok = causal3_wait(done, dir * ncell + cell(c[0], c[1], c[2]), epoch, abort_flag, it);
+      }
+      if (dir > 0 && ok) {
+        const int pd = (dir - 1) * ncell;
+        ok = causal3_wait(done, pd + cell(C[0], C[1], C[2]), epoch, abort_flag, it);
+        for (int a = 0; a < 3 && ok; ++a)
+          for (int e = -1; e <= 1 && ok; e += 2) {
+            int c[3] = {C[0], C[1], C[2]};
+            c[a] += e;
+            if (c[a] >= 0 && c[a] < CN[a]) ok = causal3_wait(done, pd + cell(c[0], c[1], c[2]), epoch, abort_flag, it);
+          }
+      }
+      if (!ok) atomicOr(&A.counters[3], 1ull);
+      sh_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    const bool ok = sh_ok != 0;
+    // U is read and written device-coherently inside the sweep, so a value
+    // is visible everywhere once its store has completed: every wave waits
+    // for its stores (a full s_waitcnt), then, after the barrier, thread 0
+    // sets the flag (also device-coherent)
+    if (ok) causal3_cell<true>(A, U, W, dir, C);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0 && ok)
+      __hip_atomic_store(&done[dir * ncell + cell(C[0], C[1], C[2])], epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
