@@ -29,6 +29,7 @@ import math
 import numpy as np
 
 from . import fsm as _fsm  # the oracle FSM of Sec. 1.1
+from . import theta_damped as _theta_damped  # eq. thetaest
 
 
 def c_h(a: float, b: float, H: float) -> float:
@@ -129,3 +130,43 @@ class ModelStrip:
 
     def errors(self, Us):
         return [float(np.max(np.abs(U[1:, 1:] - self.uf[1:, 1:]))) for U in Us]
+
+    def run_estimate(self, kmax, theta0=0.1, omega=(1.0, 1.0, 1.0), gamma=0.75, delta=0.01, x0=0.9):
+        """The iteration with the weights of Sec. 4.2: theta^k_{i,j} from
+        eq. secthetaest, (u^{k-1} - u^{k-2}) over the omega-weighted mean of
+        the increments of C_H at the node, s = 0 being the current one
+        (C_H(U^k nbrs) - C_H(U^{k-1} nbrs)) and s = 1, 2 the two before,
+        then damped by eq. thetaest; theta0 where the history is too short
+        or the denominator is 0 (the reading of the DD solver).  Returns
+        the iterates U^0..U^kmax."""
+        def c_all(U):
+            C = np.full_like(U, np.nan)
+            for i in range(1, self.N + 1):
+                for j in range(1, self.M + 1):
+                    C[i, j] = self.ch(U, i, j)
+            return C
+
+        Us = [self.coarse_init()]
+        us, Cs = [], [c_all(Us[0])]
+        wsum = (omega[0] + omega[1]) + omega[2]
+        for _ in range(kmax):
+            Uo = Us[-1]
+            uo = self.fine(Uo)
+            us.append(uo)
+            Un = np.zeros_like(Uo)
+            Un[0, :] = self.uf[0, :]
+            Un[:, 0] = self.uf[:, 0]
+            for i in range(1, self.N + 1):
+                for j in range(1, self.M + 1):
+                    cnew, cold = self.ch(Un, i, j), self.ch(Uo, i, j)
+                    th = theta0
+                    if len(us) >= 2 and len(Cs) >= 3:
+                        num = us[-1][i, j] - us[-2][i, j]
+                        den = (omega[0] * (cnew - cold) + omega[1] * (Cs[-1][i, j] - Cs[-2][i, j])
+                               + omega[2] * (Cs[-2][i, j] - Cs[-3][i, j])) / wsum
+                        if den != 0.0 and math.isfinite(den) and math.isfinite(num):
+                            th = _theta_damped(num / den, gamma, delta, x0)
+                    Un[i, j] = th * (cnew - cold) + uo[i, j]
+            Us.append(Un)
+            Cs.append(c_all(Un))
+        return Us
