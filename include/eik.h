@@ -122,6 +122,23 @@ typedef struct {
 #define EIK_COARSE_GODUNOV 0
 #define EIK_COARSE_L1 1
 
+/* How eik_dd_solve (d = 2, one problem) issues the kernels of its DD
+ * iterations.  Either way it launches several iterations ahead of its check of
+ * the stopping rule (a launched-ahead iteration after the one that stopped
+ * returns at once and changes nothing), with the same kernels and results:
+ *   EIK_LAUNCH_STREAM  every kernel launched on the stream.
+ *   EIK_LAUNCH_GRAPH   a block of launched-ahead iterations is captured once
+ *                      into a HIP graph and replayed; the instantiated graphs
+ *                      are kept per device and reused by the next call with
+ *                      the same arguments and workspace (else captured again).
+ *                      The first block of a call, a shorter last block, the
+ *                      debug snapshots, EIK_THETA_ESTIMATE and
+ *                      eik_dd_solve_noalloc use stream launches.  ms_fine,
+ *                      ms_correct and ms_causal then cover the stream-launched
+ *                      iterations only. */
+#define EIK_LAUNCH_STREAM 0
+#define EIK_LAUNCH_GRAPH 1
+
 /* Options of the domain-decomposition iteration (Sec. 3.2). */
 typedef struct {
     int32_t S;          /* subdomain side in fine cells; (n[a]-1) % S == 0 */
@@ -140,6 +157,7 @@ typedef struct {
                                 * REFERENCE; the paper's values are 0.75, 0.01, 0.9, -, -, -, 0.001;
                                 * the omegas are not stated there) */
     int32_t coarse_solver;     /* EIK_COARSE_*; 0 = C_H */
+    int32_t launch_mode;       /* EIK_LAUNCH_*; 0 = stream launches */
 } eik_dd_opts;
 
 /* Host-side statistics.  residual_history (host, may be NULL) receives

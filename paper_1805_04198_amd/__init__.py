@@ -56,12 +56,14 @@ class DDOpts(ctypes.Structure):
                 ("theta_mode", ctypes.c_int32), ("U_init", ctypes.c_void_p),
                 ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug)),
                 ("theta_ref", ctypes.c_void_p), ("theta_params", ctypes.c_double * 7),
-                ("coarse_solver", ctypes.c_int32)]
+                ("coarse_solver", ctypes.c_int32), ("launch_mode", ctypes.c_int32)]
 
 
 THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
 # coarse solver of Steps 1 and 4: C_H, or the homogenised solver of Sec. 5.3
 COARSE_SOLVERS = {"godunov": 0, "l1": 1}
+# how the DD iterations' kernels are issued: stream launches or HIP graphs
+LAUNCH_MODES = {"stream": 0, "graph": 1}
 # gamma, delta, x0 of eq. thetaest (the paper's values), equal omegas for
 # eq. secthetaest (not stated in the paper), margin 0.001 of the reference
 # weight
@@ -188,14 +190,18 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
              max_iter: Optional[int] = None, max_fine_sweeps: int = 256,
              max_coarse_sweeps: int = 32, U_init=None, W_init=None, debug: bool = False,
              history_cap: int = 4096, theta_mode: str = "constant", theta_params=THETA_PARAMS,
-             theta_ref=None, coarse_solver: str = "godunov", noalloc: bool = False):
+             theta_ref=None, coarse_solver: str = "godunov", noalloc: bool = False,
+             launch: str = "stream"):
     """eik_dd_solve: the two-scale DD iteration (Sec. 3.2).  Returns a dict
     with the patched fine solution u, coarse values U (NaN off the skeleton),
     coarse wind codes W, counters and timings; with debug=True also the last
     iteration's u^k, w^k and pre-causal-sweep U.  coarse_solver: "godunov"
     (C_H) or "l1" (the homogenised solver of the squares medium, Sec. 5.3).
     noalloc=True calls eik_dd_solve_noalloc (the library's fixed scratch
-    array instead of its workspace; timings are 0)."""
+    array instead of its workspace; timings are 0).  launch: "stream" or
+    "graph" (2D: whole blocks of launched-ahead iterations replayed from a
+    HIP graph; same kernels and results, phase timings cover only the
+    stream-launched iterations)."""
     torch = _torch()
     L = load_library()
     r = r.contiguous()
@@ -211,6 +217,7 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
     o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(max_iter), int(max_fine_sweeps), int(max_coarse_sweeps)
     o.theta_mode = THETA_MODES[theta_mode]
     o.coarse_solver = COARSE_SOLVERS[coarse_solver]
+    o.launch_mode = LAUNCH_MODES[launch]
     for q, v in enumerate(theta_params):
         o.theta_params[q] = float(v)
     if theta_ref is not None:

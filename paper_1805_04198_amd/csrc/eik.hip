@@ -135,6 +135,18 @@ struct Events {
     if (es_ != EIK_OK) return es_;   \
   } while (0)
 
+// Instantiated graphs of the 2D DD iteration block (EIK_LAUNCH_GRAPH), per
+// device and block parity (the residual slots alternate between blocks),
+// with the bytes of everything the captured launches depend on; guarded by
+// the device's workspace lock.  Captured on a stream of their own (default
+// priority) and kept until the process ends.
+struct DDGraph {
+  std::vector<unsigned char> key;
+  hipGraphExec_t exec = nullptr;
+};
+DDGraph g_ddgraph[kMaxDevices][2];
+hipStream_t g_capture_stream[kMaxDevices];
+
 // carve aligned sub-buffers out of the workspace
 struct Carver {
   char* base;
@@ -299,6 +311,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if (e != EIK_OK) return e;
   Carver cv{(char*)wsv};
   eik::DD2<T> A;
+  std::memset(&A, 0, sizeof A);  // defined padding: the graph cache compares its bytes
   A.n0 = n0; A.n1 = n1; A.S = S; A.M = M; A.P0 = P0; A.P1 = P1; A.NI = NI; A.NJ = NJ;
   A.hT = (T)G->h;
   A.HT = (T)((double)M * G->h);
@@ -414,36 +427,81 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.tol = o->tol;
   Events<kLag * 4> evi;  // [iteration of the block][4]
   EVCHK(evi.init(!noalloc));
+  // one DD iteration's launches on stream ls (timed: with the phase events)
+  const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
+  auto iteration = [&](int k, int E, bool timed, hipStream_t ls) -> eik_status {
+    A.res_out = resid + k % kSlots;
+    A.res_prev = k > 0 ? resid + (k - 1) % kSlots : nullptr;
+    if (timed) EVCHK(evi.rec(E + 0, ls));
+    hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, ls, A);
+    if (timed) EVCHK(evi.rec(E + 1, ls));
+    if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, ls, A);
+    if (tmode == EIK_THETA_ESTIMATE) {
+      // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
+      A.ck_out = hist_c[k % 3];
+      A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
+      A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
+      A.ukm1 = k >= 1 ? hist_u : nullptr;
+    }
+    hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, ls, A);
+    if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, ls));
+    if (timed) EVCHK(evi.rec(E + 2, ls));
+    if (dbg && dbg->U_pre_causal)
+      HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, ls));
+    causal_sweep(A, A.Un, A.Wn, ls, lds_cb, 1);  // also the residual (resid slot, zeroed by k_tile)
+    HIPCHK(hipGetLastError());
+    if (timed) EVCHK(evi.rec(E + 3, ls));
+    std::swap(A.U, A.Un);
+    std::swap(A.W, A.Wn);
+    return EIK_OK;
+  };
+  // EIK_LAUNCH_GRAPH: whole blocks after the first one replay a graph of the
+  // block's launches (A is the same at the start of every block: an even
+  // number of swaps; the residual slots depend on the block's parity)
+  const bool use_graph = o->launch_mode == EIK_LAUNCH_GRAPH && !noalloc && !dbg && tmode != EIK_THETA_ESTIMATE;
+  auto graph_block = [&](int k0) -> eik_status {
+    DDGraph& g = g_ddgraph[dev][(k0 / kLag) & 1];
+    const int shape[6] = {ntile, nlat, (int)lds_tile, (int)lds_lat, (int)lds_cb, (k0 / kLag) & 1};
+    std::vector<unsigned char> key(sizeof A + sizeof shape + sizeof resid);
+    std::memcpy(key.data(), &A, sizeof A);
+    std::memcpy(key.data() + sizeof A, shape, sizeof shape);
+    std::memcpy(key.data() + sizeof A + sizeof shape, &resid, sizeof resid);
+    if (g.exec == nullptr || g.key != key) {
+      if (g.exec) {
+        HIPCHK(hipGraphExecDestroy(g.exec));
+        g.exec = nullptr;
+      }
+      if (!g_capture_stream[dev]) HIPCHK(hipStreamCreateWithFlags(&g_capture_stream[dev], hipStreamNonBlocking));
+      hipStream_t cs = g_capture_stream[dev];
+      HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      eik_status ce = EIK_OK;
+      for (int k = k0; k < k0 + kLag && ce == EIK_OK; ++k) ce = iteration(k, 0, false, cs);
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(cs, &graph);
+      if (ce != EIK_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return ce;
+      }
+      HIPCHK(ee);
+      const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(ie);
+      g.key = key;
+    } else {
+      // the host-side effect of the block's iterations: none (even swaps)
+    }
+    HIPCHK(hipGraphLaunch(g.exec, s));
+    return EIK_OK;
+  };
   int launched = 0;
   bool done = false;
   while (!done && launched < o->max_iter) {
     const int k0 = launched, k1 = std::min(o->max_iter, k0 + lag);
-    for (int k = k0; k < k1; ++k) {
-      const int E = (k - k0) * 4;
-      A.res_out = resid + k % kSlots;
-      A.res_prev = k > 0 ? resid + (k - 1) % kSlots : nullptr;
-      EVCHK(evi.rec(E + 0, s));
-      hipLaunchKernelGGL(eik::k_tile<T>, dim3(ntile), dim3(eik::kBlock), lds_tile, s, A);
-      EVCHK(evi.rec(E + 1, s));
-      const int64_t nrec = (int64_t)(P0 - 1) * n1 + (int64_t)(P1 - 1) * n0;
-      if (nrec > 0) hipLaunchKernelGGL(eik::k_reconcile<T>, dim3(nblocks(nrec, bs)), dim3(bs), 0, s, A);
-      if (tmode == EIK_THETA_ESTIMATE) {
-        // C^k goes to hist_c[k % 3]; the other two hold C^{k-1}, C^{k-2}
-        A.ck_out = hist_c[k % 3];
-        A.ckm1 = k >= 1 ? hist_c[(k + 2) % 3] : nullptr;
-        A.ckm2 = k >= 2 ? hist_c[(k + 1) % 3] : nullptr;
-        A.ukm1 = k >= 1 ? hist_u : nullptr;
-      }
-      hipLaunchKernelGGL(eik::k_lattice_correct<T>, dim3(nlat), dim3(eik::kBlock), lds_lat, s, A);
-      if (tmode == EIK_THETA_ESTIMATE) HIPCHK(hipMemcpyAsync(hist_u, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
-      EVCHK(evi.rec(E + 2, s));
-      if (dbg && dbg->U_pre_causal)
-        HIPCHK(hipMemcpyAsync(dbg->U_pre_causal, A.Un, N * szT, hipMemcpyDeviceToDevice, s));
-      causal_sweep(A, A.Un, A.Wn, s, lds_cb, 1);  // also the residual (resid slot, zeroed by k_tile)
-      HIPCHK(hipGetLastError());
-      EVCHK(evi.rec(E + 3, s));
-      std::swap(A.U, A.Un);
-      std::swap(A.W, A.Wn);
+    const bool timed = !(use_graph && k0 > 0 && k1 - k0 == kLag);
+    if (timed) {
+      for (int k = k0; k < k1; ++k) EVCHK(iteration(k, (k - k0) * 4, true, s));
+    } else {
+      EVCHK(graph_block(k0));
     }
     launched = k1;
     HIPCHK(hipMemcpyAsync(host, resid, kSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
@@ -452,9 +510,11 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     for (int k = k0; k < k1; ++k) {
       float a = 0.f, b = 0.f, c = 0.f;
       const int E = (k - k0) * 4;
-      EVCHK(evi.ms(E + 0, E + 1, &a));
-      EVCHK(evi.ms(E + 1, E + 2, &b));
-      EVCHK(evi.ms(E + 2, E + 3, &c));
+      if (timed) {
+        EVCHK(evi.ms(E + 0, E + 1, &a));
+        EVCHK(evi.ms(E + 1, E + 2, &b));
+        EVCHK(evi.ms(E + 2, E + 3, &c));
+      }
       ms_fine += a;
       ms_correct += b;
       ms_causal += c;
