@@ -249,6 +249,7 @@ struct PipeSync {
   int ch[2];       // whether the last sweep of the leader [0] / follower [1] changed a node
   int ftmax;       // leader: the follower's last step that reaches a node next to its changes
   Range2 lrng;     // follower: the next leader sweep's steps that reach the nodes next to its changes
+  int smax;        // leader: sweeps that still run once a cycle was found (else no limit)
 };
 
 __device__ __forceinline__ void pipe_init(PipeSync& ps) {
@@ -256,7 +257,18 @@ __device__ __forceinline__ void pipe_init(PipeSync& ps) {
   ps.fin = 0;
   ps.err = 0;
   ps.ch[0] = ps.ch[1] = 0;
+  ps.smax = 0x7fffffff;
 }
+
+// Rules whose sweeps need not settle (Step 4 assigns, it takes no minimum)
+// may provide cycle_check(s): called by the leader between sweeps s-1 and s
+// (s a multiple of 4, both waves off the box), it returns p > 0 when the
+// values equal those after sweep s-1-p (p a multiple of 4: the same
+// directions follow, so the run repeats with period p from there on).
+template <typename Rule>
+struct HasCycleCheck {
+  static constexpr bool value = false;
+};
 __device__ __forceinline__ int lds_load_acq(int* p) {
   return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
 }
@@ -612,9 +624,15 @@ __device__ __forceinline__ bool sweep_any(Rule& R, int L0, int L1, int SP, int d
 // sweeps' values, winds and sweep count.  Runs on waves 0 and 1 of the block
 // (PipeSync, initialised by pipe_init and a block barrier); returns the
 // number of sweeps in wave 0.
+//
+// With a rule that has cycle_check, a run found periodic (period p from
+// sweep s on) runs only the (max_sweeps - s) mod p sweeps that decide the
+// state the cap would leave, and still counts max_sweeps: the values equal
+// those of the whole run to the cap.
 template <bool EXTRA, typename Rule>
 __device__ __forceinline__ int fsm_leader(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
   Range2 P{0, L0 + L1 - 2 + (EXTRA ? 1 : 0)};
+  int smax = max_sweeps;
   for (int s = 0;; s += 2) {
     if (s > 0) {
       // the follower's sweep s-1 has ended: it gives this sweep's steps
@@ -629,10 +647,21 @@ __device__ __forceinline__ int fsm_leader(Rule& R, int L0, int L1, int SP, int m
       P.t0 = __builtin_amdgcn_readfirstlane(ps->lrng.t0);
       P.tmax = __builtin_amdgcn_readfirstlane(ps->lrng.tmax);
     }
-    if (s >= max_sweeps) return max_sweeps;
+    if (s >= smax) return max_sweeps;
+    if constexpr (HasCycleCheck<Rule>::value) {
+      if ((s & 3) == 0 && smax == max_sweeps) {
+        const int p = __builtin_amdgcn_readfirstlane(R.cycle_check(s));
+        if (p > 0) {
+          smax = s + (max_sweeps - s) % p;
+          lds_store_rel(&ps->smax, smax);
+          if (s >= smax) return max_sweeps;
+        }
+      }
+    }
     const bool ch = (s & 2) ? sweep_lead<1, -1, EXTRA>(R, L0, L1, SP, P, ps, s)
                             : sweep_lead<-1, -1, EXTRA>(R, L0, L1, SP, P, ps, s);
-    if (!ch || s + 1 >= max_sweeps) return s + 1;
+    if (!ch) return s + 1;
+    if (s + 1 >= smax) return max_sweeps;
   }
 }
 
@@ -640,14 +669,18 @@ template <bool EXTRA, typename Rule>
 __device__ __forceinline__ void fsm_follower(Rule& R, int L0, int L1, int SP, int max_sweeps, PipeSync* ps) {
   const int lag = follow_lag(L1, EXTRA);
   for (int s = 1; s < max_sweeps; s += 2) {
-    // the leader has begun sweep s-1 ...
+    // the leader has begun sweep s-1 (or has ended the run before it, having
+    // found a cycle) ...
     for (int n = 0; lds_load_acq(&ps->lsweep) < s - 1; ++n) {
+      if (HasCycleCheck<Rule>::value && s - 1 >= lds_load_acq(&ps->smax)) return;
       if (n >= kPipeSpin) {
         if ((threadIdx.x & (kWave - 1)) == 0) ps->err = 1;
         return;
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    // ... and sweep s is within the run (the end is set before sweep s-1)
+    if (HasCycleCheck<Rule>::value && s >= lds_load_acq(&ps->smax)) return;
     // ... and has changed a node and run far enough past this sweep's first
     // step, or has ended
     int t0 = 0, tmax = 0x7fffffff, allowed = 0;
@@ -994,6 +1027,27 @@ struct CorrectRuleF32 {
     *dst = v;
     return v;
   }
+  // The values after s-4 and s-8 sweeps are kept in pad0 and pad1 of every
+  // record (bit patterns; every record of the box, its ring and the unused
+  // part of the fixed geometry, which never change).  Kept from s = 8 on.
+  __device__ int cycle_check(int s) const {
+    if (s < 8) return 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    bool d4 = false, d8 = false;
+    for (int x = lane; x < kCntf; x += kWave) {
+      const uint4 q = *reinterpret_cast<const uint4*>(&rec[x]);  // u, m, pad0, pad1
+      d4 = d4 || q.x != q.z;
+      d8 = d8 || q.x != q.w;
+      *reinterpret_cast<uint2*>(&rec[x].pad0) = make_uint2(q.x, q.z);
+    }
+    if (s >= 12 && !__any(d4)) return 4;
+    if (s >= 16 && !__any(d8)) return 8;
+    return 0;
+  }
+};
+template <>
+struct HasCycleCheck<CorrectRuleF32> {
+  static constexpr bool value = true;
 };
 
 // ---------------------------------------------------------------------------
