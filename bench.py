@@ -42,6 +42,12 @@ OPS_PER_CORRECTION = 18
 # = 39.3 T lane-ops/s (the published 157.3 TFLOP/s fp32 counts an FMA as two
 # flops and packed fp32 as two lanes; 78.6 TFLOP/s fp64 counts the FMA).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Instructions on the dependency path that carries a lane's value from one
+# anti-diagonal step to the next, counted in this build's gfx950 ISA of the
+# fp32 step loops (DPP receive, neighbour minimum, local solve with the
+# correctly rounded square root, the minimum / weighted assignment, the
+# lane's carried value); each costs at least one dependent-issue latency.
+CHAIN_INSTS = {"k_tile": 21, "k_lattice_correct": 24}
 # 3D local solve: 3 neighbour minima (6 compares), a 3-element sort (3
 # compares), the one-, two- and three-sided roots (~12 ops and 2 sqrt, one
 # division), the FSM minimum compare: about 25 algorithmic ops per update
@@ -91,6 +97,27 @@ def measured_traffic(kernel_prefix, dtype):
                 return None
             return {"bytes": int(kv["read_bytes"]) + int(kv["write_bytes"]),
                     "read_bytes": int(kv["read_bytes"]), "write_bytes": int(kv["write_bytes"])}
+    return None
+
+
+def measured_pmc(kernel_prefix, dtype):
+    """Per-dispatch SQ counters of a kernel from the committed rocprofv3
+    summary (profiles/pmc_config2_<dtype>.md), or None when there is none or
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_config2_{dtype}.md")
+    if not os.path.exists(path):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1805_04198_amd", "csrc", f), "rb").read()
+                   for f in ("kernels2d.hpp", "eik.hip"))
+    h = hashlib.sha256(src).hexdigest()[:16]
+    for line in open(path):
+        parts = line.split()
+        if len(parts) > 2 and parts[0] == "pmc" and parts[1].startswith(kernel_prefix):
+            kv = dict(x.split("=") for x in parts[2:])
+            if kv.pop("source_sha256_16") != h:
+                return None
+            return {k: float(v) for k, v in kv.items()}
     return None
 
 
@@ -485,22 +512,46 @@ def main():
     init = E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=a.theta, tol=tol, max_iter=0)
     corr_updates = sum(o["coarse_updates"] - init["coarse_updates"] for o in tims)
 
-    def kernel_line(name, sym, updates, ms, ops):
+    ceil = measured_ceilings()
+
+    def kernel_line(name, sym, updates, ms, ops, q):
         upl = updates / iters
         msl = ms / iters
         ach = upl * ops / (msl * 1e-3) / 1e12
-        tr = measured_traffic(f"eik::{sym}<{'float' if a.dtype == 'f32' else 'double'}>", a.dtype)
-        return {"bound": "alu", "kernel": name, "achieved": ach, "peak": ALU_PEAK_TOPS,
+        kname = f"eik::{sym}<{'float' if a.dtype == 'f32' else 'double'}>"
+        tr = measured_traffic(kname, a.dtype)
+        line = {"bound": "alu", "kernel": name, "achieved": ach, "peak": ALU_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": ach / ALU_PEAK_TOPS,
                 "traffic": None if tr is None else tr["bytes"],
                 "traffic_detail": tr,
                 "per_launch": {"updates": upl, "ms": msl, "ops_per_update": ops}}
+        # the dependent-step time of the boxes' leading waves (clock64 ticks
+        # per anti-diagonal step, measured in the kernels of these solves)
+        # against the latency of the step's dependency path
+        steps = sum(o["lead_steps"][q] for o in tims)
+        ticks = sum(o["lead_ticks"][q] for o in tims)
+        if steps > 0:
+            cps = ticks / steps
+            line["cycles_per_step"] = cps
+            if ceil and a.dtype == "f32":
+                chain = CHAIN_INSTS[sym] * ceil["dependent_add_cycles"]
+                line["chain_cycles_per_step"] = chain
+                line["critical_path_frac"] = chain / cps
+        pmc = measured_pmc(kname, a.dtype)
+        line["pmc"] = pmc
+        if pmc is not None and pmc.get("GRBM_GUI_ACTIVE"):
+            # AMD's VALU-busy measure: VALU issue cycles (4 per wave64
+            # instruction) over the dispatch's cycles on all 1024 SIMDs
+            line["valu_util"] = pmc["SQ_ACTIVE_INST_VALU"] * 4 / (1024 * pmc["GRBM_GUI_ACTIVE"])
+            if "lds_bytes" in pmc:
+                line["lds_bytes_per_s"] = pmc["lds_bytes"] / (msl * 1e-3)
+        return line
 
     k_fine = kernel_line("k_tile (Step 3 subdomain FSM)", "k_tile", fine_t,
-                         sum(o["ms_fine"] for o in tims), OPS_PER_UPDATE)
+                         sum(o["ms_fine"] for o in tims), OPS_PER_UPDATE, 0)
     k_corr = kernel_line("k_lattice_correct (Step 4 weighted correction sweeps)",
                          "k_lattice_correct", corr_updates,
-                         sum(o["ms_correct"] for o in tims), OPS_PER_CORRECTION)
+                         sum(o["ms_correct"] for o in tims), OPS_PER_CORRECTION, 1)
     dominant, other = (k_corr, k_fine) if k_corr["per_launch"]["ms"] > k_fine["per_launch"]["ms"] \
         else (k_fine, k_corr)
 
@@ -549,7 +600,7 @@ def main():
         "roofline": dominant,
         "roofline_secondary": other,
     }
-    line["measured_ceilings"] = measured_ceilings()
+    line["measured_ceilings"] = ceil
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.theta, tol, dt)
         # the oracle's own u^f (fp64, serial), the error reference of the metric

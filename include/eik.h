@@ -176,6 +176,13 @@ typedef struct {
     float ms_coarse;         /* device time in everything else (Steps 1, 2, 4, causal sweeps, residuals) */
     float ms_correct;        /* device time of the Step 4 lattice sweeps (incl. the reconciliation) */
     float ms_causal;         /* device time of the causal sweeps after Step 4 and the residuals */
+    /* eik_dd_solve with d = 2 (eik_dd_solve_noalloc too) writes these; other
+     * calls leave them as they are.  The leading wave of every subdomain box
+     * [0] (Step 3) and lattice box [1] (Step 4): anti-diagonal steps it ran
+     * and clock64 ticks it spent in them, summed over boxes and iterations
+     * (ticks / steps = the time of one dependent step). */
+    int64_t lead_steps[2];
+    int64_t lead_ticks[2];
 } eik_stats;
 
 /* eik_solve -- the fast sweeping method on the whole fine grid (Sec. 1.1:

@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("residual_history", ctypes.POINTER(ctypes.c_double)),
                 ("history_cap", ctypes.c_int32), ("ms_total", ctypes.c_float),
                 ("ms_fine", ctypes.c_float), ("ms_coarse", ctypes.c_float),
-                ("ms_correct", ctypes.c_float), ("ms_causal", ctypes.c_float)]
+                ("ms_correct", ctypes.c_float), ("ms_causal", ctypes.c_float),
+                ("lead_steps", ctypes.c_int64 * 2), ("lead_ticks", ctypes.c_int64 * 2)]
 
 
 _lib = None
@@ -247,7 +248,9 @@ def dd_solve(r, gamma_idx, gamma_val, h, S: int, M: int, theta: float = 0.5, tol
            "coarse_updates": int(st.coarse_updates), "residuals": list(hist[: min(it, history_cap)]),
            "ms_total": float(st.ms_total), "ms_fine": float(st.ms_fine),
            "ms_coarse": float(st.ms_coarse), "ms_correct": float(st.ms_correct),
-           "ms_causal": float(st.ms_causal)}
+           "ms_causal": float(st.ms_causal),
+           "lead_steps": [int(st.lead_steps[0]), int(st.lead_steps[1])],
+           "lead_ticks": [int(st.lead_ticks[0]), int(st.lead_ticks[1])]}
     if debug:
         out.update(dbg_t)
     return out

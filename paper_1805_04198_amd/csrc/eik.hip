@@ -345,7 +345,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.hseg_l = cv.take<uint8_t>(std::max(nH, 1));
   A.vseg_p = cv.take<T>(std::max(nV, 1));
   A.vseg_l = cv.take<uint8_t>(std::max(nV, 1));
-  A.counters = cv.take<unsigned long long>(4);
+  A.counters = cv.take<unsigned long long>(8);
+  A.sweep_prof = A.counters + 4;
   unsigned int* dflag = cv.take<unsigned int>(4);
   A.u_out = as<T>(u_outv);
   A.theta_mode = tmode;
@@ -377,7 +378,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
 
   const T nanT = (T)NAN;
   const int bs = 256;
-  HIPCHK(hipMemsetAsync(A.counters, 0, 4 * sizeof(unsigned long long), s));
+  HIPCHK(hipMemsetAsync(A.counters, 0, 8 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, nanT, N);
   if (gam->count > 0)
     hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
@@ -541,7 +542,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   if (W_out) HIPCHK(hipMemcpyAsync(W_out, A.W, N, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->uk) HIPCHK(hipMemcpyAsync(dbg->uk, A.uk, N * szT, hipMemcpyDeviceToDevice, s));
   if (dbg && dbg->wk) HIPCHK(hipMemcpyAsync(dbg->wk, A.wk, N, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipMemcpyAsync(host, A.counters, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(host, A.counters, 8 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
   EVCHK(ev.rec(1, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
@@ -559,6 +560,10 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
     st->ms_coarse = tot - ms_fine;
     st->ms_correct = ms_correct;
     st->ms_causal = ms_causal;
+    for (int q = 0; q < 2; ++q) {
+      st->lead_steps[q] = (int64_t)host[4 + 2 * q];
+      st->lead_ticks[q] = (int64_t)host[5 + 2 * q];
+    }
   }
   if (host[3]) return fail(EIK_ERR_INTERNAL, "a wait between the two waves of a box sweep gave up");
   if (o->max_iter > 0 && !conv) return fail(EIK_ERR_NOCONV, "no convergence in %d iterations (residual %g)", it, last);
@@ -732,6 +737,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.vseg_p = cv.take<T>(std::max(q.nV, 1));
     A.vseg_l = cv.take<uint8_t>(std::max(q.nV, 1));
     A.counters = d_cnt + 4 * (size_t)p;
+    A.sweep_prof = nullptr;
     A.u_out = as<T>(u_out[p]);
     A.theta_mode = q.tmode;
     A.coarse_homog = op->coarse_solver;

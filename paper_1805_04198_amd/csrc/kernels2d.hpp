@@ -180,6 +180,20 @@ __device__ __forceinline__ double dpp_ror1(double v) {
   const int hi = dpp_ror1((int)(b >> 32));
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
+// Lane i receives lane i-1's value, lane 0 receives fill: DPP wave_shr:1
+// (lane 0 has no source lane and keeps the old operand).
+__device__ __forceinline__ int dpp_shr1(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float dpp_shr1(float v, float fill) {
+  return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, v), __builtin_bit_cast(int, fill)));
+}
+__device__ __forceinline__ double dpp_shr1(double v, double fill) {
+  const long long b = __builtin_bit_cast(long long, v), f = __builtin_bit_cast(long long, fill);
+  const int lo = dpp_shr1((int)(b & 0xffffffffll), (int)(f & 0xffffffffll));
+  const int hi = dpp_shr1((int)(b >> 32), (int)(f >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Smaller neighbour per axis with the flow-direction wind sign of its side
 // (ties take the plus side, as the strict '<' of the paper's algorithms).
@@ -250,6 +264,8 @@ struct PipeSync {
   int ftmax;       // leader: the follower's last step that reaches a node next to its changes
   Range2 lrng;     // follower: the next leader sweep's steps that reach the nodes next to its changes
   int smax;        // leader: sweeps that still run once a cycle was found (else no limit)
+  int lsteps;      // leader: anti-diagonal steps run, and the clock64 ticks spent in them
+  long long lcyc;
 };
 
 __device__ __forceinline__ void pipe_init(PipeSync& ps) {
@@ -258,6 +274,8 @@ __device__ __forceinline__ void pipe_init(PipeSync& ps) {
   ps.err = 0;
   ps.ch[0] = ps.ch[1] = 0;
   ps.smax = 0x7fffffff;
+  ps.lsteps = 0;
+  ps.lcyc = 0;
 }
 
 // Rules whose sweeps need not settle (Step 4 assigns, it takes no minimum)
@@ -284,13 +302,12 @@ __device__ __forceinline__ void lds_store_rel(int* p, int v) {
 // order, which the compiler's own partial waits rely on), so a store issued
 // after the wave's earlier LDS accesses is performed after them, and a load
 // issued after a load is performed after it.  Only the compiler must be kept
-// from moving memory accesses across these, which saves the full LDS wait of
-// a release or acquire on every step pair.
+// from moving memory accesses across these: release / acquire at wavefront
+// scope order them for the compiler and need no wait instruction, which
+// saves the full LDS wait of a workgroup-scope release or acquire on every
+// step pair.
 __device__ __forceinline__ int lds_peek(int* p) {
-  __asm__ __volatile__("" ::: "memory");
-  const int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __asm__ __volatile__("" ::: "memory");
-  return v;
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 // The first step of the follower's sweep that reaches a node next to a change
 // of the leader's sweep (key as in PipeSync), and the step count the leader
@@ -322,6 +339,7 @@ __device__ __forceinline__ int pipe_wait(PipeSync* ps, int need, int& tmax) {
 struct StepSpan {
   int cmin = 0x7fffffff, cmax = -1;
   bool rowB = false;
+  int steps = 0;  // steps run (set at the end of the sweep)
 };
 
 // One directional Gauss-Seidel sweep (signs SX, SY) over an L0 x L1 box in
@@ -420,14 +438,21 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
     pn = R.template load<SX, SY>(x1);
     // keep the loads at the top of the step, a whole step ahead of their use
     __builtin_amdgcn_sched_barrier(0);
-    const T ex = (EXTRA && PH != 1 && lane == kWave - 1) ? cur_prev : cur;
-    const T from_prev_row = dpp_ror1(ex);
-    const bool top = PH == 2 ? false : PH == 1 ? lane == 0 : ytop;
     T yprev, xprev;
-    if (Rule::kHalo) {
+    if (!Rule::kHalo && (PH == 1 || !EXTRA)) {
+      // lane 0 holds the first row (no upwind-y neighbour: the halo, +inf)
+      yprev = dpp_shr1(cur, inf);
+      xprev = cur;
+    } else if (Rule::kHalo) {
+      const T ex = (EXTRA && PH != 1 && lane == kWave - 1) ? cur_prev : cur;
+      const T from_prev_row = dpp_ror1(ex);
+      const bool top = PH == 2 ? false : PH == 1 ? lane == 0 : ytop;
       yprev = top ? p.hy : from_prev_row;
       xprev = (iq == 0) ? p.hx : cur;
     } else {
+      const T ex = (EXTRA && PH != 1 && lane == kWave - 1) ? cur_prev : cur;
+      const T from_prev_row = dpp_ror1(ex);
+      const bool top = PH == 2 ? false : PH == 1 ? lane == 0 : ytop;
       // the halo is +inf: the first row has no upwind-y neighbour, and a
       // lane's cur is +inf until its row starts (the delayed row restarts)
       yprev = top ? inf : from_prev_row;
@@ -448,50 +473,65 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   using Any = std::integral_constant<int, 0>;
   using RowA = std::integral_constant<int, 1>;
   using RowB = std::integral_constant<int, 2>;
-  // the step pair (t, t+1): with EXTRA, pairs wholly before step kWave or
-  // wholly after step kWave + 1 take the lean steps (t only grows, so the
-  // state the full steps keep is not needed after the first lean row-64 pair)
-  auto pair = [&](int t) {
-    if (EXTRA && t + 1 < kWave) {
-      step(RowA{}, t, pa, pb);
-      step(RowA{}, t + 1, pb, pa);
-    } else if (EXTRA && t > kWave + 1) {
-      step(RowB{}, t, pa, pb);
-      step(RowB{}, t + 1, pb, pa);
-    } else {
-      step(Any{}, t, pa, pb);
-      step(Any{}, t + 1, pb, pa);
-    }
-  };
-  // unrolled by two so that the prefetch buffers alternate without copies;
-  // a trailing step past the end is idle in every lane.  Up to tmax the
-  // steps run unconditionally; after that the sweep ends with the first step
-  // pair that changes nothing.
+  // Step pairs (t, t+1) from t while t < tend: pre(t) before a pair (true:
+  // leave without running it), post() after it (true: leave).  With EXTRA,
+  // pairs wholly before step kWave and wholly after step kWave + 1 take the
+  // lean steps (t only grows, so the state the full steps keep is not needed
+  // after the first lean row-64 pair).  Each phase is a loop of its own, so
+  // that the loop bodies carry no per-pair dispatch.  Unrolled by two so that
+  // the prefetch buffers alternate without copies; a trailing step past the
+  // end is idle in every lane.
   int t = t0;
-  if (PIPE == 2) {
+  auto pairs = [&](int tend, auto&& pre, auto&& post) -> bool {
+    auto seg = [&](auto ph, int e) -> bool {
+      for (; t < e; t += 2) {
+        if (pre(t)) return true;
+        step(ph, t, pa, pb);
+        step(ph, t + 1, pb, pa);
+        if (post()) {
+          t += 2;
+          return true;
+        }
+      }
+      return false;
+    };
+    if (EXTRA) {
+      if (t < kWave - 1 && seg(RowA{}, min(tend, kWave - 1))) return true;
+      if (t < kWave + 2 && seg(Any{}, min(tend, kWave + 2))) return true;
+      return seg(RowB{}, tend);
+    }
+    return seg(Any{}, tend);
+  };
+  auto no_pre = [](int) { return false; };
+  if (PIPE == 2 && allowed < kPipeDone) {
     // while the leader runs: every pair waits until the leader is far enough
     // ahead (the progress for the next pair is read during this one, its wait
-    // merges with the steps' own); tmax arrives when the leader ends
-    const int lag = follow_lag(L1, EXTRA);
-    while (allowed < kPipeDone && t < nsteps) {
-      if (t + lag > allowed) {
-        allowed = pipe_wait(ps, t + lag, tmax);
-        if (allowed >= kPipeDone) break;
-      }
-      const int seen = lds_peek(&ps->kp[0].y);
-      pair(t);
-      t += 2;
-      const int seen_u = __builtin_amdgcn_readfirstlane(seen);
-      if (seen_u >= kPipeDone) {
-        tmax = __builtin_amdgcn_readfirstlane(ps->ftmax);
-        allowed = 0x7fffffff;
-      } else if (seen_u > allowed) {
-        allowed = seen_u;
-      }
-    }
-    // then as a lone sweep (below).  Pairs this phase ran past tmax without
+    // merges with the steps' own); tmax arrives when the leader ends.  Then
+    // as a lone sweep (below).  Pairs this phase ran past tmax without
     // checking for a change are harmless: after a pair past tmax that changes
     // nothing, no later step can change anything either.
+    const int lag = follow_lag(L1, EXTRA);
+    int seen = 0;
+    pairs(
+        nsteps,
+        [&](int tt) {
+          if (tt + lag > allowed) {
+            allowed = pipe_wait(ps, tt + lag, tmax);
+            if (allowed >= kPipeDone) return true;
+          }
+          seen = lds_peek(&ps->kp[0].y);
+          return false;
+        },
+        [&]() {
+          const int seen_u = __builtin_amdgcn_readfirstlane(seen);
+          if (seen_u >= kPipeDone) {
+            tmax = __builtin_amdgcn_readfirstlane(ps->ftmax);
+            allowed = 0x7fffffff;
+            return true;
+          }
+          if (seen_u > allowed) allowed = seen_u;
+          return false;
+        });
   }
   // leader: the key of this lane's changes (lane 0 also holds row 64: a
   // smaller key than its own only widens the follower's sweep; no change
@@ -500,20 +540,24 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   int2* const kp_lane = PIPE == 1 ? &ps->kp[lane] : nullptr;
   auto publish = [&](int done) {
     const int k = span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane);
-    __asm__ __volatile__("" ::: "memory");
-    *kp_lane = make_int2(k, done);
-    __asm__ __volatile__("" ::: "memory");
+    const unsigned long long word = ((unsigned long long)(unsigned)done << 32) | (unsigned)k;  // int2{k, done}
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(kp_lane), word, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_WAVEFRONT);
   };
-  for (; t + 1 < tmax && t < nsteps; t += 2) {
-    pair(t);
+  // up to tmax the steps run unconditionally; after that the sweep ends with
+  // the first step pair that changes nothing
+  pairs(min(tmax - 1, nsteps), no_pre, [&]() {
     if (PIPE == 1) publish(t + 2);
-  }
-  for (; t < nsteps; t += 2) {
+    return false;
+  });
+  recent = 0;
+  pairs(nsteps, no_pre, [&]() {
+    if (PIPE == 1) publish(t + 2);
+    if (recent == 0) return true;
     recent = 0;
-    pair(t);
-    if (PIPE == 1) publish(t + 2);
-    if (recent == 0) break;
-  }
+    return false;
+  });
+  span.steps = t - t0;
   return span.cmax >= 0;  // a change has a column >= 0
 }
 
@@ -562,8 +606,18 @@ __device__ __forceinline__ bool sweep_lead(Rule& R, int L0, int L1, int SP, cons
   ps->kp[lane] = make_int2(0x7fffffff, t0);  // steps before t0 change nothing
   lds_store_rel(&ps->lsweep, s);
   StepSpan sp;
+  // the clock read is a scalar memory operation, which completes out of
+  // order: take its value before the sweep, so that the sweep's LDS waits
+  // need not wait for it
+  long long c0 = clock64();
+  __asm__ __volatile__("" : "+s"(c0));
   const bool lane_ch = sweep_dir<SX, SY, EXTRA, 1>(R, L0, L1, SP, t0, tmax, sp, ps);
+  const long long c1 = clock64();
   const bool ch = __any(lane_ch);
+  if (lane == 0) {
+    ps->lsteps += sp.steps;
+    ps->lcyc += c1 - c0;
+  }
   // lane 0's row 64 (column - 64) never exceeds its row 0 (column - 0)
   const int kx = wave_max(sp.cmax >= 0 ? sp.cmax - lane : (int)0x80000000);
   if (lane == 0) {
@@ -1090,6 +1144,9 @@ struct DD2 {
   unsigned long long* near_key;  // Step 1 nearest-Gamma keys (full grid)
   long long* near_win;
   unsigned long long* counters;  // [0] fine updates, [1] coarse updates, [2] residual bits, [3] nonzero if a two-wave sweep wait gave up
+  // or NULL: the leading waves' anti-diagonal steps and the clock64 ticks
+  // spent in them, summed over the boxes: [0], [1] Step 3, [2], [3] Step 4
+  unsigned long long* sweep_prof;
   // Step 4 weight (ThetaPar, theta_at): mode, parameters, u_ref or theta per
   // node, and the history u^{k-1}, C^{k-1}, C^{k-2} (NULL until it exists);
   // this iteration's C^k goes to ck_out
@@ -1428,6 +1485,10 @@ __device__ __forceinline__ void lattice_correct_f32(const DD2<float>& A, int bx)
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && A.sweep_prof) {
+    atomicAdd(&A.sweep_prof[2], (unsigned long long)ps.lsteps);
+    atomicAdd(&A.sweep_prof[3], (unsigned long long)ps.lcyc);
+  }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 
@@ -1591,6 +1652,10 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[1], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && A.sweep_prof) {
+    atomicAdd(&A.sweep_prof[2], (unsigned long long)ps.lsteps);
+    atomicAdd(&A.sweep_prof[3], (unsigned long long)ps.lcyc);
+  }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 template <typename T>
@@ -1700,6 +1765,10 @@ __device__ __forceinline__ void tile_body_f32(const DD2<float>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && A.sweep_prof) {
+    atomicAdd(&A.sweep_prof[0], (unsigned long long)ps.lsteps);
+    atomicAdd(&A.sweep_prof[1], (unsigned long long)ps.lcyc);
+  }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 
@@ -1803,6 +1872,10 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)sh_ns);
+  if (threadIdx.x == 0 && A.sweep_prof) {
+    atomicAdd(&A.sweep_prof[0], (unsigned long long)ps.lsteps);
+    atomicAdd(&A.sweep_prof[1], (unsigned long long)ps.lcyc);
+  }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 template <typename T>
