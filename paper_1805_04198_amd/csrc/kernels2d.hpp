@@ -2196,23 +2196,25 @@ __device__ __forceinline__ Seg seg_of(const DD2<T>& A, int s) {
 }
 
 // The corner recurrence U(C) = max(B(C), [ax] U(C - sx e_x), [ay] U(C - sy e_y))
-// on the coarse grid of corners.
-// The corner recurrence of one direction by one wave, without the sweep
-// engine's bookkeeping (nothing here can stop a sweep early): lane j holds
-// row j in sweep order and at step t takes column t - j, its x predecessor
-// being its own previous value and its y predecessor lane j-1's (DPP); a
-// 65th row runs on lane 0 one step late (steps 65 .. 65 + CI - 1), taking
-// lane 63's value of two steps back.  Each node's {V, links} record is read
-// one step ahead.  Links exist only where the predecessor does, so the
-// values a lane holds outside its row are never used.
+// on the coarse grid of corners, by one wave, without the sweep engine's
+// bookkeeping (nothing here can stop a sweep early): lane j holds row j in
+// sweep order and at step t takes column t - j, its x predecessor being its
+// own previous value and its y predecessor lane j-1's (DPP); a 65th row runs
+// on lane 0 one step late (steps 65 .. 65 + CI - 1), taking lane 63's value
+// of two steps back.  Each node's record {V, link addends} is read four
+// steps ahead.  A link is the addend -0 (linked) or -inf (not): value + -0
+// is the value itself (bit for bit, -0 included), value + -inf is -inf (or
+// NaN, from +inf - inf), which never wins the strict comparison of the
+// maximum, so the maximum is the same as with a link test.  Links exist only where the predecessor
+// does, so the values a lane holds outside its row are never used.
 template <typename T>
-struct alignas(2 * sizeof(T)) CornerOp {
+struct alignas(16) CornerOp {
   T b;
-  unsigned a;
+  float lx, ly;
 };
 // LDS bytes of the corner kernel: the records and the values
 __host__ __device__ __forceinline__ size_t corner_lds_bytes(int CI, int CJ, size_t szT) {
-  return (size_t)(halo_count(CI, CJ) + 2 * kGuard) * (3 * szT);
+  return (size_t)(halo_count(CI, CJ) + 2 * kGuard) * (sizeof(CornerOp<double>) + szT);
 }
 template <int SX, int SY, typename T>
 __device__ __forceinline__ void corner_wave(T* cu, const CornerOp<T>* op, int CI, int CJ, int SP) {
@@ -2234,32 +2236,42 @@ __device__ __forceinline__ void corner_wave(T* cu, const CornerOp<T>* op, int CI
     const int off = B ? kWave + 1 : lane;
     const bool rowok = B || rowA;
     const int dmy = dummy_slot();
-    auto index = [=](int t, bool& act) {
-      act = rowok && (unsigned)(t - off) < (unsigned)CI;
+    auto index = [=](int t) {
+      const bool act = rowok && (unsigned)(t - off) < (unsigned)CI;
       return act ? x0 + SX * t : dmy;
     };
-    bool act;
-    int x = index(t0, act);
-    CornerOp<T> o = op[x];
-    for (int t = t0; t <= t1; ++t) {
-      bool nact;
-      const int nx = index(t + 1, nact);
-      const CornerOp<T> no = op[nx];
+    // four slots of {record index, record}: step t uses slot t % 4 and then
+    // refills it with step t + 4's
+    int x0s = index(t0), x1s = index(t0 + 1), x2s = index(t0 + 2), x3s = index(t0 + 3);
+    CornerOp<T> o0 = op[x0s], o1 = op[x1s], o2 = op[x2s], o3 = op[x3s];
+    auto step = [&](int t, int& xs, CornerOp<T>& o) {
+      const int x = xs;
       T py = dpp_ror1(cur);
       if (P2) {
         const T py2 = dpp_ror1(prev);
         py = B ? py2 : py;
       }
+      const T cx = cur + (T)o.lx, cy = py + (T)o.ly;
       T v = o.b;
-      v = (o.a & 1u) ? vmax(v, cur) : v;
-      v = (o.a & 2u) ? vmax(v, py) : v;
+      v = v < cx ? cx : v;
+      v = v < cy ? cy : v;
       prev = cur;
+      const bool act = x != dmy;
       cur = act ? v : cur;
-      cu[act ? x : dmy] = v;
-      x = nx;
-      o = no;
-      act = nact;
+      cu[x] = v;
+      xs = index(t + 4);
+      o = op[xs];
+    };
+    int t = t0;
+    for (; t + 3 <= t1; t += 4) {
+      step(t, x0s, o0);
+      step(t + 1, x1s, o1);
+      step(t + 2, x2s, o2);
+      step(t + 3, x3s, o3);
     }
+    if (t <= t1) step(t, x0s, o0);
+    if (t + 1 <= t1) step(t + 1, x1s, o1);
+    if (t + 2 <= t1) step(t + 2, x2s, o2);
   };
   // steps 0 .. kWave: rows 0 .. 63; then lane 0 switches to row 64
   run(std::integral_constant<bool, false>{}, 0, min(last, kWave));
@@ -2268,7 +2280,8 @@ __device__ __forceinline__ void corner_wave(T* cu, const CornerOp<T>* op, int CI
 
 // phase B for one direction, by one block: the corners' V and links (from
 // U, W, the segments' phase-A results and ncx / ncy) into LDS, the
-// recurrence by one wave, the corner values back to U
+// recurrence by one wave (meanwhile the other waves read the old corner
+// values the residual needs), the corner values back to U
 template <typename T>
 __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const uint8_t* W, int dir, bool res) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -2282,6 +2295,14 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
   unsigned char* lc = smem;
   CornerOp<T>* op = carve<CornerOp<T>>(lc, cnt);
   T* cu = carve<T>(lc, cnt);
+  const float ninf = -__builtin_huge_valf();
+  // corner t = I + CI J: J from a float reciprocal (exact: t < 2^20, and
+  // (t + 1/2) / CI stays more than 1/(2 CI) away from an integer)
+  const float rCI = 1.0f / (float)CI;
+  auto corner_ij = [&](int t, int& I, int& J) {
+    J = (int)(((float)t + 0.5f) * rCI);
+    I = t - J * CI;
+  };
   // a thread's corners are blockDim.x apart; all loads of up to kPer corners
   // are issued before any is used (the loads are independent; in a loop
   // they would wait one corner at a time)
@@ -2294,7 +2315,8 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
     for (int k = 0; k < kPer; ++k) {
       const int t = base + k * (int)blockDim.x;
       if (t < nc) {
-        const int I = t % CI, J = t / CI;
+        int I, J;
+        corner_ij(t, I, J);
         // incoming segments in sweep order (clamped; used only when linked)
         const int hs = min(max((sx > 0 ? I - 1 : I) + A.NI * J, 0), nH - 1);
         const int vs = min(max(I + CI * (sy > 0 ? J - 1 : J), 0), nV - 1);
@@ -2313,10 +2335,11 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
     for (int k = 0; k < kPer; ++k) {
       const int t = base + k * (int)blockDim.x;
       if (t >= nc) break;
-      const int I = t % CI, J = t / CI;
+      int I, J;
+      corner_ij(t, I, J);
       const int xi = I * M, yi = J * M;
       T b = u[k];
-      uint8_t al = 0;
+      float lx = ninf, ly = ninf;
       if (gm[k] == 0) {
         const int ex = wx_of(cw[k]), ey = wy_of(cw[k]);
         const int nxi = xi + sx, nyi = yi + sy;
@@ -2325,18 +2348,23 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
         const int pxi = xi - sx, pyi = yi - sy;
         if (ex == sx && pxi >= 0 && pxi < A.n0) {
           b = vmax(b, hp[k]);
-          if (hl[k]) al |= 1;
+          if (hl[k]) lx = -0.f;
         }
         if (ey == sy && pyi >= 0 && pyi < A.n1) {
           b = vmax(b, vp[k]);
-          if (vl[k]) al |= 2;
+          if (vl[k]) ly = -0.f;
         }
       }
       const int x = (J + 1) * SP + (I + 1);
-      op[x] = CornerOp<T>{b, (unsigned)al};
+      op[x] = CornerOp<T>{b, lx, ly};
     }
   }
   __syncthreads();
+  // the residual's old corner values, read by waves 1.. while wave 0 runs
+  // the recurrence (up to kPer per thread; the rest after it)
+  const int nt = (int)blockDim.x - kWave;
+  const int tid = (int)threadIdx.x - kWave;
+  T old[kPer];
   if (threadIdx.x < kWave) {
     switch (dir) {
       case 0: corner_wave<-1, -1>(cu, op, CI, CJ, SP); break;
@@ -2344,29 +2372,44 @@ __device__ __forceinline__ void causal_corner_body(const DD2<T>& A, T* U, const 
       case 2: corner_wave<1, -1>(cu, op, CI, CJ, SP); break;
       default: corner_wave<1, 1>(cu, op, CI, CJ, SP); break;
     }
+  } else if (res) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int t = tid + k * nt;
+      if (t < nc) {
+        int I, J;
+        corner_ij(t, I, J);
+        old[k] = A.U[I * M + A.n0 * (J * M)];
+      }
+    }
   }
   __syncthreads();
   double dv = 0.0;
-  for (int base = threadIdx.x; base < nc; base += kPer * (int)blockDim.x) {
-    T prev[kPer];
-    if (res) {
+  if (tid >= 0) {
+    for (int base = tid; base < nc; base += kPer * nt) {
+      if (res && base != tid) {
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+          const int t = base + k * nt;
+          if (t < nc) {
+            int I, J;
+            corner_ij(t, I, J);
+            old[k] = A.U[I * M + A.n0 * (J * M)];
+          }
+        }
+      }
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
-        const int t = base + k * (int)blockDim.x;
-        if (t < nc) prev[k] = A.U[(t % CI) * M + A.n0 * ((t / CI) * M)];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int t = base + k * (int)blockDim.x;
-      if (t >= nc) break;
-      const int I = t % CI, J = t / CI;
-      const int X = (I * M) + A.n0 * (J * M);
-      const T v = cu[(J + 1) * SP + (I + 1)];
-      U[X] = v;
-      if (res) {
-        const double d = res_term(v, prev[k]);
-        dv = dv < d ? d : dv;
+        const int t = base + k * nt;
+        if (t >= nc) break;
+        int I, J;
+        corner_ij(t, I, J);
+        const T v = cu[(J + 1) * SP + (I + 1)];
+        U[I * M + A.n0 * (J * M)] = v;
+        if (res) {
+          const double d = res_term(v, old[k]);
+          dv = dv < d ? d : dv;
+        }
       }
     }
   }
