@@ -1022,28 +1022,9 @@ __device__ __forceinline__ void causal3_cell(const DD3<T>& A, T* U, const uint8_
 // return at once) and counters[3], which the host reports as an internal
 // error.
 // abort_flag[0]: set by the first wait that gives up, which also records
-// its item, the flag it waited for, the value it last read there, the epoch
+// its item, a flag it waited for, the value it last read there, the epoch
 // and its block in abort_flag[1..5] (reported by the host).
 constexpr int kCausalSpin = 1 << 20;
-__device__ __forceinline__ bool causal3_wait(const int* done, int fi, int epoch, int* abort_flag, int item) {
-  int v = 0;
-  for (int n = 0;; ++n) {
-    // device-coherent polls
-    v = __hip_atomic_load(&done[fi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (v == epoch) return true;
-    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-    if (n >= kCausalSpin) break;
-    __builtin_amdgcn_s_sleep(2);
-  }
-  if (atomicCAS(abort_flag, 0, 1) == 0) {
-    abort_flag[1] = item;
-    abort_flag[2] = fi;
-    abort_flag[3] = v;
-    abort_flag[4] = epoch;
-    abort_flag[5] = (int)blockIdx.x;
-  }
-  return false;
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_causal3p(DD3<T> A, T* U, const uint8_t* W, const int* items, int nitems,
@@ -1057,26 +1038,54 @@ __global__ __launch_bounds__(256) void k_causal3p(DD3<T> A, T* U, const uint8_t*
     const int C[3] = {(code >> 3) & 63, (code >> 9) & 63, (code >> 15) & 63};
     const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
     auto cell = [&](int i, int j, int k) { return i + CN[0] * (j + CN[1] * k); };
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
+      // the flags this item waits for, one per lane, polled together (one
+      // device round trip per poll): lanes 0-2 the upwind face neighbours in
+      // its own direction, lane 3 the cell in the previous direction, lanes
+      // 4-9 its face neighbours there; -1: none
+      const int lane = (int)threadIdx.x;
+      int fi = -1;
+      int c[3] = {C[0], C[1], C[2]};
+      if (lane < 3) {
+        c[lane] -= s[lane];
+        if (c[lane] >= 0 && c[lane] < CN[lane]) fi = dir * ncell + cell(c[0], c[1], c[2]);
+      } else if (dir > 0 && lane == 3) {
+        fi = (dir - 1) * ncell + cell(C[0], C[1], C[2]);
+      } else if (dir > 0 && lane < 10) {
+        const int a = (lane - 4) >> 1;
+        c[a] += (lane & 1) ? 1 : -1;
+        if (c[a] >= 0 && c[a] < CN[a]) fi = (dir - 1) * ncell + cell(c[0], c[1], c[2]);
+      }
       bool ok = true;
-      for (int a = 0; a < 3 && ok; ++a) {
-        int c[3] = {C[0], C[1], C[2]};
-        c[a] -= s[a];
-        if (c[a] >= 0 && c[a] < CN[a])
-          ok = causal3_wait(done, dir * ncell + cell(c[0], c[1], c[2]), epoch, abort_flag, it);
-      }
-      if (dir > 0 && ok) {
-        const int pd = (dir - 1) * ncell;
-        ok = causal3_wait(done, pd + cell(C[0], C[1], C[2]), epoch, abort_flag, it);
-        for (int a = 0; a < 3 && ok; ++a)
-          for (int e = -1; e <= 1 && ok; e += 2) {
-            int c[3] = {C[0], C[1], C[2]};
-            c[a] += e;
-            if (c[a] >= 0 && c[a] < CN[a]) ok = causal3_wait(done, pd + cell(c[0], c[1], c[2]), epoch, abort_flag, it);
+      int v = epoch;
+      for (int n = 0;; ++n) {
+        if (fi >= 0) v = __hip_atomic_load(&done[fi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const bool mine = fi < 0 || v == epoch;
+        if (__all(mine)) break;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = false;
+          break;
+        }
+        if (n >= kCausalSpin) {
+          // the first lane still waiting records the item, the flag, the value
+          // it last read there, the epoch and the block (reported by the host)
+          const unsigned long long w = __ballot(!mine);
+          if (lane == (int)__builtin_ctzll(w) && atomicCAS(abort_flag, 0, 1) == 0) {
+            abort_flag[1] = it;
+            abort_flag[2] = fi;
+            abort_flag[3] = v;
+            abort_flag[4] = epoch;
+            abort_flag[5] = (int)blockIdx.x;
           }
+          ok = false;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
       }
-      if (!ok) atomicOr(&A.counters[3], 1ull);
-      sh_ok = ok ? 1 : 0;
+      if (lane == 0) {
+        if (!ok) atomicOr(&A.counters[3], 1ull);
+        sh_ok = ok ? 1 : 0;
+      }
     }
     __syncthreads();
     const bool ok = sh_ok != 0;
