@@ -273,9 +273,11 @@ def bench_config3(a):
 
 
 def bench_config4(a):
-    """64 independent 2D problems (257^2..2049^2), autotuned S, M, theta per
-    size, one batched solve; compared with the same problems solved one by
-    one with the same parameters (identical results)."""
+    """64 independent 2D problems (257^2..2049^2): the partition S, M
+    autotuned per size and the launch schedule of Steps 3 and 4 for the whole
+    batch, at the given weight (not tuned), one batched solve; compared with
+    the same problems solved one by one with the same parameters (identical
+    results)."""
     import numpy as np
     import torch
 
@@ -287,36 +289,42 @@ def bench_config4(a):
     gams = [(torch.from_numpy(p.gamma_idx).cuda(), torch.from_numpy(p.gamma_val.astype(np.float32)).cuda())
             for p in P]
     hs = [p.h for p in P]
+    th = a.theta
     t0 = time.perf_counter()
-    best, table = autotune.tune(rs, gams, hs, tol=1e-6, max_iter=300)
+    best, table = autotune.tune(rs, gams, hs, theta=th, tol=1e-6, max_iter=300)
+    S, M = autotune.apply(rs, best)
+    launch, launch_ms = autotune.tune_launch(rs, gams, hs, S, M, theta=th, tol=1e-6, max_iter=600)
     t_tune = time.perf_counter() - t0
-    S, M, th = autotune.apply(rs, best)
-    kw = dict(tol=1e-6, max_iter=600)
+    kw = dict(theta=th, tol=1e-6, max_iter=600)
     for _ in range(a.warmup):
-        E.dd_solve_batch(rs, gams, hs, S, M, theta=th, **kw)
+        E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        B = E.dd_solve_batch(rs, gams, hs, S, M, theta=th, **kw)
+        B = E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fine = sum(b["fine_updates"] for b in B)
     t0 = time.perf_counter()
     same = 0
     for i in range(len(P)):
-        R = E.dd_solve(rs[i], gams[i][0], gams[i][1], hs[i], S[i], M[i], theta=th[i], **kw)
+        R = E.dd_solve(rs[i], gams[i][0], gams[i][1], hs[i], S[i], M[i], **kw)
         same += int(R["iterations"] == B[i]["iterations"] and torch.equal(R["u"], B[i]["u"]))
     torch.cuda.synchronize()
     t_single = time.perf_counter() - t0
     extra = {"problems": len(P), "converged": sum(b["converged"] for b in B), "identical_to_single": same,
              "fine_updates_per_batch": fine, "ms_single_solves_total": t_single * 1e3,
              "speedup_vs_single_solves": t_single / (wall / a.steps), "autotune_s": t_tune,
-             "tuned": {f"{k[1]}x{k[0]}": {"S": v[0], "M": v[1], "theta": v[2]} for k, v in best.items()},
+             "theta": th, "launch": launch, "launch_ms": launch_ms,
+             "tuned": {f"{k[1]}x{k[0]}": {"S": v[0], "M": v[1]} for k, v in best.items()},
+             "tuning_table": [{"shape": f"{t[0][1]}x{t[0][0]}", "S": t[1], "M": t[2], "converged": t[3],
+                               "iterations": t[4], "ms": t[5]} for t in table],
              "max_iterations": max(b["iterations"] for b in B)}
     common(a, "fine-grid Godunov updates/s + DD time-to-solution at stated error vs FP64 oracle", fine / wall,
            "updates/s", wall * 1e3 / a.steps, "f32",
-           "config 4: 64 independent 2D problems, sides {257,513,1025,2049} (seed 4), 64^2-cell subdomains "
-           "(autotuned), random-Fourier media, random point sources, tol=1e-6, one batched solve", extra)
+           f"config 4: 64 independent 2D problems, sides {{257,513,1025,2049}} (seed 4), partition (S, M) "
+           f"autotuned per size, launch schedule autotuned, theta={th}, random-Fourier media, random point "
+           f"sources, tol=1e-6, one batched solve", extra)
 
 
 def bench_config5(a):

@@ -122,22 +122,31 @@ typedef struct {
 #define EIK_COARSE_GODUNOV 0
 #define EIK_COARSE_L1 1
 
-/* How eik_dd_solve (d = 2, one problem) issues the kernels of its DD
- * iterations.  Either way it launches several iterations ahead of its check of
- * the stopping rule (a launched-ahead iteration after the one that stopped
- * returns at once and changes nothing), with the same kernels and results:
- *   EIK_LAUNCH_STREAM  every kernel launched on the stream.
- *   EIK_LAUNCH_GRAPH   a block of launched-ahead iterations is captured once
- *                      into a HIP graph and replayed; the instantiated graphs
- *                      are kept per device and reused by the next call with
- *                      the same arguments and workspace (else captured again).
- *                      The first block of a call, a shorter last block, the
- *                      debug snapshots, EIK_THETA_ESTIMATE and
- *                      eik_dd_solve_noalloc use stream launches.  ms_fine,
- *                      ms_correct and ms_causal then cover the stream-launched
- *                      iterations only. */
+/* How the DD iteration issues its kernels; the kernels and the results are
+ * the same in every mode.  A mode that does not apply to a call is taken as
+ * EIK_LAUNCH_STREAM.
+ *   EIK_LAUNCH_STREAM      every kernel launched on the stream; the
+ *                          subdomain and lattice kernels with one block per
+ *                          box.  eik_dd_solve (d = 2) launches several
+ *                          iterations ahead of its check of the stopping rule
+ *                          (an iteration after the one that stopped returns
+ *                          at once and changes nothing).
+ *   EIK_LAUNCH_GRAPH       eik_dd_solve, d = 2: each whole block of launched-
+ *                          ahead iterations after the first is replayed from
+ *                          a HIP graph, captured once and kept per device
+ *                          for the next call with the same arguments and
+ *                          workspace (else captured again).  The debug
+ *                          snapshots, EIK_THETA_ESTIMATE and
+ *                          eik_dd_solve_noalloc use stream launches;
+ *                          ms_fine, ms_correct and ms_causal cover only the
+ *                          stream-launched iterations.
+ *   EIK_LAUNCH_PERSISTENT  eik_dd_solve_batch (from the first problem's
+ *                          options): Steps 3 and 4 run on a grid of the
+ *                          blocks that are resident at once, each taking the
+ *                          (problem, box) items in order from a counter. */
 #define EIK_LAUNCH_STREAM 0
 #define EIK_LAUNCH_GRAPH 1
+#define EIK_LAUNCH_PERSISTENT 2
 
 /* Options of the domain-decomposition iteration (Sec. 3.2). */
 typedef struct {
@@ -157,7 +166,7 @@ typedef struct {
                                 * REFERENCE; the paper's values are 0.75, 0.01, 0.9, -, -, -, 0.001;
                                 * the omegas are not stated there) */
     int32_t coarse_solver;     /* EIK_COARSE_*; 0 = C_H */
-    int32_t launch_mode;       /* EIK_LAUNCH_*; 0 = stream launches */
+    int32_t launch_mode;       /* EIK_LAUNCH_*; 0 = stream launches, one block per box */
 } eik_dd_opts;
 
 /* Host-side statistics.  residual_history (host, may be NULL) receives

@@ -62,8 +62,9 @@ class DDOpts(ctypes.Structure):
 THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
 # coarse solver of Steps 1 and 4: C_H, or the homogenised solver of Sec. 5.3
 COARSE_SOLVERS = {"godunov": 0, "l1": 1}
-# how the DD iterations' kernels are issued: stream launches or HIP graphs
-LAUNCH_MODES = {"stream": 0, "graph": 1}
+# how the DD iterations' kernels are issued: stream launches, HIP graph
+# replays (single 2D solves), persistent Step 3/4 grids (batches)
+LAUNCH_MODES = {"stream": 0, "graph": 1, "persistent": 2}
 # gamma, delta, x0 of eq. thetaest (the paper's values), equal omegas for
 # eq. secthetaest (not stated in the paper), margin 0.001 of the reference
 # weight
@@ -284,12 +285,14 @@ def solve_batch(r, gammas, h, max_sweeps: int = 100000, with_wind: bool = False)
 
 def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
                    max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
-                   theta_refs=None, history_cap: int = 4096, coarse_solver="godunov"):
+                   theta_refs=None, history_cap: int = 4096, coarse_solver="godunov", launch: str = "stream"):
     """eik_dd_solve_batch: the DD iteration on independent 2D problems at
     once (every DD step is one launch over all problems that have not
     converged).  rs: list of device slowness tensors (one dtype); gammas:
     list of (idx, val); hs: list of spacings; S, M, theta, tol, max_iter,
-    theta_mode, coarse_solver: one value for all or a list.  Returns a list of result dicts
+    theta_mode, coarse_solver: one value for all or a list.  launch: "stream" (one
+    block per subdomain / lattice) or "persistent" (resident grids that take
+    the boxes from a counter; same results).  Returns a list of result dicts
     as dd_solve, plus the batch's device time in each."""
     torch = _torch()
     L = load_library()
@@ -320,6 +323,7 @@ def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, ma
         o.max_iter, o.max_fine_sweeps, o.max_coarse_sweeps = int(mi), int(max_fine_sweeps), int(max_coarse_sweeps)
         o.theta_mode = THETA_MODES[modes[p]]
         o.coarse_solver = COARSE_SOLVERS[solvers[p]]
+        o.launch_mode = LAUNCH_MODES[launch]
         for q_, v in enumerate(theta_params):
             o.theta_params[q_] = float(v)
         if refs[p] is not None:

@@ -1,26 +1,33 @@
-"""Autotuner for batched DD solves: per problem size, the subdomain side S,
-the coarse spacing M = H/h and the weight theta that give the shortest
-time to solution.
+"""Autotuner for batched DD solves.
 
-For every distinct grid shape in a batch it times eik_dd_solve on the first
-problem of that shape for each admissible candidate (S from `sides`, M from
-`spacings` with S % M == 0, lattices of at most 65 nodes per axis, theta
-from `thetas`), skips candidates that do not reach the tolerance within
-`max_iter` iterations, and keeps the fastest.  The choice changes the
-iterates (another partition or weight), not the target: every accepted run
-has converged to the same tolerance.  Timing uses the library's device time
-of the solve after one warm-up call per candidate."""
+Two searches, both timed with the library's own device time after one
+warm-up call per candidate:
+
+  * per problem size, the partition: subdomain side S and coarse spacing
+    M = H/h (S from `sides`, M from `spacings` with S % M == 0 and lattices
+    of at most 65 nodes per axis), on the first problem of that size, at the
+    caller's weight theta.  Another partition changes the iterates but not
+    the target: candidates that do not reach the tolerance within
+    `max_iter` iterations are skipped, so every accepted run has converged
+    to the same tolerance.  The weight is not searched: it changes what the
+    iteration computes, and large weights make it unstable (Sec. 4), so it
+    stays the caller's choice.
+  * for the whole batch, the launch schedule of Steps 3 and 4: one block
+    per subdomain / lattice box ("stream") or resident grids whose blocks take
+    the boxes from a counter ("persistent").  The schedule changes nothing in
+    the results (each box is computed the same way), only the time.
+"""
 from __future__ import annotations
 
 import paper_1805_04198_amd as E
 
 SIDES = (32, 64)
 SPACINGS = (16, 32, 64)
-THETAS = (0.1, 0.25)
+LAUNCHES = ("stream", "persistent")
 MAX_NODES = 65
 
 
-def candidates(n, sides=SIDES, spacings=SPACINGS, thetas=THETAS):
+def candidates(n, sides=SIDES, spacings=SPACINGS):
     out = []
     for S in sides:
         if any((m - 1) % S for m in n) or S + 1 > MAX_NODES:
@@ -28,14 +35,13 @@ def candidates(n, sides=SIDES, spacings=SPACINGS, thetas=THETAS):
         for M in spacings:
             if M > S or S % M or any((m - 1) // M + 1 > MAX_NODES for m in n):
                 continue
-            for th in thetas:
-                out.append((S, M, th))
+            out.append((S, M))
     return out
 
 
-def tune(rs, gammas, hs, tol=1e-6, max_iter=300, sides=SIDES, spacings=SPACINGS, thetas=THETAS):
-    """rs, gammas, hs as for dd_solve_batch.  Returns ({shape: (S, M,
-    theta)}, table of (shape, S, M, theta, converged, iterations, ms))."""
+def tune(rs, gammas, hs, theta=0.1, tol=1e-6, max_iter=300, sides=SIDES, spacings=SPACINGS):
+    """rs, gammas, hs as for dd_solve_batch.  Returns ({shape: (S, M)},
+    table of (shape, S, M, converged, iterations, ms))."""
     best, table = {}, []
     seen = {}
     for i, r in enumerate(rs):
@@ -45,20 +51,32 @@ def tune(rs, gammas, hs, tol=1e-6, max_iter=300, sides=SIDES, spacings=SPACINGS,
     for shape, i in seen.items():
         n = shape[::-1]
         pick = None
-        for S, M, th in candidates(n, sides, spacings, thetas):
-            kw = dict(theta=th, tol=tol, max_iter=max_iter)
+        for S, M in candidates(n, sides, spacings):
+            kw = dict(theta=theta, tol=tol, max_iter=max_iter)
             E.dd_solve(rs[i], gammas[i][0], gammas[i][1], hs[i], S, M, **kw)
             R = E.dd_solve(rs[i], gammas[i][0], gammas[i][1], hs[i], S, M, **kw)
-            table.append((shape, S, M, th, R["converged"], R["iterations"], R["ms_total"]))
+            table.append((shape, S, M, R["converged"], R["iterations"], R["ms_total"]))
             if R["converged"] and (pick is None or R["ms_total"] < pick[1]):
-                pick = ((S, M, th), R["ms_total"])
+                pick = ((S, M), R["ms_total"])
         if pick is None:
             raise RuntimeError(f"no candidate converged for grid {n}")
         best[shape] = pick[0]
     return best, table
 
 
+def tune_launch(rs, gammas, hs, S, M, theta=0.1, tol=1e-6, max_iter=600, launches=LAUNCHES):
+    """The fastest launch schedule of the whole batch with partitions S, M
+    (lists).  Returns (launch, {launch: ms})."""
+    times = {}
+    for lm in launches:
+        kw = dict(theta=theta, tol=tol, max_iter=max_iter, launch=lm)
+        E.dd_solve_batch(rs, gammas, hs, S, M, **kw)
+        B = E.dd_solve_batch(rs, gammas, hs, S, M, **kw)
+        times[lm] = B[0]["ms_total"]
+    return min(times, key=times.get), times
+
+
 def apply(rs, best):
-    """Per-problem S, M, theta lists from a tuning result."""
-    S, M, th = zip(*[best[tuple(r.shape)] for r in rs])
-    return list(S), list(M), list(th)
+    """Per-problem S, M lists from a tuning result."""
+    S, M = zip(*[best[tuple(r.shape)] for r in rs])
+    return list(S), list(M)

@@ -239,6 +239,8 @@ eik_status check_weight_solver(const eik_dd_opts* o) {
   }
   if (o->theta_mode == EIK_THETA_REFERENCE && !std::isfinite(o->theta_params[6]))
     return fail(EIK_ERR_ARG, "theta_params: margin must be finite");
+  if (o->launch_mode < EIK_LAUNCH_STREAM || o->launch_mode > EIK_LAUNCH_PERSISTENT)
+    return fail(EIK_ERR_ARG, "launch_mode must be one of EIK_LAUNCH_*");
   return EIK_OK;
 }
 
@@ -695,6 +697,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
   int2* w_cc = cv.take<int2>(cap_cc);
   int2* w_cb = cv.take<int2>(P);
   int2* w_near = cv.take<int2>(cap_near);
+  int* d_next = cv.take<int>(2);  // EIK_LAUNCH_PERSISTENT: item counters of Steps 3 and 4
   for (int p = 0; p < P; ++p) {
     BatchProb<T>& q = pr[p];
     const eik_dd_opts* op = &o[p];
@@ -756,6 +759,18 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     if ((e = validate<T>(A.r, N, &gam[p], dflag, host, s, G[p].h)) != EIK_OK) return e;
   }
   if ((e = allow_lds(eik::k_tile_b<T>, lds_tile)) != EIK_OK) return e;
+  // EIK_LAUNCH_PERSISTENT (o[0]): Steps 3 and 4 on as many blocks as are
+  // resident at once, each taking items from a counter
+  const bool persistent = o[0].launch_mode == EIK_LAUNCH_PERSISTENT;
+  int64_t grid_tile = 0, grid_lat = 0;
+  if (persistent) {
+    int ncu = 0, bt = 0, bl = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bt, eik::k_tile_b<T>, eik::kBlock, lds_tile));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, eik::k_lattice_correct_b<T>, eik::kBlock, lds_lat));
+    grid_tile = (int64_t)std::max(1, bt) * ncu;
+    grid_lat = (int64_t)std::max(1, bl) * ncu;
+  }
   if ((e = allow_lds(eik::k_lattice_init_b<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_lattice_correct_b<T>, lds_lat)) != EIK_OK) return e;
   if ((e = allow_lds(eik::k_causal_corner_b<T>, lds_cb)) != EIK_OK) return e;
@@ -876,12 +891,24 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     }
     if ((e = upload_desc()) != EIK_OK) return e;
     HIPCHK(hipEventRecord(ev[1], s));
-    hipLaunchKernelGGL(eik::k_tile_b<T>, dim3((unsigned)tot_tile), dim3(eik::kBlock), lds_tile, s, d_desc, w_tile);
+    if (persistent) {
+      HIPCHK(hipMemsetAsync(d_next, 0, 2 * sizeof(int), s));
+      hipLaunchKernelGGL(eik::k_tile_b<T>, dim3((unsigned)std::min<int64_t>(tot_tile, grid_tile)), dim3(eik::kBlock),
+                         lds_tile, s, d_desc, w_tile, (int)tot_tile, d_next);
+    } else {
+      hipLaunchKernelGGL(eik::k_tile_b<T>, dim3((unsigned)tot_tile), dim3(eik::kBlock), lds_tile, s, d_desc, w_tile,
+                         (int)tot_tile, (int*)nullptr);
+    }
     HIPCHK(hipEventRecord(ev[2], s));
     if (tot_rec > 0)
       hipLaunchKernelGGL(eik::k_reconcile_b<T>, dim3((unsigned)tot_rec), dim3(bs), 0, s, d_desc, w_rec);
-    hipLaunchKernelGGL(eik::k_lattice_correct_b<T>, dim3((unsigned)tot_lat), dim3(eik::kBlock), lds_lat, s, d_desc,
-                       w_lat);
+    if (persistent) {
+      hipLaunchKernelGGL(eik::k_lattice_correct_b<T>, dim3((unsigned)std::min<int64_t>(tot_lat, grid_lat)),
+                         dim3(eik::kBlock), lds_lat, s, d_desc, w_lat, (int)tot_lat, d_next + 1);
+    } else {
+      hipLaunchKernelGGL(eik::k_lattice_correct_b<T>, dim3((unsigned)tot_lat), dim3(eik::kBlock), lds_lat, s, d_desc,
+                         w_lat, (int)tot_lat, (int*)nullptr);
+    }
     for (int p = 0; p < P; ++p)
       if (pr[p].active && pr[p].tmode == EIK_THETA_ESTIMATE)
         HIPCHK(hipMemcpyAsync(pr[p].hist_u, pr[p].A.uk, pr[p].N * szT, hipMemcpyDeviceToDevice, s));

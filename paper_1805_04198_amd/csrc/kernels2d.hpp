@@ -1660,11 +1660,32 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) { lattice_correct_body(A, (int)blockIdx.x); }
+// Batched launches over a work table of (problem, box) items: next == NULL,
+// one block per item; else a resident grid whose blocks take the items in
+// table order from the counter *next (zero at launch) until nwork.  Each
+// item is computed the same either way.
+template <typename T, typename Body>
+__device__ __forceinline__ void batch_items(const DD2<T>* descs, const int2* work, int nwork, int* next, Body body) {
+  if (!next) {
+    const int2 w = work[blockIdx.x];
+    body(descs[w.x], w.y);
+    return;
+  }
+  __shared__ int sh_item;
+  for (;;) {
+    if (threadIdx.x == 0) sh_item = atomicAdd(next, 1);
+    __syncthreads();
+    const int i = sh_item;
+    __syncthreads();
+    if (i >= nwork) return;
+    const int2 w = work[i];
+    body(descs[w.x], w.y);
+  }
+}
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* descs, const int2* work) {
-  const int2 w = work[blockIdx.x];
-  const DD2<T> A = descs[w.x];
-  lattice_correct_body(A, w.y);
+__global__ __launch_bounds__(kBlock) void k_lattice_correct_b(const DD2<T>* descs, const int2* work, int nwork,
+                                                              int* next) {
+  batch_items(descs, work, nwork, next, [](const DD2<T>& A, int bx) { lattice_correct_body(A, bx); });
 }
 
 
@@ -1881,10 +1902,8 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) { tile_body(A, (int)blockIdx.x); }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tile_b(const DD2<T>* descs, const int2* work) {
-  const int2 w = work[blockIdx.x];
-  const DD2<T> A = descs[w.x];
-  tile_body(A, w.y);
+__global__ __launch_bounds__(kBlock) void k_tile_b(const DD2<T>* descs, const int2* work, int nwork, int* next) {
+  batch_items(descs, work, nwork, next, [](const DD2<T>& A, int bx) { tile_body(A, bx); });
 }
 
 

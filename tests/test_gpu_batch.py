@@ -36,8 +36,9 @@ MIX = [
 ]
 
 
+@pytest.mark.parametrize("launch", ["stream", "persistent"])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-def test_batch_equals_single_solves(dtype):
+def test_batch_equals_single_solves(dtype, launch):
     probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=2, kind=c["kind"]) for c in MIX]
     tol = 1e-6 if dtype == np.float32 else 1e-12
     rs, gams, refs = [], [], []
@@ -46,10 +47,10 @@ def test_batch_equals_single_solves(dtype):
         rs.append(r)
         gams.append(g)
         refs.append(dev(np.full(p.r.shape, 0.35), dtype) if c["mode"] == "field" else None)
-    print(f"batch of {len(probs)} dtype={np.dtype(dtype).name}", flush=True)
+    print(f"batch of {len(probs)} dtype={np.dtype(dtype).name} launch={launch}", flush=True)
     B = E.dd_solve_batch(rs, gams, [p.h for p in probs], [c["S"] for c in MIX], [c["M"] for c in MIX],
                          theta=[c["theta"] for c in MIX], tol=tol, max_iter=60,
-                         theta_mode=[c["mode"] for c in MIX], theta_refs=refs)
+                         theta_mode=[c["mode"] for c in MIX], theta_refs=refs, launch=launch)
     for i, (c, p) in enumerate(zip(MIX, probs)):
         S_ = E.dd_solve(rs[i], gams[i][0], gams[i][1], p.h, c["S"], c["M"], theta=c["theta"], tol=tol, max_iter=60,
                         theta_mode=c["mode"], theta_ref=refs[i])
@@ -61,14 +62,15 @@ def test_batch_equals_single_solves(dtype):
         assert same_t(b["u"], S_["u"]) and same_t(b["U"], S_["U"]) and torch.equal(b["W"], S_["W"]), i
 
 
-def test_batch_against_oracle():
+@pytest.mark.parametrize("launch", ["stream", "persistent"])
+def test_batch_against_oracle(launch):
     cases = [dict(seed=90, n=(65, 65), S=16, M=8), dict(seed=91, n=(97, 65), S=32, M=16),
              dict(seed=92, n=(129, 129), S=32, M=8)]
     probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=1) for c in cases]
     rs, gams = zip(*[inputs(p, np.float64) for p in probs])
-    print("batch vs oracle fp64", flush=True)
+    print(f"batch vs oracle fp64 launch={launch}", flush=True)
     B = E.dd_solve_batch(list(rs), list(gams), [p.h for p in probs], [c["S"] for c in cases],
-                         [c["M"] for c in cases], theta=0.25, tol=0.0, max_iter=5)
+                         [c["M"] for c in cases], theta=0.25, tol=0.0, max_iter=5, launch=launch)
     for b, p in zip(B, probs):
         O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, theta=0.25, tol=0.0, max_iter=5)
         assert np.array_equal(b["U"].cpu().numpy().reshape(-1), O["U"], equal_nan=True)

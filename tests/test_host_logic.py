@@ -10,14 +10,17 @@ def test_autotune_candidates_respect_the_solver_limits():
     for n in [(257, 257), (513, 513), (1025, 1025), (2049, 2049), (97, 161)]:
         cands = autotune.candidates(n)
         assert cands, n
-        for S, M, th in cands:
+        for S, M in cands:
             assert all((m - 1) % S == 0 for m in n) and S + 1 <= 65
             assert S % M == 0 and M <= S
             assert all((m - 1) // M + 1 <= 65 for m in n)
-            assert th in autotune.THETAS
     # 2049: M = 16 would give 129-node lattices
-    assert all(M >= 32 for _, M, _ in autotune.candidates((2049, 2049)))
+    assert all(M >= 32 for _, M in autotune.candidates((2049, 2049)))
     assert autotune.candidates((100, 100)) == []
+    # the weight is the caller's, never searched; the launch schedules are
+    # the two the batch API offers
+    assert not hasattr(autotune, "THETAS")
+    assert set(autotune.LAUNCHES) == {"stream", "persistent"}
 
 
 def test_config4_generator():
