@@ -2,12 +2,13 @@
 assigns instead of taking a minimum, so a lattice's sweeps need not settle:
 many repeat with period 4, 8 or 12 sweeps until the sweep cap.  The fp32
 kernel compares the lattice values every 4 sweeps with those kept 4 and 8
-sweeps before and, on a repeat, runs only the sweeps that decide the state
-the cap leaves.  These cases have many such lattices (found with a copy of
+sweeps before (in the records' spare LDS words) and, on a repeat, runs only
+the sweeps that decide the state the cap leaves; the fp64 kernel runs every
+sweep to the cap.  These cases have many such lattices (found with a copy of
 the oracle that records when its capped Step-4 runs first repeat: at sweeps
 12-28, periods 4, 8 and 12); caps below, at and above the detection points,
 odd and even, must give the oracle's values, winds, counts and residuals bit
-for bit."""
+for bit in both precisions."""
 import numpy as np
 import pytest
 
@@ -26,17 +27,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("cap", [13, 17, 30, 32, 33, 64])
 @pytest.mark.parametrize("name", list(CASES))
-def test_cycling_step4_bitwise(name, cap):
+def test_cycling_step4_bitwise(name, cap, dtype):
     p = CASES[name]()
-    print(f"case={name} cap={cap}", flush=True)
-    r = torch.from_numpy(p.r.astype(np.float32)).cuda()
+    print(f"case={name} cap={cap} dtype={np.dtype(dtype).name}", flush=True)
+    r = torch.from_numpy(p.r.astype(dtype)).cuda()
     gi = torch.from_numpy(p.gamma_idx).cuda()
-    gv = torch.from_numpy(p.gamma_val.astype(np.float32)).cuda()
+    gv = torch.from_numpy(p.gamma_val.astype(dtype)).cuda()
     kw = dict(theta=0.3, tol=0.0, max_iter=6, max_coarse_sweeps=cap)
     G = E.dd_solve(r, gi, gv, p.h, p.S, p.M, debug=True, **kw)
-    O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, dtype=np.float32, **kw)
+    O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, p.S, p.M, dtype=dtype, **kw)
     flat = lambda t: t.cpu().numpy().reshape(-1)
     assert np.array_equal(flat(G["Upre"]), O["Upre"], equal_nan=True)
     assert np.array_equal(flat(G["U"]), O["U"], equal_nan=True)
