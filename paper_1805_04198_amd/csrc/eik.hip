@@ -301,6 +301,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const int nH = NI * (NJ + 1), nV = (NI + 1) * NJ;
   size_t need = 0;
   need += 7 * (N * szT + 256);           // gfull U Un uk cwork + spare
+  need += (N + 31) / 32 * 4 + 256;       // Gamma bit mask
   need += 6 * (N + 256);                 // W Wn wk cflag
   need += 2 * (N * 8 + 256);             // near keys
   need += ntile * 4 * L * (szT + 1) + 512;
@@ -326,6 +327,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.ng = gam->count;
   T* gfull = cv.take<T>(N);
   A.gfull = gfull;
+  uint32_t* gbits = cv.take<uint32_t>((N + 31) / 32);
+  A.gbits = gbits;
   A.U = cv.take<T>(N);
   A.Un = cv.take<T>(N);
   A.uk = cv.take<T>(N);
@@ -382,9 +385,13 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const int bs = 256;
   HIPCHK(hipMemsetAsync(A.counters, 0, 8 * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, gfull, nanT, N);
-  if (gam->count > 0)
+  HIPCHK(hipMemsetAsync(gbits, 0, (N + 31) / 32 * 4, s));
+  if (gam->count > 0) {
     hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gfull,
                        gam->idx, as<T>(gam->g), gam->count);
+    hipLaunchKernelGGL(eik::k_gamma_bits, dim3(nblocks(gam->count, bs)), dim3(bs), 0, s, gbits, gam->idx,
+                       gam->count);
+  }
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.u_out, nanT, N);
   hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.uk, nanT, N);
   HIPCHK(hipMemsetAsync(A.wk, 0, N, s));
@@ -588,6 +595,7 @@ struct BatchProb {
   T* hist_u = nullptr;
   T* hist_c[3] = {nullptr, nullptr, nullptr};
   T* gfull = nullptr;
+  uint32_t* gbits = nullptr;
   bool active = true, conv = false, resumed = false;
   int it = 0;
   double last = 0.0;
@@ -658,6 +666,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     q.resumed = op->U_init != nullptr;
     size_t nd = 0;
     nd += 7 * (q.N * szT + 256);
+    nd += (q.N + 31) / 32 * 4 + 256;  // Gamma bit mask
     nd += 6 * (q.N + 256);
     nd += 2 * (q.N * 8 + 256);
     nd += (size_t)q.ntile * 4 * L * (szT + 1) + 512;
@@ -718,6 +727,8 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.ng = gam[p].count;
     q.gfull = cv.take<T>(N);
     A.gfull = q.gfull;
+    q.gbits = cv.take<uint32_t>((N + 31) / 32);
+    A.gbits = q.gbits;
     A.U = cv.take<T>(N);
     A.Un = cv.take<T>(N);
     A.uk = cv.take<T>(N);
@@ -802,9 +813,13 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     eik::DD2<T>& A = pr[p].A;
     const int64_t N = pr[p].N;
     hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, pr[p].gfull, nanT, N);
-    if (gam[p].count > 0)
+    HIPCHK(hipMemsetAsync(pr[p].gbits, 0, (N + 31) / 32 * 4, s));
+    if (gam[p].count > 0) {
       hipLaunchKernelGGL(eik::k_scatter_gamma<T>, dim3(nblocks(gam[p].count, bs)), dim3(bs), 0, s, pr[p].gfull,
                          gam[p].idx, as<T>(gam[p].g), gam[p].count);
+      hipLaunchKernelGGL(eik::k_gamma_bits, dim3(nblocks(gam[p].count, bs)), dim3(bs), 0, s, pr[p].gbits,
+                         gam[p].idx, gam[p].count);
+    }
     hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.u_out, nanT, N);
     hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A.uk, nanT, N);
     HIPCHK(hipMemsetAsync(A.wk, 0, N, s));

@@ -1118,6 +1118,7 @@ struct DD2 {
   int max_fine_sweeps, max_coarse_sweeps;
   const T* r;
   const T* gfull;      // Gamma value per node, NaN if not a Gamma node
+  const uint32_t* gbits;  // Gamma flag per node: bit X % 32 of word X / 32
   const int64_t* gidx; // sorted Gamma indices
   const T* gval;
   int64_t ng;
@@ -1208,6 +1209,18 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
+__global__ void k_gamma_bits(uint32_t* bits, const int64_t* gidx, int64_t ng) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ng) atomicOr(&bits[gidx[i] >> 5], 1u << (gidx[i] & 31));
+}
+// the Gamma value of node X (NaN if it is not a Gamma node), read from the
+// full-grid values only where the bit mask has the node
+template <typename T>
+__device__ __forceinline__ T gamma_at(const DD2<T>& A, int X) {
+  T g = T(__builtin_nan(""));
+  if ((A.gbits[X >> 5] >> (X & 31)) & 1u) g = A.gfull[X];
+  return g;
+}
 template <typename T>
 __global__ void k_scatter_gamma(T* gfull, const int64_t* gidx, const T* gval, int64_t ng) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1345,7 +1358,7 @@ __device__ __forceinline__ void lattice_init_body(const DD2<T>& A, int bx) {
     const int xi = o0 + p0 * A.M, yi = o1 + p1 * A.M;
     const int X = xi + A.n0 * yi;
     const int x = (p1 + 1) * SP + (p0 + 1);
-    const T g = A.gfull[X];
+    const T g = gamma_at(A, X);
     if (!disnan(g)) {
       u[x] = g; w[x] = 0; rd[x] = nan;
     } else if (A.near_win[X] != 0x7fffffffffffffffll) {
@@ -1419,7 +1432,7 @@ __device__ __forceinline__ void lattice_correct_f32(const DD2<float>& A, int bx)
     const int X = (o0 + p0 * A.M) + A.n0 * (o1 + p1 * A.M);
     const int x = (p1 + 1) * kSPf + (p0 + 1);
     const float Uk = A.U[X];
-    const float g = A.gfull[X];
+    const float g = gamma_at(A, X);
     const float ukX = A.uk[X];
     const float r = A.r[X];
     const uint8_t wkX = A.wk[X], WkX = A.W[X];
@@ -1534,7 +1547,7 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     const int X = xi + A.n0 * yi;
     const int x = (p1 + 1) * SP + (p0 + 1);
     const T Uk = A.U[X];
-    const T g = A.gfull[X];
+    const T g = gamma_at(A, X);
     const T ukX = A.uk[X];
     const T r = A.r[X];
     const uint8_t wkX = A.wk[X], WkX = A.W[X];
@@ -1722,7 +1735,7 @@ __device__ __forceinline__ void tile_body_f32(const DD2<float>& A, int bx) {
     const int x = (lj + 1) * kSPf + (li + 1);
     const bool bxi = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
     const bool byi = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
-    const float g = A.gfull[X];
+    const float g = gamma_at(A, X);
     const float r = A.r[X];
     uint8_t Wc = 0;
     float Uc = inf;
@@ -1825,7 +1838,7 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
     // all loads of the node first (independent), then the decisions
     const bool bx = (li == 0 || li == A.S) && is_iface(xi, A.S, A.n0);
     const bool by = (lj == 0 || lj == A.S) && is_iface(yi, A.S, A.n1);
-    const T g = A.gfull[X];
+    const T g = gamma_at(A, X);
     const T r = A.r[X];
     uint8_t Wc = 0;
     T Uc = pinf<T>();
@@ -1899,8 +1912,19 @@ __device__ __forceinline__ void tile_body(const DD2<T>& A, int bx) {
   }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
+// Workgroups go to the 8 compute dies round robin (block b to die b % 8),
+// each die with its own L2: block b takes tile (b % 8) * n/8 + b / 8, so that
+// every die holds a contiguous run of tiles (whole rows of tiles), whose
+// shared boundary rows then come from one L2.  The tiles are independent:
+// any order gives the same results.
+__device__ __forceinline__ int die_local_tile(int b, int n) {
+  if (n % 8 != 0) return b;
+  return (b % 8) * (n / 8) + b / 8;
+}
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) { tile_body(A, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_tile(DD2<T> A) {
+  tile_body(A, die_local_tile((int)blockIdx.x, (int)gridDim.x));
+}
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile_b(const DD2<T>* descs, const int2* work, int nwork, int* next) {
   batch_items(descs, work, nwork, next, [](const DD2<T>& A, int bx) { tile_body(A, bx); });
