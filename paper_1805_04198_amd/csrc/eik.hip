@@ -1116,6 +1116,8 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   if (tmode == EIK_THETA_ESTIMATE) need += 3 * (N * szT + 256);  // u^{k-1} and two more C arrays
   const int ncell = (NC[0] + 1) * (NC[1] + 1) * (NC[2] + 1);
   need += (size_t)8 * ncell * sizeof(int) * 2 + 1024;  // causal items (8 per cell) and flags
+  const int rec_stride = ncell;  // lattice nodes <= (NC+1)^3
+  if (tmode == EIK_THETA_CONSTANT) need += (size_t)nlat * rec_stride * sizeof(eik::Corr3Rec<T>) + 256;
   void* wsv;
   unsigned long long* host;
   eik_status e = ws_get(dev, need, &wsv, &host);
@@ -1152,6 +1154,8 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   A.tile_w = cv.take<uint8_t>((size_t)ntile * L * L * L);
   A.cvals = nullptr;
   A.counters = cv.take<unsigned long long>(4);
+  A.rec_stride = rec_stride;
+  A.rec = tmode == EIK_THETA_CONSTANT ? (void*)cv.take<eik::Corr3Rec<T>>((size_t)nlat * rec_stride) : nullptr;
   unsigned int* dflag = cv.take<unsigned int>(4);
   Causal3Plan cp;
   {

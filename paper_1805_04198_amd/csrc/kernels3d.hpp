@@ -142,6 +142,20 @@ struct DD3 {
   const T* ckm2;
   // coarse solver of Steps 1 and 4: 0 = C_H, 1 = the homogenised solver
   int coarse_homog;
+  // Step 4 (constant weight), or NULL: each lattice's read-only operands in
+  // lattice-major records (lattice q at rec + q rec_stride), gathered once
+  // per launch so that every sweep reads them contiguously
+  void* rec;
+  int rec_stride;
+};
+
+// Step 4's read-only operands of a lattice node in one record
+template <typename T>
+struct alignas(4 * sizeof(T)) Corr3Rec {
+  T rd;    // r*H, NaN at Gamma nodes
+  T ukx;   // u^k
+  T ckx;   // C^k
+  unsigned mask;
 };
 
 __device__ __forceinline__ int64_t idx3(const int (&n)[3], int i, int j, int k) {
@@ -803,7 +817,32 @@ __global__ __launch_bounds__(kBlock3) void k_lattice_correct3(DD3<T> A) {
     }
   } R{u, L[0], L[1], L[2], A.gfull, A.rdH, A.mk, A.uk, A.ck, A.theta, base, gs[0], gs[1], gs[2],
       A.tref, A.ukm1, A.ckm1, A.ckm2, A.tq, A.coarse_homog != 0};
-  const int ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
+  int ns;
+  if (MODE == 0 && A.rec != nullptr) {
+    // the operands gathered once (the lattice's nodes are M apart in every
+    // axis of the full-grid arrays: a memory sector per 4-byte read), then
+    // read by every sweep from contiguous records
+    Corr3Rec<T>* rec = reinterpret_cast<Corr3Rec<T>*>(A.rec) + (size_t)blockIdx.x * A.rec_stride;
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+      const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+      const int64_t X = base + (int64_t)p0 * gs[0] + (int64_t)p1 * gs[1] + (int64_t)p2 * gs[2];
+      rec[x] = Corr3Rec<T>{A.rdH[X], A.uk[X], A.ck[X], (unsigned)A.mk[X]};
+    }
+    __syncthreads();
+    struct RecRule : Rule {
+      const Corr3Rec<T>* rec;
+      __device__ typename Rule::In load(int i, int j, int k) const {
+        const Corr3Rec<T> q = rec[i + this->L0 * (j + this->L1 * k)];
+        return typename Rule::In{q.rd, q.ukx, q.ckx, q.mask, 0.0, 0.0};
+      }
+    };
+    RecRule RR;
+    static_cast<Rule&>(RR) = R;
+    RR.rec = rec;
+    ns = fsm3(RR, L[0], L[1], L[2], A.max_coarse_sweeps);
+  } else {
+    ns = fsm3(R, L[0], L[1], L[2], A.max_coarse_sweeps);
+  }
   for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
     const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
     const int64_t X = base + (int64_t)p0 * gs[0] + (int64_t)p1 * gs[1] + (int64_t)p2 * gs[2];
