@@ -539,10 +539,12 @@ __device__ __forceinline__ bool sweep_dir(Rule& R, int L0, int L1, int SP, int t
   // count, in one store per lane
   int2* const kp_lane = PIPE == 1 ? &ps->kp[lane] : nullptr;
   auto publish = [&](int done) {
-    const int k = span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane);
-    const unsigned long long word = ((unsigned long long)(unsigned)done << 32) | (unsigned)k;  // int2{k, done}
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(kp_lane), word, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if constexpr (PIPE == 1) {
+      const int k = span.cmin - ((EXTRA && laneB && span.rowB) ? kWave : lane);
+      const unsigned long long word = ((unsigned long long)(unsigned)done << 32) | (unsigned)k;  // int2{k, done}
+      __hip_atomic_store(reinterpret_cast<unsigned long long*>(kp_lane), word, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
   };
   // up to tmax the steps run unconditionally; after that the sweep ends with
   // the first step pair that changes nothing
