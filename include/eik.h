@@ -273,7 +273,8 @@ eik_status eik_dd_solve_noalloc(const eik_grid* grid, const void* r, const eik_g
  *   wind_out  device, nb x N codes, or NULL
  *   stats     host array of nb entries or NULL (sweeps per problem; device
  *             time of the whole call)
- * This build: d = 2. */
+ * d = 2: the problems' sweeps share launches; d = 3: the problems are solved
+ * one after another on the stream, each as by its own eik_solve. */
 eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
                            int32_t max_sweeps, void* u_out, int8_t* wind_out, eik_stats* stats,
                            void* hip_stream);
@@ -320,8 +321,9 @@ eik_status eik_dd_solve_batch(int32_t nprob, const eik_grid* grids, const void* 
  *   dL_dr_out  device, N, grid dtype (overwritten)
  *   lambda_out device, nb x N, or NULL
  *   stats      host or NULL: sweeps, ms_total
- * Returns EIK_ERR_NOCONV if max_sweeps was reached.  This build: d = 2
- * (d = 3 gives EIK_ERR_UNSUPPORTED). */
+ * d = 3: three axes, six terms in the order x-, x+, y-, y+, z-, z+, and
+ * Gauss-Seidel sweeps in the eight orders of eik_solve in 3D.
+ * Returns EIK_ERR_NOCONV if max_sweeps was reached. */
 eik_status eik_adjoint_batch(const eik_grid* grid, const void* r, int32_t nb, const eik_gamma* gammas,
                              const void* u, const int8_t* wind, const void* dL_du, void* dL_dr_out,
                              void* lambda_out, int32_t max_sweeps, eik_stats* stats, void* hip_stream);

@@ -1746,6 +1746,152 @@ eik_status adjoint_t(const eik_grid* G, const void* rv, int32_t nb, const eik_ga
   return EIK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// travel-time gradient (adjoint), d = 3
+// ---------------------------------------------------------------------------
+
+template <typename T>
+eik_status adjoint3_t(const eik_grid* G, const void* rv, int32_t nb, const eik_gamma* gams, const void* uv,
+                      const int8_t* wind, const void* seedv, void* gradv, void* lamv, int32_t max_sweeps,
+                      eik_stats* st, hipStream_t s) {
+  int n[3];
+  for (int a = 0; a < 3; ++a) n[a] = (int)G->n[a];
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  const size_t szT = sizeof(T);
+  // largest box side whose lambda fits in LDS, then even box sides per axis
+  int Bmax = eik::kMaxL3;
+  while ((size_t)Bmax * Bmax * Bmax * szT > kLdsBytes) --Bmax;
+  int B = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int k = (n[a] + Bmax - 1) / Bmax;
+    B = std::max(B, (n[a] + k - 1) / k);
+  }
+  const size_t lds = (size_t)B * B * B * szT;
+  int nbx[3];
+  for (int a = 0; a < 3; ++a) nbx[a] = (n[a] + B - 1) / B;
+  const size_t nbox = (size_t)nbx[0] * nbx[1] * nbx[2];
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(EIK_ERR_HIP, "device id out of range");
+  std::lock_guard<std::mutex> lock(g_ws[dev].mu);
+  const int64_t NB = (int64_t)nb * N;
+  size_t need = (size_t)NB * (1 + 1) + 2 * 256;           // fixed, wd
+  need += (size_t)NB * szT * (3 + 1 + 6) + 3 * 256;       // c, q, pc
+  if (!lamv) need += (size_t)NB * szT + 256;
+  need += 2 * ((size_t)nb * nbox * sizeof(int) + 256);    // box stamps
+  need += 4096;
+  void* wsv;
+  unsigned long long* host;
+  eik_status e = ws_get(dev, need, &wsv, &host);
+  if (e != EIK_OK) return e;
+  Carver cv{(char*)wsv};
+  eik::ADJ3<T> A;
+  for (int a = 0; a < 3; ++a) { A.n[a] = n[a]; A.nbx[a] = nbx[a]; }
+  A.nb = nb;
+  A.B = B;
+  A.hT = (T)G->h;
+  A.r = as<T>(rv);
+  A.u = as<T>(uv);
+  A.w = wind;
+  A.seed = as<T>(seedv);
+  A.fixed = cv.take<uint8_t>(NB);
+  A.wd = cv.take<uint8_t>(NB);
+  A.c = cv.take<T>(3 * NB);
+  A.q = cv.take<T>(NB);
+  A.pc = cv.take<T>(6 * NB);
+  A.lam = lamv ? as<T>(lamv) : cv.take<T>(NB);
+  A.grad = as<T>(gradv);
+  unsigned int* dflag = cv.take<unsigned int>(8);
+  A.changed = dflag + 1;
+  A.eval_at = cv.take<int>((size_t)nb * nbox);
+  A.chg_at = cv.take<int>((size_t)nb * nbox);
+  // the slowness and every boundary set are checked like the forward solve's
+  for (int b = 0; b < nb; ++b)
+    if ((e = validate<T>(A.r, N, &gams[b], dflag, host, s, G->h)) != EIK_OK) return e;
+  if ((e = allow_lds(eik::k_adj_sweep3<T>, lds)) != EIK_OK) return e;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } evg{e0, e1};
+  HIPCHK(hipEventRecord(e0, s));
+  const int bs = 256;
+  HIPCHK(hipMemsetAsync(A.fixed, 0, NB, s));
+  for (int b = 0; b < nb; ++b)
+    if (gams[b].count > 0)
+      hipLaunchKernelGGL(eik::k_adj_mark<T>, dim3(nblocks(gams[b].count, bs)), dim3(bs), 0, s,
+                         A.fixed + (int64_t)b * N, gams[b].idx, gams[b].count);
+  const dim3 gridN(nblocks(N, bs), nb);
+  hipLaunchKernelGGL(eik::k_adj_coef3<T>, gridN, dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_adj_pull3<T>, gridN, dim3(bs), 0, s, A);
+  hipLaunchKernelGGL(eik::k_fill<T>, dim3(nblocks(NB, bs)), dim3(bs), 0, s, A.lam, T(0), NB);
+  HIPCHK(hipMemsetAsync(A.eval_at, 0xff, (size_t)nb * nbox * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(A.chg_at, 0xff, (size_t)nb * nbox * sizeof(int), s));
+  HIPCHK(hipGetLastError());
+  const int ndiag = nbx[0] + nbx[1] + nbx[2] - 2;
+  // sweeps 4m .. 4m+3 share launches with the lags of eik_solve in 3D; a
+  // sweep without change leaves every problem stationary, so the later
+  // sweeps of its group change nothing and the count stops there
+  const int off[4] = {0, nbx[2] + 1, nbx[2] + 1 + nbx[1] + nbx[2], 2 * (nbx[2] + 1) + nbx[1] + nbx[2]};
+  int sw = 0, conv = 0;
+  while (sw < max_sweeps) {
+    const int nsw = std::min(4, max_sweeps - sw);
+    HIPCHK(hipMemsetAsync(A.changed, 0, 4 * sizeof(unsigned int), s));
+    for (int tau = 0; tau < off[nsw - 1] + ndiag; ++tau) {
+      eik::GridLaunch3 L{};
+      int nbk = 0;
+      for (int k = 0; k < nsw; ++k) {
+        const int d = tau - off[k];
+        if (d < 0 || d >= ndiag) continue;
+        L.dir[L.n] = (sw + k) & 7;
+        L.diag[L.n] = d;
+        L.t[L.n] = (sw + k) * ndiag + d;
+        L.chg_off[L.n] = k;
+        L.start[L.n] = nbk;
+        nbk += cells_on_diag(nbx, d);
+        ++L.n;
+      }
+      L.start[L.n] = nbk;
+      if (nbk == 0) continue;
+      hipLaunchKernelGGL(eik::k_adj_sweep3<T>, dim3(nbk, nb), dim3(eik::kBlock3), lds, s, A, L);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, A.changed, 4 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const unsigned int* hc = (const unsigned int*)host;
+    int k0 = -1;
+    for (int k = 0; k < nsw && k0 < 0; ++k)
+      if (hc[k] == 0) k0 = k;
+    if (k0 >= 0) {
+      sw += k0 + 1;
+      conv = 1;
+      break;
+    }
+    sw += nsw;
+  }
+  hipLaunchKernelGGL(eik::k_adj_grad3<T>, dim3(nblocks(N, bs)), dim3(bs), 0, s, A);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  if (st) {
+    st->iterations = 0;
+    st->converged = conv;
+    st->sweeps = sw;
+    st->fine_updates = (int64_t)sw * NB;
+    st->coarse_updates = 0;
+    st->final_residual = 0.0;
+    st->ms_total = ms;
+    st->ms_fine = ms;
+    st->ms_coarse = st->ms_correct = st->ms_causal = 0.f;
+  }
+  if (!conv) return fail(EIK_ERR_NOCONV, "adjoint sweeps not stationary after %d sweeps", max_sweeps);
+  return EIK_OK;
+}
+
 eik_status check_common(const eik_grid* G, const void* r, const eik_gamma* gam, const void* out) {
   if (!G || !r || !gam || !out) return fail(EIK_ERR_ARG, "NULL argument");
   if (G->dim != 2 && G->dim != 3) return fail(EIK_ERR_ARG, "dim must be 2 or 3");
@@ -1814,8 +1960,40 @@ eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, cons
     eik_status e = check_common(grid, r, &gammas[b], u_out);
     if (e != EIK_OK) return e;
   }
-  if (grid->dim != 2) return fail(EIK_ERR_UNSUPPORTED, "eik_solve_batch: d = 3 is not implemented in this build");
   hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dim == 3) {
+    // the problems one after another on the stream, each a whole-grid 3D
+    // solve; stats[b]: problem b's sweeps and updates, the whole call's time
+    const int64_t N = grid->n[0] * grid->n[1] * grid->n[2];
+    const size_t szT = grid->dtype == EIK_F32 ? 4 : 8;
+    std::vector<eik_stats> one(nb);
+    float ms = 0.f;
+    int all_conv = 1;
+    for (int b = 0; b < nb; ++b) {
+      void* ub = (char*)u_out + (size_t)b * N * szT;
+      int8_t* wb = wind_out ? wind_out + (size_t)b * N : nullptr;
+      one[b] = eik_stats{};
+      const eik_status e = grid->dtype == EIK_F32
+                               ? solve3_t<float>(grid, r, &gammas[b], max_sweeps, ub, wb, &one[b], s)
+                               : solve3_t<double>(grid, r, &gammas[b], max_sweeps, ub, wb, &one[b], s);
+      if (e != EIK_OK && e != EIK_ERR_NOCONV) return e;
+      all_conv = all_conv && one[b].converged;
+      ms += one[b].ms_total;
+    }
+    if (stats)
+      for (int b = 0; b < nb; ++b) {
+        stats[b].iterations = 0;
+        stats[b].converged = one[b].converged;
+        stats[b].sweeps = one[b].sweeps;
+        stats[b].fine_updates = one[b].fine_updates;
+        stats[b].coarse_updates = 0;
+        stats[b].final_residual = 0.0;
+        stats[b].ms_total = stats[b].ms_fine = ms;
+        stats[b].ms_coarse = stats[b].ms_correct = stats[b].ms_causal = 0.f;
+      }
+    if (!all_conv) return fail(EIK_ERR_NOCONV, "no stationary sweep within %d sweeps", max_sweeps);
+    return EIK_OK;
+  }
   if (grid->dtype == EIK_F32) return solve_t<float>(grid, r, nb, gammas, max_sweeps, u_out, wind_out, stats, s);
   return solve_t<double>(grid, r, nb, gammas, max_sweeps, u_out, wind_out, stats, s);
 }
@@ -1847,8 +2025,12 @@ eik_status eik_adjoint_batch(const eik_grid* grid, const void* r, int32_t nb, co
   if (max_sweeps < 1) return fail(EIK_ERR_ARG, "max_sweeps must be >= 1");
   if (dL_dr_out == u || dL_dr_out == dL_du || (lambda_out && (lambda_out == u || lambda_out == dL_du)))
     return fail(EIK_ERR_ARG, "outputs must not alias inputs");
-  if (grid->dim != 2) return fail(EIK_ERR_UNSUPPORTED, "eik_adjoint: d = 3 is not implemented in this build");
   hipStream_t s = (hipStream_t)hip_stream;
+  if (grid->dim == 3) {
+    if (grid->dtype == EIK_F32)
+      return adjoint3_t<float>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);
+    return adjoint3_t<double>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);
+  }
   if (grid->dtype == EIK_F32)
     return adjoint_t<float>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);
   return adjoint_t<double>(grid, r, nb, gammas, u, wind, dL_du, dL_dr_out, lambda_out, max_sweeps, stats, s);

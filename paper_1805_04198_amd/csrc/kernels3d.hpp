@@ -1227,6 +1227,33 @@ __device__ __forceinline__ bool box_needed3(const int* eval_at, const int* chg_a
   return false;
 }
 
+// The box that block b of a whole-grid launch sweeps: the launch holds the
+// box diagonals GL.diag[g] of up to four sweeps (blocks [start[g],
+// start[g+1]) for sweep g), and a diagonal's boxes are taken by increasing
+// first, then second box index in sweep order.  Returns false for a block
+// past the last box.
+__device__ inline bool grid_box3(const GridLaunch3& GL, const int (&nb)[3], int b, int& g, int (&Tb)[3]) {
+  g = 0;
+  while (g + 1 < GL.n && b >= GL.start[g + 1]) ++g;
+  const int dir = GL.dir[g], diag = GL.diag[g];
+  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
+  int rem = b - GL.start[g];
+  int Iq = -1, Jq = -1, Kq = -1;
+  for (int i = max(0, diag - (nb[1] - 1) - (nb[2] - 1)); i <= min(diag, nb[0] - 1); ++i) {
+    const int r2 = diag - i;
+    const int jlo = max(0, r2 - (nb[2] - 1)), jhi = min(r2, nb[1] - 1);
+    const int cntj = jhi - jlo + 1;
+    if (cntj <= 0) continue;
+    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; break; }
+    rem -= cntj;
+  }
+  if (Iq < 0) return false;
+  Tb[0] = s[0] > 0 ? Iq : nb[0] - 1 - Iq;
+  Tb[1] = s[1] > 0 ? Jq : nb[1] - 1 - Jq;
+  Tb[2] = s[2] > 0 ? Kq : nb[2] - 1 - Kq;
+  return true;
+}
+
 template <typename T>
 __global__ void k_grid_init3(GS3<T> A) {
   const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
@@ -1242,24 +1269,10 @@ __global__ __launch_bounds__(kBlock3) void k_grid_sweep3(GS3<T> A, GridLaunch3 G
   extern __shared__ __align__(16) unsigned char smem[];
   // blocks [start[g], start[g+1]) take boxes of diagonal diag[g] of sweep g
   // of the launch (as the causal sweep's groups of directions)
-  int g = 0;
-  while (g + 1 < GL.n && (int)blockIdx.x >= GL.start[g + 1]) ++g;
-  const int dir = GL.dir[g], diag = GL.diag[g], t = GL.t[g];
+  int g, Tb[3];
+  if (!grid_box3(GL, A.nb, (int)blockIdx.x, g, Tb)) return;
+  const int dir = GL.dir[g], t = GL.t[g];
   A.changed += GL.chg_off[g];
-  const int s[3] = {(dir & 4) ? 1 : -1, (dir & 2) ? 1 : -1, (dir & 1) ? 1 : -1};
-  int rem = (int)blockIdx.x - GL.start[g];
-  int Iq = -1, Jq = -1, Kq = -1;
-  for (int i = max(0, diag - (A.nb[1] - 1) - (A.nb[2] - 1)); i <= min(diag, A.nb[0] - 1); ++i) {
-    const int r2 = diag - i;
-    const int jlo = max(0, r2 - (A.nb[2] - 1)), jhi = min(r2, A.nb[1] - 1);
-    const int cntj = jhi - jlo + 1;
-    if (cntj <= 0) continue;
-    if (rem < cntj) { Iq = i; Jq = jlo + rem; Kq = r2 - Jq; break; }
-    rem -= cntj;
-  }
-  if (Iq < 0) return;
-  const int Tb[3] = {s[0] > 0 ? Iq : A.nb[0] - 1 - Iq, s[1] > 0 ? Jq : A.nb[1] - 1 - Jq,
-                     s[2] > 0 ? Kq : A.nb[2] - 1 - Kq};
   if (!box_needed3(A.eval_at, A.chg_at, Tb, A.nb)) return;
   int o[3], L[3];
   for (int a = 0; a < 3; ++a) {

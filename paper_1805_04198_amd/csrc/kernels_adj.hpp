@@ -1,4 +1,4 @@
-// Device code of the travel-time gradient (2D): the adjoint of the
+// Device code of the travel-time gradient (2D and 3D): the adjoint of the
 // converged upwind system (eq. godonuv) for a batch of problems that share
 // the grid and the slowness (one per source).
 //
@@ -8,7 +8,7 @@
 //     c_a = (u - u_a) / S,   q = (r h) h / S,
 // and the adjoint field solves  lambda(y) = s(y) + sum of the terms
 // pm_0 lambda(y - e_0), pp_0 lambda(y + e_0), pm_1 lambda(y - e_1),
-// pp_1 lambda(y + e_1)  (in that order; pm_a is c_a of the node y - e_a if
+// pp_1 lambda(y + e_1) (, pm_2, pp_2 in 3D)  (in that order; pm_a is c_a of the node y - e_a if
 // that node uses y, pp_a the same for y + e_a; a term is exactly 0 where its
 // coefficient is 0).  The gradient is dL/dr = sum over the batch (in order)
 // of lambda_b q_b.  The system is triangular in decreasing u; it is solved
@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "kernels2d.hpp"
+#include "kernels3d.hpp"
 
 namespace eik {
 
@@ -267,6 +268,215 @@ __global__ __launch_bounds__(kBlock) void k_adj_sweep(ADJ2<T> A, GridLaunch2 L) 
 template <typename T>
 __global__ void k_adj_grad(ADJ2<T> A) {
   const int64_t N = (int64_t)A.n0 * A.n1;
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  T acc = T(0);
+  for (int b = 0; b < A.nb; ++b) acc = acc + A.lam[(int64_t)b * N + x] * A.q[(int64_t)b * N + x];
+  A.grad[x] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// 3D: the same equations with three axes; the whole grid is swept in boxes
+// of side B held in LDS (as eik_solve in 3D), eight orders.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct ADJ3 {
+  int n[3];
+  int nb;             // problems in the batch
+  int B;              // sweep box side
+  int nbx[3];         // boxes per axis
+  T hT;
+  const T* r;
+  const T* u;         // [nb][N]
+  const int8_t* w;    // [nb][N] wind codes (2 bits per axis), or NULL: recomputed from u
+  const T* seed;      // [nb][N] dL/du
+  uint8_t* fixed;     // [nb][N] Gamma flags
+  T* c;               // [nb][3][N] c_a of each node's own equation
+  uint8_t* wd;        // [nb][N] used wind codes
+  T* q;               // [nb][N] du/dr
+  T* pc;              // [nb][6][N] pm_0, pp_0, pm_1, pp_1, pm_2, pp_2
+  T* lam;             // [nb][N]
+  T* grad;            // [N]
+  unsigned int* changed;
+  int* eval_at;       // [nb][box] as in GS3 (box_needed3)
+  int* chg_at;
+};
+
+// the coefficients of node x's own equation (problem blockIdx.y)
+template <typename T>
+__global__ void k_adj_coef3(ADJ3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= N) return;
+  const int64_t o = (int64_t)blockIdx.y * N;
+  const T* u = A.u + o;
+  const T inf = pinf<T>();
+  T ca[3] = {T(0), T(0), T(0)};
+  T qv = T(0);
+  uint8_t code = 0;
+  const T ux = u[x];
+  const int64_t st[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
+  if (!A.fixed[o + x] && ux < inf) {
+    const int c[3] = {(int)(x % A.n[0]), (int)((x / A.n[0]) % A.n[1]), (int)(x / st[2])};
+    int wt[3];
+    if (A.w) {
+      const uint8_t cw = (uint8_t)A.w[o + x];
+      for (int a = 0; a < 3; ++a) wt[a] = w_of(cw, a);
+    } else {
+      // fine wind rule (the used axes of the local solve) on the final values
+      T m[3];
+      int ws[3];
+      for (int a = 0; a < 3; ++a) {
+        const T lo = c[a] > 0 ? u[x - st[a]] : inf;
+        const T hi = c[a] < A.n[a] - 1 ? u[x + st[a]] : inf;
+        const bool lt = lo < hi;
+        m[a] = lt ? lo : hi;
+        ws[a] = lt ? 1 : -1;
+      }
+      uint8_t cw;
+      (void)godunov3<T, false>(m, ws, A.r[x] * A.hT, cw);
+      for (int a = 0; a < 3; ++a) wt[a] = w_of(cw, a);
+    }
+    // S in axis order, starting from the first used axis
+    T S = T(0), ua[3] = {T(0), T(0), T(0)};
+    bool first = true;
+    for (int a = 0; a < 3; ++a) {
+      if (wt[a] == 0) continue;
+      ua[a] = u[x - wt[a] * st[a]];
+      S = first ? (ux - ua[a]) : (S + (ux - ua[a]));
+      first = false;
+    }
+    if (!first && S > T(0)) {
+      for (int a = 0; a < 3; ++a)
+        if (wt[a] != 0) ca[a] = (ux - ua[a]) / S;
+      qv = ((A.r[x] * A.hT) * A.hT) / S;
+      code = wenc3(wt[0], wt[1], wt[2]);
+    }
+  }
+  for (int a = 0; a < 3; ++a) A.c[o * 3 + a * N + x] = ca[a];
+  A.q[o + x] = qv;
+  A.wd[o + x] = code;
+}
+
+// pull coefficients of node y: the coefficients of its neighbours that use it
+template <typename T>
+__global__ void k_adj_pull3(ADJ3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t y = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (y >= N) return;
+  const int64_t o = (int64_t)blockIdx.y * N;
+  const int64_t st[3] = {1, A.n[0], (int64_t)A.n[0] * A.n[1]};
+  const int c[3] = {(int)(y % A.n[0]), (int)((y / A.n[0]) % A.n[1]), (int)(y / st[2])};
+  const uint8_t* wd = A.wd + o;
+  const T* ca = A.c + o * 3;
+  T* pc = A.pc + o * 6;
+  for (int a = 0; a < 3; ++a) {
+    const T* cc = ca + a * N;
+    // y - e_a uses y when its wind along a is -1; y + e_a when it is +1
+    pc[(2 * a) * N + y] = (c[a] > 0 && w_of(wd[y - st[a]], a) == -1) ? cc[y - st[a]] : T(0);
+    pc[(2 * a + 1) * N + y] = (c[a] < A.n[a] - 1 && w_of(wd[y + st[a]], a) == 1) ? cc[y + st[a]] : T(0);
+  }
+}
+
+// One directional sweep of the boxes of a whole-grid launch (grid_box3),
+// problem blockIdx.y: lambda(y) = s(y) + the six terms in order, direct
+// assignment.  Neighbours outside the box come from global memory (upwind
+// boxes finished, downwind boxes untouched); a term whose coefficient is 0
+// reads nothing (outside the grid every coefficient is 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock3) void k_adj_sweep3(ADJ3<T> A, GridLaunch3 GL) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int g, Tb[3];
+  if (!grid_box3(GL, A.nbx, (int)blockIdx.x, g, Tb)) return;
+  const int dir = GL.dir[g], t = GL.t[g];
+  unsigned int* changed = A.changed + GL.chg_off[g];
+  const int nbox = A.nbx[0] * A.nbx[1] * A.nbx[2];
+  // lambda(y) is a function of its neighbours only, so the stationary-box
+  // test of the forward sweeps applies unchanged
+  int* eval_at = A.eval_at + (int64_t)blockIdx.y * nbox;
+  int* chg_at = A.chg_at + (int64_t)blockIdx.y * nbox;
+  if (!box_needed3(eval_at, chg_at, Tb, A.nbx)) return;
+  int o3[3], L[3];
+  for (int a = 0; a < 3; ++a) {
+    o3[a] = Tb[a] * A.B;
+    L[a] = min(A.B, A.n[a] - o3[a]);
+  }
+  const int cnt = L[0] * L[1] * L[2];
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
+  const int64_t o = (int64_t)blockIdx.y * N;
+  T* lamg = A.lam + o;
+  T* lam = (T*)smem;
+  const int64_t base = idx3(A.n, o3[0], o3[1], o3[2]);
+  const int64_t gs1 = A.n[0], gs2 = (int64_t)A.n[0] * A.n[1];
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    lam[x] = lamg[base + p0 + p1 * gs1 + p2 * gs2];
+  }
+  __syncthreads();
+  struct Rule {
+    T* u;  // lambda of the box
+    int L0, L1, L2;
+    const T* lamg;
+    const T* s;
+    const T* pc;
+    int64_t N, base, gs1, gs2;
+    struct In {
+      T s, p[6];  // seed; pm_0, pp_0, pm_1, pp_1, pm_2, pp_2
+    };
+    __device__ In load(int i, int j, int k) const {
+      const int64_t X = base + i + j * gs1 + k * gs2;
+      In in;
+      in.s = s[X];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) in.p[e] = pc[e * N + X];
+      return in;
+    }
+    __device__ bool update(int i, int j, int k, const In& in) const {
+      const int64_t X = base + i + j * gs1 + k * gs2;
+      const int x = i + L0 * (j + L1 * k);
+      const int c[3] = {i, j, k};
+      const int L[3] = {L0, L1, L2};
+      const int st[3] = {1, L0, L0 * L1};
+      const int64_t gst[3] = {1, gs1, gs2};
+      T acc = T(0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T pm = in.p[2 * a], pp = in.p[2 * a + 1];
+        T tm = T(0), tp = T(0);
+        if (pm != T(0)) tm = pm * (c[a] > 0 ? u[x - st[a]] : lamg[X - gst[a]]);
+        if (pp != T(0)) tp = pp * (c[a] < L[a] - 1 ? u[x + st[a]] : lamg[X + gst[a]]);
+        acc = a == 0 ? tm : acc + tm;
+        acc = acc + tp;
+      }
+      const T v = in.s + acc;
+      if (v != u[x]) {
+        u[x] = v;
+        return true;
+      }
+      return false;
+    }
+  } R{lam, L[0], L[1], L[2], lamg, A.seed + o, A.pc + o * 6, N, base, gs1, gs2};
+  Range3 P{0, L[0] + L[1] + L[2] - 3};
+  const bool ch = sweep3(R, L[0], L[1], L[2], dir, dir, P);
+  for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+    const int p0 = x % L[0], p1 = (x / L[0]) % L[1], p2 = x / (L[0] * L[1]);
+    lamg[base + p0 + p1 * gs1 + p2 * gs2] = lam[x];
+  }
+  if (threadIdx.x == 0) {
+    const int bidx = Tb[0] + A.nbx[0] * (Tb[1] + A.nbx[1] * Tb[2]);
+    eval_at[bidx] = t;
+    if (ch) {
+      chg_at[bidx] = t;
+      atomicOr(changed, 1u);
+    }
+  }
+}
+
+// dL/dr = sum over the batch, in order, of lambda_b q_b
+template <typename T>
+__global__ void k_adj_grad3(ADJ3<T> A) {
+  const int64_t N = (int64_t)A.n[0] * A.n[1] * A.n[2];
   const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (x >= N) return;
   T acc = T(0);

@@ -165,11 +165,20 @@ def test_solve_batch_equals_single_solves(dtype):
         assert info[b]["sweeps"] == i1["sweeps"]
 
 
-def test_adjoint_errors():
-    p = W.random_problem(12, (9, 9, 9), 1, 1)
+@pytest.mark.parametrize("n", [(9, 9), (9, 9, 9)])
+def test_adjoint_errors(n):
+    p = W.random_problem(12, n, 1, 1)
     r = dev(p.r, np.float64)
     gams = [(torch.tensor([0]).cuda(), torch.zeros(1, dtype=r.dtype).cuda())]
-    u = torch.zeros((1,) + p.r.shape, dtype=r.dtype).cuda()
+    u, _, _ = E.solve(r, gams[0][0], gams[0][1], p.h)
+    u = u.reshape((1,) + p.r.shape)
+    seed_ = torch.ones_like(u)
     with pytest.raises(E.EikError) as ei:
-        E.adjoint(r, gams, u, u.clone(), p.h)
-    assert ei.value.status == E.EIK_ERR_UNSUPPORTED
+        E.adjoint(r, gams, u, seed_, p.h, max_sweeps=0)
+    assert ei.value.status == E.EIK_ERR_ARG
+    # the first sweep changes every free lambda, so a cap of one sweep is
+    # reported (the outputs are written, the status says the cap was hit)
+    _, _, info = E.adjoint(r, gams, u, seed_, p.h, max_sweeps=1)
+    assert info["status"] == E.EIK_ERR_NOCONV and not info["converged"]
+    _, _, info = E.adjoint(r, gams, u, seed_, p.h)
+    assert info["status"] == E.EIK_OK and info["converged"]
