@@ -280,10 +280,12 @@ eik_status eik_solve_batch(const eik_grid* grid, const void* r, int32_t nb, cons
                            void* hip_stream);
 
 /* eik_dd_solve_batch -- eik_dd_solve on nprob independent problems at once
- * (d = 2, one dtype; the subdomains of Sec. 3.2 and the problems are all
- * independent work): every DD step is one launch over the subdomains,
- * lattices and causal-sweep segments of all problems that have not yet
- * converged, and one readback per iteration serves all residuals.  Problem
+ * (one dtype; the subdomains of Sec. 3.2 and the problems are all
+ * independent work).  d = 2: every DD step is one launch over the
+ * subdomains, lattices and causal-sweep segments of all problems that have
+ * not yet converged, and one readback per iteration serves all residuals.
+ * d = 3 (every problem 3D; mixing 2D and 3D gives EIK_ERR_UNSUPPORTED): the
+ * problems run one after another on the stream.  Problem
  * p stops like its own eik_dd_solve would (its tol / max_iter), and its
  * outputs are exactly those of eik_dd_solve(grids[p], r[p], &gammas[p],
  * &opts[p], u_out[p], U_out[p], W_out[p]).

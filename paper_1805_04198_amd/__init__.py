@@ -286,9 +286,10 @@ def solve_batch(r, gammas, h, max_sweeps: int = 100000, with_wind: bool = False)
 def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
                    max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
                    theta_refs=None, history_cap: int = 4096, coarse_solver="godunov", launch: str = "stream"):
-    """eik_dd_solve_batch: the DD iteration on independent 2D problems at
-    once (every DD step is one launch over all problems that have not
-    converged).  rs: list of device slowness tensors (one dtype); gammas:
+    """eik_dd_solve_batch: the DD iteration on independent problems at once
+    (2D: every DD step is one launch over all problems that have not
+    converged; 3D: the problems one after another).  rs: list of device
+    slowness tensors (one dtype, all 2D or all 3D); gammas:
     list of (idx, val); hs: list of spacings; S, M, theta, tol, max_iter,
     theta_mode, coarse_solver: one value for all or a list.  launch: "stream" (one
     block per subdomain / lattice) or "persistent" (resident grids that take

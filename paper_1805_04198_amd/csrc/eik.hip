@@ -2002,11 +2002,49 @@ eik_status eik_dd_solve_batch(int32_t nprob, const eik_grid* grids, const void* 
                               const eik_dd_opts* opts, void* const* u_out, void* const* U_out, int8_t* const* W_out,
                               eik_stats* stats, void* hip_stream) {
   if (nprob < 1 || !grids || !r || !gammas || !opts || !u_out) return fail(EIK_ERR_ARG, "NULL argument or nprob < 1");
+  int n3 = 0;
   for (int p = 0; p < nprob; ++p) {
     eik_status e = check_common(&grids[p], r[p], &gammas[p], u_out[p]);
     if (e != EIK_OK) return e;
+    n3 += grids[p].dim == 3;
   }
   hipStream_t s = (hipStream_t)hip_stream;
+  if (n3 > 0) {
+    // 3D: the problems one after another on the stream, each exactly as its
+    // own eik_dd_solve (a 3D problem's subdomains and lattices fill the
+    // device by themselves); the device-time fields hold the batch's totals
+    if (n3 != nprob) return fail(EIK_ERR_UNSUPPORTED, "batch: 2D and 3D problems cannot be mixed");
+    for (int p = 0; p < nprob; ++p) {
+      if (grids[p].dtype != grids[0].dtype) return fail(EIK_ERR_ARG, "batch: all problems need the same dtype");
+      if (opts[p].debug) return fail(EIK_ERR_ARG, "problem %d: debug snapshots are not available in a batch", p);
+    }
+    eik_status agg = EIK_OK;
+    float tot[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    std::vector<eik_stats> own(nprob);
+    for (int p = 0; p < nprob; ++p) {
+      eik_stats* sp = stats ? &stats[p] : &own[p];
+      void* Up = U_out ? U_out[p] : nullptr;
+      int8_t* Wp = W_out ? W_out[p] : nullptr;
+      const eik_status e =
+          grids[0].dtype == EIK_F32
+              ? dd_solve3_t<float>(&grids[p], r[p], &gammas[p], &opts[p], u_out[p], Up, Wp, sp, s)
+              : dd_solve3_t<double>(&grids[p], r[p], &gammas[p], &opts[p], u_out[p], Up, Wp, sp, s);
+      if (e != EIK_OK && e != EIK_ERR_NOCONV) return e;
+      if (e == EIK_ERR_NOCONV) agg = e;
+      const float f[5] = {sp->ms_total, sp->ms_fine, sp->ms_coarse, sp->ms_correct, sp->ms_causal};
+      for (int k = 0; k < 5; ++k) tot[k] += f[k];
+    }
+    if (stats)
+      for (int p = 0; p < nprob; ++p) {
+        stats[p].ms_total = tot[0];
+        stats[p].ms_fine = tot[1];
+        stats[p].ms_coarse = tot[2];
+        stats[p].ms_correct = tot[3];
+        stats[p].ms_causal = tot[4];
+      }
+    if (agg != EIK_OK) return fail(agg, "batch: a problem reached its max_iter");
+    return EIK_OK;
+  }
   if (grids[0].dtype == EIK_F32)
     return dd_solve_batch_t<float>(nprob, grids, r, gammas, opts, u_out, U_out, W_out, stats, s);
   return dd_solve_batch_t<double>(nprob, grids, r, gammas, opts, u_out, U_out, W_out, stats, s);

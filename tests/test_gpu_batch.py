@@ -101,3 +101,36 @@ def test_batch_argument_errors():
     with pytest.raises(E.EikError) as ei:
         E.dd_solve_batch([r, r], [g, g], [p.h, p.h], [16, 12], 8, max_iter=2)
     assert ei.value.status == E.EIK_ERR_SHAPE
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batch3d_equals_single_solves_and_oracle(dtype):
+    """3D problems in a batch run one after another: each gives exactly its
+    own eik_dd_solve's results, and the first the oracle's."""
+    cases = [dict(seed=94, n=(17, 17, 17), S=8, M=4, theta=0.3, mode="constant"),
+             dict(seed=95, n=(25, 17, 33), S=8, M=4, theta=0.5, mode="estimate"),
+             dict(seed=96, n=(33, 33, 17), S=16, M=8, theta=0.25, mode="constant")]
+    probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=2) for c in cases]
+    tol = 1e-6 if dtype == np.float32 else 1e-12
+    rs, gams = zip(*[inputs(p, dtype) for p in probs])
+    print(f"batch 3D dtype={np.dtype(dtype).name}", flush=True)
+    B = E.dd_solve_batch(list(rs), list(gams), [p.h for p in probs], [c["S"] for c in cases],
+                         [c["M"] for c in cases], theta=[c["theta"] for c in cases], tol=tol, max_iter=40,
+                         theta_mode=[c["mode"] for c in cases])
+    for i, (c, p) in enumerate(zip(cases, probs)):
+        S_ = E.dd_solve(rs[i], gams[i][0], gams[i][1], p.h, c["S"], c["M"], theta=c["theta"], tol=tol,
+                        max_iter=40, theta_mode=c["mode"])
+        b = B[i]
+        assert b["iterations"] == S_["iterations"] and b["converged"] == S_["converged"], i
+        assert b["fine_updates"] == S_["fine_updates"] and b["coarse_updates"] == S_["coarse_updates"]
+        assert b["residuals"] == S_["residuals"]
+        assert same_t(b["u"], S_["u"]) and same_t(b["U"], S_["U"]) and torch.equal(b["W"], S_["W"]), i
+    p, c = probs[0], cases[0]
+    O = oracle.dd(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, c["S"], c["M"], theta=c["theta"], tol=tol, max_iter=40,
+                  dtype=dtype)
+    assert np.array_equal(B[0]["u"].cpu().numpy().reshape(-1), O["u"], equal_nan=True)
+    assert B[0]["iterations"] == O["iterations"]
+    r2, g2 = inputs(W.random_problem(97, (33, 33), 16, 8), dtype)
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve_batch([rs[0], r2], [gams[0], g2], [p.h, 1 / 32], [8, 16], [4, 8], max_iter=2)
+    assert ei.value.status == E.EIK_ERR_UNSUPPORTED
