@@ -228,8 +228,8 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
  * This build: d = 2 with subdomain side S+1 <= 65 nodes and lattice extents
  * (n-1)/M + 1 <= 65; d = 3 with S+1 <= 34 and (n-1)/M + 1 <= 34 and the box
  * in 160 KB of LDS ((S+1)^3 values of the grid dtype); with a non-constant
- * theta_mode in 2D, a 65-node lattice fits only in fp32 (else
- * EIK_ERR_UNSUPPORTED). */
+ * theta_mode on 65-node lattices in fp64, Step 4 keeps its per-node weight
+ * terms in global memory (they do not fit in LDS beside the lattice). */
 eik_status eik_dd_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma,
                         const eik_dd_opts* opts, void* u_out, void* U_out, int8_t* W_out,
                         eik_stats* stats, void* hip_stream);

@@ -43,10 +43,15 @@ constexpr size_t kLdsBytes = 160 * 1024;
 // LDS bytes of the lattice kernels (Steps 1 and 4) for NI x NJ coarse cells;
 // packed: whether Step 4 runs on its fp32 records (CorrRecF32: fp32 with a
 // constant weight, 150 KB at the fixed 65-node geometry)
-inline size_t lattice_lds(int NI, int NJ, int tmode, size_t szT, bool& packed) {
+// LDS bytes of the lattice kernels.  Step 4 holds two doubles more per node
+// when the weight varies; where that does not fit (fp64, 65 x 65) they go to
+// global memory instead (tglob: halo_count doubles twice per lattice).
+inline size_t lattice_lds(int NI, int NJ, int tmode, size_t szT, bool& packed, bool& tglob) {
   const int cnt = eik::halo_count(NI + 1, NJ + 1);
-  // Step 4 holds two doubles more per node when the weight varies
-  const size_t step4 = eik::box_bytes(cnt, 4, 1, szT) + (tmode ? eik::box_bytes(cnt, 2, 0, 8) : 0);
+  const size_t base4 = eik::box_bytes(cnt, 4, 1, szT);
+  size_t step4 = base4 + (tmode ? eik::box_bytes(cnt, 2, 0, 8) : 0);
+  tglob = tmode != 0 && step4 > kLdsBytes && base4 <= kLdsBytes;
+  if (tglob) step4 = base4;
   const size_t step1 = eik::box_bytes(cnt, 2, 1, szT);
   packed = szT == 4 && tmode == 0 && eik::corr_f32_lds_bytes() <= kLdsBytes;
   return std::max(packed ? eik::corr_f32_lds_bytes() : step4, step1);
@@ -280,8 +285,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   eik_status e = check_weight_solver(o);
   if (e != EIK_OK) return e;
   const int tmode = o->theta_mode;
-  bool corr_packed = false;
-  const size_t lds_lat = lattice_lds(NI, NJ, tmode, szT, corr_packed);
+  bool corr_packed = false, tglob = false;
+  const size_t lds_lat = lattice_lds(NI, NJ, tmode, szT, corr_packed, tglob);
   const int nC = (NI + 1) * (NJ + 1);
   const size_t lds_cb = eik::corner_lds_bytes(NI + 1, NJ + 1, szT);
   if (lds_tile > kLdsBytes || lds_cb > kLdsBytes)
@@ -308,6 +313,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   need += 3 * nC * szT + 2 * nC + (nH + nV) * (szT + 1) + 4096;
   need += 4096;
   if (tmode == EIK_THETA_ESTIMATE) need += 4 * (N * szT + 256);  // u^{k-1}, C^k, C^{k-1}, C^{k-2}
+  const int tg_stride = eik::halo_count(NI + 1, NJ + 1);
+  if (tglob) need += (size_t)(2 * M - 1) * 2 * tg_stride * sizeof(double) + 256;  // Step 4 weight terms
   void* wsv;
   unsigned long long* host;
   e = noalloc ? scratch_get(dev, need, &wsv, &host) : ws_get(dev, need, &wsv, &host);
@@ -357,6 +364,8 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   A.theta_mode = tmode;
   A.coarse_homog = o->coarse_solver;
   A.corr_packed = corr_packed ? 1 : 0;
+  A.tglob = tglob ? cv.take<double>((size_t)(2 * M - 1) * 2 * tg_stride) : nullptr;
+  A.tglob_stride = tglob ? tg_stride : 0;
   A.res_out = nullptr;   // set per DD iteration
   A.res_prev = nullptr;  // Step 1 always runs
   A.tol = o->tol;
@@ -592,6 +601,7 @@ struct BatchProb {
   size_t lds_tile = 0, lds_lat = 0, lds_cb = 0;
   int tmode = 0;
   bool corr_packed = false;  // Step 4's CorrPack records (lattice_lds)
+  bool tglob = false;        // Step 4's weight terms in global memory (lattice_lds)
   T* hist_u = nullptr;
   T* hist_c[3] = {nullptr, nullptr, nullptr};
   T* gfull = nullptr;
@@ -647,7 +657,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     q.tmode = op->theta_mode;
     const int L = S + 1;
     q.lds_tile = eik::tile_lds_bytes(L, szT);
-    q.lds_lat = lattice_lds(NI, NJ, q.tmode, szT, q.corr_packed);
+    q.lds_lat = lattice_lds(NI, NJ, q.tmode, szT, q.corr_packed, q.tglob);
     q.lds_cb = eik::corner_lds_bytes(NI + 1, NJ + 1, szT);
     if (q.lds_tile > kLdsBytes || q.lds_lat > kLdsBytes || q.lds_cb > kLdsBytes)
       return fail(EIK_ERR_UNSUPPORTED, "problem %d: LDS footprint too large", p);
@@ -672,6 +682,7 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     nd += (size_t)q.ntile * 4 * L * (szT + 1) + 512;
     nd += 3 * q.nC * szT + 2 * q.nC + (q.nH + q.nV) * (szT + 1) + 4096;
     if (q.tmode == EIK_THETA_ESTIMATE) nd += 4 * (q.N * szT + 256);
+    if (q.tglob) nd += (size_t)q.nlat * 2 * eik::halo_count(NI + 1, NJ + 1) * sizeof(double) + 256;
     need += nd;
     tot_tile += q.ntile;
     tot_lat += q.nlat;
@@ -756,6 +767,9 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     A.theta_mode = q.tmode;
     A.coarse_homog = op->coarse_solver;
     A.corr_packed = q.corr_packed ? 1 : 0;
+    const int tg_stride = eik::halo_count(A.NI + 1, A.NJ + 1);
+    A.tglob = q.tglob ? cv.take<double>((size_t)q.nlat * 2 * tg_stride) : nullptr;
+    A.tglob_stride = q.tglob ? tg_stride : 0;
     A.res_out = A.counters + 2;  // read back after every iteration
     A.res_prev = nullptr;        // the batch checks on the host
     A.tol = op->tol;

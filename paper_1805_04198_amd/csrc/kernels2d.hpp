@@ -1154,6 +1154,10 @@ struct DD2 {
   // node, and the history u^{k-1}, C^{k-1}, C^{k-2} (NULL until it exists);
   // this iteration's C^k goes to ck_out
   int theta_mode;
+  // Step 4's weight terms in global memory (2 x tglob_stride doubles per
+  // lattice) when they do not fit in LDS; NULL: in LDS
+  double* tglob = nullptr;
+  int tglob_stride = 0;
   ThetaPar tq;
   const T* tref;
   const T* ukm1;
@@ -1507,11 +1511,12 @@ __device__ __forceinline__ void lattice_correct_f32(const DD2<float>& A, int bx)
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
 }
 
-template <typename T>
-__device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
+// TG: the weight terms (varying theta) in global memory, A.tglob, where
+// they do not fit in LDS beside the lattice (fp64 lattices of 65 x 65)
+template <typename T, bool TG>
+__device__ __forceinline__ void lattice_correct_body_t(const DD2<T>& A, int bx) {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (dd_stopped(A)) return;
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4 && !TG) {
     if (A.corr_packed) {
       lattice_correct_f32(A, bx);
       return;
@@ -1526,8 +1531,15 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   // the packed records, then the weight terms, come first (16- and 8-byte
   // alignment)
   CorrPack* pk = (sizeof(T) == 4 && A.corr_packed) ? carve<CorrPack>(lc, cnt) : nullptr;
-  double* ta = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
-  double* tb = A.theta_mode != 0 ? carve<double>(lc, cnt) : nullptr;
+  double* ta = nullptr;
+  double* tb = nullptr;
+  if constexpr (TG) {
+    ta = A.tglob + (size_t)bx * 2 * A.tglob_stride;
+    tb = ta + A.tglob_stride;
+  } else if (A.theta_mode != 0) {
+    ta = carve<double>(lc, cnt);
+    tb = carve<double>(lc, cnt);
+  }
   T* u = carve<T>(lc, cnt);
   T* uk = carve<T>(lc, cnt);
   T* ck = carve<T>(lc, cnt);
@@ -1624,7 +1636,7 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
   __syncthreads();
   if (fsm_wave()) {
     int ns;
-    switch (A.theta_mode) {
+    switch (TG ? (A.theta_mode == 0 ? 1 : A.theta_mode) : A.theta_mode) {  // TG: theta varies
       case 0: {
         if constexpr (sizeof(T) == 4) {
           if (pk) {
@@ -1672,6 +1684,14 @@ __device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
     atomicAdd(&A.sweep_prof[3], (unsigned long long)ps.lcyc);
   }
   if (threadIdx.x == 0 && ps.err) atomicOr(&A.counters[3], 1ull);  // a two-wave wait gave up
+}
+template <typename T>
+__device__ __forceinline__ void lattice_correct_body(const DD2<T>& A, int bx) {
+  if (dd_stopped(A)) return;
+  if (A.tglob)
+    lattice_correct_body_t<T, true>(A, bx);
+  else
+    lattice_correct_body_t<T, false>(A, bx);
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_lattice_correct(DD2<T> A) { lattice_correct_body(A, (int)blockIdx.x); }

@@ -104,17 +104,37 @@ def test_config1_estimate_to_convergence(dtype):
     assert np.max(np.abs(u - uf)) <= bound
 
 
-def test_config2_estimate_fp32_first_iterations_and_fp64_lds_limit():
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_config2_estimate_first_iterations(dtype):
+    """65 x 65 lattices: in fp64 Step 4's weight terms do not fit in LDS
+    beside the lattice and are kept in global memory."""
     p = W.config2()
-    print("config2 estimate fp32 4 iterations", flush=True)
-    G, O = run_pair(p, np.float32, 0.25, 4, "estimate")
+    print(f"config2 estimate {np.dtype(dtype).name} 4 iterations", flush=True)
+    G, O = run_pair(p, dtype, 0.25, 4, "estimate")
     compare(G, O, 2)
+
+
+@pytest.mark.parametrize("mode", ["estimate", "reference", "field"])
+def test_theta_modes_fp64_65_node_lattices(mode):
+    """129^2 with M = 2: 65 x 65 lattices, weight terms in global memory in
+    fp64; single solve and the same problem in a batch, bitwise."""
+    p = W.random_problem(63, (129, 129), 16, 2, n_src=2, kind="fourier")
+    print(f"fp64 65-node lattices mode={mode}", flush=True)
+    G, O = run_pair(p, np.float64, 0.3, 6, mode)
+    compare(G, O, 2)
+    ref = theta_ref_for(p, mode, np.float64)
     r = dev(p.r, np.float64)
-    gi = torch.from_numpy(p.gamma_idx).cuda()
-    gv = dev(p.gamma_val, np.float64)
-    with pytest.raises(E.EikError) as ei:
-        E.dd_solve(r, gi, gv, p.h, p.S, p.M, theta=0.25, max_iter=1, theta_mode="estimate")
-    assert ei.value.status == E.EIK_ERR_UNSUPPORTED
+    g = (torch.from_numpy(p.gamma_idx).cuda(), dev(p.gamma_val, np.float64))
+    q = W.random_problem(64, (65, 65), 16, 8, n_src=1)
+    rq = dev(q.r, np.float64)
+    gq = (torch.from_numpy(q.gamma_idx).cuda(), dev(q.gamma_val, np.float64))
+    refq = theta_ref_for(q, mode, np.float64)
+    refs = [None if x is None else dev(x, np.float64) for x in (ref, refq)]
+    B = E.dd_solve_batch([r, rq], [g, gq], [p.h, q.h], [16, 16], [2, 8], theta=0.3, tol=0.0, max_iter=6,
+                         theta_mode=mode, theta_refs=refs)
+    u = B[0]["u"].cpu().numpy().reshape(-1)
+    assert same(u, O["u"]), show_diff("batch u", u, O["u"])
+    assert B[0]["coarse_updates"] == O["coarse_updates"]
 
 
 CASES_3D = [
