@@ -40,6 +40,20 @@ __device__ __forceinline__ uint8_t wenc3(int wx, int wy, int wz) {
   return (uint8_t)((wx & 3) | ((wy & 3) << 2) | ((wz & 3) << 4));
 }
 
+// x / 3 rounded to nearest.  fp32: the product with RN(1/3) corrected once
+// by its exact remainder (Markstein's correction step: r = x - 3 q0 by one
+// fused multiply-add, then q0 + r RN(1/3) by another); checked against the
+// IEEE quotient for every finite float, where it differs only at x = -0
+// (it gives +0), which is passed through.  fp64: the IEEE quotient.
+__device__ __forceinline__ float div3(float x) {
+  const float third = 0x1.555556p-2f;  // RN(1/3)
+  const float q0 = x * third;
+  const float r = __builtin_fmaf(-q0, 3.0f, x);
+  const float q = __builtin_fmaf(r, third, q0);
+  return x == 0.0f ? x : q;
+}
+__device__ __forceinline__ double div3(double x) { return x / 3.0; }
+
 // 3D local solve.  m: per-axis neighbour minima; ws: their wind signs.
 // Coarse = false: fine wind, true: coarse wind.  homog (coarse only): the
 // homogenised solver of the squares medium (Sec. 5.3), the smallest
@@ -54,30 +68,24 @@ __device__ __forceinline__ T godunov3(const T (&m)[3], const int (&ws)[3], T rd,
   const T a1 = lo01 < m[2] ? lo01 : m[2];
   const T a3 = hi01 < m[2] ? m[2] : hi01;
   const T a2 = hi01 < m[2] ? hi01 : (lo01 < m[2] ? m[2] : lo01);
-  T ut;
-  int used;
+  // the one-, two- and three-term candidates are all evaluated and the
+  // cascade's choice selected (no branches; a lane whose choice does not
+  // need a square root takes the root of 1 there)
   const T d12 = a1 - a2;
-  if ((Coarse && homog) || !(dabs(d12) < rd)) {
-    ut = a1 + rd;
-    used = 1;
-  } else {
-    T t = rd * rd;
-    t = t + t;
-    t = t - d12 * d12;
-    const T u2 = ((a1 + a2) + dsqrt(t)) * T(0.5);
-    if (!(a3 < u2)) {
-      ut = u2;
-      used = 2;
-    } else {
-      const T d13 = a1 - a3, d23 = a2 - a3;
-      T q = rd * rd;
-      q = (q + q) + q;
-      q = q - ((d12 * d12 + d13 * d13) + d23 * d23);
-      if (q < T(0)) q = T(0);
-      ut = (((a1 + a2) + a3) + dsqrt(q)) / T(3);
-      used = 3;
-    }
-  }
+  const bool one = (Coarse && homog) || !(dabs(d12) < rd);
+  T t = rd * rd;
+  t = t + t;
+  t = t - d12 * d12;
+  const T u2 = ((a1 + a2) + dsqrt(one ? T(1) : t)) * T(0.5);
+  const bool two = !one && !(a3 < u2);
+  const T d13 = a1 - a3, d23 = a2 - a3;
+  T q = rd * rd;
+  q = (q + q) + q;
+  q = q - ((d12 * d12 + d13 * d13) + d23 * d23);
+  if (q < T(0)) q = T(0);
+  const T u3 = div3(((a1 + a2) + a3) + dsqrt((one || two) ? T(1) : q));
+  const T ut = one ? a1 + rd : (two ? u2 : u3);
+  const int used = one ? 1 : (two ? 2 : 3);
   int w0, w1, w2;
   if (!Coarse) {
     // the axes of the used terms: those whose rank in the stable ascending
@@ -322,7 +330,10 @@ __device__ int fsm3(Rule& R, int L0, int L1, int L2, int max_sweeps) {
   return s;
 }
 
-// neighbour minima of box node x=(i,j,k); missing neighbours are +inf
+// neighbour minima of box node x=(i,j,k); missing neighbours are +inf.  Both
+// reads of an axis always happen (the node itself stands in for a neighbour
+// outside the box) and a missing one is then replaced by +inf: selects, not
+// branches around the reads.
 template <typename T>
 __device__ __forceinline__ void gather3(const T* u, int L0, int L1, int L2, int i, int j, int k, T (&m)[3],
                                         int (&ws)[3]) {
@@ -333,8 +344,11 @@ __device__ __forceinline__ void gather3(const T* u, int L0, int L1, int L2, int 
   const int L[3] = {L0, L1, L2};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const T lo = c[a] > 0 ? u[x - st[a]] : inf;
-    const T hi = c[a] < L[a] - 1 ? u[x + st[a]] : inf;
+    const bool hl = c[a] > 0, hh = c[a] < L[a] - 1;
+    const T lo0 = u[hl ? x - st[a] : x];
+    const T hi0 = u[hh ? x + st[a] : x];
+    const T lo = hl ? lo0 : inf;
+    const T hi = hh ? hi0 : inf;
     const bool lt = lo < hi;
     m[a] = lt ? lo : hi;
     ws[a] = lt ? 1 : -1;
