@@ -5,7 +5,10 @@ warm-up call per candidate:
 
   * per problem size, the partition: subdomain side S and coarse spacing
     M = H/h (S from `sides`, M from `spacings` with S % M == 0 and lattices
-    of at most 65 nodes per axis), on the first problem of that size, at the
+    of at most 65 nodes per axis), timed as one batched solve of up to
+    `per_shape` problems of that size (a small batch, as the problems will
+    run: a partition with more subdomains fills the device better alone but
+    costs more iterations and work once the device is full), at the
     caller's weight theta.  Another partition changes the iterates but not
     the target: candidates that do not reach the tolerance within
     `max_iter` iterations are skipped, so every accepted run has converged
@@ -39,25 +42,30 @@ def candidates(n, sides=SIDES, spacings=SPACINGS):
     return out
 
 
-def tune(rs, gammas, hs, theta=0.1, tol=1e-6, max_iter=300, sides=SIDES, spacings=SPACINGS):
+def tune(rs, gammas, hs, theta=0.1, tol=1e-6, max_iter=300, sides=SIDES, spacings=SPACINGS, per_shape=4):
     """rs, gammas, hs as for dd_solve_batch.  Returns ({shape: (S, M)},
-    table of (shape, S, M, converged, iterations, ms))."""
+    table of (shape, S, M, converged, iterations, ms)); iterations: the
+    slowest problem of the shape's sample."""
     best, table = {}, []
     seen = {}
     for i, r in enumerate(rs):
-        shape = tuple(r.shape)
-        if shape not in seen:
-            seen[shape] = i
-    for shape, i in seen.items():
+        seen.setdefault(tuple(r.shape), []).append(i)
+    for shape, idx in seen.items():
         n = shape[::-1]
+        idx = idx[:per_shape]
+        sr = [rs[i] for i in idx]
+        sg = [gammas[i] for i in idx]
+        sh = [hs[i] for i in idx]
         pick = None
         for S, M in candidates(n, sides, spacings):
             kw = dict(theta=theta, tol=tol, max_iter=max_iter)
-            E.dd_solve(rs[i], gammas[i][0], gammas[i][1], hs[i], S, M, **kw)
-            R = E.dd_solve(rs[i], gammas[i][0], gammas[i][1], hs[i], S, M, **kw)
-            table.append((shape, S, M, R["converged"], R["iterations"], R["ms_total"]))
-            if R["converged"] and (pick is None or R["ms_total"] < pick[1]):
-                pick = ((S, M), R["ms_total"])
+            E.dd_solve_batch(sr, sg, sh, S, M, **kw)
+            B = E.dd_solve_batch(sr, sg, sh, S, M, **kw)
+            conv = all(b["converged"] for b in B)
+            ms = B[0]["ms_total"]
+            table.append((shape, S, M, conv, max(b["iterations"] for b in B), ms))
+            if conv and (pick is None or ms < pick[1]):
+                pick = ((S, M), ms)
         if pick is None:
             raise RuntimeError(f"no candidate converged for grid {n}")
         best[shape] = pick[0]
