@@ -293,15 +293,15 @@ def bench_config4(a):
     t0 = time.perf_counter()
     best, table = autotune.tune(rs, gams, hs, theta=th, tol=1e-6, max_iter=300)
     S, M = autotune.apply(rs, best)
-    launch, launch_ms = autotune.tune_launch(rs, gams, hs, S, M, theta=th, tol=1e-6, max_iter=600)
+    (launch, pblocks), launch_ms = autotune.tune_launch(rs, gams, hs, S, M, theta=th, tol=1e-6, max_iter=600)
     t_tune = time.perf_counter() - t0
     kw = dict(theta=th, tol=1e-6, max_iter=600)
     for _ in range(a.warmup):
-        E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, **kw)
+        E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, persistent_blocks=pblocks, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        B = E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, **kw)
+        B = E.dd_solve_batch(rs, gams, hs, S, M, launch=launch, persistent_blocks=pblocks, **kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fine = sum(b["fine_updates"] for b in B)
@@ -315,7 +315,7 @@ def bench_config4(a):
     extra = {"problems": len(P), "converged": sum(b["converged"] for b in B), "identical_to_single": same,
              "fine_updates_per_batch": fine, "ms_single_solves_total": t_single * 1e3,
              "speedup_vs_single_solves": t_single / (wall / a.steps), "autotune_s": t_tune,
-             "theta": th, "launch": launch, "launch_ms": launch_ms,
+             "theta": th, "launch": launch, "persistent_blocks": pblocks, "launch_ms": launch_ms,
              "tuned": {f"{k[1]}x{k[0]}": {"S": v[0], "M": v[1]} for k, v in best.items()},
              "tuning_table": [{"shape": f"{t[0][1]}x{t[0][0]}", "S": t[1], "M": t[2], "converged": t[3],
                                "iterations": t[4], "ms": t[5]} for t in table],

@@ -167,6 +167,10 @@ typedef struct {
                                 * the omegas are not stated there) */
     int32_t coarse_solver;     /* EIK_COARSE_*; 0 = C_H */
     int32_t launch_mode;       /* EIK_LAUNCH_*; 0 = stream launches, one block per box */
+    int32_t persistent_blocks; /* EIK_LAUNCH_PERSISTENT: resident blocks per compute unit for
+                                * Steps 3 and 4, capped at what fits (0 = as many as fit); each
+                                * block takes boxes until none is left, so fewer blocks means
+                                * more boxes per block.  >= 0 */
 } eik_dd_opts;
 
 /* Host-side statistics.  residual_history (host, may be NULL) receives

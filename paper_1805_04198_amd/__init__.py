@@ -56,7 +56,8 @@ class DDOpts(ctypes.Structure):
                 ("theta_mode", ctypes.c_int32), ("U_init", ctypes.c_void_p),
                 ("W_init", ctypes.c_void_p), ("debug", ctypes.POINTER(DDDebug)),
                 ("theta_ref", ctypes.c_void_p), ("theta_params", ctypes.c_double * 7),
-                ("coarse_solver", ctypes.c_int32), ("launch_mode", ctypes.c_int32)]
+                ("coarse_solver", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
+                ("persistent_blocks", ctypes.c_int32)]
 
 
 THETA_MODES = {"constant": 0, "estimate": 1, "reference": 2, "field": 3}
@@ -285,7 +286,8 @@ def solve_batch(r, gammas, h, max_sweeps: int = 100000, with_wind: bool = False)
 
 def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, max_fine_sweeps: int = 256,
                    max_coarse_sweeps: int = 32, theta_mode="constant", theta_params=THETA_PARAMS,
-                   theta_refs=None, history_cap: int = 4096, coarse_solver="godunov", launch: str = "stream"):
+                   theta_refs=None, history_cap: int = 4096, coarse_solver="godunov", launch: str = "stream",
+                   persistent_blocks: int = 0):
     """eik_dd_solve_batch: the DD iteration on independent problems at once
     (2D: every DD step is one launch over all problems that have not
     converged; 3D: the problems one after another).  rs: list of device
@@ -293,8 +295,9 @@ def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, ma
     list of (idx, val); hs: list of spacings; S, M, theta, tol, max_iter,
     theta_mode, coarse_solver: one value for all or a list.  launch: "stream" (one
     block per subdomain / lattice) or "persistent" (resident grids that take
-    the boxes from a counter; same results).  Returns a list of result dicts
-    as dd_solve, plus the batch's device time in each."""
+    the boxes from a counter; same results), with persistent_blocks resident
+    blocks per compute unit (0: as many as fit).  Returns a list of result
+    dicts as dd_solve, plus the batch's device time in each."""
     torch = _torch()
     L = load_library()
     P = len(rs)
@@ -325,6 +328,7 @@ def dd_solve_batch(rs, gammas, hs, S, M, theta=0.25, tol=1e-6, max_iter=None, ma
         o.theta_mode = THETA_MODES[modes[p]]
         o.coarse_solver = COARSE_SOLVERS[solvers[p]]
         o.launch_mode = LAUNCH_MODES[launch]
+        o.persistent_blocks = int(persistent_blocks)
         for q_, v in enumerate(theta_params):
             o.theta_params[q_] = float(v)
         if refs[p] is not None:

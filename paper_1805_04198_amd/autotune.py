@@ -17,8 +17,10 @@ warm-up call per candidate:
     stays the caller's choice.
   * for the whole batch, the launch schedule of Steps 3 and 4: one block
     per subdomain / lattice box ("stream") or resident grids whose blocks take
-    the boxes from a counter ("persistent").  The schedule changes nothing in
-    the results (each box is computed the same way), only the time.
+    the boxes from a counter ("persistent"), with as many blocks per compute
+    unit as fit or fewer (`PERSISTENT_BLOCKS`; fewer blocks take more boxes
+    each).  The schedule changes nothing in the results (each box is
+    computed the same way), only the time.
 """
 from __future__ import annotations
 
@@ -27,6 +29,7 @@ import paper_1805_04198_amd as E
 SIDES = (32, 64)
 SPACINGS = (16, 32, 64)
 LAUNCHES = ("stream", "persistent")
+PERSISTENT_BLOCKS = (0, 1, 2)  # resident blocks per compute unit; 0 = as many as fit
 MAX_NODES = 65
 
 
@@ -72,16 +75,28 @@ def tune(rs, gammas, hs, theta=0.1, tol=1e-6, max_iter=300, sides=SIDES, spacing
     return best, table
 
 
-def tune_launch(rs, gammas, hs, S, M, theta=0.1, tol=1e-6, max_iter=600, launches=LAUNCHES):
-    """The fastest launch schedule of the whole batch with partitions S, M
-    (lists).  Returns (launch, {launch: ms})."""
-    times = {}
+def launch_candidates(launches=LAUNCHES, blocks=PERSISTENT_BLOCKS):
+    """(launch, persistent_blocks) pairs to time: the stream schedule once,
+    the persistent one per grid size."""
+    out = []
     for lm in launches:
-        kw = dict(theta=theta, tol=tol, max_iter=max_iter, launch=lm)
+        for b in (blocks if lm == "persistent" else (0,)):
+            out.append((lm, b))
+    return out
+
+
+def tune_launch(rs, gammas, hs, S, M, theta=0.1, tol=1e-6, max_iter=600, launches=LAUNCHES,
+                blocks=PERSISTENT_BLOCKS):
+    """The fastest launch schedule of the whole batch with partitions S, M
+    (lists).  Returns ((launch, persistent_blocks), {"launch/blocks": ms})."""
+    times = {}
+    for lm, b in launch_candidates(launches, blocks):
+        kw = dict(theta=theta, tol=tol, max_iter=max_iter, launch=lm, persistent_blocks=b)
         E.dd_solve_batch(rs, gammas, hs, S, M, **kw)
         B = E.dd_solve_batch(rs, gammas, hs, S, M, **kw)
-        times[lm] = B[0]["ms_total"]
-    return min(times, key=times.get), times
+        times[(lm, b)] = B[0]["ms_total"]
+    best = min(times, key=times.get)
+    return best, {f"{lm}/{b}": t for (lm, b), t in times.items()}
 
 
 def apply(rs, best):

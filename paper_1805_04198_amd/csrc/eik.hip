@@ -246,6 +246,7 @@ eik_status check_weight_solver(const eik_dd_opts* o) {
     return fail(EIK_ERR_ARG, "theta_params: margin must be finite");
   if (o->launch_mode < EIK_LAUNCH_STREAM || o->launch_mode > EIK_LAUNCH_PERSISTENT)
     return fail(EIK_ERR_ARG, "launch_mode must be one of EIK_LAUNCH_*");
+  if (o->persistent_blocks < 0) return fail(EIK_ERR_ARG, "persistent_blocks must be >= 0");
   return EIK_OK;
 }
 
@@ -793,6 +794,10 @@ eik_status dd_solve_batch_t(int P, const eik_grid* G, const void* const* rv, con
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bt, eik::k_tile_b<T>, eik::kBlock, lds_tile));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bl, eik::k_lattice_correct_b<T>, eik::kBlock, lds_lat));
+    if (o[0].persistent_blocks > 0) {
+      bt = std::min(bt, o[0].persistent_blocks);
+      bl = std::min(bl, o[0].persistent_blocks);
+    }
     grid_tile = (int64_t)std::max(1, bt) * ncu;
     grid_lat = (int64_t)std::max(1, bl) * ncu;
   }

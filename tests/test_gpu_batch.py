@@ -36,7 +36,7 @@ MIX = [
 ]
 
 
-@pytest.mark.parametrize("launch", ["stream", "persistent"])
+@pytest.mark.parametrize("launch", ["stream", "persistent", "persistent/1"])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_batch_equals_single_solves(dtype, launch):
     probs = [W.random_problem(c["seed"], c["n"], c["S"], c["M"], n_src=2, kind=c["kind"]) for c in MIX]
@@ -48,9 +48,11 @@ def test_batch_equals_single_solves(dtype, launch):
         gams.append(g)
         refs.append(dev(np.full(p.r.shape, 0.35), dtype) if c["mode"] == "field" else None)
     print(f"batch of {len(probs)} dtype={np.dtype(dtype).name} launch={launch}", flush=True)
+    lm, _, nb = launch.partition("/")  # "persistent/1": one resident block per compute unit
     B = E.dd_solve_batch(rs, gams, [p.h for p in probs], [c["S"] for c in MIX], [c["M"] for c in MIX],
                          theta=[c["theta"] for c in MIX], tol=tol, max_iter=60,
-                         theta_mode=[c["mode"] for c in MIX], theta_refs=refs, launch=launch)
+                         theta_mode=[c["mode"] for c in MIX], theta_refs=refs, launch=lm,
+                         persistent_blocks=int(nb or 0))
     for i, (c, p) in enumerate(zip(MIX, probs)):
         S_ = E.dd_solve(rs[i], gams[i][0], gams[i][1], p.h, c["S"], c["M"], theta=c["theta"], tol=tol, max_iter=60,
                         theta_mode=c["mode"], theta_ref=refs[i])
@@ -101,6 +103,9 @@ def test_batch_argument_errors():
     with pytest.raises(E.EikError) as ei:
         E.dd_solve_batch([r, r], [g, g], [p.h, p.h], [16, 12], 8, max_iter=2)
     assert ei.value.status == E.EIK_ERR_SHAPE
+    with pytest.raises(E.EikError) as ei:
+        E.dd_solve_batch([r, r], [g, g], [p.h, p.h], 16, 8, max_iter=2, launch="persistent", persistent_blocks=-1)
+    assert ei.value.status == E.EIK_ERR_ARG
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])

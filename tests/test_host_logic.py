@@ -21,6 +21,25 @@ def test_autotune_candidates_respect_the_solver_limits():
     # the two the batch API offers
     assert not hasattr(autotune, "THETAS")
     assert set(autotune.LAUNCHES) == {"stream", "persistent"}
+    # the launch search: the stream schedule once, the persistent one per
+    # grid size (0 = as many resident blocks as fit)
+    lc = autotune.launch_candidates()
+    assert lc[0] == ("stream", 0) and len(lc) == len(set(lc))
+    assert {b for lm, b in lc if lm == "persistent"} == set(autotune.PERSISTENT_BLOCKS)
+    assert all(b >= 0 for _, b in lc)
+
+
+def test_options_struct_matches_the_header():
+    """The binding's eik_dd_opts mirrors include/eik.h field for field."""
+    import ctypes
+    import os
+    import re
+    import paper_1805_04198_amd as E
+    hdr = open(os.path.join(os.path.dirname(E.__file__), "..", "include", "eik.h")).read()
+    body = hdr[hdr.index("typedef struct {", hdr.index("eik_dd_debug;")):hdr.index("} eik_dd_opts;")]
+    names = re.findall(r"\b(\w+)(?:\[\d+\])?;", re.sub(r"/\*.*?\*/", "", body, flags=re.S))
+    assert [f[0] for f in E.DDOpts._fields_] == names
+    assert ctypes.sizeof(E.DDOpts) % 8 == 0
 
 
 def test_config4_generator():
