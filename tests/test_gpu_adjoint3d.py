@@ -148,3 +148,44 @@ def test_autograd_travel_times3d_matches_oracle_and_central_differences():
             lm = float(loss_of(rr.reshape(p.r.shape)))
             fd = (lp - lm) / (2 * eps)
             assert abs(fd - g[cidx]) <= 1e-5 * max(abs(fd), abs(g[cidx])) + 1e-9, (cidx, fd, g[cidx])
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_adjoint3d_face_source_bitwise(dtype):
+    """Gamma = the whole face z = 0 (every node there fixed, carrying no
+    equation); receivers on the opposite face."""
+    n = (19, 15, 23)
+    p = W.random_problem(26, n, 1, 1, kind="blocks", edge=2)
+    print(f"adjoint3d face source dtype={np.dtype(dtype).name}", flush=True)
+    u, w = oracle.fsm(p.n, p.h, p.r, p.gamma_idx, p.gamma_val, dtype=dtype)
+    rng = np.random.default_rng(27)
+    rc = np.array(face_nodes(n, n[2] - 1, 12, rng))
+    seed_ = np.zeros((1, u.size), dtype=dtype)
+    seed_[0, rc] = rng.uniform(-1, 1, rc.size).astype(dtype)
+    go, lo, _ = oracle.adjoint(p.n, p.h, p.r, [p.gamma_idx], u[None], seed_, winds=w[None], dtype=dtype)
+    shape = (1,) + p.r.shape
+    r = dev(p.r, dtype)
+    gams = [(torch.from_numpy(p.gamma_idx).cuda(), dev(p.gamma_val, dtype))]
+    grad, lam, info = E.adjoint(r, gams, dev(u, dtype).reshape(shape), dev(seed_, dtype).reshape(shape), p.h,
+                                wind=dev(encode3(w[None]), np.int8).reshape(shape), with_lambda=True)
+    assert info["converged"]
+    assert same(grad.cpu().numpy().reshape(-1), go), show_diff("grad", grad.cpu().numpy(), go)
+    assert same(lam.cpu().numpy().reshape(1, -1), lo)
+
+
+@pytest.mark.parametrize("n", [(9, 7), (9, 7, 5)])
+def test_adjoint_without_boundary_is_the_seed(n):
+    """No Gamma: every node unreached (u = +inf), no equation anywhere, so
+    lambda = dL/du and dL/dr = 0, as in the oracle."""
+    p = W.random_problem(28, n, 1, 1)
+    r = dev(p.r, np.float64)
+    gams = [(torch.zeros(0, dtype=torch.int64).cuda(), torch.zeros(0, dtype=torch.float64).cuda())]
+    u, _, _ = E.solve(r, gams[0][0], gams[0][1], p.h)
+    assert torch.isinf(u).all()
+    seed_ = torch.from_numpy(np.random.default_rng(29).uniform(-1, 1, (1,) + p.r.shape)).cuda()
+    grad, lam, info = E.adjoint(r, gams, u.reshape((1,) + p.r.shape), seed_, p.h, with_lambda=True)
+    assert info["converged"]
+    assert torch.equal(lam, seed_) and torch.count_nonzero(grad) == 0
+    go, lo, _ = oracle.adjoint(p.n, p.h, p.r, [np.zeros(0, dtype=np.int64)], u.cpu().numpy().reshape(1, -1),
+                               seed_.cpu().numpy().reshape(1, -1))
+    assert same(lo, lam.cpu().numpy().reshape(1, -1)) and same(go, grad.cpu().numpy().reshape(-1))
