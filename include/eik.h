@@ -142,8 +142,10 @@ typedef struct {
  *                          stream-launched iterations.
  *   EIK_LAUNCH_PERSISTENT  eik_dd_solve_batch (from the first problem's
  *                          options): Steps 3 and 4 run on a grid of the
- *                          blocks that are resident at once, each taking the
- *                          (problem, box) items in order from a counter. */
+ *                          blocks that are resident at once (at most
+ *                          persistent_blocks per compute unit when that is
+ *                          set), each taking the (problem, box) items in
+ *                          order from a counter. */
 #define EIK_LAUNCH_STREAM 0
 #define EIK_LAUNCH_GRAPH 1
 #define EIK_LAUNCH_PERSISTENT 2
