@@ -43,7 +43,7 @@ OPS_PER_CORRECTION = 18
 # flops and packed fp32 as two lanes; 78.6 TFLOP/s fp64 counts the FMA).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Instructions on the dependency path that carries a lane's value from one
-# anti-diagonal step to the next, counted in this build's gfx950 ISA of the
+# anti-diagonal step to the next, counted in the library's gfx950 ISA of the
 # fp32 step loops (DPP receive, neighbour minimum, local solve with the
 # correctly rounded square root, the minimum / weighted assignment, the
 # lane's carried value); each costs at least one dependent-issue latency.
@@ -468,7 +468,7 @@ def main():
         copy_calibration()
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {a.gpus}); the DD "
+        print(f"bench.py: the solver runs on one GPU only (got --gpus {a.gpus}); the DD "
               "path would shard subdomains across GPUs with one skeleton exchange per "
               "iteration, which is not built.", file=sys.stderr)
         sys.exit(2)

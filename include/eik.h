@@ -44,7 +44,7 @@ typedef int32_t eik_status;
 #define EIK_ERR_SHAPE (-2)        /* (n-1) % S != 0, S % M != 0, M < 2, extents too small */
 #define EIK_ERR_NOCONV (-3)       /* max_iter reached without max|U^{k+1}-U^k| < tol; outputs and stats ARE written */
 #define EIK_ERR_HIP (-4)          /* a HIP runtime call failed */
-#define EIK_ERR_UNSUPPORTED (-5)  /* valid problem outside what this build implements (see eik_last_error) */
+#define EIK_ERR_UNSUPPORTED (-5)  /* valid problem outside what this library implements (see eik_last_error) */
 #define EIK_ERR_NONFINITE (-6)    /* the residual became NaN */
 #define EIK_ERR_INTERNAL (-7)     /* an internal bound was exceeded (a wait between the two waves of a 2D box sweep
                                      gave up); outputs unspecified */
@@ -231,7 +231,7 @@ eik_status eik_solve(const eik_grid* grid, const void* r, const eik_gamma* gamma
  *   W_out  device, N int8 codes or NULL: W of the last iterate
  * Resume: passing (U_out, W_out) of a run as opts->U_init/W_init continues
  * it exactly (the iteration reads nothing else).
- * This build: d = 2 with subdomain side S+1 <= 65 nodes and lattice extents
+ * Limits: d = 2 with subdomain side S+1 <= 65 nodes and lattice extents
  * (n-1)/M + 1 <= 65; d = 3 with S+1 <= 34 and (n-1)/M + 1 <= 34 and the box
  * in 160 KB of LDS ((S+1)^3 values of the grid dtype); with a non-constant
  * theta_mode on 65-node lattices in fp64, Step 4 keeps its per-node weight

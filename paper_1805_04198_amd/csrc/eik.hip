@@ -291,7 +291,7 @@ eik_status dd_solve_t(const eik_grid* G, const void* rv, const eik_gamma* gam, c
   const int nC = (NI + 1) * (NJ + 1);
   const size_t lds_cb = eik::corner_lds_bytes(NI + 1, NJ + 1, szT);
   if (lds_tile > kLdsBytes || lds_cb > kLdsBytes)
-    return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this build");
+    return fail(EIK_ERR_UNSUPPORTED, "LDS footprint too large for this library");
   if (lds_lat > kLdsBytes)
     return fail(EIK_ERR_UNSUPPORTED, "coarse lattice of %d x %d nodes does not fit in LDS%s", NI + 1, NJ + 1,
                 tmode ? " with a varying theta in this precision" : "");
