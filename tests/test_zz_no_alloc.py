@@ -52,3 +52,17 @@ def test_noalloc_rejects_a_problem_beyond_its_scratch():
         E.dd_solve(r, gi, gv, 1.0 / (n - 1), 64, 32, theta=0.1, max_iter=1, noalloc=True)
     assert ex.value.status == E.EIK_ERR_UNSUPPORTED
     assert "scratch" in str(ex.value)
+
+
+def test_noalloc_varying_weight_on_65_node_lattices_fp64():
+    """fp64 with the estimated weight on 65-node lattices keeps Step 4's
+    weight terms in global memory: in the allocation-free call they come
+    from the same scratch array; twice, the second problem smaller."""
+    big = W.random_problem(12, (129, 129), 16, 2, n_src=2, kind="fourier")
+    small = W.random_problem(13, (65, 129), 16, 2, n_src=1, kind="blocks")
+    for p in (big, small):
+        r, gi, gv = _inputs(p, np.float64)
+        kw = dict(theta=0.3, tol=1e-12, max_iter=8, theta_mode="estimate")
+        ref = E.dd_solve(r, gi, gv, p.h, p.S, p.M, **kw)
+        got = E.dd_solve(r, gi, gv, p.h, p.S, p.M, noalloc=True, **kw)
+        _check_same(got, ref)
