@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -1131,6 +1132,7 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   need += 2 * (N * 8 + 256);
   need += (size_t)ntile * 6 * L * L * (szT + 1) + 512;
   need += (size_t)ntile * L * L * L + 256;
+  need += 2 * ((size_t)ntile * sizeof(int) + 256);  // subdomain order and sweep counts
   need += 4096;
   if (tmode == EIK_THETA_ESTIMATE) need += 3 * (N * szT + 256);  // u^{k-1} and two more C arrays
   const int ncell = (NC[0] + 1) * (NC[1] + 1) * (NC[2] + 1);
@@ -1171,6 +1173,16 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   A.face_u = cv.take<T>((size_t)ntile * 6 * L * L);
   A.face_w = cv.take<uint8_t>((size_t)ntile * 6 * L * L);
   A.tile_w = cv.take<uint8_t>((size_t)ntile * L * L * L);
+  // Step 3 runs one subdomain per compute unit at a time (a subdomain fills
+  // its LDS), so with more subdomains than compute units the launch ends
+  // with the last ones started.  Each iteration takes them longest first,
+  // by the time each took in the previous one (the first iteration in index
+  // order): that changes when a subdomain runs, not what it computes.
+  int* tile_order = cv.take<int>(ntile);
+  A.tile_time = cv.take<int>(ntile);
+  A.tile_order = tile_order;
+  std::vector<int> order_h(ntile), time_h(ntile);
+  for (int i = 0; i < ntile; ++i) order_h[i] = i;
   A.cvals = nullptr;
   A.counters = cv.take<unsigned long long>(4);
   A.rec_stride = rec_stride;
@@ -1272,6 +1284,9 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
   int it = 0, conv = 0;
   double last = 0.0;
   for (int k = 0; k < o->max_iter; ++k) {
+    // the order (host memory read by the copy) changes only after the
+    // stream has been synchronised again
+    HIPCHK(hipMemcpyAsync(tile_order, order_h.data(), (size_t)ntile * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL(eik::k_tile3<T>, dim3(ntile), dim3(eik::kBlock3), lds_tile, s, A);
     HIPCHK(hipEventRecord(ev[2], s));
@@ -1295,7 +1310,10 @@ eik_status dd_solve3_t(const eik_grid* G, const void* rv, const eik_gamma* gam, 
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], s));
     HIPCHK(hipMemcpyAsync(host, &A.counters[2], sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(time_h.data(), A.tile_time, (size_t)ntile * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    std::iota(order_h.begin(), order_h.end(), 0);
+    std::stable_sort(order_h.begin(), order_h.end(), [&](int x, int y) { return time_h[x] > time_h[y]; });
     float a = 0.f, b = 0.f, c = 0.f;
     HIPCHK(hipEventElapsedTime(&a, ev[1], ev[2]));
     HIPCHK(hipEventElapsedTime(&b, ev[2], ev[4]));

@@ -137,6 +137,8 @@ struct DD3 {
   T* face_u;          // [tile][6][(S+1)^2]
   uint8_t* face_w;
   uint8_t* tile_w;    // [tile][(S+1)^3] winds of the subdomain sweep
+  const int* tile_order;  // block b sweeps subdomain tile_order[b] (NULL: b)
+  int* tile_time;         // [tile] duration of the subdomain's last block, 10 ns units (NULL: not kept)
   T* cvals;           // causal sweep scratch: V per coarse node (full grid)
   unsigned long long* near_key;
   long long* near_win;
@@ -544,7 +546,8 @@ template <typename T>
 __global__ __launch_bounds__(kBlock3) void k_tile3(DD3<T> A) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int L = A.S + 1;
-  const int tile = blockIdx.x;
+  const long long t_start = (long long)wall_clock64();  // constant 100 MHz clock
+  const int tile = A.tile_order ? A.tile_order[blockIdx.x] : (int)blockIdx.x;
   const int T0 = tile % A.P[0], T1 = (tile / A.P[0]) % A.P[1], T2 = tile / (A.P[0] * A.P[1]);
   const int b0 = T0 * A.S, b1 = T1 * A.S, b2 = T2 * A.S;
   const int cnt = L * L * L;
@@ -625,6 +628,7 @@ __global__ __launch_bounds__(kBlock3) void k_tile3(DD3<T> A) {
   if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&sh_free, nfree);
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(&A.counters[0], (unsigned long long)sh_free * (unsigned long long)ns);
+  if (threadIdx.x == 0 && A.tile_time) A.tile_time[tile] = (int)((long long)wall_clock64() - t_start);
 }
 
 // Reconciliation at every interface node (up to 8 candidates: the subdomains
